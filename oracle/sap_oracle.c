@@ -1,0 +1,555 @@
+/*
+ * Plain CPU oracle for sketch-and-precondition least squares with sparse sign
+ * sketches (Chen, Epperly, et al., arXiv 2506.03070).
+ *
+ * TEST INFRASTRUCTURE ONLY. Nothing in the product library links, calls or
+ * includes this file; only the test suite, the smoke check and the CPU
+ * baseline leg of the benchmark use it.  It shares no code, header, table or
+ * constant generator with the HIP path.
+ *
+ * Everything is double precision, single-threaded and written in the order of
+ * the paper's definitions so that it can be checked against the paper by eye:
+ *
+ *   - Philox4x64-10 counter-based RNG (Salmon, Moraes, Dror, Shaw, SC'11).
+ *     The paper does not name its generator (Alg. 3 draws with a library
+ *     randint), so the stream layout below is this project's reading.
+ *   - Lemire's multiply-shift bounded integer with rejection (ACM TOMACS 2019)
+ *     for exactly uniform draws in [0, d).
+ *   - Rejection-sampled column generation (Sec. 3.1.2 and Alg. 3): draw zeta
+ *     rows with replacement, sort, redraw the first entry of every equal
+ *     neighbour pair, repeat until distinct.  Signs +-1/sqrt(zeta) (Alg. 3),
+ *     attached to the sorted positions.
+ *   - Sketch apply Y = S [A b] (Alg. 1, "Form Y = SA"), dense and sparse route.
+ *   - Unblocked Householder QR with the LAPACK dlarfg sign convention
+ *     (Alg. 1, "Factor Q, R = QR(Y)").
+ *   - Back / forward substitution with R and R^T (the preconditioner M = R^-1
+ *     of Alg. 1 applied by triangular solves).
+ *   - Preconditioned LSQR exactly as Alg. 2 (Paige & Saunders 1982).
+ *   - The whole of Alg. 1, and a direct Householder solve of [A b] for tiny
+ *     problems.
+ *
+ * Parity pins for each function live in the CPU test suite.
+ */
+#define _POSIX_C_SOURCE 199309L
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#include <time.h>
+
+typedef unsigned __int128 orc_u128;
+
+/* ------------------------------------------------------------------------ */
+/* Philox4x64-10 (SC'11, Sec. 5): two 64x64->128 multiplies per round, key    */
+/* bumped by the Weyl constants between rounds.                               */
+/* ------------------------------------------------------------------------ */
+#define ORC_PHILOX_M0 0xD2E7470EE14C6C93ULL
+#define ORC_PHILOX_M1 0xCA5A826395121157ULL
+#define ORC_PHILOX_W0 0x9E3779B97F4A7C15ULL
+#define ORC_PHILOX_W1 0xBB67AE8584CAA73BULL
+
+void orc_philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4])
+{
+    uint64_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
+    uint64_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) {
+            k0 += ORC_PHILOX_W0;
+            k1 += ORC_PHILOX_W1;
+        }
+        orc_u128 prod0 = (orc_u128)ORC_PHILOX_M0 * x0;
+        orc_u128 prod1 = (orc_u128)ORC_PHILOX_M1 * x2;
+        uint64_t y0 = (uint64_t)(prod1 >> 64) ^ x1 ^ k0;
+        uint64_t y1 = (uint64_t)prod1;
+        uint64_t y2 = (uint64_t)(prod0 >> 64) ^ x3 ^ k1;
+        uint64_t y3 = (uint64_t)prod0;
+        x0 = y0; x1 = y1; x2 = y2; x3 = y3;
+    }
+    out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
+}
+
+/* Stream layout (project reading; the paper leaves the generator open):
+ *   key     = (seed, stream)
+ *   w(i,r,j,k) = word (j mod 4) of Philox(key, counter = (i, r, floor(j/4), k))
+ *   column i's sign word = word 0 of Philox(key, counter = (i, 2^64-1, 0, 0))   */
+uint64_t orc_word(uint64_t seed, uint64_t stream, uint64_t i, uint64_t r, uint64_t j, uint64_t k)
+{
+    uint64_t ctr[4] = {i, r, j / 4, k};
+    uint64_t key[2] = {seed, stream};
+    uint64_t out[4];
+    orc_philox4x64_10(ctr, key, out);
+    return out[j % 4];
+}
+
+uint64_t orc_sign_word(uint64_t seed, uint64_t stream, uint64_t i)
+{
+    uint64_t ctr[4] = {i, ~(uint64_t)0, 0, 0};
+    uint64_t key[2] = {seed, stream};
+    uint64_t out[4];
+    orc_philox4x64_10(ctr, key, out);
+    return out[0];
+}
+
+/* One step of Lemire's method: returns 1 and writes floor(w*d / 2^64) when the
+ * low half of w*d is at least (2^64 - d) mod d, else returns 0 (reject). */
+int orc_lemire_step(uint64_t w, uint64_t d, uint64_t *value)
+{
+    orc_u128 prod = (orc_u128)w * d;
+    uint64_t low = (uint64_t)prod;
+    uint64_t threshold = (0 - d) % d; /* (2^64 - d) mod d */
+    if (low < threshold)
+        return 0;
+    *value = (uint64_t)(prod >> 64);
+    return 1;
+}
+
+/* U(i,r,j): exactly uniform in [0,d) from the words w(i,r,j,k), k = 0,1,... */
+uint64_t orc_bounded(uint64_t seed, uint64_t stream, uint64_t i, uint64_t r, uint64_t j, uint64_t d)
+{
+    uint64_t value = 0;
+    for (uint64_t k = 0;; ++k) {
+        if (orc_lemire_step(orc_word(seed, stream, i, r, j, k), d, &value))
+            return value;
+    }
+}
+
+static void orc_sort_ascending(int64_t *c, int n)
+{
+    /* insertion sort: the columns hold at most 64 entries */
+    for (int a = 1; a < n; ++a) {
+        int64_t key = c[a];
+        int b = a - 1;
+        while (b >= 0 && c[b] > key) {
+            c[b + 1] = c[b];
+            --b;
+        }
+        c[b + 1] = key;
+    }
+}
+
+#define ORC_MAX_ZETA 64
+#define ORC_MAX_ROUNDS (1 << 16)
+
+/* Column i of the sparse sign sketch (Sec. 3.1.2 steps (i)-(iv); Alg. 3).
+ * Writes zeta ascending distinct rows and the sign word masked to zeta bits.
+ * Returns the number of redraw rounds used, or -1 on invalid arguments or if
+ * the round cap is hit (which needs zeta close to d and astronomically bad
+ * luck).  Redraw rule: on the sorted column, every position j with
+ * c[j] == c[j+1] (found before any replacement) is redrawn from U(i, r, j). */
+int orc_sketch_column(uint64_t seed, uint64_t stream, uint64_t i, int32_t d, int32_t zeta,
+                      int32_t *idx_out, uint64_t *sign_out)
+{
+    if (zeta < 1 || zeta > ORC_MAX_ZETA || d < zeta)
+        return -1;
+    int64_t c[ORC_MAX_ZETA];
+    int dup[ORC_MAX_ZETA];
+    for (int j = 0; j < zeta; ++j)
+        c[j] = (int64_t)orc_bounded(seed, stream, i, 0, (uint64_t)j, (uint64_t)d);
+    orc_sort_ascending(c, zeta);
+    int rounds = 0;
+    for (uint64_t r = 1;; ++r) {
+        int any = 0;
+        for (int j = 0; j + 1 < zeta; ++j) {
+            dup[j] = (c[j] == c[j + 1]);
+            any |= dup[j];
+        }
+        if (!any)
+            break;
+        if (r >= ORC_MAX_ROUNDS)
+            return -1;
+        for (int j = 0; j + 1 < zeta; ++j)
+            if (dup[j])
+                c[j] = (int64_t)orc_bounded(seed, stream, i, r, (uint64_t)j, (uint64_t)d);
+        orc_sort_ascending(c, zeta);
+        rounds = (int)r;
+    }
+    for (int j = 0; j < zeta; ++j)
+        idx_out[j] = (int32_t)c[j];
+    uint64_t mask = (zeta == 64) ? ~(uint64_t)0 : (((uint64_t)1 << zeta) - 1);
+    *sign_out = orc_sign_word(seed, stream, i) & mask;
+    return rounds;
+}
+
+/* The whole sketch: idx is m x zeta (row i = column i of S), sign has m words.
+ * rounds_out (nullable) receives the per-column round counts.  Returns 0, or
+ * -1 on invalid arguments. */
+int orc_sketch(uint64_t seed, uint64_t stream, int64_t m, int32_t d, int32_t zeta,
+               int32_t *idx, uint64_t *sign, int32_t *rounds_out)
+{
+    for (int64_t i = 0; i < m; ++i) {
+        int rr = orc_sketch_column(seed, stream, (uint64_t)i, d, zeta, idx + i * zeta, sign + i);
+        if (rr < 0)
+            return -1;
+        if (rounds_out)
+            rounds_out[i] = rr;
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Sketch apply Y = h * sum_i sum_k s_ik e_{idx[i][k]} [A b](i, :)            */
+/* h = 1/sqrt(zeta) (Alg. 3 values), s_ik = +1 if bit k of sign[i] else -1.   */
+/* A is row-major m x n (lda), b has m entries (nullable: then only n columns */
+/* are formed), Y is column-major d x ncols (ldy).                            */
+/* ------------------------------------------------------------------------ */
+
+/* Sparse route: accumulate with i ascending, k ascending; scale once at the
+ * end.  cols (nullable) restricts the work to a list of ncols_sel columns of
+ * [A b]; column c of the selection goes to Y column c. */
+void orc_apply_sparse(int64_t m, int32_t d, int32_t zeta, const int32_t *idx, const uint64_t *sign,
+                      const double *A, int64_t lda, const double *b, int32_t n, double h,
+                      double *Y, int64_t ldy, const int32_t *cols, int32_t ncols_sel)
+{
+    int32_t ncols = cols ? ncols_sel : (b ? n + 1 : n);
+    for (int32_t cc = 0; cc < ncols; ++cc)
+        for (int32_t r = 0; r < d; ++r)
+            Y[r + (int64_t)cc * ldy] = 0.0;
+    for (int64_t i = 0; i < m; ++i) {
+        for (int32_t cc = 0; cc < ncols; ++cc) {
+            int32_t c = cols ? cols[cc] : cc;
+            double a = (c < n) ? A[i * lda + c] : b[i];
+            for (int k = 0; k < zeta; ++k) {
+                int32_t r = idx[i * zeta + k];
+                double s = ((sign[i] >> k) & 1) ? 1.0 : -1.0;
+                Y[r + (int64_t)cc * ldy] += s * a;
+            }
+        }
+    }
+    for (int32_t cc = 0; cc < ncols; ++cc)
+        for (int32_t r = 0; r < d; ++r)
+            Y[r + (int64_t)cc * ldy] *= h;
+}
+
+/* Dense route: build the +-1 pattern of S (d x m) explicitly, triple loop,
+ * then scale by h.  For small m only. */
+void orc_apply_dense(int64_t m, int32_t d, int32_t zeta, const int32_t *idx, const uint64_t *sign,
+                     const double *A, int64_t lda, const double *b, int32_t n, double h,
+                     double *Y, int64_t ldy)
+{
+    int32_t ncols = b ? n + 1 : n;
+    double *S = (double *)calloc((size_t)d * (size_t)m, sizeof(double));
+    for (int64_t i = 0; i < m; ++i)
+        for (int k = 0; k < zeta; ++k)
+            S[(int64_t)idx[i * zeta + k] * m + i] = ((sign[i] >> k) & 1) ? 1.0 : -1.0;
+    for (int32_t r = 0; r < d; ++r) {
+        for (int32_t c = 0; c < ncols; ++c) {
+            double acc = 0.0;
+            for (int64_t i = 0; i < m; ++i) {
+                double a = (c < n) ? A[i * lda + c] : b[i];
+                acc += S[(int64_t)r * m + i] * a;
+            }
+            Y[r + (int64_t)c * ldy] = h * acc;
+        }
+    }
+    free(S);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Householder QR (Golub & Van Loan, Alg. 5.2.1) with the LAPACK dlarfg sign  */
+/* convention: beta = -sign(alpha) * ||(alpha, x)||, tau = (beta - alpha) /    */
+/* beta, v = (1, x / (alpha - beta)).  In place on Y (rows x cols, ldy):      */
+/* R in the upper triangle, v below the diagonal, tau[k] per reflector.       */
+/* ------------------------------------------------------------------------ */
+void orc_householder_qr(double *Y, int64_t ldy, int32_t rows, int32_t cols, double *tau)
+{
+    int32_t kmax = rows < cols ? rows : cols;
+    for (int32_t k = 0; k < kmax; ++k) {
+        double *col = Y + (int64_t)k * ldy;
+        double alpha = col[k];
+        double ss = 0.0;
+        for (int32_t i = k + 1; i < rows; ++i)
+            ss += col[i] * col[i];
+        if (ss == 0.0) {
+            tau[k] = 0.0; /* H = I */
+            continue;
+        }
+        double norm = sqrt(alpha * alpha + ss);
+        double beta = (alpha >= 0.0) ? -norm : norm;
+        tau[k] = (beta - alpha) / beta;
+        double scale = 1.0 / (alpha - beta);
+        for (int32_t i = k + 1; i < rows; ++i)
+            col[i] *= scale;
+        col[k] = beta;
+        for (int32_t j = k + 1; j < cols; ++j) {
+            double *cj = Y + (int64_t)j * ldy;
+            double w = cj[k];
+            for (int32_t i = k + 1; i < rows; ++i)
+                w += col[i] * cj[i];
+            cj[k] -= tau[k] * w;
+            for (int32_t i = k + 1; i < rows; ++i)
+                cj[i] -= tau[k] * w * col[i];
+        }
+    }
+}
+
+/* Solve R x = rhs, R upper triangular n x n stored column-major in the upper
+ * triangle of (R, ldr).  Row k: x_k = (rhs_k - sum_{j>k} R[k,j] x_j) / R[k,k],
+ * inner sum with j ascending. */
+void orc_backsub(const double *R, int64_t ldr, int32_t n, const double *rhs, double *x)
+{
+    for (int32_t k = n - 1; k >= 0; --k) {
+        double acc = rhs[k];
+        for (int32_t j = k + 1; j < n; ++j)
+            acc -= R[k + (int64_t)j * ldr] * x[j];
+        x[k] = acc / R[k + (int64_t)k * ldr];
+    }
+}
+
+/* Solve R^T y = rhs (forward substitution with the lower triangular R^T). */
+void orc_forwardsub_t(const double *R, int64_t ldr, int32_t n, const double *rhs, double *y)
+{
+    for (int32_t k = 0; k < n; ++k) {
+        double acc = rhs[k];
+        for (int32_t j = 0; j < k; ++j)
+            acc -= R[j + (int64_t)k * ldr] * y[j];
+        y[k] = acc / R[k + (int64_t)k * ldr];
+    }
+}
+
+/* y = A x (row dots, columns ascending) and y = A^T u (rows ascending). */
+void orc_matvec(int64_t m, int32_t n, const double *A, int64_t lda, const double *x, double *y)
+{
+    for (int64_t i = 0; i < m; ++i) {
+        double acc = 0.0;
+        for (int32_t c = 0; c < n; ++c)
+            acc += A[i * lda + c] * x[c];
+        y[i] = acc;
+    }
+}
+
+void orc_matvec_t(int64_t m, int32_t n, const double *A, int64_t lda, const double *u, double *y)
+{
+    for (int32_t c = 0; c < n; ++c)
+        y[c] = 0.0;
+    for (int64_t i = 0; i < m; ++i)
+        for (int32_t c = 0; c < n; ++c)
+            y[c] += A[i * lda + c] * u[i];
+}
+
+static double orc_nrm2(int64_t n, const double *x)
+{
+    double s = 0.0;
+    for (int64_t i = 0; i < n; ++i)
+        s += x[i] * x[i];
+    return sqrt(s);
+}
+
+/* LSQR result record shared with the Python wrapper. */
+typedef struct orc_lsqr_info {
+    int32_t iters;     /* iterations taken */
+    int32_t converged; /* 1 when a stopping test fired before maxiter */
+    double resid_est;  /* phibar_{t+1} = ||b - A x_t|| estimate */
+    double normar_est; /* phibar_{t+1} alpha_{t+1} |c_t| = ||(AM)^T r_t|| estimate */
+} orc_lsqr_info;
+
+/* Preconditioned LSQR, Alg. 2, on the operator A M with M = R^-1 applied by
+ * triangular solves.  history (nullable, maxiter+1 rows of n) receives x_0,
+ * x_1, ... for iterate-level comparisons.
+ *
+ * Stopping (the paper only says "test for convergence"; reading after Paige &
+ * Saunders with ||AM|| ~ 1 from Lemma 2.4): stop after iteration t when
+ *   alpha_{t+1} |c_t| <= tol          (relative normal-equation residual), or
+ *   phibar_{t+1} <= tol * ||b||       (compatible system), or
+ *   beta_{t+1} == 0 or alpha_{t+1} == 0 (breakdown: x_t is exact).
+ * maxiter <= 0 runs no iteration and returns x0. */
+void orc_lsqr(int64_t m, int32_t n, const double *A, int64_t lda, const double *b,
+              const double *R, int64_t ldr, const double *x0, double tol, int32_t maxiter,
+              double *x, double *history, orc_lsqr_info *info)
+{
+    double *u = (double *)malloc(sizeof(double) * (size_t)m);
+    double *v = (double *)malloc(sizeof(double) * (size_t)n);
+    double *w = (double *)malloc(sizeof(double) * (size_t)n);
+    double *p = (double *)malloc(sizeof(double) * (size_t)n);
+    double *t1 = (double *)malloc(sizeof(double) * (size_t)n);
+    double *t2 = (double *)malloc(sizeof(double) * (size_t)n);
+
+    memcpy(x, x0, sizeof(double) * (size_t)n);
+    if (history)
+        memcpy(history, x0, sizeof(double) * (size_t)n);
+    info->iters = 0;
+    info->converged = 0;
+    double normb = orc_nrm2(m, b);
+
+    /* beta_1 u_1 = b - A x_0 */
+    orc_matvec(m, n, A, lda, x0, u);
+    for (int64_t i = 0; i < m; ++i)
+        u[i] = b[i] - u[i];
+    double beta = orc_nrm2(m, u);
+    info->resid_est = beta;
+    info->normar_est = 0.0;
+    if (beta == 0.0 || maxiter <= 0) {
+        info->converged = (beta == 0.0);
+        goto done;
+    }
+    for (int64_t i = 0; i < m; ++i)
+        u[i] /= beta;
+    /* alpha_1 v_1 = M^T A^T u_1 */
+    orc_matvec_t(m, n, A, lda, u, t1);
+    orc_forwardsub_t(R, ldr, n, t1, t2);
+    double alpha = orc_nrm2(n, t2);
+    info->normar_est = alpha * beta;
+    if (alpha == 0.0) {
+        info->converged = 1;
+        goto done;
+    }
+    for (int32_t c = 0; c < n; ++c)
+        v[c] = t2[c] / alpha;
+    /* w_1 = M v_1 */
+    orc_backsub(R, ldr, n, v, w);
+    memcpy(p, w, sizeof(double) * (size_t)n);
+    double phibar = beta, rhobar = alpha;
+
+    {
+        double *Ap = (double *)malloc(sizeof(double) * (size_t)m);
+        for (int32_t t = 1; t <= maxiter; ++t) {
+            /* u_hat = A M v_t - alpha_t u_t ; beta_{t+1} = ||u_hat|| */
+            orc_matvec(m, n, A, lda, p, Ap);
+            for (int64_t i = 0; i < m; ++i)
+                Ap[i] -= alpha * u[i];
+            beta = orc_nrm2(m, Ap);
+            double alpha_next = 0.0;
+            if (beta != 0.0) {
+                for (int64_t i = 0; i < m; ++i)
+                    u[i] = Ap[i] / beta;
+                /* v_hat = M^T A^T u_{t+1} - beta_{t+1} v_t ; alpha_{t+1} = ||v_hat|| */
+                orc_matvec_t(m, n, A, lda, u, t1);
+                orc_forwardsub_t(R, ldr, n, t1, t2);
+                for (int32_t c = 0; c < n; ++c)
+                    t2[c] -= beta * v[c];
+                alpha_next = orc_nrm2(n, t2);
+                if (alpha_next != 0.0)
+                    for (int32_t c = 0; c < n; ++c)
+                        v[c] = t2[c] / alpha_next;
+            }
+            /* plane rotation */
+            double rho = sqrt(rhobar * rhobar + beta * beta);
+            double cs = rhobar / rho;
+            double sn = beta / rho;
+            double theta = sn * alpha_next;
+            rhobar = -cs * alpha_next;
+            double phi = cs * phibar;
+            phibar = sn * phibar;
+            /* x_t = x_{t-1} + (phi_t / rho_t) w_t */
+            for (int32_t c = 0; c < n; ++c)
+                x[c] += (phi / rho) * w[c];
+            /* w_{t+1} = M v_{t+1} - (theta_{t+1} / rho_t) w_t */
+            if (alpha_next != 0.0 && beta != 0.0) {
+                orc_backsub(R, ldr, n, v, p);
+                for (int32_t c = 0; c < n; ++c)
+                    w[c] = p[c] - (theta / rho) * w[c];
+            }
+            alpha = alpha_next;
+            info->iters = t;
+            info->resid_est = phibar;
+            info->normar_est = phibar * alpha * fabs(cs);
+            if (history)
+                memcpy(history + (int64_t)t * n, x, sizeof(double) * (size_t)n);
+            if (beta == 0.0 || alpha == 0.0 || alpha * fabs(cs) <= tol || phibar <= tol * normb) {
+                info->converged = 1;
+                break;
+            }
+        }
+        free(Ap);
+    }
+done:
+    free(u); free(v); free(w); free(p); free(t1); free(t2);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Alg. 1 end to end.                                                         */
+/* ------------------------------------------------------------------------ */
+typedef struct orc_solve_info {
+    int32_t status;    /* 0 ok, 3 rank deficient, 4 not converged, 1 invalid */
+    int32_t iters;
+    double resid_est;
+    double normar_est;
+    double t_generate, t_apply, t_qr, t_iterate; /* seconds */
+} orc_solve_info;
+
+static double orc_now(void)
+{
+    struct timespec ts;
+    clock_gettime(CLOCK_MONOTONIC, &ts);
+    return (double)ts.tv_sec + 1e-9 * (double)ts.tv_nsec;
+}
+
+/* Rank test (the paper is silent; reading): R is declared rank deficient when
+ * min_k |R_kk| <= d * 2^-53 * max_k |R_kk|. */
+int orc_rank_deficient(const double *R, int64_t ldr, int32_t n, int32_t d)
+{
+    double mx = 0.0, mn = INFINITY;
+    for (int32_t k = 0; k < n; ++k) {
+        double a = fabs(R[k + (int64_t)k * ldr]);
+        if (a > mx) mx = a;
+        if (a < mn) mn = a;
+    }
+    return !(mn > (double)d * ldexp(1.0, -53) * mx);
+}
+
+/* Sample S, form Y = S[A b], QR of Y, x0 = R^-1 (Q^T S b)[0:n], LSQR.
+ * Y_out (nullable, d x (n+1) column-major, ld d) receives the factored Y
+ * (R in the upper triangle).  x receives the solution. */
+void orc_solve(int64_t m, int32_t n, const double *A, int64_t lda, const double *b,
+               int32_t d, int32_t zeta, uint64_t seed, double tol, int32_t maxiter,
+               double *x, double *x0_out, double *Y_out, orc_solve_info *info)
+{
+    memset(info, 0, sizeof(*info));
+    if (zeta < 1 || zeta > ORC_MAX_ZETA || d < zeta || d < n + 1 || m < 1 || n < 1) {
+        info->status = 1;
+        return;
+    }
+    int32_t nc = n + 1;
+    int32_t *idx = (int32_t *)malloc(sizeof(int32_t) * (size_t)m * (size_t)zeta);
+    uint64_t *sign = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)m);
+    double *Y = (double *)malloc(sizeof(double) * (size_t)d * (size_t)nc);
+    double *tau = (double *)malloc(sizeof(double) * (size_t)nc);
+    double *x0 = (double *)malloc(sizeof(double) * (size_t)n);
+
+    double t0 = orc_now();
+    orc_sketch(seed, 0, m, d, zeta, idx, sign, NULL);
+    double t1 = orc_now();
+    orc_apply_sparse(m, d, zeta, idx, sign, A, lda, b, n, 1.0 / sqrt((double)zeta), Y, d, NULL, 0);
+    double t2 = orc_now();
+    orc_householder_qr(Y, d, d, nc, tau);
+    double t3 = orc_now();
+    info->t_generate = t1 - t0;
+    info->t_apply = t2 - t1;
+    info->t_qr = t3 - t2;
+    if (orc_rank_deficient(Y, d, n, d)) {
+        info->status = 3;
+    } else {
+        /* x0 = R^-1 z with z = (Q^T S b)[0:n] = column n of the factored Y */
+        orc_backsub(Y, d, n, Y + (int64_t)n * d, x0);
+        if (x0_out)
+            memcpy(x0_out, x0, sizeof(double) * (size_t)n);
+        orc_lsqr_info li;
+        orc_lsqr(m, n, A, lda, b, Y, d, x0, tol, maxiter, x, NULL, &li);
+        info->iters = li.iters;
+        info->resid_est = li.resid_est;
+        info->normar_est = li.normar_est;
+        info->status = li.converged ? 0 : 4;
+    }
+    info->t_iterate = orc_now() - t3;
+    if (Y_out)
+        memcpy(Y_out, Y, sizeof(double) * (size_t)d * (size_t)nc);
+    free(idx); free(sign); free(Y); free(tau); free(x0);
+}
+
+/* Direct solve of min ||b - A x|| by Householder QR of [A b] (m x (n+1)),
+ * then back substitution: the textbook method of the paper's introduction,
+ * used as a reference on tiny inputs.  A is row-major; it is copied. */
+void orc_direct_solve(int64_t m, int32_t n, const double *A, int64_t lda, const double *b, double *x)
+{
+    int32_t nc = n + 1;
+    double *W = (double *)malloc(sizeof(double) * (size_t)m * (size_t)nc);
+    double *tau = (double *)malloc(sizeof(double) * (size_t)nc);
+    for (int64_t i = 0; i < m; ++i) {
+        for (int32_t c = 0; c < n; ++c)
+            W[i + (int64_t)c * m] = A[i * lda + c];
+        W[i + (int64_t)n * m] = b[i];
+    }
+    orc_householder_qr(W, m, (int32_t)m, nc, tau);
+    orc_backsub(W, m, n, W + (int64_t)n * m, x);
+    free(W);
+    free(tau);
+}
