@@ -1,0 +1,203 @@
+/*
+ * sap.h - C ABI of the MI355X (gfx950) sketch-and-precondition least-squares
+ * library.
+ *
+ * The library solves the overdetermined least-squares problem
+ *     min_x || b - A x ||,   A in R^{m x n}, m >> n          (paper eq. 1.1)
+ * with the sketch-and-precondition method of Alg. 1: sample a sparse sign
+ * sketch S (Def. 2.2; rejection sampling of Sec. 3.1.2 / Alg. 3), form
+ * Y = S [A b], take the Householder QR of Y, use M = R^-1 as a right
+ * preconditioner and x0 = M (Q^T S b) as the initial guess, then run
+ * preconditioned LSQR (Alg. 2).
+ *
+ * Conventions shared by every call:
+ *   - Pointers named as device pointers must point to device memory of the
+ *     context's GPU.  All of them are owned by the caller; the library never
+ *     frees or retains them beyond the call (sap_submit: until sap_poll
+ *     reports a terminal status).  The library owns only its internal
+ *     workspace, bounded by the context's HBM budget.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *     Calls enqueue their kernels on it; a call returns when the documented
+ *     result is available unless it says it is asynchronous.
+ *   - Matrices: A is row-major m x n with leading dimension lda >= n
+ *     (element (i, j) at A[i*lda + j]).  Y and R are column-major
+ *     (element (r, c) at Y[r + c*ldy]).
+ *   - Errors: every call returns a sap_status; no exception crosses the ABI.
+ *     On SAP_EINVAL / SAP_ENOMEM outputs are untouched.  sap_last_error()
+ *     gives a human-readable reason for the last failure on that context.
+ *   - Threads: one caller per context at a time, except sap_submit /
+ *     sap_poll / sap_cancel which are thread-safe.
+ */
+#ifndef SAP_H
+#define SAP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum sap_status {
+    SAP_OK = 0,
+    SAP_EINVAL = 1,          /* invalid argument (shape, pointer, dtype, non-finite b) */
+    SAP_ENOMEM = 2,          /* workspace would exceed the context's HBM budget */
+    SAP_RANK_DEFICIENT = 3,  /* min |R_kk| <= d * 2^-53 * max |R_kk| */
+    SAP_NOT_CONVERGED = 4,   /* maxiter reached; x holds the last iterate */
+    SAP_PENDING = 5,         /* served request not finished yet */
+    SAP_EDEVICE = 6,         /* HIP runtime error or device-side failure */
+    SAP_ECANCELED = 7        /* served request cancelled */
+} sap_status;
+
+typedef enum sap_dtype { SAP_F64 = 0, SAP_F32 = 1, SAP_BF16 = 2 } sap_dtype;
+
+/* Precision forms of sap_solve.  FP64: every step in double.  MIXED_FP32:
+ * A stored FP32; sketch apply and the LSQR GEMVs in FP32 with FP32
+ * accumulation; QR of the sketch, the R triangular solves, the LSQR scalar
+ * recurrences and the residual refinement passes in FP64.  MIXED_BF16SA: as
+ * MIXED_FP32, but the sketch is applied to a bfloat16 rounding of A. */
+typedef enum sap_mode { SAP_MODE_FP64 = 0, SAP_MODE_MIXED_FP32 = 1, SAP_MODE_MIXED_BF16SA = 2 } sap_mode;
+
+typedef struct sap_ctx sap_ctx;
+
+/* Create a context on HIP device `device` whose internal workspace may use at
+ * most `hbm_budget` bytes (0 = 90% of the device's free memory).
+ * Errors: SAP_EINVAL (bad device / null out), SAP_EDEVICE. */
+sap_status sap_create(sap_ctx **out, int device, size_t hbm_budget);
+void sap_destroy(sap_ctx *ctx);
+const char *sap_last_error(const sap_ctx *ctx);
+const char *sap_status_string(sap_status s);
+
+/* ------------------------------------------------------------------------
+ * Sparse sign sketch (Def. 2.2; generation by rejection sampling, Sec. 3.1.2
+ * and Alg. 3).  S is d x m; column i holds exactly zeta nonzeros, at the
+ * distinct rows idx[i*zeta + 0 .. zeta-1] (strictly ascending), with value
+ * +1/sqrt(zeta) where bit k of sign[i] is 1 and -1/sqrt(zeta) where it is 0
+ * (bit k belongs to the k-th smallest row).  Bits >= zeta of sign[i] are 0.
+ *
+ * Random stream: Philox4x64-10 with key (seed, stream).  Draw j of redraw
+ * round r of column i is Lemire's bounded integer in [0, d) taken from word
+ * (j mod 4) of Philox(counter = (i, r, floor(j/4), k)), k = 0, 1, ... until
+ * accepted; the sign word is word 0 of Philox(counter = (i, 2^64-1, 0, 0)).
+ * Round 0 draws zeta values; each later round redraws, on the sorted column,
+ * every position j whose value equals that of position j+1.
+ * ---------------------------------------------------------------------- */
+typedef struct sps_sketch {
+    int64_t m;        /* columns of S (rows of A), >= 1 */
+    int32_t d;        /* rows of S (embedding dimension), 1 <= d < 2^31 */
+    int32_t zeta;     /* nonzeros per column, 1 <= zeta <= min(d, 64) */
+    uint64_t seed;    /* Philox key word 0 */
+    uint64_t stream;  /* Philox key word 1 (0 for single solves) */
+    int32_t *idx;     /* device, m*zeta int32 (row i of idx = column i of S) */
+    uint64_t *sign;   /* device, m words */
+} sps_sketch;
+
+/* Fill S->idx and S->sign.  Asynchronous on `stream`.
+ * Errors: SAP_EINVAL if zeta < 1, zeta > 64, zeta > d, m < 1, d < 1 or a
+ * pointer is NULL. */
+sap_status sps_generate(sap_ctx *ctx, const sps_sketch *S, void *stream);
+
+/* Y = S [A b]  (Alg. 1, "form Y = SA"; b is sketched as column n of Y so that
+ * Q^T S b comes out of the same factorisation).  A: device, row-major m x n,
+ * lda >= n, dtype a_type in {F64, F32, BF16}.  b: device, m doubles, or NULL
+ * (then Y has n columns).  Y: device, column-major d x (n + (b != NULL)),
+ * ldy >= d, dtype y_type in {F64, F32}; it is overwritten.  Accumulation is
+ * in y_type; the 1/sqrt(zeta) scale is applied once after summation.
+ * Asynchronous on `stream`.  Errors: SAP_EINVAL (shapes, dtypes, NULL),
+ * SAP_ENOMEM (partial-sum workspace). */
+sap_status sps_apply(sap_ctx *ctx, const sps_sketch *S, const void *A, int64_t lda,
+                     sap_dtype a_type, const double *b, int32_t n, void *Y, int64_t ldy,
+                     sap_dtype y_type, void *stream);
+
+/* Householder QR of Y (Alg. 1, "factor Q, R = QR(Y)"), in place, FP64.
+ * Y: device, column-major rows x cols (ldy >= rows), rows >= cols.  On return
+ * the upper triangle holds R and the strict lower part the Householder
+ * vectors v_k (unit leading entry implicit); tau (device, cols doubles)
+ * holds the reflector scalars, H_k = I - tau_k v_k v_k^T, with the LAPACK
+ * dlarfg sign convention R_kk = -sign(alpha_k) ||x_k||.
+ * Asynchronous on `stream`.  Errors: SAP_EINVAL, SAP_ENOMEM. */
+sap_status sap_qr(sap_ctx *ctx, double *Y, int64_t ldy, int32_t rows, int32_t cols,
+                  double *tau, void *stream);
+
+/* Triangular solve with the preconditioner factor (M = R^-1 applied without
+ * forming the inverse).  R: device, upper triangle of a column-major n x n
+ * array with leading dimension ldr (entries below the diagonal are ignored).
+ * trans = 0 solves R x = rhs; trans = 1 solves R^T x = rhs.  rhs and x are
+ * device arrays of n doubles (they may alias).  Asynchronous.
+ * Errors: SAP_EINVAL. */
+sap_status sap_trsv(sap_ctx *ctx, const double *R, int64_t ldr, int32_t n, int32_t trans,
+                    const double *rhs, double *x, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Least-squares problems and solver parameters.
+ * ---------------------------------------------------------------------- */
+typedef struct sap_problem {
+    int64_t m;          /* rows of A, m >= n + 1 */
+    int32_t n;          /* columns of A, n >= 1 */
+    const void *A;      /* device, row-major m x n, lda >= n */
+    int64_t lda;
+    sap_dtype a_type;   /* F64 for SAP_MODE_FP64, F32 for the mixed modes */
+    const double *b;    /* device, m doubles */
+} sap_problem;
+
+typedef struct sap_params {
+    int32_t d;          /* embedding dimension, n + 1 <= d (paper: d = O(n)) */
+    int32_t zeta;       /* sketch nonzeros per column, 1..min(d, 64) */
+    uint64_t seed;      /* sketch seed (stream word is 0 for sap_solve) */
+    double tol;         /* LSQR stopping tolerance (see below), e.g. 1e-12 */
+    int32_t maxiter;    /* LSQR iteration cap (total over refinements) */
+    int32_t mode;       /* sap_mode */
+    int32_t max_refine; /* mixed modes: refinement passes cap (0 = default 8) */
+    double inner_tol;   /* mixed modes: inner FP32 LSQR tolerance (0 = 1e-6) */
+} sap_params;
+
+typedef struct sap_info {
+    int32_t status;      /* final sap_status of the solve */
+    int32_t iters;       /* LSQR iterations (summed over refinements) */
+    int32_t refinements; /* FP64 residual refinement passes (mixed modes) */
+    int32_t reserved;
+    double resid_est;    /* estimate of ||b - A x|| */
+    double normar_est;   /* estimate of ||(A M)^T (b - A x)|| */
+    double t_generate_ms, t_apply_ms, t_qr_ms, t_iterate_ms; /* phase times */
+} sap_info;
+
+/* Solve min ||b - A x|| by Alg. 1 with a sparse sign sketch and LSQR (Alg. 2)
+ * on A R^-1.  x: device, n doubles (output).  info: host pointer (nullable).
+ * Stopping (the paper leaves the test open; reading after Paige & Saunders,
+ * with ||A M|| ~ 1 by Lemma 2.4): stop after iteration t when
+ * alpha_{t+1} |c_t| <= tol, or phibar_{t+1} <= tol ||b||, or on breakdown
+ * (beta or alpha exactly 0).  Blocking: returns when x is written.
+ * Errors: SAP_EINVAL (shapes, dtype/mode mismatch, non-finite b),
+ * SAP_ENOMEM, SAP_RANK_DEFICIENT (x untouched), SAP_NOT_CONVERGED (x holds
+ * the last iterate), SAP_EDEVICE. */
+sap_status sap_solve(sap_ctx *ctx, const sap_problem *prob, const sap_params *params, double *x,
+                     sap_info *info, void *stream);
+
+/* Preconditioned LSQR alone (Alg. 2) on A M with M = R^-1 for a given R
+ * (device, upper triangle of column-major n x n, leading dimension ldr) and
+ * initial guess x0 (device, n doubles; may alias x).  The FP64 form only
+ * (prob->a_type must be F64).  Blocking.  Same stopping rule and errors as
+ * sap_solve. */
+sap_status sap_lsqr(sap_ctx *ctx, const sap_problem *prob, const double *R, int64_t ldr,
+                    const double *x0, double tol, int32_t maxiter, double *x, sap_info *info,
+                    void *stream);
+
+/* ------------------------------------------------------------------------
+ * Kernel timing (measurement support).  When enabled, the library brackets
+ * every launch of its two bandwidth-bound kernels with HIP events on the
+ * stream it launches them on, and accumulates their durations:
+ *   kernel 0 = the fused LSQR pass over A (u <- c (A p) + c' u, q = A^T u),
+ *   kernel 1 = the sketch apply (S [A b] accumulation, plus its slice
+ *              reduction when there is one).
+ * Events are resolved at the end of each blocking call (sap_solve,
+ * sap_lsqr) or by sap_profile_read.  Disabled by default.
+ * ---------------------------------------------------------------------- */
+sap_status sap_profile_enable(sap_ctx *ctx, int enable);
+/* Reset (reset != 0) or read the totals: launches and summed milliseconds. */
+sap_status sap_profile_read(sap_ctx *ctx, int32_t kernel, int64_t *launches, double *total_ms, int reset);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SAP_H */

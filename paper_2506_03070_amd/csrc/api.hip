@@ -1,0 +1,426 @@
+// C ABI entry points (declared in include/sap.h): argument validation,
+// workspace management and the orchestration of Alg. 1 on one stream.
+#include <cmath>
+#include <cstring>
+#include <string>
+
+#include "common.h"
+
+namespace sap {
+
+sap_status fail(sap_ctx *ctx, sap_status s, const std::string &msg) {
+  if (ctx) ctx->err = msg;
+  return s;
+}
+
+sap_status hip_fail(sap_ctx *ctx, hipError_t e, const char *what) {
+  std::string msg = std::string("HIP error ") + hipGetErrorName(e) + " (" + hipGetErrorString(e) + ") in " + what;
+  return fail(ctx, SAP_EDEVICE, msg);
+}
+
+sap_status ensure_workspace(sap_ctx *ctx, size_t bytes, hipStream_t stream) {
+  bytes = (bytes + 4095) & ~size_t(4095);
+  if (bytes <= ctx->ws_size) return SAP_OK;
+  if (bytes > ctx->budget)
+    return fail(ctx, SAP_ENOMEM, "workspace of " + std::to_string(bytes) + " bytes exceeds the HBM budget of " +
+                                     std::to_string(ctx->budget) + " bytes");
+  if (ctx->ws) {
+    SAP_HIP_TRY(hipStreamSynchronize(stream));
+    SAP_HIP_TRY(hipFree(ctx->ws));
+    ctx->ws = nullptr;
+    ctx->ws_size = 0;
+  }
+  if (hipMalloc(&ctx->ws, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    ctx->ws = nullptr;
+    return fail(ctx, SAP_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+  }
+  ctx->ws_size = bytes;
+  return SAP_OK;
+}
+
+static hipEvent_t take_event(sap_ctx *ctx) {
+  if (!ctx->free_events.empty()) {
+    hipEvent_t e = ctx->free_events.back();
+    ctx->free_events.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+hipEvent_t prof_begin(sap_ctx *ctx, hipStream_t st) {
+  if (!ctx->profiling) return nullptr;
+  hipEvent_t e = take_event(ctx);
+  if (e) (void)hipEventRecord(e, st);
+  return e;
+}
+
+void prof_end(sap_ctx *ctx, int kernel, hipEvent_t begin, hipStream_t st) {
+  if (!ctx->profiling || !begin) return;
+  hipEvent_t e = take_event(ctx);
+  if (!e) return;
+  (void)hipEventRecord(e, st);
+  ctx->pending[kernel].emplace_back(begin, e);
+}
+
+void prof_resolve(sap_ctx *ctx) {
+  for (int k = 0; k < 2; ++k) {
+    for (auto &pr : ctx->pending[k]) {
+      float ms = 0.f;
+      if (hipEventSynchronize(pr.second) == hipSuccess && hipEventElapsedTime(&ms, pr.first, pr.second) == hipSuccess) {
+        ctx->prof_launches[k] += 1;
+        ctx->prof_ms[k] += ms;
+      }
+      ctx->free_events.push_back(pr.first);
+      ctx->free_events.push_back(pr.second);
+    }
+    ctx->pending[k].clear();
+  }
+}
+
+namespace {
+
+// Flags written by device checks and read back once per solve.
+struct SolveFlags {
+  int gen_error;
+  int rank_deficient;
+  int nonfinite_b;
+  int pad;
+};
+
+__global__ void zero_flags_kernel(SolveFlags *f) {
+  if (threadIdx.x == 0) {
+    f->gen_error = 0;
+    f->rank_deficient = 0;
+    f->nonfinite_b = 0;
+  }
+}
+
+__global__ __launch_bounds__(256) void finite_check_kernel(const double *__restrict__ b, int64_t m,
+                                                           int *__restrict__ flag) {
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * 256;
+  int bad = 0;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; i < m; i += stride)
+    bad |= !isfinite(b[i]);
+  if (bad) atomicOr(flag, 1);
+}
+
+__global__ __launch_bounds__(256) void f32_to_f64_kernel(const float *__restrict__ src, int64_t lds_,
+                                                         double *__restrict__ dst, int64_t ldd, int rows,
+                                                         int cols) {
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  if (e >= static_cast<int64_t>(rows) * cols) return;
+  const int r = static_cast<int>(e % rows), c = static_cast<int>(e / rows);
+  dst[r + c * ldd] = static_cast<double>(src[r + c * lds_]);
+}
+
+sap_status check_sketch(sap_ctx *ctx, const sps_sketch *S) {
+  if (!S) return fail(ctx, SAP_EINVAL, "sketch descriptor is NULL");
+  if (S->m < 1) return fail(ctx, SAP_EINVAL, "sketch: m must be >= 1");
+  if (S->d < 1) return fail(ctx, SAP_EINVAL, "sketch: d must be >= 1");
+  if (S->zeta < 1 || S->zeta > 64) return fail(ctx, SAP_EINVAL, "sketch: zeta must be in [1, 64]");
+  if (S->zeta > S->d) return fail(ctx, SAP_EINVAL, "sketch: zeta must not exceed d");
+  if (!S->idx || !S->sign) return fail(ctx, SAP_EINVAL, "sketch: idx/sign must be device pointers");
+  return SAP_OK;
+}
+
+}  // namespace
+}  // namespace sap
+
+using namespace sap;
+
+extern "C" {
+
+const char *sap_status_string(sap_status s) {
+  switch (s) {
+    case SAP_OK: return "SAP_OK";
+    case SAP_EINVAL: return "SAP_EINVAL";
+    case SAP_ENOMEM: return "SAP_ENOMEM";
+    case SAP_RANK_DEFICIENT: return "SAP_RANK_DEFICIENT";
+    case SAP_NOT_CONVERGED: return "SAP_NOT_CONVERGED";
+    case SAP_PENDING: return "SAP_PENDING";
+    case SAP_EDEVICE: return "SAP_EDEVICE";
+    case SAP_ECANCELED: return "SAP_ECANCELED";
+  }
+  return "SAP_UNKNOWN";
+}
+
+sap_status sap_create(sap_ctx **out, int device, size_t hbm_budget) {
+  if (!out) return SAP_EINVAL;
+  *out = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) return SAP_EINVAL;
+  if (hipSetDevice(device) != hipSuccess) return SAP_EDEVICE;
+  sap_ctx *ctx = new sap_ctx();
+  ctx->device = device;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess) {
+    delete ctx;
+    return SAP_EDEVICE;
+  }
+  ctx->num_cus = prop.multiProcessorCount;
+  size_t free_b = 0, total_b = 0;
+  if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
+    delete ctx;
+    return SAP_EDEVICE;
+  }
+  ctx->budget = hbm_budget ? hbm_budget : static_cast<size_t>(0.9 * static_cast<double>(free_b));
+  *out = ctx;
+  return SAP_OK;
+}
+
+void sap_destroy(sap_ctx *ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->device);
+  (void)hipDeviceSynchronize();
+  prof_resolve(ctx);
+  for (hipEvent_t e : ctx->free_events) (void)hipEventDestroy(e);
+  if (ctx->ws) (void)hipFree(ctx->ws);
+  delete ctx;
+}
+
+sap_status sap_profile_enable(sap_ctx *ctx, int enable) {
+  if (!ctx) return SAP_EINVAL;
+  ctx->profiling = enable != 0;
+  return SAP_OK;
+}
+
+sap_status sap_profile_read(sap_ctx *ctx, int32_t kernel, int64_t *launches, double *total_ms, int reset) {
+  if (!ctx || kernel < 0 || kernel > 1) return SAP_EINVAL;
+  SAP_HIP_TRY(hipSetDevice(ctx->device));
+  prof_resolve(ctx);
+  if (launches) *launches = ctx->prof_launches[kernel];
+  if (total_ms) *total_ms = ctx->prof_ms[kernel];
+  if (reset) {
+    ctx->prof_launches[kernel] = 0;
+    ctx->prof_ms[kernel] = 0.0;
+  }
+  return SAP_OK;
+}
+
+const char *sap_last_error(const sap_ctx *ctx) { return ctx ? ctx->err.c_str() : "NULL context"; }
+
+sap_status sps_generate(sap_ctx *ctx, const sps_sketch *S, void *stream) {
+  if (!ctx) return SAP_EINVAL;
+  sap_status s = check_sketch(ctx, S);
+  if (s != SAP_OK) return s;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  SAP_HIP_TRY(hipSetDevice(ctx->device));
+  s = ensure_workspace(ctx, 256, st);
+  if (s != SAP_OK) return s;
+  return launch_generate(ctx, S, static_cast<int *>(ctx->ws), st);
+}
+
+sap_status sps_apply(sap_ctx *ctx, const sps_sketch *S, const void *A, int64_t lda, sap_dtype a_type,
+                     const double *b, int32_t n, void *Y, int64_t ldy, sap_dtype y_type, void *stream) {
+  if (!ctx) return SAP_EINVAL;
+  sap_status s = check_sketch(ctx, S);
+  if (s != SAP_OK) return s;
+  if (!A || !Y) return fail(ctx, SAP_EINVAL, "sps_apply: A and Y must be device pointers");
+  if (n < 1) return fail(ctx, SAP_EINVAL, "sps_apply: n must be >= 1");
+  if (lda < n) return fail(ctx, SAP_EINVAL, "sps_apply: lda must be >= n");
+  if (ldy < S->d) return fail(ctx, SAP_EINVAL, "sps_apply: ldy must be >= d");
+  if (a_type != SAP_F64 && a_type != SAP_F32 && a_type != SAP_BF16)
+    return fail(ctx, SAP_EINVAL, "sps_apply: a_type must be F64, F32 or BF16");
+  if (y_type != SAP_F64 && y_type != SAP_F32) return fail(ctx, SAP_EINVAL, "sps_apply: y_type must be F64 or F32");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  SAP_HIP_TRY(hipSetDevice(ctx->device));
+  const int ncols = n + (b ? 1 : 0);
+  s = ensure_workspace(ctx, apply_workspace_bytes(ctx, S->m, S->d, ncols, y_type) + 256, st);
+  if (s != SAP_OK) return s;
+  hipEvent_t pb = prof_begin(ctx, st);
+  s = launch_apply(ctx, S, A, lda, a_type, b, n, Y, ldy, y_type, ctx->ws, st);
+  prof_end(ctx, kProfApply, pb, st);
+  return s;
+}
+
+sap_status sap_qr(sap_ctx *ctx, double *Y, int64_t ldy, int32_t rows, int32_t cols, double *tau, void *stream) {
+  if (!ctx) return SAP_EINVAL;
+  if (!Y || !tau) return fail(ctx, SAP_EINVAL, "sap_qr: Y and tau must be device pointers");
+  if (rows < 1 || cols < 1 || rows < cols) return fail(ctx, SAP_EINVAL, "sap_qr: need rows >= cols >= 1");
+  if (ldy < rows) return fail(ctx, SAP_EINVAL, "sap_qr: ldy must be >= rows");
+  if (rows > 16384) return fail(ctx, SAP_EINVAL, "sap_qr: more than 16384 rows is not supported");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  SAP_HIP_TRY(hipSetDevice(ctx->device));
+  sap_status s = ensure_workspace(ctx, qr_workspace_bytes(rows, cols), st);
+  if (s != SAP_OK) return s;
+  return launch_qr(ctx, Y, ldy, rows, cols, tau, ctx->ws, st);
+}
+
+sap_status sap_trsv(sap_ctx *ctx, const double *R, int64_t ldr, int32_t n, int32_t trans, const double *rhs,
+                    double *x, void *stream) {
+  if (!ctx) return SAP_EINVAL;
+  if (!R || !rhs || !x) return fail(ctx, SAP_EINVAL, "sap_trsv: NULL pointer");
+  if (n < 1 || ldr < n) return fail(ctx, SAP_EINVAL, "sap_trsv: need n >= 1 and ldr >= n");
+  if (trans != 0 && trans != 1) return fail(ctx, SAP_EINVAL, "sap_trsv: trans must be 0 or 1");
+  SAP_HIP_TRY(hipSetDevice(ctx->device));
+  return launch_trsv(ctx, R, ldr, n, trans, rhs, x, static_cast<hipStream_t>(stream));
+}
+
+static sap_status check_problem(sap_ctx *ctx, const sap_problem *p) {
+  if (!p) return fail(ctx, SAP_EINVAL, "problem descriptor is NULL");
+  if (p->n < 1) return fail(ctx, SAP_EINVAL, "problem: n must be >= 1");
+  if (p->m < static_cast<int64_t>(p->n) + 1) return fail(ctx, SAP_EINVAL, "problem: need m >= n + 1");
+  if (p->lda < p->n) return fail(ctx, SAP_EINVAL, "problem: lda must be >= n");
+  if (!p->A || !p->b) return fail(ctx, SAP_EINVAL, "problem: A and b must be device pointers");
+  if (p->n > 8192) return fail(ctx, SAP_EINVAL, "problem: n > 8192 is not supported");
+  return SAP_OK;
+}
+
+sap_status sap_lsqr(sap_ctx *ctx, const sap_problem *prob, const double *R, int64_t ldr, const double *x0,
+                    double tol, int32_t maxiter, double *x, sap_info *info, void *stream) {
+  if (!ctx) return SAP_EINVAL;
+  sap_status s = check_problem(ctx, prob);
+  if (s != SAP_OK) return s;
+  if (prob->a_type != SAP_F64) return fail(ctx, SAP_EINVAL, "sap_lsqr: A must be F64");
+  if (!R || !x0 || !x) return fail(ctx, SAP_EINVAL, "sap_lsqr: NULL pointer");
+  if (ldr < prob->n) return fail(ctx, SAP_EINVAL, "sap_lsqr: ldr must be >= n");
+  if (maxiter < 0 || !(tol >= 0.0)) return fail(ctx, SAP_EINVAL, "sap_lsqr: need maxiter >= 0 and tol >= 0");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  SAP_HIP_TRY(hipSetDevice(ctx->device));
+  s = ensure_workspace(ctx, lsqr_workspace_bytes(ctx, prob->m, prob->n, 0), st);
+  if (s != SAP_OK) return s;
+  if (info) std::memset(info, 0, sizeof(*info));
+  hipEvent_t e0, e1;
+  SAP_HIP_TRY(hipEventCreate(&e0));
+  SAP_HIP_TRY(hipEventCreate(&e1));
+  SAP_HIP_TRY(hipEventRecord(e0, st));
+  s = run_lsqr(ctx, prob, R, ldr, x0, tol, maxiter, 0, 0, 0.0, x, info, ctx->ws, st);
+  (void)hipEventRecord(e1, st);
+  (void)hipEventSynchronize(e1);
+  prof_resolve(ctx);
+  float ms = 0.f;
+  (void)hipEventElapsedTime(&ms, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (info) {
+    info->status = s;
+    info->t_iterate_ms = ms;
+  }
+  return s;
+}
+
+sap_status sap_solve(sap_ctx *ctx, const sap_problem *prob, const sap_params *par, double *x, sap_info *info,
+                     void *stream) {
+  if (!ctx) return SAP_EINVAL;
+  sap_status s = check_problem(ctx, prob);
+  if (s != SAP_OK) return s;
+  if (!par || !x) return fail(ctx, SAP_EINVAL, "sap_solve: NULL params or x");
+  const int64_t m = prob->m;
+  const int n = prob->n, d = par->d, nc = n + 1;
+  if (d < nc) return fail(ctx, SAP_EINVAL, "sap_solve: need d >= n + 1");
+  if (d > 16384) return fail(ctx, SAP_EINVAL, "sap_solve: d > 16384 is not supported");
+  if (par->zeta < 1 || par->zeta > 64 || par->zeta > d) return fail(ctx, SAP_EINVAL, "sap_solve: zeta must be in [1, min(d, 64)]");
+  if (par->maxiter < 0 || !(par->tol >= 0.0)) return fail(ctx, SAP_EINVAL, "sap_solve: need maxiter >= 0, tol >= 0");
+  const int mode = par->mode;
+  if (mode == SAP_MODE_FP64) {
+    if (prob->a_type != SAP_F64) return fail(ctx, SAP_EINVAL, "sap_solve: FP64 mode needs an F64 A");
+  } else if (mode == SAP_MODE_MIXED_FP32) {
+    if (prob->a_type != SAP_F32) return fail(ctx, SAP_EINVAL, "sap_solve: mixed mode needs an F32 A");
+  } else {
+    return fail(ctx, SAP_EINVAL, "sap_solve: unsupported mode");
+  }
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  SAP_HIP_TRY(hipSetDevice(ctx->device));
+
+  const sap_dtype y_type = (mode == SAP_MODE_FP64) ? SAP_F64 : SAP_F32;
+  const size_t bytes_flags = 256;
+  const size_t bytes_idx = static_cast<size_t>(m) * par->zeta * sizeof(int32_t);
+  const size_t bytes_sign = static_cast<size_t>(m) * sizeof(uint64_t);
+  const size_t bytes_Y = static_cast<size_t>(d) * nc * sizeof(double);
+  const size_t bytes_Yf = (mode == SAP_MODE_FP64) ? 0 : static_cast<size_t>(d) * nc * sizeof(float);
+  const size_t bytes_tau = static_cast<size_t>(nc) * sizeof(double);
+  const size_t bytes_apply = apply_workspace_bytes(ctx, m, d, nc, y_type);
+  const size_t bytes_qr = qr_workspace_bytes(d, nc);
+  const size_t bytes_lsqr = lsqr_workspace_bytes(ctx, m, n, mode == SAP_MODE_FP64 ? 0 : 1);
+  size_t scratch = bytes_apply > bytes_qr ? bytes_apply : bytes_qr;
+  scratch = scratch > bytes_lsqr ? scratch : bytes_lsqr;
+  const size_t total = 8 * 256 + bytes_flags + bytes_idx + bytes_sign + bytes_Y + bytes_Yf + bytes_tau + scratch;
+  s = ensure_workspace(ctx, total, st);
+  if (s != SAP_OK) return s;
+  Carve cv(ctx->ws);
+  SolveFlags *flags = cv.take<SolveFlags>(1);
+  int32_t *idx = cv.take<int32_t>(static_cast<size_t>(m) * par->zeta);
+  uint64_t *sign = cv.take<uint64_t>(static_cast<size_t>(m));
+  double *Y = cv.take<double>(static_cast<size_t>(d) * nc);
+  float *Yf = bytes_Yf ? cv.take<float>(static_cast<size_t>(d) * nc) : nullptr;
+  double *tau = cv.take<double>(nc);
+  void *work = cv.take<char>(scratch);
+
+  if (info) std::memset(info, 0, sizeof(*info));
+  hipEvent_t ev[5];
+  for (auto &e : ev) SAP_HIP_TRY(hipEventCreate(&e));
+  struct EvGuard {
+    hipEvent_t *e;
+    ~EvGuard() {
+      for (int k = 0; k < 5; ++k) (void)hipEventDestroy(e[k]);
+    }
+  } guard{ev};
+
+  zero_flags_kernel<<<1, 64, 0, st>>>(flags);
+  finite_check_kernel<<<256, 256, 0, st>>>(prob->b, m, &flags->nonfinite_b);
+  SAP_HIP_TRY(hipGetLastError());
+  SAP_HIP_TRY(hipEventRecord(ev[0], st));
+  sps_sketch S{m, d, par->zeta, par->seed, 0, idx, sign};
+  s = launch_generate(ctx, &S, &flags->gen_error, st);
+  if (s != SAP_OK) return s;
+  SAP_HIP_TRY(hipEventRecord(ev[1], st));
+  hipEvent_t pb_apply = prof_begin(ctx, st);
+  if (mode == SAP_MODE_FP64) {
+    s = launch_apply(ctx, &S, prob->A, prob->lda, SAP_F64, prob->b, n, Y, d, SAP_F64, work, st);
+  } else {
+    s = launch_apply(ctx, &S, prob->A, prob->lda, SAP_F32, prob->b, n, Yf, d, SAP_F32, work, st);
+    if (s == SAP_OK) {
+      const int64_t tot = static_cast<int64_t>(d) * nc;
+      f32_to_f64_kernel<<<static_cast<unsigned>((tot + 255) / 256), 256, 0, st>>>(Yf, d, Y, d, d, nc);
+      SAP_HIP_TRY(hipGetLastError());
+    }
+  }
+  if (s != SAP_OK) return s;
+  prof_end(ctx, kProfApply, pb_apply, st);
+  SAP_HIP_TRY(hipEventRecord(ev[2], st));
+  s = launch_qr(ctx, Y, d, d, nc, tau, work, st);
+  if (s != SAP_OK) return s;
+  s = launch_rank_check(ctx, Y, d, n, d, &flags->rank_deficient, st);
+  if (s != SAP_OK) return s;
+  SAP_HIP_TRY(hipEventRecord(ev[3], st));
+  SolveFlags hf{};
+  SAP_HIP_TRY(hipMemcpyAsync(&hf, flags, sizeof(hf), hipMemcpyDeviceToHost, st));
+  SAP_HIP_TRY(hipStreamSynchronize(st));
+  if (hf.nonfinite_b) return fail(ctx, SAP_EINVAL, "sap_solve: b has non-finite entries");
+  if (hf.gen_error) return fail(ctx, SAP_EDEVICE, "sap_solve: sketch generation hit its round cap");
+  if (hf.rank_deficient) {
+    if (info) info->status = SAP_RANK_DEFICIENT;
+    return fail(ctx, SAP_RANK_DEFICIENT, "sap_solve: R is numerically singular (A rank deficient)");
+  }
+  // x0 = R^-1 (Q^T S b)[0:n]: column n of the factored sketch.
+  s = launch_trsv(ctx, Y, d, n, 0, Y + static_cast<int64_t>(n) * d, x, st);
+  if (s != SAP_OK) return s;
+  const int lsqr_mode = (mode == SAP_MODE_FP64) ? 0 : 1;
+  sap_info li{};
+  s = run_lsqr(ctx, prob, Y, d, x, par->tol, par->maxiter, lsqr_mode, par->max_refine,
+               par->inner_tol > 0.0 ? par->inner_tol : 1e-6, x, &li, work, st);
+  if (s != SAP_OK && s != SAP_NOT_CONVERGED) return s;
+  SAP_HIP_TRY(hipEventRecord(ev[4], st));
+  SAP_HIP_TRY(hipEventSynchronize(ev[4]));
+  prof_resolve(ctx);
+  if (info) {
+    *info = li;
+    info->status = s;
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, ev[0], ev[1]);
+    info->t_generate_ms = ms;
+    (void)hipEventElapsedTime(&ms, ev[1], ev[2]);
+    info->t_apply_ms = ms;
+    (void)hipEventElapsedTime(&ms, ev[2], ev[3]);
+    info->t_qr_ms = ms;
+    (void)hipEventElapsedTime(&ms, ev[3], ev[4]);
+    info->t_iterate_ms = ms;
+  }
+  if (s == SAP_NOT_CONVERGED) ctx->err = "sap_solve: maxiter reached before the stopping test";
+  return s;
+}
+
+}  // extern "C"

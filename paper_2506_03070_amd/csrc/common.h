@@ -1,0 +1,191 @@
+// Internal helpers shared by the gfx950 kernels and the host-side API.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/sap.h"
+
+namespace sap {
+
+constexpr int kWave = 64;  // CDNA wavefront width
+
+// ---------------------------------------------------------------- device ---
+// Butterfly sum over the 64 lanes of a wavefront; every lane receives the
+// total.  The order of additions is fixed, so the result is deterministic.
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_max(T v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    T o = __shfl_xor(v, off, kWave);
+    v = v > o ? v : o;
+  }
+  return v;
+}
+
+// DPP lane permutation of a double (both 32-bit halves moved alike).
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+
+__device__ __forceinline__ double readlane(double v, int src) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), src);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ float readlane(float v, int src) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
+}
+
+// Sum over the 64 lanes of a wavefront returned as a wave-uniform value.
+// Within each row of 16 lanes: quad_perm [1,0,3,2], quad_perm [2,3,0,1],
+// row_half_mirror, row_mirror leave the row sum in every lane; the four row
+// sums are then combined from lanes 0, 16, 32, 48.  Fixed order, so the
+// result is deterministic.  Every lane of the wave must be active.
+template <typename T>
+__device__ __forceinline__ T wave_sum_u(T v) {
+  v += dpp_mov<0xB1>(v);
+  v += dpp_mov<0x4E>(v);
+  v += dpp_mov<0x141>(v);
+  v += dpp_mov<0x140>(v);
+  return (readlane(v, 0) + readlane(v, 16)) + (readlane(v, 32) + readlane(v, 48));
+}
+
+// Broadcast a double held by lane `src` (wave-uniform) to all lanes.
+__device__ __forceinline__ double wave_bcast(double v, int src) {
+  int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
+  int hi = __builtin_amdgcn_readlane(__double2hiint(v), src);
+  return __hiloint2double(hi, lo);
+}
+
+// Sum over a workgroup of `nwaves` waves.  `scratch` is LDS of >= nwaves
+// doubles.  All threads receive the total.  Contains two barriers.
+__device__ __forceinline__ double block_sum(double v, double *scratch, int nwaves) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wave = threadIdx.x / kWave;
+  __syncthreads();
+  if (lane == 0) scratch[wave] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int w = 0; w < nwaves; ++w) s += scratch[w];
+  return s;
+}
+
+// ------------------------------------------------------------------ host ---
+#define SAP_HIP_TRY(expr)                                          \
+  do {                                                             \
+    hipError_t _e = (expr);                                        \
+    if (_e != hipSuccess) return ::sap::hip_fail(ctx, _e, #expr);  \
+  } while (0)
+
+// Device-resident LSQR state.  All recurrence scalars stay on the device so
+// that an iteration needs no host round trip.
+struct LsqrState {
+  double alpha, beta, rhobar, phibar;
+  double c_ap, c_u;      // next pass computes u <- c_ap * (A p) + c_u * u
+  double beta_sq;        // reduced ||u_hat||^2 of the last pass
+  double normb, tol;
+  double resid_est, normar_est;
+  int32_t iter, maxiter;
+  int32_t done, converged;
+  int32_t init;          // 1: the next step is the initialisation step
+  int32_t total_iters;   // iterations summed over refinements
+};
+
+}  // namespace sap
+
+struct sap_ctx {
+  int device = 0;
+  int num_cus = 256;
+  size_t budget = 0;
+  std::string err;
+  void *ws = nullptr;
+  size_t ws_size = 0;
+  // kernel timing (sap_profile_enable): pending event pairs per kernel,
+  // resolved into launch counts and milliseconds; free events are reused
+  bool profiling = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[2];
+  std::vector<hipEvent_t> free_events;
+  int64_t prof_launches[2] = {0, 0};
+  double prof_ms[2] = {0.0, 0.0};
+};
+
+namespace sap {
+
+sap_status fail(sap_ctx *ctx, sap_status s, const std::string &msg);
+sap_status hip_fail(sap_ctx *ctx, hipError_t e, const char *what);
+// Grow the context workspace to at least `bytes` (synchronises `stream` when
+// it has to reallocate).  Returns SAP_ENOMEM beyond the budget.
+sap_status ensure_workspace(sap_ctx *ctx, size_t bytes, hipStream_t stream);
+
+// Bump allocator over a workspace region (256-byte aligned pieces).
+struct Carve {
+  char *base;
+  size_t off = 0;
+  explicit Carve(void *b) : base(static_cast<char *>(b)) {}
+  template <typename T>
+  T *take(size_t count) {
+    off = (off + 255) & ~size_t(255);
+    T *p = reinterpret_cast<T *>(base + off);
+    off += count * sizeof(T);
+    return p;
+  }
+  size_t used() const { return (off + 255) & ~size_t(255); }
+};
+
+// Kernel timing helpers: begin records an event before a launch, end after
+// it; resolve waits for pending events and accumulates their durations.
+enum ProfKernel { kProfPass = 0, kProfApply = 1 };
+hipEvent_t prof_begin(sap_ctx *ctx, hipStream_t st);
+void prof_end(sap_ctx *ctx, int kernel, hipEvent_t begin, hipStream_t st);
+void prof_resolve(sap_ctx *ctx);
+
+// ------------------------------------------------------- internal launchers
+// Sketch generation (sketch.hip).
+sap_status launch_generate(sap_ctx *ctx, const sps_sketch *S, int *err_word, hipStream_t st);
+
+// Sketch apply (apply.hip).  Workspace bytes for partial sums first.
+size_t apply_workspace_bytes(sap_ctx *ctx, int64_t m, int d, int ncols, sap_dtype y_type);
+sap_status launch_apply(sap_ctx *ctx, const sps_sketch *S, const void *A, int64_t lda,
+                        sap_dtype a_type, const double *b, int n, void *Y, int64_t ldy,
+                        sap_dtype y_type, void *work, hipStream_t st);
+
+// Householder QR (qr.hip).
+size_t qr_workspace_bytes(int rows, int cols);
+sap_status launch_qr(sap_ctx *ctx, double *Y, int64_t ldy, int rows, int cols, double *tau,
+                     void *work, hipStream_t st);
+// Rank test of R's diagonal; writes 1 to *flag when deficient.
+sap_status launch_rank_check(sap_ctx *ctx, const double *R, int64_t ldr, int n, int d, int *flag,
+                             hipStream_t st);
+
+// Triangular solves (lsqr.hip).
+sap_status launch_trsv(sap_ctx *ctx, const double *R, int64_t ldr, int n, int trans,
+                       const double *rhs, double *x, hipStream_t st);
+
+// LSQR driver (lsqr.hip).
+struct LsqrPlan;
+size_t lsqr_workspace_bytes(sap_ctx *ctx, int64_t m, int n, int mode);
+sap_status run_lsqr(sap_ctx *ctx, const sap_problem *prob, const double *R, int64_t ldr,
+                    const double *x0, double tol, int maxiter, int mode, int max_refine,
+                    double inner_tol, double *x, sap_info *info, void *work, hipStream_t st);
+
+}  // namespace sap

@@ -1,0 +1,202 @@
+"""GPU parity: each step of the hot path through the C ABI against the oracle.
+
+Bars (floating point from the arithmetic; see the tolerance section of the
+design notes): sketch indices and signs bit-exact; Y bitwise for integer
+inputs, ||dY||_F/||Y||_F <= 1e-12 (FP64) or 1e-5 (FP32) otherwise; R backward
+error ||R^T R - R_or^T R_or|| / ||R_or||^2 <= 1e-12; triangular solves within
+a small multiple of cond(R) * 2^-53.
+"""
+import numpy as np
+import pytest
+
+import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sap():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2506_03070_amd as sap
+    sap.lib()
+    return sap
+
+
+def _note(msg):
+    print(msg, flush=True)
+
+
+# ------------------------------------------------------------- sketch -----
+SKETCH_CASES = [
+    # (m, d, zeta, seed, stream)
+    (20000, 400, 8, inputs.config_seed(0) + 1, 0),
+    (1 << 20, 4000, 8, inputs.config_seed(1) + 1, 0),
+    (50000, 6, 3, 11, 0),          # heavy rejection: p = 0.556 per column
+    (3000, 64, 64, 12, 5),          # zeta = d: every row in every column
+    (7777, 100, 24, 13, 2),
+    (4097, 8192, 8, 14, 511),
+    (1000, 1, 1, 15, 0),
+    (1, 5, 2, 16, 0),
+    (12345, 2**31 - 1, 8, 17, 0),   # largest d
+    (2000, 300, 17, 18, 1),         # zeta not a power of two, > 16
+    (2000, 300, 33, 18, 1),
+]
+
+
+@pytest.mark.parametrize("m,d,zeta,seed,stream", SKETCH_CASES)
+def test_sketch_bit_exact(sap, orc, m, d, zeta, seed, stream):
+    import torch
+    _note(f"sketch m={m} d={d} zeta={zeta} seed={seed} stream={stream}")
+    idx, sign = sap.sps_generate(m, d, zeta, seed, stream)
+    torch.cuda.synchronize()
+    ref_idx, ref_sign = orc.sketch(seed, stream, m, d, zeta)
+    assert np.array_equal(idx.cpu().numpy(), ref_idx)
+    assert np.array_equal(sign.cpu().numpy().view(np.uint64), ref_sign)
+
+
+def test_sketch_invalid_args(sap):
+    import torch
+    for (m, d, zeta) in [(10, 4, 5), (10, 100, 0), (10, 100, 65), (0, 10, 2)]:
+        idx = torch.empty((max(m, 1), max(zeta, 1)), dtype=torch.int32, device="cuda")
+        sign = torch.empty(max(m, 1), dtype=torch.int64, device="cuda")
+        with pytest.raises(sap.SapError) as e:
+            sap.sps_generate(m, d, zeta, 1, 0, idx=idx, sign=sign)
+        assert e.value.status == sap.SAP_EINVAL
+
+
+# -------------------------------------------------------------- apply -----
+def _apply_case(sap, orc, m, n, d, zeta, kind, adtype, ydtype, with_b=True, lda_pad=0, seed=3):
+    import torch
+    p = inputs.make_problem(m, n, kind=kind, cond=1e4, seed=seed)
+    A_np = p.A
+    if adtype == "f32":
+        A_np = A_np.astype(np.float32)
+    if lda_pad:
+        big = np.zeros((m, n + lda_pad), dtype=A_np.dtype)
+        big[:, :n] = A_np
+        A_dev = torch.from_numpy(big).cuda()[:, :n]
+    else:
+        A_dev = torch.from_numpy(np.ascontiguousarray(A_np)).cuda()
+    b_dev = torch.from_numpy(p.b).cuda() if with_b else None
+    idx_ref, sign_ref = orc.sketch(seed + 100, 0, m, d, zeta)
+    idx = torch.from_numpy(idx_ref).cuda()
+    sign = torch.from_numpy(sign_ref.view(np.int64)).cuda()
+    ydt = torch.float64 if ydtype == "f64" else torch.float32
+    Y = sap.sps_apply(idx, sign, d, zeta, A_dev, b_dev, y_dtype=ydt)
+    torch.cuda.synchronize()
+    Yg = Y.cpu().numpy().T.astype(np.float64)  # d x ncols
+    Yo = orc.apply_sparse(idx_ref, sign_ref, A_np.astype(np.float64), p.b if with_b else None, d, zeta)
+    return Yg, Yo, idx_ref, sign_ref, A_np, p.b
+
+
+APPLY_CASES = [
+    # m, n, d, zeta, kind, A dtype, Y dtype, with_b, lda_pad
+    (20000, 100, 400, 8, "svd", "f64", "f64", True, 0),      # config 0 shape
+    (30000, 257, 1000, 8, "colscale", "f64", "f64", True, 3),
+    (5000, 3, 70, 4, "colscale", "f64", "f64", False, 0),
+    (9000, 33, 30000, 8, "colscale", "f64", "f64", True, 0),  # d beyond one LDS tile: row ranges
+    (40000, 64, 512, 12, "colscale", "f32", "f32", True, 0),
+    (40000, 64, 512, 8, "colscale", "f32", "f64", True, 1),
+    (100000, 17, 8192, 8, "colscale", "f32", "f32", True, 0),
+    (1, 5, 7, 3, "colscale", "f64", "f64", True, 0),
+]
+
+
+@pytest.mark.parametrize("m,n,d,zeta,kind,adt,ydt,with_b,pad", APPLY_CASES)
+def test_apply_parity(sap, orc, m, n, d, zeta, kind, adt, ydt, with_b, pad):
+    _note(f"apply m={m} n={n} d={d} zeta={zeta} A={adt} Y={ydt} b={with_b} pad={pad}")
+    Yg, Yo, *_ = _apply_case(sap, orc, m, n, d, zeta, kind, adt, ydt, with_b, pad)
+    rel = np.linalg.norm(Yg - Yo) / np.linalg.norm(Yo)
+    bound = 1e-12 if ydt == "f64" else 1e-5
+    assert rel <= bound, rel
+
+
+@pytest.mark.parametrize("ydt", ["f64", "f32"])
+def test_apply_integer_bitwise(sap, orc, ydt):
+    """Integer A and b: every partial sum is an exact integer in the
+    accumulation type, so Y = h * sum is the same bits in any order."""
+    import torch
+    m, n, d, zeta = 60000, 31, 700, 8
+    _note(f"apply-int m={m} n={n} d={d} Y={ydt}")
+    p = inputs.make_problem(m, n, kind="integer", seed=9)
+    A_np = p.A if ydt == "f64" else p.A.astype(np.float32)
+    idx_ref, sign_ref = orc.sketch(77, 0, m, d, zeta)
+    Y = sap.sps_apply(torch.from_numpy(idx_ref).cuda(), torch.from_numpy(sign_ref.view(np.int64)).cuda(), d,
+                      zeta, torch.from_numpy(np.ascontiguousarray(A_np)).cuda(), torch.from_numpy(p.b).cuda(),
+                      y_dtype=torch.float64 if ydt == "f64" else torch.float32)
+    torch.cuda.synchronize()
+    s = orc.sign_values(sign_ref, zeta).astype(np.int64)
+    Ab = np.column_stack([p.A, p.b]).astype(np.int64)
+    exact = np.zeros((d, n + 1), dtype=np.int64)
+    for k in range(zeta):
+        np.add.at(exact, idx_ref[:, k], s[:, k:k + 1] * Ab)
+    if ydt == "f64":
+        ref = exact.astype(np.float64) * orc.sketch_scale(zeta)
+        got = Y.cpu().numpy().T
+    else:
+        assert np.abs(exact).max() < 2**24
+        ref = exact.astype(np.float32) * np.float32(orc.sketch_scale(zeta))
+        got = Y.cpu().numpy().T
+    assert np.array_equal(got, ref)
+
+
+# ----------------------------------------------------------------- QR -----
+QR_CASES = [(400, 101), (4000, 1001), (1000, 1000), (5, 3), (700, 1), (2500, 64), (8192, 130), (16384, 40),
+            (513, 100), (1100, 17)]
+
+
+@pytest.mark.parametrize("rows,cols", QR_CASES)
+def test_qr_parity(sap, orc, rows, cols):
+    import torch
+    _note(f"qr rows={rows} cols={cols}")
+    rng = np.random.default_rng(rows * 7 + cols)
+    Y = rng.standard_normal((rows, cols)) * np.logspace(0, -4, cols)[None, :]
+    Yt = torch.from_numpy(np.ascontiguousarray(Y.T)).cuda()  # rows of Yt = columns of Y
+    tau = sap.sap_qr(Yt)
+    torch.cuda.synchronize()
+    F = Yt.cpu().numpy().T
+    Fo, tau_o = orc.householder_qr(Y)
+    k = min(rows, cols)
+    R = np.triu(F[:k])
+    Ro = np.triu(Fo[:k])
+    nrm = np.linalg.norm(Ro) ** 2
+    assert np.linalg.norm(R.T @ R - Ro.T @ Ro) <= 1e-12 * nrm
+    kappa = np.linalg.cond(Ro) if k > 1 else 1.0
+    assert np.abs(R - Ro).max() <= 100 * kappa * 2.0 ** -53 * np.abs(Ro).max() * max(1, np.sqrt(rows))
+    assert np.allclose(tau.cpu().numpy(), tau_o, rtol=0, atol=1e-10)
+    # stored Householder vectors reproduce Q with Q R = Y (small cases: the
+    # explicit Q is built with rank-1 updates on the host)
+    if rows * cols <= 2_000_000:
+        Q = orc.q_factor(F, tau.cpu().numpy())
+        assert np.linalg.norm(Q @ R - Y) <= 1e-12 * np.linalg.norm(Y) * max(1, np.sqrt(rows) / 10)
+
+
+def test_qr_invalid(sap):
+    import torch
+    Yt = torch.zeros((5, 3), dtype=torch.float64, device="cuda")
+    with pytest.raises(sap.SapError):
+        sap.sap_qr(Yt)  # 3 rows x 5 columns: rows < cols
+
+
+# --------------------------------------------------------------- TRSV -----
+@pytest.mark.parametrize("n", [1, 5, 64, 65, 100, 1000, 1001, 2049])
+def test_trsv_parity(sap, orc, n):
+    import torch
+    _note(f"trsv n={n}")
+    rng = np.random.default_rng(n)
+    Y = rng.standard_normal((max(2 * n, 8), n))
+    F, _ = orc.householder_qr(Y)
+    R = np.triu(F[:n, :n])
+    rhs = rng.standard_normal(n)
+    Rt = torch.from_numpy(np.ascontiguousarray(F[:n, :n].T)).cuda()  # lower part holds junk: ignored
+    r = torch.from_numpy(rhs).cuda()
+    x = sap.sap_trsv(Rt, r, trans=False).cpu().numpy()
+    y = sap.sap_trsv(Rt, r, trans=True).cpu().numpy()
+    xo = orc.backsub(R, rhs)
+    yo = orc.forwardsub_t(R, rhs)
+    kappa = np.linalg.cond(R)
+    tol = 50 * kappa * 2.0 ** -53 * np.sqrt(n)
+    assert np.linalg.norm(x - xo) <= tol * np.linalg.norm(xo)
+    assert np.linalg.norm(y - yo) <= tol * np.linalg.norm(yo)

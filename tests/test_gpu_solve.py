@@ -1,0 +1,163 @@
+"""GPU parity of LSQR (Alg. 2) and the whole of Alg. 1 through the C ABI.
+
+Bars: the paper's accuracy metric ||A(x - x_or)|| / ||b|| <= 1e-12 in FP64
+(Thm. 2.1 measures error as ||A(x* - x)||), and the forward error
+||x - x_or|| / ||x_or|| <= 1e-8 where the least-squares perturbation bound
+kappa*u + kappa^2*u*||r||/(||A|| ||x||) lies below it.
+"""
+import numpy as np
+import pytest
+
+import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sap():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2506_03070_amd as sap
+    sap.lib()
+    return sap
+
+
+def _note(msg):
+    print(msg, flush=True)
+
+
+def _dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+LSQR_CASES = [
+    # m, n, d, cond, noise
+    (20000, 100, 400, 1e6, 1e-8),
+    (9000, 257, 1028, 1e8, 1e-6),
+    (3000, 7, 28, 1e3, 1e-2),
+    (50000, 520, 2080, 1e6, 1e-4),
+]
+
+
+@pytest.mark.parametrize("m,n,d,cond,noise", LSQR_CASES)
+def test_lsqr_parity(sap, orc, m, n, d, cond, noise):
+    """Same R and x0 on both sides: the GPU's one-pass reorganisation of the
+    iteration (App. D.4.1) must track Alg. 2."""
+    import torch
+    _note(f"lsqr m={m} n={n} d={d} cond={cond:g}")
+    p = inputs.make_problem(m, n, kind="svd", cond=cond, noise=noise, seed=m + n)
+    idx, sign = orc.sketch(5, 0, m, d, 8)
+    Y = orc.apply_sparse(idx, sign, p.A, p.b, d, 8)
+    F, _ = orc.householder_qr(Y)
+    R = np.triu(F[:n, :n])
+    x0 = orc.backsub(R, F[:n, n])
+    x_or, info_or = orc.lsqr(p.A, p.b, R, x0, tol=1e-12, maxiter=300)
+    Rt = _dev(np.ascontiguousarray(F[:n, :n].T))
+    res = sap.sap_lsqr(_dev(p.A), _dev(p.b), Rt, _dev(x0), tol=1e-12, maxiter=300)
+    torch.cuda.synchronize()
+    x = res.x.cpu().numpy()
+    nb = np.linalg.norm(p.b)
+    assert res.status == sap.SAP_OK and info_or["converged"]
+    assert np.linalg.norm(p.A @ (x - x_or)) <= 1e-12 * nb
+    assert abs(res.info["iters"] - info_or["iters"]) <= 2
+
+
+def test_lsqr_maxiter_and_zero(sap, orc):
+    import torch
+    p = inputs.make_problem(4000, 20, kind="svd", cond=1e4, noise=1e-3, seed=1)
+    idx, sign = orc.sketch(5, 0, 4000, 80, 8)
+    F, _ = orc.householder_qr(orc.apply_sparse(idx, sign, p.A, p.b, 80, 8))
+    R = np.triu(F[:20, :20])
+    x0 = orc.backsub(R, F[:20, 20])
+    Rt = _dev(np.ascontiguousarray(F[:20, :20].T))
+    for t in (0, 1, 3):
+        _note(f"lsqr maxiter={t}")
+        res = sap.sap_lsqr(_dev(p.A), _dev(p.b), Rt, _dev(x0), tol=1e-14, maxiter=t)
+        torch.cuda.synchronize()
+        xo, io = orc.lsqr(p.A, p.b, R, x0, tol=0.0, maxiter=t)
+        assert res.status == sap.SAP_NOT_CONVERGED
+        assert res.info["iters"] == t
+        assert np.linalg.norm(p.A @ (res.x.cpu().numpy() - xo)) <= 1e-12 * np.linalg.norm(p.b)
+    # b = 0: beta_1 = 0, x0 = 0 is exact
+    res = sap.sap_lsqr(_dev(p.A), _dev(np.zeros(4000)), Rt, _dev(np.zeros(20)), tol=1e-12, maxiter=10)
+    torch.cuda.synchronize()
+    assert res.status == sap.SAP_OK and np.all(res.x.cpu().numpy() == 0)
+
+
+SOLVE_CASES = [
+    # name, m, n, d, zeta, kind, cond, noise, row_scale
+    ("config0", 20000, 100, 400, 8, "svd", 1e6, 1e-8, False),
+    ("lev", 30000, 200, 800, 8, "svd", 1e8, 1e-10, True),
+    ("colscale", 40000, 300, 1200, 12, "colscale", 1e6, 1e-8, False),
+    ("wide-d", 12000, 50, 3000, 4, "svd", 1e3, 1e-4, False),
+    ("tiny", 40, 3, 12, 2, "svd", 10.0, 1e-3, False),
+    ("sparse", 50000, 120, 480, 8, "sparse_sign", 1.0, 1e-2, False),
+    ("odd-n", 25000, 333, 1337, 8, "svd", 1e5, 1e-6, False),
+]
+
+
+@pytest.mark.parametrize("name,m,n,d,zeta,kind,cond,noise,row_scale", SOLVE_CASES)
+def test_solve_parity(sap, orc, name, m, n, d, zeta, kind, cond, noise, row_scale):
+    import torch
+    _note(f"solve {name} m={m} n={n} d={d} zeta={zeta}")
+    if name == "config0":
+        p = inputs.config0()
+        seed = p.meta["sketch_seed"]
+    else:
+        p = inputs.make_problem(m, n, kind=kind, cond=cond, noise=noise, seed=m + 3, row_scale=row_scale)
+        seed = 99
+    res = sap.sap_solve(_dev(p.A), _dev(p.b), d, zeta, seed, tol=1e-12, maxiter=300)
+    torch.cuda.synchronize()
+    x = res.x.cpu().numpy()
+    x_or, info_or = orc.solve(p.A, p.b, d, zeta, seed, tol=1e-12, maxiter=300)
+    nb = np.linalg.norm(p.b)
+    assert res.status == sap.SAP_OK, res.info
+    assert info_or["status"] == "ok"
+    assert np.linalg.norm(p.A @ (x - x_or)) <= 1e-12 * nb
+    if name in ("config0", "tiny", "wide-d", "sparse"):
+        assert np.linalg.norm(x - x_or) <= 1e-8 * np.linalg.norm(x_or)
+    assert abs(res.info["iters"] - info_or["iters"]) <= 2
+
+
+def test_solve_errors(sap):
+    import torch
+    p = inputs.make_problem(3000, 10, kind="svd", cond=1e2, seed=16)
+    A = p.A.copy()
+    A[:, 7] = A[:, 2]
+    _note("solve rank-deficient")
+    with pytest.raises(sap.SapError) as e:
+        sap.sap_solve(_dev(A), _dev(p.b), 40, 8, 1)
+    assert e.value.status == sap.SAP_RANK_DEFICIENT
+    _note("solve maxiter=1")
+    res = sap.sap_solve(_dev(p.A), _dev(p.b), 40, 8, 1, maxiter=1)
+    assert res.status == sap.SAP_NOT_CONVERGED and res.info["iters"] == 1
+    _note("solve invalid d")
+    with pytest.raises(sap.SapError) as e:
+        sap.sap_solve(_dev(p.A), _dev(p.b), 10, 8, 1)
+    assert e.value.status == sap.SAP_EINVAL
+    bad = p.b.copy()
+    bad[17] = np.nan
+    _note("solve nan b")
+    with pytest.raises(sap.SapError) as e:
+        sap.sap_solve(_dev(p.A), _dev(bad), 40, 8, 1)
+    assert e.value.status == sap.SAP_EINVAL
+    _note("solve dtype mismatch")
+    with pytest.raises(sap.SapError) as e:
+        sap.sap_solve(_dev(p.A.astype(np.float32)), _dev(p.b), 40, 8, 1, mode=sap.SAP_MODE_FP64)
+    assert e.value.status == sap.SAP_EINVAL
+    torch.cuda.synchronize()
+
+
+def test_solve_deterministic(sap):
+    """Fixed reduction orders everywhere except the LDS sketch-apply adds:
+    repeated solves agree to the solver tolerance and the sketch bit for bit."""
+    import torch
+    p = inputs.make_problem(20000, 64, kind="svd", cond=1e6, noise=1e-6, seed=5)
+    r1 = sap.sap_solve(_dev(p.A), _dev(p.b), 256, 8, 3)
+    x1 = r1.x.cpu().numpy()
+    r2 = sap.sap_solve(_dev(p.A), _dev(p.b), 256, 8, 3)
+    x2 = r2.x.cpu().numpy()
+    torch.cuda.synchronize()
+    assert np.linalg.norm(p.A @ (x1 - x2)) <= 1e-13 * np.linalg.norm(p.b)
