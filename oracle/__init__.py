@@ -73,7 +73,7 @@ def lib():
                                ctypes.POINTER(LsqrInfo)]
         L.orc_rank_deficient.argtypes = [_vp, _i64, _i32, _i32]
         L.orc_rank_deficient.restype = ctypes.c_int
-        L.orc_solve.argtypes = [_i64, _i32, _vp, _i64, _vp, _i32, _i32, _u64, _f64, _i32, _vp, _vp,
+        L.orc_solve.argtypes = [_i64, _i32, _vp, _i64, _vp, _i32, _i32, _u64, _u64, _f64, _i32, _vp, _vp,
                                 _vp, ctypes.POINTER(SolveInfo)]
         L.orc_direct_solve.argtypes = [_i64, _i32, _vp, _i64, _vp, _vp]
         _lib = L
@@ -275,7 +275,7 @@ def rank_deficient(R, d):
 STATUS = {0: "ok", 1: "invalid", 3: "rank_deficient", 4: "not_converged"}
 
 
-def solve(A, b, d, zeta, seed, tol=1e-12, maxiter=200, want_y=False):
+def solve(A, b, d, zeta, seed, tol=1e-12, maxiter=200, want_y=False, stream=0):
     """Alg. 1 end to end.  Returns (x, info dict) (+ factored Y if want_y)."""
     A = _f64c(A)
     m, n = A.shape
@@ -283,7 +283,7 @@ def solve(A, b, d, zeta, seed, tol=1e-12, maxiter=200, want_y=False):
     x0 = np.zeros(n)
     Y = np.zeros((n + 1, d)) if want_y else None
     info = SolveInfo()
-    lib().orc_solve(m, n, _p(A), n, _p(_f64c(b)), d, zeta, seed, tol, maxiter, _p(x), _p(x0),
+    lib().orc_solve(m, n, _p(A), n, _p(_f64c(b)), d, zeta, seed, stream, tol, maxiter, _p(x), _p(x0),
                     _p(Y), ctypes.byref(info))
     out = dict(status=STATUS.get(info.status, str(info.status)), iters=info.iters,
                resid_est=info.resid_est, normar_est=info.normar_est, x0=x0,

@@ -486,11 +486,12 @@ int orc_rank_deficient(const double *R, int64_t ldr, int32_t n, int32_t d)
     return !(mn > (double)d * ldexp(1.0, -53) * mx);
 }
 
-/* Sample S, form Y = S[A b], QR of Y, x0 = R^-1 (Q^T S b)[0:n], LSQR.
+/* Sample S (key (seed, stream)), form Y = S[A b], QR of Y,
+ * x0 = R^-1 (Q^T S b)[0:n], LSQR.
  * Y_out (nullable, d x (n+1) column-major, ld d) receives the factored Y
  * (R in the upper triangle).  x receives the solution. */
 void orc_solve(int64_t m, int32_t n, const double *A, int64_t lda, const double *b,
-               int32_t d, int32_t zeta, uint64_t seed, double tol, int32_t maxiter,
+               int32_t d, int32_t zeta, uint64_t seed, uint64_t stream, double tol, int32_t maxiter,
                double *x, double *x0_out, double *Y_out, orc_solve_info *info)
 {
     memset(info, 0, sizeof(*info));
@@ -506,7 +507,7 @@ void orc_solve(int64_t m, int32_t n, const double *A, int64_t lda, const double 
     double *x0 = (double *)malloc(sizeof(double) * (size_t)n);
 
     double t0 = orc_now();
-    orc_sketch(seed, 0, m, d, zeta, idx, sign, NULL);
+    orc_sketch(seed, stream, m, d, zeta, idx, sign, NULL);
     double t1 = orc_now();
     orc_apply_sparse(m, d, zeta, idx, sign, A, lda, b, n, 1.0 / sqrt((double)zeta), Y, d, NULL, 0);
     double t2 = orc_now();
