@@ -24,9 +24,11 @@
  *     (element (r, c) at Y[r + c*ldy]).
  *   - Errors: every call returns a sap_status; no exception crosses the ABI.
  *     On SAP_EINVAL / SAP_ENOMEM outputs are untouched.  sap_last_error()
- *     gives a human-readable reason for the last failure on that context.
- *   - Threads: one caller per context at a time, except sap_submit /
- *     sap_poll / sap_cancel which are thread-safe.
+ *     gives a human-readable reason for the calling thread's last failure
+ *     on that context.
+ *   - Threads: one caller per context at a time, except the served-form
+ *     calls (sap_submit / sap_poll / sap_cancel / sap_serve_stats), which
+ *     are thread-safe and may run beside one other blocking call.
  */
 #ifndef SAP_H
 #define SAP_H
@@ -51,12 +53,15 @@ typedef enum sap_status {
 
 typedef enum sap_dtype { SAP_F64 = 0, SAP_F32 = 1, SAP_BF16 = 2 } sap_dtype;
 
-/* Precision forms of sap_solve.  FP64: every step in double.  MIXED_FP32:
- * A stored FP32; sketch apply and the LSQR GEMVs in FP32 with FP32
- * accumulation; QR of the sketch, the R triangular solves, the LSQR scalar
- * recurrences and the residual refinement passes in FP64.  MIXED_BF16SA: as
- * MIXED_FP32, but the sketch is applied to a bfloat16 rounding of A. */
-typedef enum sap_mode { SAP_MODE_FP64 = 0, SAP_MODE_MIXED_FP32 = 1, SAP_MODE_MIXED_BF16SA = 2 } sap_mode;
+/* Precision forms of sap_solve.  FP64: A and every step in double.
+ * MIXED_FP32: A stored in FP32 (the problem is the FP32 matrix, whose
+ * elements are exact in FP64); the sketch S [A b] is accumulated in FP32 (the
+ * preconditioner only has to be approximate), widened to FP64 for the QR;
+ * the LSQR passes read the FP32 A and widen each element, so products,
+ * accumulation, u, the triangular solves and the recurrences are FP64.  The
+ * passes, which dominate the run time, move half the bytes of the FP64 form
+ * and reach the same FP64 stopping test, with no refinement loop. */
+typedef enum sap_mode { SAP_MODE_FP64 = 0, SAP_MODE_MIXED_FP32 = 1 } sap_mode;
 
 typedef struct sap_ctx sap_ctx;
 
@@ -136,7 +141,7 @@ typedef struct sap_problem {
     int32_t n;          /* columns of A, n >= 1 */
     const void *A;      /* device, row-major m x n, lda >= n */
     int64_t lda;
-    sap_dtype a_type;   /* F64 for SAP_MODE_FP64, F32 for the mixed modes */
+    sap_dtype a_type;   /* F64 for SAP_MODE_FP64, F32 for SAP_MODE_MIXED_FP32 */
     const double *b;    /* device, m doubles */
 } sap_problem;
 
@@ -145,20 +150,18 @@ typedef struct sap_params {
     int32_t zeta;       /* sketch nonzeros per column, 1..min(d, 64) */
     uint64_t seed;      /* sketch seed (stream word is 0 for sap_solve) */
     double tol;         /* LSQR stopping tolerance (see below), e.g. 1e-12 */
-    int32_t maxiter;    /* LSQR iteration cap (total over refinements) */
+    int32_t maxiter;    /* LSQR iteration cap */
     int32_t mode;       /* sap_mode */
-    int32_t max_refine; /* mixed modes: refinement passes cap (0 = default 8) */
-    double inner_tol;   /* mixed modes: inner FP32 LSQR tolerance (0 = 1e-6) */
 } sap_params;
 
 typedef struct sap_info {
     int32_t status;      /* final sap_status of the solve */
-    int32_t iters;       /* LSQR iterations (summed over refinements) */
-    int32_t refinements; /* FP64 residual refinement passes (mixed modes) */
-    int32_t reserved;
+    int32_t iters;       /* LSQR iterations */
     double resid_est;    /* estimate of ||b - A x|| */
     double normar_est;   /* estimate of ||(A M)^T (b - A x)|| */
     double t_generate_ms, t_apply_ms, t_qr_ms, t_iterate_ms; /* phase times */
+    double t_queue_ms;   /* served form: submit -> admission */
+    double t_total_ms;   /* served form: submit -> finished */
 } sap_info;
 
 /* Solve min ||b - A x|| by Alg. 1 with a sparse sign sketch and LSQR (Alg. 2)
@@ -175,12 +178,79 @@ sap_status sap_solve(sap_ctx *ctx, const sap_problem *prob, const sap_params *pa
 
 /* Preconditioned LSQR alone (Alg. 2) on A M with M = R^-1 for a given R
  * (device, upper triangle of column-major n x n, leading dimension ldr) and
- * initial guess x0 (device, n doubles; may alias x).  The FP64 form only
- * (prob->a_type must be F64).  Blocking.  Same stopping rule and errors as
+ * initial guess x0 (device, n doubles; may alias x).  A may be F64 or F32
+ * (FP32 storage, FP64 arithmetic as in SAP_MODE_MIXED_FP32).  Blocking.  Same stopping rule and errors as
  * sap_solve. */
 sap_status sap_lsqr(sap_ctx *ctx, const sap_problem *prob, const double *R, int64_t ldr,
                     const double *x0, double tol, int32_t maxiter, double *x, sap_info *info,
                     void *stream);
+
+/* Many independent problems solved together (the batched form): each phase of
+ * Alg. 1 is one launch over all problems, and the LSQR iterations of all
+ * problems advance together (replayed from a captured hipGraph) until every
+ * problem has met its own stopping test or its maxiter.  probs, params, x and
+ * info are host arrays of `count` entries; x[k] is a device pointer to n_k
+ * doubles.  All problems share one A dtype (F32 or F64); each has its own m,
+ * n, d, zeta, seed, tol and maxiter (mode is ignored).  The sketch of problem k uses Philox stream word k.  The passes
+ * over A accumulate in FP64 whatever A's storage type.  Limits: n <= 1024,
+ * d <= 4096 and d * 16 * sizeof(A element) <= 160000 (the sketch tile of a
+ * workgroup lives in LDS), m < 2^31.  Blocking.  Returns SAP_OK when every
+ * problem converged, SAP_NOT_CONVERGED when some did not or were rank
+ * deficient (per-problem status in info[k].status); SAP_EINVAL, SAP_ENOMEM,
+ * SAP_EDEVICE as for sap_solve. */
+sap_status sap_solve_batch(sap_ctx *ctx, int32_t count, const sap_problem *probs, const sap_params *params,
+                           double *const *x, sap_info *info, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Served form (continuous batching).  A scheduler thread owned by the
+ * context admits submitted problems first in, first out whenever their
+ * workspace fits in a device arena reserved for serving, and advances all
+ * admitted problems together: each round runs the setup phases of Alg. 1
+ * (sketch, apply, QR, x0) for the problems admitted since the last round as
+ * one batch, then a few LSQR iterations (Alg. 2) of every active problem as
+ * one batch; a problem retires at the end of the round in which it meets its
+ * stopping test (same test as sap_solve) or its maxiter, and its memory goes
+ * back to the arena.  A problem's sketch is the one sap_solve draws for the
+ * same seed, and its result does not depend on what else is in flight
+ * beyond the rounding order of the sketch accumulation.  Limits as for
+ * sap_solve_batch; all problems of one context share one A dtype.
+ * ---------------------------------------------------------------------- */
+
+/* Start serving with an arena of arena_bytes of device memory (0: half the
+ * context's HBM budget, at most 64 GiB) and at most max_active problems in
+ * flight (1..4096).  Optional: the first sap_submit starts serving with the
+ * defaults (arena 0, max_active 1024).  Errors: SAP_EINVAL (already serving,
+ * bad max_active), SAP_ENOMEM. */
+sap_status sap_serve_start(sap_ctx *ctx, size_t arena_bytes, int32_t max_active);
+
+/* Queue one problem.  prob->A, prob->b (device) and x (device, n doubles,
+ * the output) must stay valid and unmodified until sap_poll reports a
+ * terminal status for the ticket.  The inputs count as written once the
+ * work already queued on `stream` has run (the scheduler waits on an event
+ * recorded there).  Non-blocking; *ticket identifies the request.  Errors:
+ * SAP_EINVAL (shapes, parameters, dtype differing from earlier requests),
+ * SAP_ENOMEM (the problem can never fit in the arena), SAP_EDEVICE (serving
+ * stopped after a device error). */
+sap_status sap_submit(sap_ctx *ctx, const sap_problem *prob, const sap_params *params, double *x, uint64_t *ticket,
+                      void *stream);
+
+/* State of a request.  wait != 0 blocks until it is finished; x is complete
+ * on the device when a terminal status is returned.  Returns
+ * SAP_PENDING while queued or running; otherwise the request's final status
+ * (SAP_OK, SAP_NOT_CONVERGED, SAP_RANK_DEFICIENT, SAP_ECANCELED,
+ * SAP_EDEVICE), fills *info (nullable; t_queue_ms and t_total_ms are the
+ * host-clock queueing time and submit-to-finish latency) and forgets the
+ * ticket: polling it again gives SAP_EINVAL. */
+sap_status sap_poll(sap_ctx *ctx, uint64_t ticket, sap_info *info, int32_t wait);
+
+/* Ask a request to stop: a queued one is dropped, a running one retires at
+ * the end of the current round (x then holds its last iterate).  Its poll
+ * status becomes SAP_ECANCELED.  Errors: SAP_EINVAL (unknown ticket). */
+sap_status sap_cancel(sap_ctx *ctx, uint64_t ticket);
+
+/* Serving counters, 7 int64 values: submitted, completed, active, queued,
+ * rejected, arena bytes in use, arena bytes. */
+sap_status sap_serve_stats(sap_ctx *ctx, int64_t *stats);
 
 /* ------------------------------------------------------------------------
  * Kernel timing (measurement support).  When enabled, the library brackets

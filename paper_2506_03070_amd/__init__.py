@@ -17,12 +17,13 @@ SAP_OK, SAP_EINVAL, SAP_ENOMEM, SAP_RANK_DEFICIENT, SAP_NOT_CONVERGED, SAP_PENDI
 STATUS_NAMES = {0: "SAP_OK", 1: "SAP_EINVAL", 2: "SAP_ENOMEM", 3: "SAP_RANK_DEFICIENT",
                 4: "SAP_NOT_CONVERGED", 5: "SAP_PENDING", 6: "SAP_EDEVICE", 7: "SAP_ECANCELED"}
 SAP_F64, SAP_F32, SAP_BF16 = 0, 1, 2
-SAP_MODE_FP64, SAP_MODE_MIXED_FP32, SAP_MODE_MIXED_BF16SA = 0, 1, 2
+SAP_MODE_FP64, SAP_MODE_MIXED_FP32 = 0, 1
 
 # Every symbol the header declares (checked by the CPU test suite).
 EXPORTS = ["sap_create", "sap_destroy", "sap_last_error", "sap_status_string", "sps_generate",
            "sps_apply", "sap_qr", "sap_trsv", "sap_solve", "sap_lsqr", "sap_profile_enable",
-           "sap_profile_read"]
+           "sap_profile_read", "sap_solve_batch", "sap_serve_start", "sap_submit", "sap_poll",
+           "sap_cancel", "sap_serve_stats"]
 PROF_PASS, PROF_APPLY = 0, 1
 
 _vp = ctypes.c_void_p
@@ -43,16 +44,16 @@ class SapProblem(ctypes.Structure):
 
 class SapParams(ctypes.Structure):
     _fields_ = [("d", _i32), ("zeta", _i32), ("seed", _u64), ("tol", _f64), ("maxiter", _i32),
-                ("mode", _i32), ("max_refine", _i32), ("inner_tol", _f64)]
+                ("mode", _i32)]
 
 
 class SapInfo(ctypes.Structure):
-    _fields_ = [("status", _i32), ("iters", _i32), ("refinements", _i32), ("reserved", _i32),
-                ("resid_est", _f64), ("normar_est", _f64), ("t_generate_ms", _f64),
-                ("t_apply_ms", _f64), ("t_qr_ms", _f64), ("t_iterate_ms", _f64)]
+    _fields_ = [("status", _i32), ("iters", _i32), ("resid_est", _f64), ("normar_est", _f64), ("t_generate_ms", _f64),
+                ("t_apply_ms", _f64), ("t_qr_ms", _f64), ("t_iterate_ms", _f64),
+                ("t_queue_ms", _f64), ("t_total_ms", _f64)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"} | {
+        return {k: getattr(self, k) for k, _ in self._fields_} | {
             "status_name": STATUS_NAMES.get(self.status, str(self.status))}
 
 
@@ -96,6 +97,20 @@ def lib():
         L.sap_lsqr.argtypes = [_vp, ctypes.POINTER(SapProblem), _vp, _i64, _vp, _f64, _i32, _vp,
                                ctypes.POINTER(SapInfo), _vp]
         L.sap_lsqr.restype = ctypes.c_int
+        L.sap_solve_batch.argtypes = [_vp, _i32, ctypes.POINTER(SapProblem), ctypes.POINTER(SapParams),
+                                      ctypes.POINTER(_vp), ctypes.POINTER(SapInfo), _vp]
+        L.sap_solve_batch.restype = ctypes.c_int
+        L.sap_serve_start.argtypes = [_vp, ctypes.c_size_t, _i32]
+        L.sap_serve_start.restype = ctypes.c_int
+        L.sap_submit.argtypes = [_vp, ctypes.POINTER(SapProblem), ctypes.POINTER(SapParams), _vp,
+                                 ctypes.POINTER(_u64), _vp]
+        L.sap_submit.restype = ctypes.c_int
+        L.sap_poll.argtypes = [_vp, _u64, ctypes.POINTER(SapInfo), _i32]
+        L.sap_poll.restype = ctypes.c_int
+        L.sap_cancel.argtypes = [_vp, _u64]
+        L.sap_cancel.restype = ctypes.c_int
+        L.sap_serve_stats.argtypes = [_vp, ctypes.POINTER(_i64)]
+        L.sap_serve_stats.restype = ctypes.c_int
         L.sap_profile_enable.argtypes = [_vp, ctypes.c_int]
         L.sap_profile_enable.restype = ctypes.c_int
         L.sap_profile_read.argtypes = [_vp, _i32, ctypes.POINTER(_i64), ctypes.POINTER(_f64), ctypes.c_int]
@@ -258,15 +273,15 @@ class SolveResult:
     info: dict
 
 
-def sap_solve(A, b, d, zeta=8, seed=1, tol=1e-12, maxiter=200, mode=None, max_refine=0, inner_tol=0.0,
-              ctx=None, x=None, allow_not_converged=True):
+def sap_solve(A, b, d, zeta=8, seed=1, tol=1e-12, maxiter=200, mode=None, ctx=None, x=None,
+              allow_not_converged=True):
     """min ||b - A x|| by sketch-and-precondition (Alg. 1) with LSQR (Alg. 2)."""
     torch = _torch()
     ctx = ctx or default_context()
     if mode is None:
         mode = SAP_MODE_FP64 if A.dtype == torch.float64 else SAP_MODE_MIXED_FP32
     prob = _problem(A, b)
-    par = SapParams(d, zeta, seed, tol, maxiter, mode, max_refine, inner_tol)
+    par = SapParams(d, zeta, seed, tol, maxiter, mode)
     x = x if x is not None else torch.empty(A.shape[1], dtype=torch.float64, device=A.device)
     info = SapInfo()
     st = lib().sap_solve(ctx.handle, ctypes.byref(prob), ctypes.byref(par), _dev(x, torch.float64, "x"),
@@ -277,7 +292,7 @@ def sap_solve(A, b, d, zeta=8, seed=1, tol=1e-12, maxiter=200, mode=None, max_re
 
 
 def sap_lsqr(A, b, Rt, x0, tol=1e-12, maxiter=200, ctx=None, x=None):
-    """Alg. 2 alone on A R^-1 from x0 (FP64)."""
+    """Alg. 2 alone on A R^-1 from x0 (A in FP64, or FP32 storage with FP64 arithmetic)."""
     torch = _torch()
     ctx = ctx or default_context()
     prob = _problem(A, b)
@@ -288,3 +303,78 @@ def sap_lsqr(A, b, Rt, x0, tol=1e-12, maxiter=200, ctx=None, x=None):
                         ctypes.byref(info), _vp(_stream()))
     ctx.check(st, (SAP_OK, SAP_NOT_CONVERGED))
     return SolveResult(x, st, info.as_dict())
+
+
+def sap_solve_batch(As, bs, ds, zetas=8, seeds=1, tol=1e-12, maxiter=200, ctx=None, xs=None):
+    """Solve many independent problems together (sap_solve_batch).  As, bs:
+    lists of device tensors (A row-major, F32 or F64; b F64).  Returns
+    (xs, statuses, infos)."""
+    torch = _torch()
+    ctx = ctx or default_context()
+    count = len(As)
+    zetas = zetas if isinstance(zetas, (list, tuple)) else [zetas] * count
+    seeds = seeds if isinstance(seeds, (list, tuple)) else [seeds] * count
+    ds = ds if isinstance(ds, (list, tuple)) else [ds] * count
+    probs = (SapProblem * count)(*[_problem(A, b) for A, b in zip(As, bs)])
+    pars = (SapParams * count)(*[SapParams(int(d), int(z), int(s), tol, maxiter, 0)
+                                 for d, z, s in zip(ds, zetas, seeds)])
+    xs = xs or [torch.empty(A.shape[1], dtype=torch.float64, device=A.device) for A in As]
+    xptrs = (_vp * count)(*[_vp(_dev(xx, torch.float64, "x")) for xx in xs])
+    infos = (SapInfo * count)()
+    st = lib().sap_solve_batch(ctx.handle, count, probs, pars, xptrs, infos, _vp(_stream()))
+    ctx.check(st, (SAP_OK, SAP_NOT_CONVERGED))
+    return xs, st, [infos[k].as_dict() for k in range(count)]
+
+
+# ---- served form ---------------------------------------------------------------
+SERVE_STATS = ("submitted", "completed", "active", "queued", "rejected", "arena_used", "arena_size")
+_inflight = {}  # (context handle, ticket) -> tensors the request reads or writes
+
+
+def sap_serve_start(arena_bytes=0, max_active=1024, ctx=None):
+    """Start the continuous-batching scheduler (optional; sap_submit starts it)."""
+    ctx = ctx or default_context()
+    ctx.check(lib().sap_serve_start(ctx.handle, int(arena_bytes), int(max_active)))
+
+
+def sap_submit(A, b, d, zeta=8, seed=1, tol=1e-12, maxiter=200, ctx=None, x=None):
+    """Queue one problem (sap_submit).  Returns the ticket; the tensors stay
+    referenced here until sap_poll reports a terminal status."""
+    torch = _torch()
+    ctx = ctx or default_context()
+    x = x if x is not None else torch.empty(A.shape[1], dtype=torch.float64, device=A.device)
+    prob = _problem(A, b)
+    par = SapParams(int(d), int(zeta), int(seed), float(tol), int(maxiter), 0)
+    ticket = _u64(0)
+    st = lib().sap_submit(ctx.handle, ctypes.byref(prob), ctypes.byref(par), _vp(_dev(x, torch.float64, "x")),
+                          ctypes.byref(ticket), _vp(_stream()))
+    ctx.check(st)
+    _inflight[(ctx.handle.value, ticket.value)] = (A, b, x)
+    return ticket.value
+
+
+def sap_poll(ticket, wait=False, ctx=None):
+    """State of a request: (status, info dict or None, x or None).  status is
+    SAP_PENDING until the request finishes."""
+    ctx = ctx or default_context()
+    info = SapInfo()
+    st = lib().sap_poll(ctx.handle, _u64(ticket), ctypes.byref(info), 1 if wait else 0)
+    if st == SAP_PENDING:
+        return st, None, None
+    if st == SAP_EINVAL and (ctx.handle.value, ticket) not in _inflight:
+        ctx.check(st)
+    held = _inflight.pop((ctx.handle.value, ticket), None)
+    return st, info.as_dict(), (held[2] if held else None)
+
+
+def sap_cancel(ticket, ctx=None):
+    ctx = ctx or default_context()
+    ctx.check(lib().sap_cancel(ctx.handle, _u64(ticket)))
+
+
+def sap_serve_stats(ctx=None):
+    ctx = ctx or default_context()
+    out = (_i64 * len(SERVE_STATS))()
+    ctx.check(lib().sap_serve_stats(ctx.handle, out))
+    return dict(zip(SERVE_STATS, list(out)))
+

@@ -8,8 +8,18 @@
 
 namespace sap {
 
+// The last error message is kept per calling thread (errno-like), so
+// concurrent sap_submit / sap_poll callers cannot race on it.
+namespace {
+thread_local std::string tl_err;
+thread_local const sap_ctx *tl_err_ctx = nullptr;
+}  // namespace
+
 sap_status fail(sap_ctx *ctx, sap_status s, const std::string &msg) {
-  if (ctx) ctx->err = msg;
+  if (ctx) {
+    tl_err = msg;
+    tl_err_ctx = ctx;
+  }
   return s;
 }
 
@@ -173,6 +183,7 @@ sap_status sap_create(sap_ctx **out, int device, size_t hbm_budget) {
 
 void sap_destroy(sap_ctx *ctx) {
   if (!ctx) return;
+  serve_destroy(ctx);
   (void)hipSetDevice(ctx->device);
   (void)hipDeviceSynchronize();
   prof_resolve(ctx);
@@ -200,7 +211,10 @@ sap_status sap_profile_read(sap_ctx *ctx, int32_t kernel, int64_t *launches, dou
   return SAP_OK;
 }
 
-const char *sap_last_error(const sap_ctx *ctx) { return ctx ? ctx->err.c_str() : "NULL context"; }
+const char *sap_last_error(const sap_ctx *ctx) {
+  if (!ctx) return "NULL context";
+  return tl_err_ctx == ctx ? tl_err.c_str() : "";
+}
 
 sap_status sps_generate(sap_ctx *ctx, const sps_sketch *S, void *stream) {
   if (!ctx) return SAP_EINVAL;
@@ -228,7 +242,7 @@ sap_status sps_apply(sap_ctx *ctx, const sps_sketch *S, const void *A, int64_t l
   hipStream_t st = static_cast<hipStream_t>(stream);
   SAP_HIP_TRY(hipSetDevice(ctx->device));
   const int ncols = n + (b ? 1 : 0);
-  s = ensure_workspace(ctx, apply_workspace_bytes(ctx, S->m, S->d, ncols, y_type) + 256, st);
+  s = ensure_workspace(ctx, apply_workspace_bytes(ctx, S->m, S->zeta, S->d, ncols, y_type) + 256, st);
   if (s != SAP_OK) return s;
   hipEvent_t pb = prof_begin(ctx, st);
   s = launch_apply(ctx, S, A, lda, a_type, b, n, Y, ldy, y_type, ctx->ws, st);
@@ -255,8 +269,12 @@ sap_status sap_trsv(sap_ctx *ctx, const double *R, int64_t ldr, int32_t n, int32
   if (!R || !rhs || !x) return fail(ctx, SAP_EINVAL, "sap_trsv: NULL pointer");
   if (n < 1 || ldr < n) return fail(ctx, SAP_EINVAL, "sap_trsv: need n >= 1 and ldr >= n");
   if (trans != 0 && trans != 1) return fail(ctx, SAP_EINVAL, "sap_trsv: trans must be 0 or 1");
+  if (n > 8192) return fail(ctx, SAP_EINVAL, "sap_trsv: n > 8192 is not supported");
   SAP_HIP_TRY(hipSetDevice(ctx->device));
-  return launch_trsv(ctx, R, ldr, n, trans, rhs, x, static_cast<hipStream_t>(stream));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  sap_status s = ensure_workspace(ctx, trsv_workspace_bytes(n), st);
+  if (s != SAP_OK) return s;
+  return launch_trsv(ctx, R, ldr, n, trans, rhs, x, ctx->ws, st);
 }
 
 static sap_status check_problem(sap_ctx *ctx, const sap_problem *p) {
@@ -274,20 +292,20 @@ sap_status sap_lsqr(sap_ctx *ctx, const sap_problem *prob, const double *R, int6
   if (!ctx) return SAP_EINVAL;
   sap_status s = check_problem(ctx, prob);
   if (s != SAP_OK) return s;
-  if (prob->a_type != SAP_F64) return fail(ctx, SAP_EINVAL, "sap_lsqr: A must be F64");
+  if (prob->a_type != SAP_F64 && prob->a_type != SAP_F32) return fail(ctx, SAP_EINVAL, "sap_lsqr: A must be F64 or F32");
   if (!R || !x0 || !x) return fail(ctx, SAP_EINVAL, "sap_lsqr: NULL pointer");
   if (ldr < prob->n) return fail(ctx, SAP_EINVAL, "sap_lsqr: ldr must be >= n");
   if (maxiter < 0 || !(tol >= 0.0)) return fail(ctx, SAP_EINVAL, "sap_lsqr: need maxiter >= 0 and tol >= 0");
   hipStream_t st = static_cast<hipStream_t>(stream);
   SAP_HIP_TRY(hipSetDevice(ctx->device));
-  s = ensure_workspace(ctx, lsqr_workspace_bytes(ctx, prob->m, prob->n, 0), st);
+  s = ensure_workspace(ctx, lsqr_workspace_bytes(ctx, prob->m, prob->n), st);
   if (s != SAP_OK) return s;
   if (info) std::memset(info, 0, sizeof(*info));
   hipEvent_t e0, e1;
   SAP_HIP_TRY(hipEventCreate(&e0));
   SAP_HIP_TRY(hipEventCreate(&e1));
   SAP_HIP_TRY(hipEventRecord(e0, st));
-  s = run_lsqr(ctx, prob, R, ldr, x0, tol, maxiter, 0, 0, 0.0, x, info, ctx->ws, st);
+  s = run_lsqr(ctx, prob, R, ldr, x0, nullptr, tol, maxiter, prob->a_type == SAP_F32 ? 1 : 0, x, info, ctx->ws, st);
   (void)hipEventRecord(e1, st);
   (void)hipEventSynchronize(e1);
   prof_resolve(ctx);
@@ -300,6 +318,14 @@ sap_status sap_lsqr(sap_ctx *ctx, const sap_problem *prob, const double *R, int6
     info->t_iterate_ms = ms;
   }
   return s;
+}
+
+sap_status sap_solve_batch(sap_ctx *ctx, int32_t count, const sap_problem *probs, const sap_params *params,
+                           double *const *x, sap_info *info, void *stream) {
+  if (!ctx) return SAP_EINVAL;
+  if (count < 1 || !probs || !params || !x) return fail(ctx, SAP_EINVAL, "sap_solve_batch: bad arguments");
+  SAP_HIP_TRY(hipSetDevice(ctx->device));
+  return run_batch(ctx, count, probs, params, x, info, static_cast<hipStream_t>(stream));
 }
 
 sap_status sap_solve(sap_ctx *ctx, const sap_problem *prob, const sap_params *par, double *x, sap_info *info,
@@ -332,9 +358,9 @@ sap_status sap_solve(sap_ctx *ctx, const sap_problem *prob, const sap_params *pa
   const size_t bytes_Y = static_cast<size_t>(d) * nc * sizeof(double);
   const size_t bytes_Yf = (mode == SAP_MODE_FP64) ? 0 : static_cast<size_t>(d) * nc * sizeof(float);
   const size_t bytes_tau = static_cast<size_t>(nc) * sizeof(double);
-  const size_t bytes_apply = apply_workspace_bytes(ctx, m, d, nc, y_type);
+  const size_t bytes_apply = apply_workspace_bytes(ctx, m, par->zeta, d, nc, y_type);
   const size_t bytes_qr = qr_workspace_bytes(d, nc);
-  const size_t bytes_lsqr = lsqr_workspace_bytes(ctx, m, n, mode == SAP_MODE_FP64 ? 0 : 1);
+  const size_t bytes_lsqr = lsqr_workspace_bytes(ctx, m, n);
   size_t scratch = bytes_apply > bytes_qr ? bytes_apply : bytes_qr;
   scratch = scratch > bytes_lsqr ? scratch : bytes_lsqr;
   const size_t total = 8 * 256 + bytes_flags + bytes_idx + bytes_sign + bytes_Y + bytes_Yf + bytes_tau + scratch;
@@ -396,12 +422,10 @@ sap_status sap_solve(sap_ctx *ctx, const sap_problem *prob, const sap_params *pa
     return fail(ctx, SAP_RANK_DEFICIENT, "sap_solve: R is numerically singular (A rank deficient)");
   }
   // x0 = R^-1 (Q^T S b)[0:n]: column n of the factored sketch.
-  s = launch_trsv(ctx, Y, d, n, 0, Y + static_cast<int64_t>(n) * d, x, st);
-  if (s != SAP_OK) return s;
   const int lsqr_mode = (mode == SAP_MODE_FP64) ? 0 : 1;
   sap_info li{};
-  s = run_lsqr(ctx, prob, Y, d, x, par->tol, par->maxiter, lsqr_mode, par->max_refine,
-               par->inner_tol > 0.0 ? par->inner_tol : 1e-6, x, &li, work, st);
+  s = run_lsqr(ctx, prob, Y, d, nullptr, Y + static_cast<int64_t>(n) * d, par->tol, par->maxiter, lsqr_mode, x,
+               &li, work, st);
   if (s != SAP_OK && s != SAP_NOT_CONVERGED) return s;
   SAP_HIP_TRY(hipEventRecord(ev[4], st));
   SAP_HIP_TRY(hipEventSynchronize(ev[4]));
@@ -419,8 +443,34 @@ sap_status sap_solve(sap_ctx *ctx, const sap_problem *prob, const sap_params *pa
     (void)hipEventElapsedTime(&ms, ev[3], ev[4]);
     info->t_iterate_ms = ms;
   }
-  if (s == SAP_NOT_CONVERGED) ctx->err = "sap_solve: maxiter reached before the stopping test";
+  if (s == SAP_NOT_CONVERGED) (void)fail(ctx, s, "sap_solve: maxiter reached before the stopping test");
   return s;
+}
+
+sap_status sap_serve_start(sap_ctx *ctx, size_t arena_bytes, int32_t max_active) {
+  if (!ctx) return SAP_EINVAL;
+  return serve_start(ctx, arena_bytes, max_active);
+}
+
+sap_status sap_submit(sap_ctx *ctx, const sap_problem *prob, const sap_params *params, double *x, uint64_t *ticket,
+                      void *stream) {
+  if (!ctx) return SAP_EINVAL;
+  return serve_submit(ctx, prob, params, x, ticket, static_cast<hipStream_t>(stream));
+}
+
+sap_status sap_poll(sap_ctx *ctx, uint64_t ticket, sap_info *info, int32_t wait) {
+  if (!ctx) return SAP_EINVAL;
+  return serve_poll(ctx, ticket, info, wait);
+}
+
+sap_status sap_cancel(sap_ctx *ctx, uint64_t ticket) {
+  if (!ctx) return SAP_EINVAL;
+  return serve_cancel(ctx, ticket);
+}
+
+sap_status sap_serve_stats(sap_ctx *ctx, int64_t *stats) {
+  if (!ctx || !stats) return SAP_EINVAL;
+  return serve_stats(ctx, stats);
 }
 
 }  // extern "C"

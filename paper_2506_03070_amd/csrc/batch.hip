@@ -1,0 +1,1306 @@
+// Batched sketch-and-precondition: many independent, unevenly sized
+// least-squares problems solved together, each phase of Alg. 1 one launch
+// over all problems.
+//
+//   generate : one lane per sketch column of every problem (binary search of
+//              the column prefix), stream word = problem index;
+//   apply    : one workgroup per (problem, 16-column tile), the tile's d rows
+//              in LDS (d <= 2048 for FP32 accumulation, <= 1250 for FP64);
+//   QR       : one launch per panel step for all problems (2-D grid:
+//              trailing block x problem), shapes from the largest d;
+//   LSQR     : per iteration one packed pass over all problems (work items =
+//              (problem, row chunk); several short rows per wavefront), then
+//              the two chain triangular solves on a (block, problem) grid;
+//              the iterations are replayed from a captured hipGraph until a
+//              device counter says every problem has stopped.
+// The pass reads A in its storage precision (FP32 or FP64) and accumulates
+// in FP64: on gfx950 the FP64 vector rate keeps this pass HBM-bound, so the
+// batched form needs no refinement loop.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <tuple>
+#include <type_traits>
+#include <vector>
+
+#include "common.h"
+#include "lsqr_dev.h"
+#include "qr_dev.h"
+#include "sketch_dev.h"
+#include "trsv.h"
+
+namespace sap {
+
+// Per-problem descriptor (device resident).
+struct BatchItem {
+  const void *A;
+  int64_t lda;
+  const double *b;
+  double *x;
+  int64_t m;
+  int32_t n, d, zeta, maxiter;
+  double tol, h;
+  uint64_t seed, stream;
+  int64_t col_base;  // prefix of m over the problems (sketch columns)
+  int32_t *idx;
+  uint64_t *sign;
+  void *Ysk;         // sketch accumulator (FP32 or FP64), d x (n+1)
+  double *Y;         // FP64 sketch for the QR, d x (n+1)
+  double *tau, *T0, *T1;
+  double *Rt, *Dup, *Dlo;
+  int *flags;        // 3 * nblk: lower, upper, x0
+  LsqrState *st;
+  double *u, *y, *v, *w, *p;
+  double *qpart, *nrmpart;
+  int32_t G, nblk;
+  int64_t rows_per_chunk;
+  int32_t rank_deficient, pad;
+};
+
+namespace {
+
+using namespace qr_dev;
+
+constexpr int kBThreads = 1024;
+constexpr int kBWaves = kBThreads / kWave;
+constexpr int kTileColsB = 16;
+constexpr int kXcdsB = 8;
+
+// ---- generate --------------------------------------------------------------
+template <int ZMAX>
+__global__ __launch_bounds__(256) void batch_generate_kernel(const BatchItem *__restrict__ items, int count,
+                                                             int64_t total, int *__restrict__ err) {
+  const int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (g >= total) return;
+  int lo = 0, hi = count - 1;  // last item with col_base <= g
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (items[mid].col_base <= g) lo = mid;
+    else hi = mid - 1;
+  }
+  const BatchItem &it = items[lo];
+  sketch_dev::generate_column<ZMAX>(g - it.col_base, it.d, it.zeta, it.seed, it.stream, it.idx, it.sign, err);
+}
+
+// ---- apply -----------------------------------------------------------------
+template <typename TA, typename TY>
+__global__ __launch_bounds__(kBThreads) void batch_apply_kernel(const BatchItem *__restrict__ items,
+                                                                const int2 *__restrict__ work, int nwork) {
+  extern __shared__ unsigned char lds_raw[];
+  TY *acc = reinterpret_cast<TY *>(lds_raw);
+  const int per_xcd = (nwork + kXcdsB - 1) / kXcdsB;
+  const int wi = (blockIdx.x % kXcdsB) * per_xcd + blockIdx.x / kXcdsB;
+  if (wi >= nwork) return;
+  const int2 wk = work[wi];
+  const BatchItem &it = items[wk.x];
+  const int c0 = wk.y * kTileColsB;
+  const int d = it.d, n = it.n, ncols = it.n + 1, zeta = it.zeta;
+  const TA *__restrict__ A = static_cast<const TA *>(it.A);
+  for (int e = threadIdx.x; e < d * kTileColsB; e += kBThreads) acc[e] = TY(0);
+  __syncthreads();
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  const int g = lane / kTileColsB, c = lane % kTileColsB;
+  const int col = c0 + c;
+  const bool col_a = col < n, col_b = col == n;
+  const int64_t nnz = it.m * zeta;
+  constexpr int U = 8;
+  constexpr int64_t kStride = static_cast<int64_t>(kBWaves) * 4 * U;
+  for (int64_t base = static_cast<int64_t>(wave) * 4 * U; base < nnz; base += kStride) {
+    TY val[U];
+    int rloc[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t e = base + u * 4 + g;
+      rloc[u] = -1;
+      val[u] = TY(0);
+      if (e < nnz) {
+        const int64_t i = e / zeta;
+        const int k = static_cast<int>(e - i * zeta);
+        const int r = it.idx[e];
+        const bool plus = ((it.sign[i] >> k) & 1ull) != 0;
+        TY a = TY(0);
+        if (col_a) a = static_cast<TY>(A[i * it.lda + col]);
+        else if (col_b) a = static_cast<TY>(it.b[i]);
+        val[u] = plus ? a : -a;
+        rloc[u] = static_cast<unsigned>(r) < static_cast<unsigned>(d) ? r : -1;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (rloc[u] >= 0) atomicAdd(acc + rloc[u] * kTileColsB + c, val[u]);
+  }
+  __syncthreads();
+  TY *Ysk = static_cast<TY *>(it.Ysk);
+  const TY hs = static_cast<TY>(it.h);
+  for (int e = threadIdx.x; e < d * kTileColsB; e += kBThreads) {
+    const int q = e / d, r = e % d;
+    const int cc = c0 + q;
+    if (cc < ncols) Ysk[r + static_cast<int64_t>(cc) * d] = acc[r * kTileColsB + q] * hs;
+  }
+}
+
+__global__ __launch_bounds__(256) void batch_widen_kernel(const BatchItem *__restrict__ items) {
+  const BatchItem &it = items[blockIdx.y];
+  const int64_t tot = static_cast<int64_t>(it.d) * (it.n + 1);
+  const float *src = static_cast<const float *>(it.Ysk);
+  for (int64_t e = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; e < tot; e += static_cast<int64_t>(gridDim.x) * 256)
+    it.Y[e] = static_cast<double>(src[e]);
+}
+
+// ---- QR ----------------------------------------------------------------------
+template <int S, int NB>
+__global__ __launch_bounds__(kPanelThreads) void batch_qr_first_kernel(const BatchItem *__restrict__ items) {
+  __shared__ PanelShared<NB> sh;
+  const BatchItem &it = items[blockIdx.x];
+  const int rows = it.d, cols = it.n + 1;
+  const int nb = cols < NB ? cols : NB;
+  double P[S][NB];
+  load_block<S, NB>(it.Y, rows, 0, rows, 0, nb, P);
+  factor_panel<S, NB>(P, sh, nb, rows, 0, 0, it.tau, it.T0);
+  store_block<S, NB>(it.Y, rows, 0, rows, 0, nb, P);
+}
+
+template <int S, int NB>
+__global__ __launch_bounds__(kPanelThreads) void batch_qr_step_kernel(const BatchItem *__restrict__ items, int step) {
+  __shared__ PanelShared<NB> sh;
+  const BatchItem &it = items[blockIdx.y];
+  const int rows = it.d, cols = it.n + 1;
+  const int k0 = step * NB;
+  const int nb = min(NB, cols - k0);
+  if (nb <= 0 || k0 + nb >= cols) return;  // no trailing columns at this step
+  const int trailing = cols - (k0 + nb);
+  if (static_cast<int>(blockIdx.x) * NB >= trailing) return;
+  const int c0 = k0 + nb + static_cast<int>(blockIdx.x) * NB;
+  const int ncb = min(NB, cols - c0);
+  const int dr = rows - k0;
+  const double *Tcur = (step & 1) ? it.T1 : it.T0;
+  double *Tnext = (step & 1) ? it.T0 : it.T1;
+  double C[S][NB];
+  load_block<S, NB>(it.Y, rows, k0, dr, c0, ncb, C);
+  apply_panel_qt<S, NB>(it.Y, rows, dr, k0, nb, Tcur, C, ncb, sh);
+  if (blockIdx.x == 0) factor_panel<S, NB>(C, sh, ncb, rows - c0, c0 - k0, c0, it.tau, Tnext);
+  store_block<S, NB>(it.Y, rows, k0, dr, c0, ncb, C);
+}
+
+__global__ __launch_bounds__(256) void batch_rank_kernel(BatchItem *__restrict__ items) {
+  __shared__ double smax[4], smin[4];
+  BatchItem &it = items[blockIdx.x];
+  double mx = 0.0, mn = INFINITY;
+  for (int k = threadIdx.x; k < it.n; k += 256) {
+    const double a = fabs(it.Y[k + static_cast<int64_t>(k) * it.d]);
+    mx = fmax(mx, a);
+    mn = fmin(mn, a);
+  }
+  mx = wave_max(mx);
+  mn = -wave_max(-mn);
+  if ((threadIdx.x & 63) == 0) {
+    smax[threadIdx.x / 64] = mx;
+    smin[threadIdx.x / 64] = mn;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 0; w < 4; ++w) {
+      mx = fmax(mx, smax[w]);
+      mn = fmin(mn, smin[w]);
+    }
+    it.rank_deficient = !(mn > static_cast<double>(it.d) * 0x1p-53 * mx);
+  }
+}
+
+// ---- triangular-solve preparation and x0 ------------------------------------
+__global__ __launch_bounds__(256) void batch_trsv_prepare_kernel(const BatchItem *__restrict__ items) {
+  __shared__ TrsvPrepShared sh;
+  const BatchItem &it = items[blockIdx.y];
+  if (static_cast<int>(blockIdx.x) >= it.nblk) return;
+  trsv_invert_diag_block(it.Y, it.d, it.n, static_cast<int>(blockIdx.x), it.Dup, it.Dlo, sh);
+}
+
+__global__ __launch_bounds__(256) void batch_transpose_kernel(const BatchItem *__restrict__ items) {
+  __shared__ double tile[32][33];
+  const BatchItem &it = items[blockIdx.z];
+  const int nt = (it.n + 31) / 32;
+  if (static_cast<int>(blockIdx.x) >= nt || static_cast<int>(blockIdx.y) >= nt) return;
+  trsv_transpose_tile(it.Y, it.d, it.n, static_cast<int>(blockIdx.x), static_cast<int>(blockIdx.y), it.Rt, tile);
+}
+
+// Fresh LSQR state, cleared flags, ||b||.
+__global__ __launch_bounds__(1024) void batch_init_kernel(const BatchItem *__restrict__ items) {
+  __shared__ double scr[16];
+  const BatchItem &it = items[blockIdx.x];
+  for (int i = threadIdx.x; i < 3 * it.nblk; i += 1024) it.flags[i] = 0;
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < it.m; i += 1024) s += it.b[i] * it.b[i];
+  s = wg_sum(s, scr);
+  if (threadIdx.x == 0) {
+    LsqrState *st = it.st;
+    st->alpha = st->beta = st->rhobar = st->phibar = 0.0;
+    st->alpha_new = st->beta_new = 0.0;
+    st->c_ap = -1.0;
+    st->c_u = 1.0;
+    st->normb = sqrt(s);
+    st->tol = it.tol;
+    st->resid_est = st->normar_est = 0.0;
+    st->iter = 0;
+    st->maxiter = it.maxiter;
+    st->done = it.rank_deficient ? 1 : 0;
+    st->converged = 0;
+    st->init = 1;
+    st->proceed = 0;
+    st->total_iters = 0;
+    st->steps = 0;
+  }
+}
+
+// x0 = R^-1 z (z = column n of the factored sketch), chain over the blocks.
+__global__ __launch_bounds__(kTrsvThreads) void batch_x0_kernel(const BatchItem *__restrict__ items, int *err) {
+  __shared__ LowerShared sh;
+  const BatchItem &it = items[blockIdx.y];
+  if (static_cast<int>(blockIdx.x) >= it.nblk) return;
+  if (it.rank_deficient) return;
+  const int n = it.n;
+  const int b = it.nblk - 1 - static_cast<int>(blockIdx.x);
+  const double *z = it.Y + static_cast<int64_t>(n) * it.d;
+  if (threadIdx.x < kTrsvB) {
+    const int row = b * kTrsvB + threadIdx.x;
+    sh.rb[threadIdx.x] = row < n ? z[row] : 0.0;
+  }
+  __syncthreads();
+  chain_block<true>(it.Y, it.d, n, it.Dup, it.x, it.flags + 2 * it.nblk, 1, b, sh.rb, sh.red, err);
+}
+
+// ---- LSQR iteration -----------------------------------------------------------
+// Packed pass: L lanes serve one row (L = the power of two covering n/VEC,
+// at most 64, chosen per problem), so a wavefront handles 64/L rows at once.
+// u <- c_ap (A p) + c_u u_in with FP64 accumulation; q += u_i A[i, :].
+// At the initialisation step (st->init) the pass reads u_in = b and p = x.
+template <typename TA, int VEC, int KJ>
+__global__ __launch_bounds__(kBThreads) void batch_pass_kernel(const BatchItem *__restrict__ items,
+                                                               const int2 *__restrict__ work, int nwork, int tune) {
+  __shared__ double qsh[kBWaves][64 * VEC * KJ];
+  __shared__ double nsh[kBWaves];
+  const int2 wk = work[blockIdx.x];
+  const BatchItem &it = items[wk.x];
+  const LsqrState *st = it.st;
+  if (st->done && !tune) return;
+  const int n = it.n;
+  const bool init = st->init != 0;
+  const double *__restrict__ pv = init ? it.x : it.p;
+  const double *__restrict__ uin = init ? it.b : it.u;
+  double *uout = it.u;
+  const double c_ap = st->c_ap, c_u = st->c_u;
+  int L = 1;
+  while (L * VEC * KJ < n && L < 64) L <<= 1;
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  const int slot = lane / L, sub = lane % L;
+  const int RS = kWave / L;  // rows per wavefront step
+  const TA *__restrict__ A = static_cast<const TA *>(it.A);
+  const int64_t lda = it.lda;
+  const bool vec_ok = (VEC > 1);
+
+  double preg[KJ][VEC], q[KJ][VEC];
+#pragma unroll
+  for (int j = 0; j < KJ; ++j)
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) {
+      const int c = (sub + L * j) * VEC + e;
+      preg[j][e] = c < n ? pv[c] : 0.0;
+      q[j][e] = 0.0;
+    }
+  const int64_t r0 = static_cast<int64_t>(wk.y) * it.rows_per_chunk;
+  const int64_t r1 = min(it.m, r0 + it.rows_per_chunk);
+  double nrm = 0.0;
+  constexpr int U = 2;
+  for (int64_t base = r0 + static_cast<int64_t>(wave) * RS * U; base < r1; base += static_cast<int64_t>(kBWaves) * RS * U) {
+    double a[U][KJ][VEC];
+#pragma unroll
+    for (int uu = 0; uu < U; ++uu) {
+      const int64_t row = base + uu * RS + slot;
+      const bool rv = row < r1;
+      const TA *arow = A + row * lda;
+#pragma unroll
+      for (int j = 0; j < KJ; ++j) {
+        const int c = (sub + L * j) * VEC;
+        if (rv && vec_ok && c + VEC <= n) {
+          const auto v = *reinterpret_cast<const typename std::conditional<
+              std::is_same<TA, float>::value,
+              typename std::conditional<VEC == 4, float4, float2>::type,
+              typename std::conditional<VEC == 2, double2, double>::type>::type *>(arow + c);
+          const TA *vv = reinterpret_cast<const TA *>(&v);
+#pragma unroll
+          for (int e = 0; e < VEC; ++e) a[uu][j][e] = static_cast<double>(vv[e]);
+        } else {
+#pragma unroll
+          for (int e = 0; e < VEC; ++e) a[uu][j][e] = (rv && c + e < n) ? static_cast<double>(arow[c + e]) : 0.0;
+        }
+      }
+    }
+#pragma unroll
+    for (int uu = 0; uu < U; ++uu) {
+      const int64_t row = base + uu * RS + slot;
+      double s = 0.0;
+#pragma unroll
+      for (int j = 0; j < KJ; ++j)
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) s += a[uu][j][e] * preg[j][e];
+      for (int off = L >> 1; off >= 1; off >>= 1) s += __shfl_xor(s, off, kWave);
+      if (row < r1) {
+        const double uh = c_ap * s + c_u * uin[row];
+#pragma unroll
+        for (int j = 0; j < KJ; ++j)
+#pragma unroll
+          for (int e = 0; e < VEC; ++e) q[j][e] += uh * a[uu][j][e];
+        if (sub == 0) {
+          if (!tune) uout[row] = uh;
+          nrm += uh * uh;
+        }
+      }
+    }
+  }
+  // combine the row slots of the wavefront (lanes with equal `sub`), then waves
+#pragma unroll
+  for (int j = 0; j < KJ; ++j)
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) {
+      double v = q[j][e];
+      for (int off = L; off < kWave; off <<= 1) v += __shfl_xor(v, off, kWave);
+      q[j][e] = v;
+    }
+  if (slot == 0) {
+#pragma unroll
+    for (int j = 0; j < KJ; ++j)
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) qsh[wave][(sub + L * j) * VEC + e] = q[j][e];
+  }
+  nrm = wave_sum(nrm);
+  if (lane == 0) nsh[wave] = nrm;
+  __syncthreads();
+  double *qdst = it.qpart + static_cast<int64_t>(wk.y) * n;
+  for (int c = threadIdx.x; c < n; c += kBThreads) {
+    double s = 0.0;
+    for (int w = 0; w < kBWaves; ++w) s += qsh[w][c];
+    qdst[c] = s;
+  }
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int w = 0; w < kBWaves; ++w) s += nsh[w];
+    it.nrmpart[wk.y] = s;
+  }
+}
+
+__global__ __launch_bounds__(kTrsvThreads) void batch_lower_kernel(const BatchItem *__restrict__ items, int *err) {
+  __shared__ LowerShared sh;
+  const BatchItem &it = items[blockIdx.y];
+  if (static_cast<int>(blockIdx.x) >= it.nblk) return;
+  LsqrState *st = it.st;
+  if (st->done) return;
+  const int n = it.n, b = blockIdx.x;
+  const int epoch = st->steps + 1;
+  reduce_q_block(it.qpart, it.G, n, b, sh);
+  chain_block<false>(it.Rt, n, n, it.Dlo, it.y, it.flags, epoch, b, sh.rb, sh.red, err);
+  if (b != it.nblk - 1) return;
+  lower_epilogue(n, it.G, it.nrmpart, it.y, it.v, st, sh);
+}
+
+__global__ __launch_bounds__(kTrsvThreads) void batch_upper_kernel(const BatchItem *__restrict__ items, int *err,
+                                                                   int *done_count) {
+  __shared__ LowerShared sh;
+  const BatchItem &it = items[blockIdx.y];
+  if (static_cast<int>(blockIdx.x) >= it.nblk) return;
+  LsqrState *st = it.st;
+  if (st->done) return;
+  const int n = it.n;
+  const int b = it.nblk - 1 - static_cast<int>(blockIdx.x);
+  const int epoch = st->steps + 1;
+  if (threadIdx.x < kTrsvB) {
+    const int row = b * kTrsvB + threadIdx.x;
+    sh.rb[threadIdx.x] = row < n ? it.v[row] : 0.0;
+  }
+  __syncthreads();
+  chain_block<true>(it.Y, it.d, n, it.Dup, it.p, it.flags + it.nblk, epoch, b, sh.rb, sh.red, err);
+  if (b != 0) return;
+  upper_epilogue(n, it.p, it.w, it.x, st, done_count);
+}
+
+__global__ void batch_count_rank_kernel(const BatchItem *__restrict__ items, int count, int *done_count) {
+  if (threadIdx.x != 0) return;
+  int c = 0;
+  for (int k = 0; k < count; ++k) c += items[k].rank_deficient ? 1 : 0;
+  *done_count = c;
+}
+
+// done[k] = problem k has stopped (served form).
+__global__ void serve_done_kernel(const BatchItem *__restrict__ items, int count, int *__restrict__ done) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < count) done[k] = items[k].st->done;
+}
+
+template <int S, int NB>
+void launch_batch_qr(const BatchItem *items, int count, int max_cols, hipStream_t st) {
+  batch_qr_first_kernel<S, NB><<<count, kPanelThreads, 0, st>>>(items);
+  const int nsteps = (max_cols + NB - 1) / NB;
+  for (int step = 0; step < nsteps; ++step) {
+    const int trailing = max_cols - step * NB - NB;
+    if (trailing <= 0) break;
+    const int blocks = (trailing + NB - 1) / NB;
+    batch_qr_step_kernel<S, NB><<<dim3(blocks, count), kPanelThreads, 0, st>>>(items, step);
+  }
+}
+
+struct PassChoice {
+  const void *fn;
+  int vec, kj;
+};
+
+template <typename TA>
+PassChoice pick_batch_pass(int n_max, bool aligned) {
+  constexpr int vmax = 16 / static_cast<int>(sizeof(TA));
+  const int vec = aligned ? vmax : 1;
+  const int per = 64 * vec;
+  const int kj = (n_max + per - 1) / per;
+  if (vec == 1) {
+    if (kj <= 1) return {reinterpret_cast<const void *>(&batch_pass_kernel<TA, 1, 1>), 1, 1};
+    if (kj <= 2) return {reinterpret_cast<const void *>(&batch_pass_kernel<TA, 1, 2>), 1, 2};
+    if (kj <= 4) return {reinterpret_cast<const void *>(&batch_pass_kernel<TA, 1, 4>), 1, 4};
+    return {reinterpret_cast<const void *>(&batch_pass_kernel<TA, 1, 16>), 1, 16};
+  }
+  if (kj <= 1) return {reinterpret_cast<const void *>(&batch_pass_kernel<TA, vmax, 1>), vmax, 1};
+  if (kj <= 2) return {reinterpret_cast<const void *>(&batch_pass_kernel<TA, vmax, 2>), vmax, 2};
+  return {reinterpret_cast<const void *>(&batch_pass_kernel<TA, vmax, 4>), vmax, 4};
+}
+
+void launch_pass_fn(const void *fn, const BatchItem *items, const int2 *work, int nwork, int tune, hipStream_t st) {
+  const BatchItem *it_ = items;
+  const int2 *w_ = work;
+  int nw = nwork, tn = tune;
+  void *args[] = {&it_, &w_, &nw, &tn};
+  (void)hipLaunchKernel(fn, dim3(nwork), dim3(kBThreads), args, 0, st);
+}
+
+}  // namespace
+
+// ----------------------------------------------------------------------------
+// Shared pieces of the batched and served forms.
+
+// Bytes of one problem's workspace (rows_per_chunk >= kMinRowsPerChunk).
+constexpr int64_t kMinRowsPerChunk = 1024;
+
+size_t item_bytes(int64_t m, int n, int d, int zeta, sap_dtype at) {
+  const size_t ya = (at == SAP_F32) ? 4 : 8;
+  const int nc = n + 1;
+  const int nblk = (n + kTrsvB - 1) / kTrsvB;
+  const int64_t gmax = (m + kMinRowsPerChunk - 1) / kMinRowsPerChunk;
+  size_t b = 0;
+  b += 256 + sizeof(int32_t) * m * zeta;
+  b += 256 + sizeof(uint64_t) * m;
+  b += 256 + ya * d * nc;
+  b += (at == SAP_F32 ? 256 + sizeof(double) * d * nc : 0);
+  b += 3 * (256 + sizeof(double) * 256);
+  b += 256 + sizeof(double) * n * n;
+  b += 2 * (256 + sizeof(double) * nblk * kTrsvB * kTrsvB);
+  b += 256 + sizeof(int) * 3 * nblk;
+  b += 256 + sizeof(LsqrState);
+  b += 256 + sizeof(double) * m;
+  b += 4 * (256 + sizeof(double) * n);
+  b += 256 + sizeof(double) * gmax * n;
+  b += 256 + sizeof(double) * gmax;
+  return b + 256;
+}
+
+// Fill the workspace pointers of `it` from memory at `base`.
+void carve_item(BatchItem &it, void *base, sap_dtype at, int64_t rows_per_chunk) {
+  Carve cv(base);
+  const int64_t m = it.m;
+  const int n = it.n, d = it.d, nc = n + 1;
+  it.nblk = (n + kTrsvB - 1) / kTrsvB;
+  it.idx = cv.take<int32_t>(static_cast<size_t>(m) * it.zeta);
+  it.sign = cv.take<uint64_t>(m);
+  it.Ysk = (at == SAP_F32) ? static_cast<void *>(cv.take<float>(static_cast<size_t>(d) * nc))
+                           : static_cast<void *>(cv.take<double>(static_cast<size_t>(d) * nc));
+  it.Y = (at == SAP_F32) ? cv.take<double>(static_cast<size_t>(d) * nc) : static_cast<double *>(it.Ysk);
+  it.tau = cv.take<double>(256);
+  it.T0 = cv.take<double>(256);
+  it.T1 = cv.take<double>(256);
+  it.Rt = cv.take<double>(static_cast<size_t>(n) * n);
+  it.Dup = cv.take<double>(static_cast<size_t>(it.nblk) * kTrsvB * kTrsvB);
+  it.Dlo = cv.take<double>(static_cast<size_t>(it.nblk) * kTrsvB * kTrsvB);
+  it.flags = cv.take<int>(3 * it.nblk);
+  it.st = cv.take<LsqrState>(1);
+  it.u = cv.take<double>(m);
+  it.y = cv.take<double>(n);
+  it.v = cv.take<double>(n);
+  it.w = cv.take<double>(n);
+  it.p = cv.take<double>(n);
+  const int64_t gmax = (m + kMinRowsPerChunk - 1) / kMinRowsPerChunk;
+  it.qpart = cv.take<double>(static_cast<size_t>(gmax) * n);
+  it.nrmpart = cv.take<double>(gmax);
+  it.rows_per_chunk = rows_per_chunk;
+  it.G = static_cast<int>((m + rows_per_chunk - 1) / rows_per_chunk);
+}
+
+// Phases S1-S7 setup for the `count` problems of a device items array:
+// sketches, apply, QR, rank test, factor preparation, LSQR state and x0.
+// dflags: [0] wait error, [1] done counter (incremented for rank-deficient
+// problems here), [2] generation error.
+sap_status setup_items(sap_ctx *ctx, BatchItem *ditems, const std::vector<BatchItem> &items, const int2 *dapply,
+                       int napply, int *dflags, sap_dtype at, hipStream_t st) {
+  const int count = static_cast<int>(items.size());
+  int n_max = 0, d_max = 0, zeta_max = 0;
+  int64_t total_cols = 0;
+  for (const auto &it : items) {
+    n_max = std::max(n_max, it.n);
+    d_max = std::max(d_max, it.d);
+    zeta_max = std::max(zeta_max, it.zeta);
+    total_cols = std::max(total_cols, it.col_base + it.m);
+  }
+  const unsigned grid = static_cast<unsigned>((total_cols + 255) / 256);
+  if (zeta_max <= 8) batch_generate_kernel<8><<<grid, 256, 0, st>>>(ditems, count, total_cols, dflags + 2);
+  else if (zeta_max <= 16) batch_generate_kernel<16><<<grid, 256, 0, st>>>(ditems, count, total_cols, dflags + 2);
+  else if (zeta_max <= 32) batch_generate_kernel<32><<<grid, 256, 0, st>>>(ditems, count, total_cols, dflags + 2);
+  else batch_generate_kernel<64><<<grid, 256, 0, st>>>(ditems, count, total_cols, dflags + 2);
+  const size_t ya = (at == SAP_F32) ? 4 : 8;
+  const int per_xcd = (napply + kXcdsB - 1) / kXcdsB;
+  const size_t lds = static_cast<size_t>(d_max) * kTileColsB * ya;
+  if (at == SAP_F32) {
+    batch_apply_kernel<float, float><<<per_xcd * kXcdsB, kBThreads, lds, st>>>(ditems, dapply, napply);
+    batch_widen_kernel<<<dim3(64, count), 256, 0, st>>>(ditems);
+  } else {
+    batch_apply_kernel<double, double><<<per_xcd * kXcdsB, kBThreads, lds, st>>>(ditems, dapply, napply);
+  }
+  SAP_HIP_TRY(hipGetLastError());
+  const int sh = (d_max + kPanelThreads - 1) / kPanelThreads;
+  const int cols = n_max + 1;
+  if (sh <= 1) launch_batch_qr<1, 8>(ditems, count, cols, st);
+  else if (sh <= 2) launch_batch_qr<2, 8>(ditems, count, cols, st);
+  else if (sh <= 4) launch_batch_qr<4, 8>(ditems, count, cols, st);
+  else launch_batch_qr<8, 4>(ditems, count, cols, st);
+  SAP_HIP_TRY(hipGetLastError());
+  batch_rank_kernel<<<count, 256, 0, st>>>(ditems);
+  const int nblk_max = (n_max + kTrsvB - 1) / kTrsvB;
+  const int nt_max = (n_max + 31) / 32;
+  batch_trsv_prepare_kernel<<<dim3(nblk_max, count), 256, 0, st>>>(ditems);
+  batch_transpose_kernel<<<dim3(nt_max, nt_max, count), 256, 0, st>>>(ditems);
+  batch_init_kernel<<<count, 1024, 0, st>>>(ditems);
+  batch_x0_kernel<<<dim3(nblk_max, count), kTrsvThreads, 0, st>>>(ditems, dflags);
+  SAP_HIP_TRY(hipGetLastError());
+  return SAP_OK;
+}
+
+// Shapes of the batch that select kernels, and the cached autotune choice.
+struct BatchTuneKey {
+  int a_type, n_bucket, count;
+  bool operator<(const BatchTuneKey &o) const {
+    return std::tie(a_type, n_bucket, count) < std::tie(o.a_type, o.n_bucket, o.count);
+  }
+};
+static std::map<BatchTuneKey, int64_t> g_tune_rows;
+
+sap_status run_batch(sap_ctx *ctx, int count, const sap_problem *probs, const sap_params *par, double *const *x,
+                     sap_info *infos, hipStream_t user_stream) {
+  if (count < 1) return fail(ctx, SAP_EINVAL, "sap_solve_batch: count must be >= 1");
+  const sap_dtype at = probs[0].a_type;
+  int n_max = 0, maxiter_max = 0;
+  bool aligned = true;
+  for (int k = 0; k < count; ++k) {
+    const sap_problem &p = probs[k];
+    const sap_params &q = par[k];
+    if (p.a_type != at) return fail(ctx, SAP_EINVAL, "sap_solve_batch: all problems need the same A dtype");
+    if (at != SAP_F32 && at != SAP_F64) return fail(ctx, SAP_EINVAL, "sap_solve_batch: A must be F32 or F64");
+    if (!p.A || !p.b || !x[k]) return fail(ctx, SAP_EINVAL, "sap_solve_batch: NULL pointer");
+    if (p.n < 1 || p.m < static_cast<int64_t>(p.n) + 1 || p.lda < p.n || p.m > (int64_t(1) << 31))
+      return fail(ctx, SAP_EINVAL, "sap_solve_batch: bad problem shape");
+    if (q.d < p.n + 1 || q.zeta < 1 || q.zeta > 64 || q.zeta > q.d || q.maxiter < 0 || !(q.tol >= 0.0))
+      return fail(ctx, SAP_EINVAL, "sap_solve_batch: bad parameters");
+    const size_t es = (at == SAP_F32) ? 4 : 8;
+    if (static_cast<size_t>(q.d) * 16 * es > 160000 || q.d > 4096)
+      return fail(ctx, SAP_EINVAL, "sap_solve_batch: d too large for the batched form");
+    n_max = std::max(n_max, p.n);
+    maxiter_max = std::max(maxiter_max, q.maxiter);
+    const int vm = 16 / static_cast<int>(es);
+    if (reinterpret_cast<uintptr_t>(p.A) % 16 != 0 || p.lda % vm != 0) aligned = false;
+  }
+  if (n_max > 1024) return fail(ctx, SAP_EINVAL, "sap_solve_batch: n > 1024 is not supported");
+
+  // ---- workspace layout ---------------------------------------------------------
+  const BatchTuneKey key{static_cast<int>(at), (n_max + 63) / 64, count};
+  int64_t rows_per_chunk = 4096;
+  auto tit = g_tune_rows.find(key);
+  const bool have_tune = tit != g_tune_rows.end();
+  if (have_tune) rows_per_chunk = tit->second;
+  std::vector<size_t> need(count);
+  size_t total = 8 * 256 + sizeof(BatchItem) * count;
+  int64_t total_chunks_max = 0;
+  for (int k = 0; k < count; ++k) {
+    need[k] = item_bytes(probs[k].m, probs[k].n, par[k].d, par[k].zeta, at);
+    total += need[k];
+    total_chunks_max += (probs[k].m + kMinRowsPerChunk - 1) / kMinRowsPerChunk;
+  }
+  const int tiles_max = (n_max + 1 + 15) / 16;
+  total += 256 + sizeof(int2) * (total_chunks_max + 16);
+  total += 256 + sizeof(int2) * (static_cast<size_t>(count) * tiles_max + 16);
+  sap_status s = ensure_workspace(ctx, total, user_stream);
+  if (s != SAP_OK) return s;
+  Carve cv(ctx->ws);
+  int *dflags = cv.take<int>(8);  // [0] wait error, [1] done count, [2] generation error
+  BatchItem *ditems = cv.take<BatchItem>(count);
+  std::vector<BatchItem> items(count);
+  int64_t col_base = 0;
+  for (int k = 0; k < count; ++k) {
+    BatchItem &it = items[k];
+    const sap_problem &p = probs[k];
+    const sap_params &q = par[k];
+    it = BatchItem{};
+    it.A = p.A;
+    it.lda = p.lda;
+    it.b = p.b;
+    it.x = x[k];
+    it.m = p.m;
+    it.n = p.n;
+    it.d = q.d;
+    it.zeta = q.zeta;
+    it.maxiter = q.maxiter;
+    it.tol = q.tol;
+    it.h = 1.0 / std::sqrt(static_cast<double>(q.zeta));
+    it.seed = q.seed;
+    it.stream = static_cast<uint64_t>(k);
+    it.col_base = col_base;
+    col_base += p.m;
+    carve_item(it, cv.take<char>(need[k]), at, rows_per_chunk);
+  }
+  int2 *dpass = cv.take<int2>(total_chunks_max + 16);
+  int2 *dapply = cv.take<int2>(static_cast<size_t>(count) * tiles_max + 16);
+
+  // work tables
+  std::vector<int2> apply_work;
+  for (int k = 0; k < count; ++k) {
+    const int tiles = (items[k].n + 1 + 15) / 16;
+    for (int t = 0; t < tiles; ++t) apply_work.push_back(make_int2(k, t));
+  }
+  auto pass_table = [&](int64_t rpc_) {
+    std::vector<int2> wt;
+    for (int k = 0; k < count; ++k) {
+      const int G = static_cast<int>((items[k].m + rpc_ - 1) / rpc_);
+      for (int g = 0; g < G; ++g) wt.push_back(make_int2(k, g));
+    }
+    return wt;
+  };
+
+  // internal stream (graph capture needs a non-default stream)
+  hipStream_t st = nullptr;
+  SAP_HIP_TRY(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+  struct StreamGuard {
+    hipStream_t s;
+    ~StreamGuard() { (void)hipStreamDestroy(s); }
+  } sguard{st};
+  hipEvent_t ev_in;
+  SAP_HIP_TRY(hipEventCreateWithFlags(&ev_in, hipEventDisableTiming));
+  SAP_HIP_TRY(hipEventRecord(ev_in, user_stream));
+  SAP_HIP_TRY(hipStreamWaitEvent(st, ev_in, 0));
+  (void)hipEventDestroy(ev_in);
+
+  SAP_HIP_TRY(hipMemsetAsync(dflags, 0, 8 * sizeof(int), st));
+  SAP_HIP_TRY(hipMemcpyAsync(ditems, items.data(), sizeof(BatchItem) * count, hipMemcpyHostToDevice, st));
+  SAP_HIP_TRY(hipMemcpyAsync(dapply, apply_work.data(), sizeof(int2) * apply_work.size(), hipMemcpyHostToDevice, st));
+  s = setup_items(ctx, ditems, items, dapply, static_cast<int>(apply_work.size()), dflags, at, st);
+  if (s != SAP_OK) return s;
+  batch_count_rank_kernel<<<1, 64, 0, st>>>(ditems, count, dflags + 1);
+  const int nblk_max = (n_max + kTrsvB - 1) / kTrsvB;
+  // The rank test wrote its flag into the device items: take them back so
+  // that the re-uploads below keep it.
+  SAP_HIP_TRY(hipMemcpyAsync(items.data(), ditems, sizeof(BatchItem) * count, hipMemcpyDeviceToHost, st));
+  SAP_HIP_TRY(hipStreamSynchronize(st));
+
+  // ---- autotune the pass chunking once per batch shape ----
+  const PassChoice pc = (at == SAP_F32) ? pick_batch_pass<float>(n_max, aligned) : pick_batch_pass<double>(n_max, aligned);
+  if (!have_tune) {
+    const int64_t cands[] = {2048, 4096, 8192, 16384};
+    float best_ms = 1e30f;
+    int64_t best = rows_per_chunk;
+    hipEvent_t e0, e1;
+    SAP_HIP_TRY(hipEventCreate(&e0));
+    SAP_HIP_TRY(hipEventCreate(&e1));
+    for (int64_t c : cands) {
+      std::vector<int2> wt = pass_table(c);
+      std::vector<BatchItem> tmp = items;
+      for (auto &it : tmp) {
+        it.rows_per_chunk = c;
+        it.G = static_cast<int>((it.m + c - 1) / c);
+      }
+      SAP_HIP_TRY(hipMemcpyAsync(ditems, tmp.data(), sizeof(BatchItem) * count, hipMemcpyHostToDevice, st));
+      SAP_HIP_TRY(hipMemcpyAsync(dpass, wt.data(), sizeof(int2) * wt.size(), hipMemcpyHostToDevice, st));
+      float ms_best = 1e30f;
+      for (int rep = 0; rep < 2; ++rep) {
+        SAP_HIP_TRY(hipEventRecord(e0, st));
+        launch_pass_fn(pc.fn, ditems, dpass, static_cast<int>(wt.size()), 1, st);
+        SAP_HIP_TRY(hipEventRecord(e1, st));
+        SAP_HIP_TRY(hipEventSynchronize(e1));
+        float ms = 0.f;
+        SAP_HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+        ms_best = std::min(ms_best, ms);
+      }
+      if (ms_best < best_ms) {
+        best_ms = ms_best;
+        best = c;
+      }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    rows_per_chunk = best;
+    g_tune_rows[key] = best;
+    for (auto &it : items) {
+      it.rows_per_chunk = best;
+      it.G = static_cast<int>((it.m + best - 1) / best);
+    }
+    SAP_HIP_TRY(hipMemcpyAsync(ditems, items.data(), sizeof(BatchItem) * count, hipMemcpyHostToDevice, st));
+  }
+  std::vector<int2> pass_work = pass_table(rows_per_chunk);
+  SAP_HIP_TRY(hipMemcpyAsync(dpass, pass_work.data(), sizeof(int2) * pass_work.size(), hipMemcpyHostToDevice, st));
+  const int npass = static_cast<int>(pass_work.size());
+
+  // ---- S7-S8: iterations, replayed from a captured graph ----
+  const int kIterPerGraph = 8;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  SAP_HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+  for (int k = 0; k < kIterPerGraph; ++k) {
+    launch_pass_fn(pc.fn, ditems, dpass, npass, 0, st);
+    batch_lower_kernel<<<dim3(nblk_max, count), kTrsvThreads, 0, st>>>(ditems, dflags);
+    batch_upper_kernel<<<dim3(nblk_max, count), kTrsvThreads, 0, st>>>(ditems, dflags, dflags + 1);
+  }
+  hipError_t ce = hipStreamEndCapture(st, &graph);
+  if (ce != hipSuccess) return hip_fail(ctx, ce, "hipStreamEndCapture");
+  ce = hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0);
+  if (ce != hipSuccess) {
+    (void)hipGraphDestroy(graph);
+    return hip_fail(ctx, ce, "hipGraphInstantiate");
+  }
+  struct GraphGuard {
+    hipGraph_t g;
+    hipGraphExec_t e;
+    ~GraphGuard() {
+      (void)hipGraphExecDestroy(e);
+      (void)hipGraphDestroy(g);
+    }
+  } gguard{graph, gexec};
+  int hflags[3] = {0, 0, 0};
+  const int max_launches = (maxiter_max + 1) / kIterPerGraph + 2;
+  bool finished = false;
+  for (int l = 0; l < max_launches; ++l) {
+    SAP_HIP_TRY(hipGraphLaunch(gexec, st));
+    SAP_HIP_TRY(hipMemcpyAsync(hflags, dflags, sizeof(hflags), hipMemcpyDeviceToHost, st));
+    SAP_HIP_TRY(hipStreamSynchronize(st));
+    if (hflags[0]) return fail(ctx, SAP_EDEVICE, "sap_solve_batch: a triangular-solve wait expired");
+    if (hflags[1] >= count) {
+      finished = true;
+      break;
+    }
+  }
+  if (hflags[2]) return fail(ctx, SAP_EDEVICE, "sap_solve_batch: sketch generation hit its round cap");
+  if (!finished) return fail(ctx, SAP_EDEVICE, "sap_solve_batch: device never reported completion");
+
+  // per-problem results
+  std::vector<LsqrState> states(count);
+  std::vector<BatchItem> back(count);
+  SAP_HIP_TRY(hipMemcpyAsync(back.data(), ditems, sizeof(BatchItem) * count, hipMemcpyDeviceToHost, st));
+  SAP_HIP_TRY(hipStreamSynchronize(st));
+  for (int k = 0; k < count; ++k)
+    SAP_HIP_TRY(hipMemcpyAsync(&states[k], back[k].st, sizeof(LsqrState), hipMemcpyDeviceToHost, st));
+  SAP_HIP_TRY(hipStreamSynchronize(st));
+  // order the caller's stream after this work
+  hipEvent_t ev_out;
+  SAP_HIP_TRY(hipEventCreateWithFlags(&ev_out, hipEventDisableTiming));
+  SAP_HIP_TRY(hipEventRecord(ev_out, st));
+  SAP_HIP_TRY(hipStreamWaitEvent(user_stream, ev_out, 0));
+  (void)hipEventDestroy(ev_out);
+  bool all_ok = true;
+  for (int k = 0; k < count; ++k) {
+    sap_status sk = back[k].rank_deficient ? SAP_RANK_DEFICIENT : (states[k].converged ? SAP_OK : SAP_NOT_CONVERGED);
+    if (sk != SAP_OK) all_ok = false;
+    if (infos) {
+      std::memset(&infos[k], 0, sizeof(sap_info));
+      infos[k].status = sk;
+      infos[k].iters = states[k].total_iters;
+      infos[k].resid_est = states[k].resid_est;
+      infos[k].normar_est = states[k].normar_est;
+    }
+  }
+  if (!all_ok) (void)fail(ctx, SAP_NOT_CONVERGED, "sap_solve_batch: some problems did not converge or were rank deficient (see info)");
+  return all_ok ? SAP_OK : SAP_NOT_CONVERGED;
+}
+
+// ----------------------------------------------------------------------------
+// Served form: continuous batching.  A scheduler thread owns a device arena
+// and admits queued requests (first in, first out) whenever their workspace
+// footprint fits; a round runs the setup phases of the newly admitted
+// requests as one batch and then a few LSQR iterations of every active
+// request as one batch; finished requests retire at the end of a round and
+// free their memory, so requests that arrive while others run join the next
+// round.  Requests are independent: a result does not depend on what else is
+// in flight (only the floating-point order of the LDS sketch adds varies).
+
+struct ServeRequest {
+  uint64_t ticket = 0;
+  sap_problem prob{};
+  sap_params par{};
+  double *x = nullptr;
+  size_t bytes = 0, offset = 0;
+  BatchItem item{};
+  hipEvent_t ready = nullptr;  // inputs written: recorded on the submitter's stream
+  int state = 0;  // 0 queued, 1 active, 2 finished
+  bool cancel = false;
+  sap_status status = SAP_PENDING;
+  sap_info info{};
+  std::chrono::steady_clock::time_point t_submit, t_admit, t_done;
+};
+
+struct Arena {  // first-fit sub-allocator over one device allocation
+  char *base = nullptr;
+  size_t size = 0, used = 0;
+  std::map<size_t, size_t> free_;  // offset -> length
+  void init(void *b, size_t n) {
+    base = static_cast<char *>(b);
+    size = n;
+    free_.clear();
+    free_[0] = n;
+    used = 0;
+  }
+  bool alloc(size_t n, size_t *off) {
+    n = (n + 4095) & ~size_t(4095);
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second >= n) {
+        *off = it->first;
+        const size_t rest = it->second - n;
+        const size_t o = it->first;
+        free_.erase(it);
+        if (rest) free_[o + n] = rest;
+        used += n;
+        return true;
+      }
+    }
+    return false;
+  }
+  void release(size_t off, size_t n) {
+    n = (n + 4095) & ~size_t(4095);
+    used -= n;
+    auto it = free_.emplace(off, n).first;
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_.erase(nx);
+    }
+    if (it != free_.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+};
+
+struct Server {
+  sap_ctx *ctx = nullptr;
+  std::mutex mu;
+  std::condition_variable cv, cv_done;
+  std::deque<ServeRequest *> queued;
+  std::vector<ServeRequest *> active;
+  std::unordered_map<uint64_t, std::unique_ptr<ServeRequest>> reqs;
+  std::thread th;
+  bool stop = false;
+  bool failed = false;
+  std::string fail_msg;
+  uint64_t next_ticket = 1;
+  sap_dtype at = SAP_F32;
+  bool at_set = false;
+  Arena arena;
+  void *arena_mem = nullptr;
+  hipStream_t st = nullptr;
+  int max_slots = 0;
+  int iters_per_round = 8;
+  BatchItem *d_active = nullptr, *d_new = nullptr;
+  int2 *d_pass = nullptr, *d_apply = nullptr;
+  int *d_flags = nullptr, *d_done = nullptr;
+  void *scratch = nullptr;
+  int64_t n_submitted = 0, n_completed = 0, n_rejected = 0;
+};
+
+namespace {
+
+constexpr int64_t kServeRowsPerChunk = 4096;
+constexpr int kServeMaxChunks = 1 << 20;
+constexpr int kServeMaxApply = 1 << 18;
+
+// A device error ends serving: every request not finished yet fails.
+void serve_fail_all(Server *S, const std::string &msg, std::vector<ServeRequest *> &fresh) {
+  std::lock_guard<std::mutex> lk(S->mu);
+  S->failed = true;
+  S->fail_msg = msg;
+  auto fail_one = [](ServeRequest *r) {
+    if (r->ready) (void)hipEventDestroy(r->ready);
+    r->ready = nullptr;
+    r->state = 2;
+    r->status = SAP_EDEVICE;
+    r->info.status = SAP_EDEVICE;
+  };
+  for (ServeRequest *r : S->active) fail_one(r);
+  for (ServeRequest *r : fresh) fail_one(r);
+  for (ServeRequest *r : S->queued) fail_one(r);
+  S->active.clear();
+  S->queued.clear();
+  fresh.clear();
+  S->cv_done.notify_all();
+}
+
+hipError_t serve_round(Server *S, std::vector<ServeRequest *> &fresh) {
+  hipStream_t st = S->st;
+  const sap_dtype at = S->at;
+  hipError_t e;
+  // setup of the newly admitted requests as one batch
+  if (!fresh.empty()) {
+    std::vector<BatchItem> items(fresh.size());
+    std::vector<int2> apply_work;
+    int64_t col_base = 0;
+    for (size_t k = 0; k < fresh.size(); ++k) {
+      ServeRequest *r = fresh[k];
+      BatchItem &it = r->item;
+      it.col_base = col_base;
+      col_base += it.m;
+      items[k] = it;
+      const int tiles = (it.n + 1 + 15) / 16;
+      for (int t = 0; t < tiles; ++t) apply_work.push_back(make_int2(static_cast<int>(k), t));
+    }
+    if (static_cast<int>(apply_work.size()) > kServeMaxApply) return hipErrorInvalidValue;
+    for (ServeRequest *r : fresh)
+      if ((e = hipStreamWaitEvent(st, r->ready, 0)) != hipSuccess) return e;
+    if ((e = hipMemsetAsync(S->d_flags, 0, 8 * sizeof(int), st)) != hipSuccess) return e;
+    if ((e = hipMemcpyAsync(S->d_new, items.data(), sizeof(BatchItem) * items.size(), hipMemcpyHostToDevice, st)) != hipSuccess) return e;
+    if ((e = hipMemcpyAsync(S->d_apply, apply_work.data(), sizeof(int2) * apply_work.size(), hipMemcpyHostToDevice, st)) != hipSuccess) return e;
+    if (setup_items(S->ctx, S->d_new, items, S->d_apply, static_cast<int>(apply_work.size()), S->d_flags, at, st) != SAP_OK)
+      return hipErrorLaunchFailure;
+    // the rank test wrote its flag into the device copy of each item
+    if ((e = hipMemcpyAsync(items.data(), S->d_new, sizeof(BatchItem) * items.size(), hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
+    int hf[8];
+    if ((e = hipMemcpyAsync(hf, S->d_flags, sizeof(hf), hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
+    if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+    if (hf[0] || hf[2]) return hipErrorLaunchFailure;
+    std::lock_guard<std::mutex> lk(S->mu);
+    for (size_t k = 0; k < fresh.size(); ++k) {
+      (void)hipEventDestroy(fresh[k]->ready);
+      fresh[k]->ready = nullptr;
+      fresh[k]->item = items[k];
+      S->active.push_back(fresh[k]);
+    }
+    fresh.clear();
+  }
+  std::vector<ServeRequest *> act;
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    act = S->active;
+  }
+  if (act.empty()) return hipSuccess;
+  const int count = static_cast<int>(act.size());
+  std::vector<BatchItem> items(count);
+  std::vector<int2> pass_work;
+  int n_max = 0;
+  bool aligned = true;
+  const int vm = (at == SAP_F32) ? 4 : 2;
+  for (int k = 0; k < count; ++k) {
+    items[k] = act[k]->item;
+    n_max = std::max(n_max, items[k].n);
+    if (reinterpret_cast<uintptr_t>(items[k].A) % 16 != 0 || items[k].lda % vm != 0) aligned = false;
+    for (int g = 0; g < items[k].G; ++g) pass_work.push_back(make_int2(k, g));
+  }
+  if (static_cast<int>(pass_work.size()) > kServeMaxChunks) return hipErrorInvalidValue;
+  if ((e = hipMemcpyAsync(S->d_active, items.data(), sizeof(BatchItem) * count, hipMemcpyHostToDevice, st)) != hipSuccess) return e;
+  if ((e = hipMemcpyAsync(S->d_pass, pass_work.data(), sizeof(int2) * pass_work.size(), hipMemcpyHostToDevice, st)) != hipSuccess) return e;
+  const PassChoice pc = (at == SAP_F32) ? pick_batch_pass<float>(n_max, aligned) : pick_batch_pass<double>(n_max, aligned);
+  const int nblk_max = (n_max + kTrsvB - 1) / kTrsvB;
+  for (int k = 0; k < S->iters_per_round; ++k) {
+    launch_pass_fn(pc.fn, S->d_active, S->d_pass, static_cast<int>(pass_work.size()), 0, st);
+    batch_lower_kernel<<<dim3(nblk_max, count), kTrsvThreads, 0, st>>>(S->d_active, S->d_flags);
+    batch_upper_kernel<<<dim3(nblk_max, count), kTrsvThreads, 0, st>>>(S->d_active, S->d_flags, S->d_flags + 1);
+  }
+  serve_done_kernel<<<(count + 255) / 256, 256, 0, st>>>(S->d_active, count, S->d_done);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  std::vector<int> done(count), hflags(8);
+  if ((e = hipMemcpyAsync(done.data(), S->d_done, sizeof(int) * count, hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
+  if ((e = hipMemcpyAsync(hflags.data(), S->d_flags, sizeof(int) * 8, hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
+  if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+  if (hflags[0] || hflags[2]) return hipErrorLaunchFailure;
+  // retire finished (or cancelled) requests
+  std::vector<ServeRequest *> finished;
+  for (int k = 0; k < count; ++k) {
+    ServeRequest *r = act[k];
+    bool cancel;
+    {
+      std::lock_guard<std::mutex> lk(S->mu);
+      cancel = r->cancel;
+    }
+    if (done[k] || cancel) finished.push_back(r);
+  }
+  if (finished.empty()) return hipSuccess;
+  std::vector<LsqrState> states(finished.size());
+  for (size_t k = 0; k < finished.size(); ++k) {
+    if ((e = hipMemcpyAsync(&states[k], finished[k]->item.st, sizeof(LsqrState), hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
+  }
+  if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+  const auto now = std::chrono::steady_clock::now();
+  std::lock_guard<std::mutex> lk(S->mu);
+  for (size_t k = 0; k < finished.size(); ++k) {
+    ServeRequest *r = finished[k];
+    sap_status stt;
+    if (r->cancel) stt = SAP_ECANCELED;
+    else if (r->item.rank_deficient) stt = SAP_RANK_DEFICIENT;
+    else stt = states[k].converged ? SAP_OK : SAP_NOT_CONVERGED;
+    r->status = stt;
+    r->t_done = now;
+    std::memset(&r->info, 0, sizeof(r->info));
+    r->info.status = stt;
+    r->info.iters = states[k].total_iters;
+    r->info.resid_est = states[k].resid_est;
+    r->info.normar_est = states[k].normar_est;
+    r->info.t_queue_ms = std::chrono::duration<double, std::milli>(r->t_admit - r->t_submit).count();
+    r->info.t_total_ms = std::chrono::duration<double, std::milli>(r->t_done - r->t_submit).count();
+    r->state = 2;
+    S->arena.release(r->offset, r->bytes);
+    S->active.erase(std::find(S->active.begin(), S->active.end(), r));
+    S->n_completed += 1;
+  }
+  S->cv_done.notify_all();
+  S->cv.notify_all();
+  return hipSuccess;
+}
+
+void serve_loop(Server *S) {
+  (void)hipSetDevice(S->ctx->device);
+  for (;;) {
+    std::vector<ServeRequest *> fresh;
+    {
+      std::unique_lock<std::mutex> lk(S->mu);
+      S->cv.wait(lk, [&] { return S->stop || !S->queued.empty() || !S->active.empty(); });
+      if (S->stop) return;
+      // drop cancelled requests still in the queue
+      for (auto it = S->queued.begin(); it != S->queued.end();) {
+        if ((*it)->cancel) {
+          (void)hipEventDestroy((*it)->ready);
+          (*it)->ready = nullptr;
+          (*it)->state = 2;
+          (*it)->status = SAP_ECANCELED;
+          (*it)->info.status = SAP_ECANCELED;
+          it = S->queued.erase(it);
+          S->cv_done.notify_all();
+        } else {
+          ++it;
+        }
+      }
+      // admit in arrival order while the head of the queue fits
+      const auto now = std::chrono::steady_clock::now();
+      while (!S->queued.empty() && static_cast<int>(S->active.size() + fresh.size()) < S->max_slots) {
+        ServeRequest *r = S->queued.front();
+        size_t off = 0;
+        if (!S->arena.alloc(r->bytes, &off)) break;
+        r->offset = off;
+        r->state = 1;
+        r->t_admit = now;
+        carve_item(r->item, S->arena.base + off, S->at, kServeRowsPerChunk);
+        S->queued.pop_front();
+        fresh.push_back(r);
+      }
+    }
+    const hipError_t e = serve_round(S, fresh);
+    if (e != hipSuccess) {
+      serve_fail_all(S, std::string("served round failed: ") + hipGetErrorString(e), fresh);
+      return;
+    }
+  }
+}
+
+}  // namespace
+
+void serve_destroy(sap_ctx *ctx) {
+  Server *S = ctx->server;
+  if (!S) return;
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->stop = true;
+  }
+  S->cv.notify_all();
+  if (S->th.joinable()) S->th.join();
+  (void)hipSetDevice(ctx->device);
+  for (auto &kv : S->reqs)
+    if (kv.second->ready) (void)hipEventDestroy(kv.second->ready);
+  if (S->st) (void)hipStreamSynchronize(S->st);
+  if (S->st) (void)hipStreamDestroy(S->st);
+  if (S->arena_mem) (void)hipFree(S->arena_mem);
+  if (S->scratch) (void)hipFree(S->scratch);
+  delete S;
+  ctx->server = nullptr;
+}
+
+sap_status serve_start(sap_ctx *ctx, size_t arena_bytes, int max_slots) {
+  if (ctx->server) return fail(ctx, SAP_EINVAL, "sap_serve_start: already serving");
+  if (max_slots < 1 || max_slots > 4096) return fail(ctx, SAP_EINVAL, "sap_serve_start: max_slots must be in [1, 4096]");
+  if (arena_bytes == 0) arena_bytes = std::min<size_t>(ctx->budget / 2, size_t(64) << 30);
+  if (arena_bytes > ctx->budget) return fail(ctx, SAP_ENOMEM, "sap_serve_start: arena exceeds the HBM budget");
+  std::unique_ptr<Server> S(new Server());
+  S->ctx = ctx;
+  S->max_slots = max_slots;
+  SAP_HIP_TRY(hipSetDevice(ctx->device));
+  if (hipMalloc(&S->arena_mem, arena_bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(ctx, SAP_ENOMEM, "sap_serve_start: could not allocate the arena");
+  }
+  S->arena.init(S->arena_mem, arena_bytes);
+  const size_t scratch = 8 * 256 + 2 * sizeof(BatchItem) * max_slots + sizeof(int2) * (kServeMaxChunks + kServeMaxApply) +
+                         sizeof(int) * (8 + max_slots);
+  if (hipMalloc(&S->scratch, scratch) != hipSuccess) {
+    (void)hipGetLastError();
+    (void)hipFree(S->arena_mem);
+    return fail(ctx, SAP_ENOMEM, "sap_serve_start: could not allocate the scheduler scratch");
+  }
+  Carve cv(S->scratch);
+  S->d_flags = cv.take<int>(8);
+  S->d_done = cv.take<int>(max_slots);
+  S->d_active = cv.take<BatchItem>(max_slots);
+  S->d_new = cv.take<BatchItem>(max_slots);
+  S->d_pass = cv.take<int2>(kServeMaxChunks);
+  S->d_apply = cv.take<int2>(kServeMaxApply);
+  SAP_HIP_TRY(hipStreamCreateWithFlags(&S->st, hipStreamNonBlocking));
+  ctx->server = S.release();
+  ctx->server->th = std::thread(serve_loop, ctx->server);
+  return SAP_OK;
+}
+
+sap_status serve_submit(sap_ctx *ctx, const sap_problem *p, const sap_params *q, double *x, uint64_t *ticket,
+                        hipStream_t stream) {
+  if (!p || !q || !x || !ticket) return fail(ctx, SAP_EINVAL, "sap_submit: NULL argument");
+  {
+    static std::mutex start_mu;
+    std::lock_guard<std::mutex> lk(start_mu);
+    if (!ctx->server) {
+      sap_status s = serve_start(ctx, 0, 1024);
+      if (s != SAP_OK) return s;
+    }
+  }
+  Server *S = ctx->server;
+  if (p->a_type != SAP_F32 && p->a_type != SAP_F64) return fail(ctx, SAP_EINVAL, "sap_submit: A must be F32 or F64");
+  if (!p->A || !p->b) return fail(ctx, SAP_EINVAL, "sap_submit: NULL device pointer");
+  if (p->n < 1 || p->n > 1024 || p->m < static_cast<int64_t>(p->n) + 1 || p->lda < p->n || p->m > (int64_t(1) << 31))
+    return fail(ctx, SAP_EINVAL, "sap_submit: bad problem shape (n <= 1024, m >= n + 1)");
+  const size_t es = (p->a_type == SAP_F32) ? 4 : 8;
+  if (q->d < p->n + 1 || q->d > 4096 || static_cast<size_t>(q->d) * 16 * es > 160000 || q->zeta < 1 || q->zeta > 64 ||
+      q->zeta > q->d || q->maxiter < 0 || !(q->tol >= 0.0))
+    return fail(ctx, SAP_EINVAL, "sap_submit: bad parameters");
+  const size_t bytes = item_bytes(p->m, p->n, q->d, q->zeta, p->a_type);
+  hipEvent_t ready = nullptr;
+  SAP_HIP_TRY(hipSetDevice(ctx->device));
+  SAP_HIP_TRY(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
+  if (hipEventRecord(ready, stream) != hipSuccess) {
+    (void)hipEventDestroy(ready);
+    return fail(ctx, SAP_EDEVICE, "sap_submit: could not record the input event");
+  }
+  struct EvOwner {
+    hipEvent_t e;
+    ~EvOwner() {
+      if (e) (void)hipEventDestroy(e);
+    }
+  } owner{ready};
+  std::lock_guard<std::mutex> lk(S->mu);
+  if (S->failed) return fail(ctx, SAP_EDEVICE, S->fail_msg);
+  if (S->at_set && p->a_type != S->at) return fail(ctx, SAP_EINVAL, "sap_submit: all served problems share one A dtype");
+  if (bytes > S->arena.size) {
+    S->n_rejected += 1;
+    return fail(ctx, SAP_ENOMEM, "sap_submit: the request can never fit in the serving arena");
+  }
+  S->at = p->a_type;
+  S->at_set = true;
+  std::unique_ptr<ServeRequest> r(new ServeRequest());
+  r->ticket = S->next_ticket++;
+  r->prob = *p;
+  r->par = *q;
+  r->x = x;
+  r->bytes = bytes;
+  r->ready = ready;
+  owner.e = nullptr;
+  r->t_submit = std::chrono::steady_clock::now();
+  BatchItem &it = r->item;
+  it.A = p->A;
+  it.lda = p->lda;
+  it.b = p->b;
+  it.x = x;
+  it.m = p->m;
+  it.n = p->n;
+  it.d = q->d;
+  it.zeta = q->zeta;
+  it.maxiter = q->maxiter;
+  it.tol = q->tol;
+  it.h = 1.0 / std::sqrt(static_cast<double>(q->zeta));
+  it.seed = q->seed;
+  it.stream = 0;  // the sketch sap_solve draws for the same seed
+  *ticket = r->ticket;
+  S->queued.push_back(r.get());
+  S->reqs[r->ticket] = std::move(r);
+  S->n_submitted += 1;
+  S->cv.notify_all();
+  return SAP_OK;
+}
+
+sap_status serve_poll(sap_ctx *ctx, uint64_t ticket, sap_info *info, int wait) {
+  Server *S = ctx->server;
+  if (!S) return fail(ctx, SAP_EINVAL, "sap_poll: nothing was submitted");
+  std::unique_lock<std::mutex> lk(S->mu);
+  auto it = S->reqs.find(ticket);
+  if (it == S->reqs.end()) return fail(ctx, SAP_EINVAL, "sap_poll: unknown ticket");
+  ServeRequest *r = it->second.get();
+  if (wait) S->cv_done.wait(lk, [&] { return r->state == 2; });
+  if (r->state != 2) {
+    if (info) {
+      std::memset(info, 0, sizeof(*info));
+      info->status = SAP_PENDING;
+    }
+    return SAP_PENDING;
+  }
+  const sap_status s = r->status;
+  if (info) *info = r->info;
+  S->reqs.erase(it);
+  return s;
+}
+
+sap_status serve_cancel(sap_ctx *ctx, uint64_t ticket) {
+  Server *S = ctx->server;
+  if (!S) return fail(ctx, SAP_EINVAL, "sap_cancel: nothing was submitted");
+  std::lock_guard<std::mutex> lk(S->mu);
+  auto it = S->reqs.find(ticket);
+  if (it == S->reqs.end()) return fail(ctx, SAP_EINVAL, "sap_cancel: unknown ticket");
+  it->second->cancel = true;
+  S->cv.notify_all();
+  return SAP_OK;
+}
+
+sap_status serve_stats(sap_ctx *ctx, int64_t *out) {
+  Server *S = ctx->server;
+  if (!S) {
+    for (int k = 0; k < 7; ++k) out[k] = 0;
+    return SAP_OK;
+  }
+  std::lock_guard<std::mutex> lk(S->mu);
+  out[0] = S->n_submitted;
+  out[1] = S->n_completed;
+  out[2] = static_cast<int64_t>(S->active.size());
+  out[3] = static_cast<int64_t>(S->queued.size());
+  out[4] = S->n_rejected;
+  out[5] = static_cast<int64_t>(S->arena.used);
+  out[6] = static_cast<int64_t>(S->arena.size);
+  return SAP_OK;
+}
+
+}  // namespace sap

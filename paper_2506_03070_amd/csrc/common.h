@@ -101,23 +101,30 @@ __device__ __forceinline__ double block_sum(double v, double *scratch, int nwave
 // that an iteration needs no host round trip.
 struct LsqrState {
   double alpha, beta, rhobar, phibar;
-  double c_ap, c_u;      // next pass computes u <- c_ap * (A p) + c_u * u
-  double beta_sq;        // reduced ||u_hat||^2 of the last pass
+  double c_ap, c_u;           // next pass computes u <- c_ap * (A p) + c_u * u
+  double alpha_new, beta_new; // alpha_{t+1}, beta_{t+1} from the lower solve
   double normb, tol;
   double resid_est, normar_est;
   int32_t iter, maxiter;
   int32_t done, converged;
   int32_t init;          // 1: the next step is the initialisation step
-  int32_t total_iters;   // iterations summed over refinements
+  int32_t total_iters;   // iterations done
+  int32_t proceed;       // alpha_{t+1} > 0 and beta_{t+1} > 0
+  int32_t steps;         // completed lower/upper solve pairs (flag epoch)
 };
 
 }  // namespace sap
 
+namespace sap {
+struct Server;
+}
+
 struct sap_ctx {
+  sap::Server *server = nullptr;  // served form (continuous batching), created on demand
   int device = 0;
   int num_cus = 256;
   size_t budget = 0;
-  std::string err;
+
   void *ws = nullptr;
   size_t ws_size = 0;
   // kernel timing (sap_profile_enable): pending event pairs per kernel,
@@ -164,7 +171,7 @@ void prof_resolve(sap_ctx *ctx);
 sap_status launch_generate(sap_ctx *ctx, const sps_sketch *S, int *err_word, hipStream_t st);
 
 // Sketch apply (apply.hip).  Workspace bytes for partial sums first.
-size_t apply_workspace_bytes(sap_ctx *ctx, int64_t m, int d, int ncols, sap_dtype y_type);
+size_t apply_workspace_bytes(sap_ctx *ctx, int64_t m, int zeta, int d, int ncols, sap_dtype y_type);
 sap_status launch_apply(sap_ctx *ctx, const sps_sketch *S, const void *A, int64_t lda,
                         sap_dtype a_type, const double *b, int n, void *Y, int64_t ldy,
                         sap_dtype y_type, void *work, hipStream_t st);
@@ -177,15 +184,30 @@ sap_status launch_qr(sap_ctx *ctx, double *Y, int64_t ldy, int rows, int cols, d
 sap_status launch_rank_check(sap_ctx *ctx, const double *R, int64_t ldr, int n, int d, int *flag,
                              hipStream_t st);
 
-// Triangular solves (lsqr.hip).
+// Triangular solves (lsqr.hip, trsv.hip).  Blocking (reads an error word).
+size_t trsv_workspace_bytes(int n);
 sap_status launch_trsv(sap_ctx *ctx, const double *R, int64_t ldr, int n, int trans,
-                       const double *rhs, double *x, hipStream_t st);
+                       const double *rhs, double *x, void *work, hipStream_t st);
 
-// LSQR driver (lsqr.hip).
-struct LsqrPlan;
-size_t lsqr_workspace_bytes(sap_ctx *ctx, int64_t m, int n, int mode);
+// LSQR driver (lsqr.hip).  When z is non-null, x0 is ignored and the initial
+// guess is R^-1 z (the sketch-and-solve solution of Alg. 1).
+// mode 0: A in FP64; mode 1: A stored in FP32 (FP64 arithmetic).
+size_t lsqr_workspace_bytes(sap_ctx *ctx, int64_t m, int n);
 sap_status run_lsqr(sap_ctx *ctx, const sap_problem *prob, const double *R, int64_t ldr,
-                    const double *x0, double tol, int maxiter, int mode, int max_refine,
-                    double inner_tol, double *x, sap_info *info, void *work, hipStream_t st);
+                    const double *x0, const double *z, double tol, int maxiter, int mode, double *x,
+                    sap_info *info, void *work, hipStream_t st);
+
+// Served form (batch.hip).
+sap_status serve_start(sap_ctx *ctx, size_t arena_bytes, int max_slots);
+sap_status serve_submit(sap_ctx *ctx, const sap_problem *p, const sap_params *q, double *x, uint64_t *ticket,
+                        hipStream_t stream);
+sap_status serve_poll(sap_ctx *ctx, uint64_t ticket, sap_info *info, int wait);
+sap_status serve_cancel(sap_ctx *ctx, uint64_t ticket);
+sap_status serve_stats(sap_ctx *ctx, int64_t *out);
+void serve_destroy(sap_ctx *ctx);
+
+// Batched form (batch.hip).
+sap_status run_batch(sap_ctx *ctx, int count, const sap_problem *probs, const sap_params *par, double *const *x,
+                     sap_info *infos, hipStream_t user_stream);
 
 }  // namespace sap

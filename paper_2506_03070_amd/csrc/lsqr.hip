@@ -1,116 +1,44 @@
 // Preconditioned LSQR (Alg. 2) on A M, M = R^-1, for gfx950.
 //
 // One iteration is three kernels on one stream, with no host round trip:
-//   1. pass   : one sweep over A computing, for every row i,
-//                 u_i <- c_ap (A p)_i + c_u u_i        (p = M v_t)
-//               and accumulating q = A^T u and ||u||^2 from the same
-//               registers.  This is the one-synchronisation reorganisation of
-//               App. D.4.1: A^T is applied to the unnormalised u_hat, and the
-//               scale 1/beta is folded into the next step, so A is read once
-//               per iteration instead of twice.
-//   2. reduce : fixed-order sum of the per-workgroup partials of q and ||u||^2.
-//   3. step   : a single 1024-thread workgroup doing the O(n^2) and O(n) work:
-//               v_hat = R^-T q / beta - beta v, alpha = ||v_hat||, v = v_hat/alpha,
-//               p = R^-1 v (two blocked triangular solves), the Givens
-//               recurrences, x += (phi/rho) w, w = p - (theta/rho) w, and the
-//               convergence test.  All scalars stay in device memory.
-// Kernels early-exit once the device `done` flag is set, so the host enqueues
-// iterations in batches and reads the flag once per batch.
+//   1. pass  : one sweep over A computing, for every row i,
+//                u_i <- c_ap (A p)_i + c_u u_i        (p = M v_t)
+//              and accumulating q = A^T u and ||u||^2 from the same
+//              registers.  This is the one-synchronisation reorganisation of
+//              App. D.4.1: A^T is applied to the unnormalised u_hat and the
+//              scale 1/beta is folded into the next step, so A is read once
+//              per iteration instead of twice.  One 16-wave workgroup per CU
+//              writes one partial q.
+//   2. lower : the chain solve y = R^-T q (trsv.h), whose workgroups first
+//              reduce the partials of their block of q (fixed order); the
+//              last block's workgroup then forms v_hat = y/beta - beta v,
+//              alpha = ||v_hat||, v = v_hat/alpha.
+//   3. upper : the chain solve p = R^-1 v; the last block's workgroup does the
+//              plane rotation, x += (phi/rho) w, w = p - (theta/rho) w, the
+//              convergence test and the coefficients of the next pass.
+// All scalars stay in device memory.  Kernels early-exit once the device
+// `done` flag is set, so the host enqueues iterations in batches and reads
+// the flag once per batch.
+#include <algorithm>
 #include <cmath>
 #include <mutex>
 #include <unordered_map>
 
 #include "common.h"
+#include "trsv.h"
+#include "lsqr_dev.h"
 
 namespace sap {
 namespace {
 
-constexpr int kStepThreads = 1024;
-constexpr int kStepWaves = kStepThreads / kWave;
-constexpr int kTB = 64;  // triangular-solve block
+constexpr int kPassThreads = 1024;
+constexpr int kPassWaves = kPassThreads / kWave;
 constexpr int kMaxN = 8192;
 
 // --------------------------------------------------------------------------
-// Blocked triangular solve by one 1024-thread workgroup; xs (LDS, n doubles)
-// holds the right-hand side on entry and the solution on exit.
-//   trans = false: R x = rhs (back substitution, blocks from the bottom);
-//   trans = true : R^T x = rhs (forward substitution, blocks from the top).
-// The diagonal 64 x 64 block is solved by wave 0 with register broadcasts;
-// the off-diagonal parts are coalesced column reads shared by all waves.
-__device__ void wg_trsv(const double *__restrict__ R, int64_t ldr, int n, bool trans, double *xs,
-                        double *Dblk) {
-  const int t = threadIdx.x, lane = t & (kWave - 1), wave = t / kWave;
-  const int nblk = (n + kTB - 1) / kTB;
-  for (int bi = 0; bi < nblk; ++bi) {
-    const int kb = trans ? bi : nblk - 1 - bi;
-    const int k0 = kb * kTB, kn = min(kTB, n - k0);
-    if (trans && k0 > 0) {
-      // xs[k0+j] -= R[0:k0, k0+j] . xs[0:k0]  (column k0+j of R is contiguous)
-      for (int j = wave; j < kn; j += kStepWaves) {
-        const double *col = R + static_cast<int64_t>(k0 + j) * ldr;
-        double acc = 0.0;
-        for (int l = lane; l < k0; l += kWave) acc += col[l] * xs[l];
-        acc = wave_sum(acc);
-        if (lane == 0) xs[k0 + j] -= acc;
-      }
-    }
-    for (int e = t; e < kn * kTB; e += kStepThreads) {
-      const int c = e / kTB, r = e % kTB;
-      if (r < kn) Dblk[r * (kTB + 1) + c] = R[(k0 + r) + static_cast<int64_t>(k0 + c) * ldr];
-    }
-    __syncthreads();
-    if (wave == 0) {
-      double val = lane < kn ? xs[k0 + lane] : 0.0;
-      if (!trans) {
-        for (int j = kn - 1; j >= 0; --j) {
-          const double rj = Dblk[lane * (kTB + 1) + j];
-          const double xj = wave_bcast(val, j) / Dblk[j * (kTB + 1) + j];
-          if (lane == j) val = xj;
-          else if (lane < j) val -= rj * xj;
-        }
-      } else {
-        for (int j = 0; j < kn; ++j) {
-          const double rj = Dblk[j * (kTB + 1) + lane];
-          const double xj = wave_bcast(val, j) / Dblk[j * (kTB + 1) + j];
-          if (lane == j) val = xj;
-          else if (lane > j && lane < kn) val -= rj * xj;
-        }
-      }
-      if (lane < kn) xs[k0 + lane] = val;
-    }
-    __syncthreads();
-    if (!trans && k0 > 0) {
-      // xs[0:k0] -= R[0:k0, k0:k0+kn] xs[k0:k0+kn]
-      for (int i = t; i < k0; i += kStepThreads) {
-        double acc = 0.0;
-        for (int c = 0; c < kn; ++c) acc += R[i + static_cast<int64_t>(k0 + c) * ldr] * xs[k0 + c];
-        xs[i] -= acc;
-      }
-      __syncthreads();
-    }
-  }
-}
-
-__global__ __launch_bounds__(kStepThreads) void trsv_kernel(const double *__restrict__ R, int64_t ldr,
-                                                             int n, int trans,
-                                                             const double *__restrict__ rhs,
-                                                             double *__restrict__ x) {
-  extern __shared__ double lds[];
-  double *xs = lds;
-  double *Dblk = lds + n;
-  for (int c = threadIdx.x; c < n; c += kStepThreads) xs[c] = rhs[c];
-  __syncthreads();
-  wg_trsv(R, ldr, n, trans != 0, xs, Dblk);
-  for (int c = threadIdx.x; c < n; c += kStepThreads) x[c] = xs[c];
-}
-
-size_t trsv_lds_bytes(int n) { return sizeof(double) * (static_cast<size_t>(n) + kTB * (kTB + 1)); }
-
-// --------------------------------------------------------------------------
-// Fused pass.  MODE 0: A, accumulation and u in FP64.  MODE 1: A, p,
-// accumulation and u in FP32 (inner iterations of the mixed form).  MODE 2:
-// FP32 A with FP64 accumulation, u_in FP64 (b), u_out FP32 (the residual
-// refinement pass of the mixed form).
+// Fused pass.  MODE 0: A in FP64.  MODE 1: A stored in FP32 (the mixed
+// form).  In both, p, the accumulation and u are FP64: an FP32 element is
+// widened exactly, so the pass reads half the bytes for the same arithmetic.
 template <int MODE>
 struct PassTypes;
 template <>
@@ -119,11 +47,7 @@ struct PassTypes<0> {
 };
 template <>
 struct PassTypes<1> {
-  using TA = float; using TC = float; using TUI = float; using TUO = float;
-};
-template <>
-struct PassTypes<2> {
-  using TA = float; using TC = double; using TUI = double; using TUO = float;
+  using TA = float; using TC = double; using TUI = double; using TUO = double;
 };
 
 template <typename T, int V>
@@ -131,20 +55,22 @@ struct alignas(sizeof(T) * V) VecT {
   T e[V];
 };
 
-template <int MODE, int VEC, int J, int WC, int WR>
-__global__ __launch_bounds__(kWave * WC * WR) void lsqr_pass_kernel(
+// WC waves split the columns of a row (64*VEC*J columns each); WR = 16/WC
+// row groups share the workgroup.
+template <int MODE, int VEC, int J, int WC>
+__global__ __launch_bounds__(kPassThreads) void lsqr_pass_kernel(
     const typename PassTypes<MODE>::TA *__restrict__ A, int64_t lda, int64_t m, int n,
-    const typename PassTypes<MODE>::TC *__restrict__ p,
-    const typename PassTypes<MODE>::TUI *u_in, typename PassTypes<MODE>::TUO *u_out,
-    const LsqrState *__restrict__ st, double *__restrict__ qpart, double *__restrict__ nrmpart,
-    int64_t rows_per_wg) {
+    const typename PassTypes<MODE>::TC *__restrict__ p, const typename PassTypes<MODE>::TUI *u_in,
+    typename PassTypes<MODE>::TUO *u_out, const LsqrState *__restrict__ st, double *__restrict__ qpart,
+    double *__restrict__ nrmpart, int64_t rows_per_wg) {
   using TA = typename PassTypes<MODE>::TA;
   using TC = typename PassTypes<MODE>::TC;
+  constexpr int WR = kPassWaves / WC;
   constexpr int R = (J * VEC >= 16) ? 1 : (16 / (J * VEC) > 4 ? 4 : 16 / (J * VEC));
   constexpr int COLS = kWave * VEC * J;  // columns per wave
-  __shared__ double xch[WC > 1 ? 2 : 1][R][WC];
-  __shared__ double qbuf[WR > 1 ? COLS : 1];
-  __shared__ double nbuf[WC * WR];
+  __shared__ double xch[WC > 1 ? 2 : 1][WC > 1 ? WR : 1][R][WC];
+  __shared__ double qbuf[WR > 1 ? WC * COLS : 1];
+  __shared__ double nbuf[kPassWaves];
   if (st->done) return;
 
   const int lane = threadIdx.x & (kWave - 1);
@@ -166,9 +92,10 @@ __global__ __launch_bounds__(kWave * WC * WR) void lsqr_pass_kernel(
 
   const int64_t i_begin = static_cast<int64_t>(blockIdx.x) * rows_per_wg;
   const int64_t i_end = min(m, i_begin + rows_per_wg);
+  const int64_t nsteps = i_end > i_begin ? (i_end - i_begin + WR * R - 1) / (WR * R) : 0;
   double nrm = 0.0;
-  int parity = 0;
-  for (int64_t base = i_begin + static_cast<int64_t>(wr) * R; base < i_end; base += static_cast<int64_t>(WR) * R) {
+  for (int64_t step = 0; step < nsteps; ++step) {
+    const int64_t base = i_begin + step * (WR * R) + wr * R;
     TA a[R][J][VEC];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -196,22 +123,22 @@ __global__ __launch_bounds__(kWave * WC * WR) void lsqr_pass_kernel(
       for (int j = 0; j < J; ++j)
 #pragma unroll
         for (int e = 0; e < VEC; ++e) s += static_cast<TC>(a[r][j][e]) * preg[j][e];
-      dot[r] = wave_sum(s);
+      dot[r] = wave_sum_u(s);
     }
     if constexpr (WC > 1) {
+      const int parity = static_cast<int>(step & 1);
       if (lane == 0) {
 #pragma unroll
-        for (int r = 0; r < R; ++r) xch[parity][r][wc] = static_cast<double>(dot[r]);
+        for (int r = 0; r < R; ++r) xch[parity][wr][r][wc] = static_cast<double>(dot[r]);
       }
       __syncthreads();
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         double s = 0.0;
 #pragma unroll
-        for (int w = 0; w < WC; ++w) s += xch[parity][r][w];
+        for (int w = 0; w < WC; ++w) s += xch[parity][wr][r][w];
         dot[r] = static_cast<TC>(s);
       }
-      parity ^= 1;
     }
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -230,8 +157,8 @@ __global__ __launch_bounds__(kWave * WC * WR) void lsqr_pass_kernel(
     }
   }
 
-  // Per-workgroup partials: q over this wave's columns (row groups combined in
-  // a fixed order through LDS), ||u||^2 over all rows.
+  // Per-workgroup partials: q (row groups combined in a fixed order through
+  // LDS) and ||u||^2.
   double *qdst = qpart + static_cast<int64_t>(blockIdx.x) * n;
   if constexpr (WR > 1) {
     for (int g = 0; g < WR; ++g) {
@@ -241,16 +168,13 @@ __global__ __launch_bounds__(kWave * WC * WR) void lsqr_pass_kernel(
         for (int j = 0; j < J; ++j)
 #pragma unroll
           for (int e = 0; e < VEC; ++e) {
-            const int cl = (j * kWave + lane) * VEC + e;
+            const int cl = wc * COLS + (j * kWave + lane) * VEC + e;
             qbuf[cl] = (g == 0 ? 0.0 : qbuf[cl]) + static_cast<double>(q[j][e]);
           }
       }
     }
     __syncthreads();
-    for (int cl = threadIdx.x; cl < COLS; cl += kWave * WC * WR) {
-      const int c = col0 + cl;  // WC == 1 whenever WR > 1
-      if (c < n) qdst[c] = qbuf[cl];
-    }
+    for (int c = threadIdx.x; c < n && c < WC * COLS; c += kPassThreads) qdst[c] = qbuf[c];
   } else {
 #pragma unroll
     for (int j = 0; j < J; ++j)
@@ -264,150 +188,54 @@ __global__ __launch_bounds__(kWave * WC * WR) void lsqr_pass_kernel(
   __syncthreads();
   if (threadIdx.x == 0) {
     double s = 0.0;
-    for (int w = 0; w < WC * WR; ++w) s += nbuf[w];
+    for (int w = 0; w < kPassWaves; ++w) s += nbuf[w];
     nrmpart[blockIdx.x] = s;
   }
 }
 
-// q[c] = sum_g qpart[g][c]; beta_sq = sum_g nrmpart[g]  (fixed order).
-__global__ __launch_bounds__(256) void lsqr_reduce_kernel(const double *__restrict__ qpart,
-                                                          const double *__restrict__ nrmpart, int G,
-                                                          int n, double *__restrict__ q,
-                                                          LsqrState *__restrict__ st) {
-  __shared__ double sm[4][64];
-  if (st->done) return;
-  const int cl = threadIdx.x & 63, g0 = threadIdx.x >> 6;
-  const int c = blockIdx.x * 64 + cl;
-  double s = 0.0;
-  if (c < n)
-    for (int g = g0; g < G; g += 4) s += qpart[static_cast<int64_t>(g) * n + c];
-  sm[g0][cl] = s;
-  __syncthreads();
-  if (threadIdx.x < 64 && c < n) q[c] = ((sm[0][cl] + sm[1][cl]) + sm[2][cl]) + sm[3][cl];
-  if (blockIdx.x == 0) {
-    __syncthreads();
-    double t = 0.0;
-    for (int g = threadIdx.x; g < G; g += 256) t += nrmpart[g];
-    // fixed-order: wave sums then wave 0 combines
-    t = wave_sum(t);
-    __shared__ double ws[4];
-    if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = t;
-    __syncthreads();
-    if (threadIdx.x == 0) st->beta_sq = ((ws[0] + ws[1]) + ws[2]) + ws[3];
-  }
-}
-
 // --------------------------------------------------------------------------
-// The O(n^2) part of an iteration (see the file comment).  p32 (nullable)
-// receives an FP32 copy of p for the FP32 passes of the mixed form.
-__global__ __launch_bounds__(kStepThreads) void lsqr_step_kernel(
-    const double *__restrict__ R, int64_t ldr, int n, const double *__restrict__ q,
-    double *__restrict__ v, double *__restrict__ w, double *__restrict__ x, double *__restrict__ p,
-    float *__restrict__ p32, LsqrState *__restrict__ st, double outer_tol) {
-  extern __shared__ double lds[];
-  __shared__ double red[kStepWaves];
-  double *xs = lds;
-  double *Dblk = lds + n;
+// Kernel 2: y = R^-T q, then v_hat = y/beta - beta v, alpha, v.
+__global__ __launch_bounds__(kTrsvThreads) void lsqr_lower_kernel(
+    const double *__restrict__ Rt, int n, const double *__restrict__ Dlo, const double *__restrict__ qpart, int G,
+    const double *__restrict__ nrmpart, double *y, double *__restrict__ v, LsqrState *st, int *flags, int *err) {
+  __shared__ LowerShared sh;
   if (st->done) return;
-  const int t = threadIdx.x;
-  const bool init = st->init != 0;
-  const double beta = sqrt(st->beta_sq);
-  const double rhobar_old = st->rhobar, phibar_old = st->phibar;
-
-  double alpha = 0.0;
-  if (beta > 0.0) {
-    for (int c = t; c < n; c += kStepThreads) xs[c] = q[c];
-    __syncthreads();
-    wg_trsv(R, ldr, n, true, xs, Dblk);  // xs = R^-T A^T u_hat
-    double part = 0.0;
-    for (int c = t; c < n; c += kStepThreads) {
-      const double vh = xs[c] / beta - (init ? 0.0 : beta * v[c]);
-      xs[c] = vh;
-      part += vh * vh;
-    }
-    alpha = sqrt(block_sum(part, red, kStepWaves));
-  }
-  const bool proceed = beta > 0.0 && alpha > 0.0;
-  if (proceed) {
-    for (int c = t; c < n; c += kStepThreads) {
-      const double vn = xs[c] / alpha;
-      xs[c] = vn;
-      v[c] = vn;
-    }
-    __syncthreads();
-    wg_trsv(R, ldr, n, false, xs, Dblk);  // xs = p_{t+1} = R^-1 v_{t+1}
-  }
-
-  if (init) {
-    // beta_1 u_1 = b - A x0, alpha_1 v_1 = M^T A^T u_1, w_1 = M v_1.
-    if (proceed) {
-      for (int c = t; c < n; c += kStepThreads) {
-        const double pc = xs[c];
-        p[c] = pc;
-        w[c] = pc;
-        if (p32) p32[c] = static_cast<float>(pc);
-      }
-    }
-    if (t == 0) {
-      st->init = 0;
-      st->phibar = beta;
-      st->rhobar = alpha;
-      st->alpha = alpha;
-      st->beta = beta;
-      st->resid_est = beta;
-      st->normar_est = alpha * beta;
-      st->c_ap = 1.0;
-      st->c_u = beta > 0.0 ? -alpha / beta : 0.0;
-      bool stop = !proceed || st->maxiter <= st->total_iters;
-      bool conv = !proceed;
-      if (outer_tol > 0.0 && (alpha <= outer_tol || beta <= outer_tol * st->normb)) stop = conv = true;
-      st->converged = conv ? 1 : 0;
-      st->done = stop ? 1 : 0;
-    }
-    return;
-  }
-
-  // Plane rotation (Alg. 2, line 7) with beta_{t+1}, alpha_{t+1}.
-  const double rho = sqrt(rhobar_old * rhobar_old + beta * beta);
-  const double cs = rhobar_old / rho, sn = beta / rho;
-  const double theta = sn * alpha;
-  const double rhobar = -cs * alpha;
-  const double phi = cs * phibar_old;
-  const double phibar = sn * phibar_old;
-  const double fx = phi / rho, fw = theta / rho;
-  for (int c = t; c < n; c += kStepThreads) {
-    const double wc = w[c];
-    x[c] += fx * wc;
-    if (proceed) {
-      const double pc = xs[c];
-      p[c] = pc;
-      if (p32) p32[c] = static_cast<float>(pc);
-      w[c] = pc - fw * wc;
-    }
-  }
-  if (t == 0) {
-    st->iter += 1;
-    st->total_iters += 1;
-    st->rhobar = rhobar;
-    st->phibar = phibar;
-    st->alpha = alpha;
-    st->beta = beta;
-    st->c_ap = 1.0;
-    st->c_u = beta > 0.0 ? -alpha / beta : 0.0;
-    st->resid_est = phibar;
-    st->normar_est = phibar * alpha * fabs(cs);
-    const bool conv = !proceed || alpha * fabs(cs) <= st->tol || phibar <= st->tol * st->normb;
-    st->converged = conv ? 1 : 0;
-    st->done = (conv || st->total_iters >= st->maxiter) ? 1 : 0;
-  }
+  const int nblk = (n + kTrsvB - 1) / kTrsvB;
+  const int b = blockIdx.x;
+  const int epoch = st->steps + 1;
+  reduce_q_block(qpart, G, n, b, sh);
+  chain_block<false>(Rt, n, n, Dlo, y, flags, epoch, b, sh.rb, sh.red, err);
+  if (b != nblk - 1) return;
+  lower_epilogue(n, G, nrmpart, y, v, st, sh);
 }
 
-__global__ void lsqr_init_state_kernel(LsqrState *st, double tol, int maxiter, int total_iters) {
+// Kernel 3: p = R^-1 v, then the plane rotation and the x, w updates.
+__global__ __launch_bounds__(kTrsvThreads) void lsqr_upper_kernel(
+    const double *__restrict__ R, int64_t ldr, int n, const double *__restrict__ Dup, const double *__restrict__ v,
+    double *p, double *__restrict__ w, double *__restrict__ x, LsqrState *st, int *flags, int *err) {
+  __shared__ LowerShared sh;
+  if (st->done) return;
+  const int nblk = (n + kTrsvB - 1) / kTrsvB;
+  const int b = nblk - 1 - static_cast<int>(blockIdx.x);
+  const int epoch = st->steps + 1;
+  if (threadIdx.x < kTrsvB) {
+    const int row = b * kTrsvB + threadIdx.x;
+    sh.rb[threadIdx.x] = row < n ? v[row] : 0.0;
+  }
+  __syncthreads();
+  chain_block<true>(R, ldr, n, Dup, p, flags, epoch, b, sh.rb, sh.red, err);
+  if (b != 0) return;
+  upper_epilogue(n, p, w, x, st, nullptr);
+}
+
+// Fresh state for an LSQR run; clears the chain flags of the two solves.
+__global__ void lsqr_init_state_kernel(LsqrState *st, double tol, int maxiter, int *flags, int nflags) {
+  for (int i = threadIdx.x; i < nflags; i += blockDim.x) flags[i] = 0;
   if (threadIdx.x != 0) return;
   st->alpha = st->beta = st->rhobar = st->phibar = 0.0;
+  st->alpha_new = st->beta_new = 0.0;
   st->c_ap = -1.0;
   st->c_u = 1.0;
-  st->beta_sq = 0.0;
   st->tol = tol;
   st->resid_est = st->normar_est = 0.0;
   st->iter = 0;
@@ -415,17 +243,36 @@ __global__ void lsqr_init_state_kernel(LsqrState *st, double tol, int maxiter, i
   st->done = 0;
   st->converged = 0;
   st->init = 1;
-  st->total_iters = total_iters;
+  st->proceed = 0;
+  st->total_iters = 0;
+  st->steps = 0;
 }
 
-// ||b||^2 into st->normb (fixed-order two-level sum).
-__global__ __launch_bounds__(1024) void norm_kernel(const double *__restrict__ b, int64_t m,
-                                                    LsqrState *__restrict__ st) {
-  __shared__ double red[16];
+// ||b|| into st->normb: per-workgroup partial sums, then a fixed-order sum
+// by the last workgroup to finish.
+__global__ __launch_bounds__(1024) void norm_kernel(const double *__restrict__ b, int64_t m, double *partial,
+                                                    unsigned int *ticket, LsqrState *__restrict__ st) {
+  __shared__ double scr[16];
+  __shared__ bool last;
   double s = 0.0;
-  for (int64_t i = threadIdx.x; i < m; i += 1024) s += b[i] * b[i];
-  s = block_sum(s, red, 16);
-  if (threadIdx.x == 0) st->normb = sqrt(s);
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * 1024 + threadIdx.x; i < m;
+       i += static_cast<int64_t>(gridDim.x) * 1024)
+    s += b[i] * b[i];
+  s = wg_sum(s, scr);
+  if (threadIdx.x == 0) {
+    partial[blockIdx.x] = s;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    last = atomicAdd(ticket, 1u) == gridDim.x - 1;
+  }
+  __syncthreads();
+  if (last && threadIdx.x == 0) {
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    double tot = 0.0;
+    for (unsigned g = 0; g < gridDim.x; ++g)
+      tot += __hip_atomic_load(&partial[g], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    st->normb = sqrt(tot);
+    *ticket = 0;
+  }
 }
 
 __global__ void copy_f64_kernel(const double *__restrict__ src, double *__restrict__ dst, int64_t n) {
@@ -435,9 +282,9 @@ __global__ void copy_f64_kernel(const double *__restrict__ src, double *__restri
 
 // --------------------------------------------------------------------------
 // Pass configuration: columns per wave = 64 * VEC * J, WC waves across the
-// columns, WR independent row groups per workgroup.
+// columns.
 struct PassCfg {
-  int vec, j, wc, wr;
+  int vec, j, wc;
 };
 
 template <int MODE>
@@ -445,53 +292,55 @@ PassCfg choose_pass(int n, int64_t lda, const void *A) {
   using TA = typename PassTypes<MODE>::TA;
   const int vmax = 16 / static_cast<int>(sizeof(TA));
   const bool aligned = (reinterpret_cast<uintptr_t>(A) % 16 == 0) && (lda % vmax == 0) && (n % vmax == 0);
-  PassCfg c{aligned ? vmax : 1, 1, 1, 4};
+  PassCfg c{aligned ? vmax : 1, 2, 1};
+  // at most 16 elements of a row per lane (A values, p and q live in registers)
+  const int jmax = std::min(8, 16 / c.vec);
   const int per_j = kWave * c.vec;
-  int need = (n + per_j - 1) / per_j;  // J * WC needed
-  if (need <= 8) {
-    int j = 1;
+  const int need = (n + per_j - 1) / per_j;  // J * WC needed
+  if (need <= jmax) {
+    int j = 2;
     while (j < need) j <<= 1;
-    c.j = j < 2 ? 2 : j;
+    c.j = j;
     c.wc = 1;
-    c.wr = 4;
   } else {
-    c.j = 8;
-    int wc = 1;
-    while (wc * 8 < need) wc <<= 1;
+    c.j = jmax;
+    int wc = 2;
+    while (wc * jmax < need) wc <<= 1;
     c.wc = wc;
-    c.wr = 1;
   }
   return c;
 }
 
-struct PassLaunch {
-  const void *fn;
-  int threads;
-};
+template <int MODE, int VEC, int J, int WC>
+const void *pass_fn() {
+  return reinterpret_cast<const void *>(&lsqr_pass_kernel<MODE, VEC, J, WC>);
+}
 
-template <int MODE, int VEC, int J, int WC, int WR>
-PassLaunch pass_fn() {
-  return PassLaunch{reinterpret_cast<const void *>(&lsqr_pass_kernel<MODE, VEC, J, WC, WR>), kWave * WC * WR};
+template <int MODE, int VEC, int J>
+const void *pick_wc(int wc) {
+  switch (wc) {
+    case 2: return pass_fn<MODE, VEC, J, 2>();
+    case 4: return pass_fn<MODE, VEC, J, 4>();
+    case 8: return pass_fn<MODE, VEC, J, 8>();
+    default: return pass_fn<MODE, VEC, J, 16>();
+  }
 }
 
 template <int MODE, int VEC>
-PassLaunch pick_vec(const PassCfg &c) {
+const void *pick_vec(const PassCfg &c) {
+  constexpr int JMAX = (16 / VEC) < 8 ? (16 / VEC) : 8;
   if (c.wc == 1) {
     switch (c.j) {
-      case 2: return pass_fn<MODE, VEC, 2, 1, 4>();
-      case 4: return pass_fn<MODE, VEC, 4, 1, 4>();
-      default: return pass_fn<MODE, VEC, 8, 1, 4>();
+      case 2: return pass_fn<MODE, VEC, 2, 1>();
+      case 4: return pass_fn<MODE, VEC, 4, 1>();
+      default: return pass_fn<MODE, VEC, JMAX, 1>();
     }
   }
-  switch (c.wc) {
-    case 2: return pass_fn<MODE, VEC, 8, 2, 1>();
-    case 4: return pass_fn<MODE, VEC, 8, 4, 1>();
-    default: return pass_fn<MODE, VEC, 8, 8, 1>();
-  }
+  return pick_wc<MODE, VEC, JMAX>(c.wc);
 }
 
 template <int MODE>
-PassLaunch pick_pass(const PassCfg &c) {
+const void *pick_pass(const PassCfg &c) {
   constexpr int vmax = 16 / static_cast<int>(sizeof(typename PassTypes<MODE>::TA));
   return c.vec == 1 ? pick_vec<MODE, 1>(c) : pick_vec<MODE, vmax>(c);
 }
@@ -499,42 +348,34 @@ PassLaunch pick_pass(const PassCfg &c) {
 std::mutex g_occ_mu;
 std::unordered_map<const void *, int> g_occ;
 
-int occupancy(const void *fn, int threads) {
+int occupancy(const void *fn) {
   std::lock_guard<std::mutex> lk(g_occ_mu);
   auto it = g_occ.find(fn);
   if (it != g_occ.end()) return it->second;
   int blocks = 1;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, fn, threads, 0) != hipSuccess || blocks < 1) blocks = 1;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, fn, kPassThreads, 0) != hipSuccess || blocks < 1)
+    blocks = 1;
   g_occ[fn] = blocks;
   return blocks;
 }
 
 struct PassPlan {
-  PassLaunch launch;
+  const void *fn;
   int grid;
   int64_t rows_per_wg;
 };
 
+int max_grid(sap_ctx *ctx) { return ctx->num_cus * 2; }
+
 PassPlan plan_pass(sap_ctx *ctx, int mode, int64_t m, int n, int64_t lda, const void *A) {
-  PassCfg c;
-  PassLaunch l;
-  if (mode == 0) {
-    c = choose_pass<0>(n, lda, A);
-    l = pick_pass<0>(c);
-  } else if (mode == 1) {
-    c = choose_pass<1>(n, lda, A);
-    l = pick_pass<1>(c);
-  } else {
-    c = choose_pass<2>(n, lda, A);
-    l = pick_pass<2>(c);
-  }
-  const int occ = occupancy(l.fn, l.threads);
-  int64_t grid = static_cast<int64_t>(ctx->num_cus) * occ;
-  const int64_t min_rows = 16;
+  const void *fn;
+  if (mode == 0) fn = pick_pass<0>(choose_pass<0>(n, lda, A));
+  else fn = pick_pass<1>(choose_pass<1>(n, lda, A));
+  int64_t grid = static_cast<int64_t>(ctx->num_cus) * std::min(2, occupancy(fn));
+  const int64_t min_rows = 64;
   if (grid * min_rows > m) grid = (m + min_rows - 1) / min_rows;
   if (grid < 1) grid = 1;
-  PassPlan p{l, static_cast<int>(grid), (m + grid - 1) / grid};
-  return p;
+  return PassPlan{fn, static_cast<int>(grid), (m + grid - 1) / grid};
 }
 
 void launch_pass(sap_ctx *ctx, const PassPlan &pl, const void *A, int64_t lda, int64_t m, int n, const void *p,
@@ -546,120 +387,130 @@ void launch_pass(sap_ctx *ctx, const PassPlan &pl, const void *A, int64_t lda, i
   void *uo = u_out, *qp = qpart, *np = nrmpart;
   void *args[] = {&A_, &lda_, &m_, &n_, &p_, &ui, &uo, &st_, &qp, &np, &rows};
   hipEvent_t pb = prof_begin(ctx, s);
-  const hipError_t e = hipLaunchKernel(pl.launch.fn, dim3(pl.grid), dim3(pl.launch.threads), args, 0, s);
+  const hipError_t e = hipLaunchKernel(pl.fn, dim3(pl.grid), dim3(kPassThreads), args, 0, s);
   if (e != hipSuccess) (void)e;  // reported by the hipGetLastError check after the batch
   prof_end(ctx, kProfPass, pb, s);
 }
 
-int max_grid(sap_ctx *ctx) { return ctx->num_cus * 16; }
-
 }  // namespace
 
-sap_status launch_trsv(sap_ctx *ctx, const double *R, int64_t ldr, int n, int trans, const double *rhs,
-                       double *x, hipStream_t st) {
-  if (n > kMaxN) return fail(ctx, SAP_EINVAL, "sap_trsv: n > 8192 is not supported");
-  trsv_kernel<<<1, kStepThreads, trsv_lds_bytes(n), st>>>(R, ldr, n, trans, rhs, x);
-  SAP_HIP_TRY(hipGetLastError());
-  return SAP_OK;
-}
-
-size_t lsqr_workspace_bytes(sap_ctx *ctx, int64_t m, int n, int mode) {
+size_t lsqr_workspace_bytes(sap_ctx *ctx, int64_t m, int n) {
   const size_t G = static_cast<size_t>(max_grid(ctx));
-  size_t bytes = 0;
-  bytes += 256 * 16;                                     // alignment slack
+  const size_t nblk = static_cast<size_t>((n + kTrsvB - 1) / kTrsvB);
+  size_t bytes = 256 * 32;                                // alignment slack
   bytes += sizeof(LsqrState);
   bytes += G * n * sizeof(double) + G * sizeof(double);  // partials
-  bytes += 5 * static_cast<size_t>(n) * sizeof(double);  // q v w p x0copy
-  bytes += static_cast<size_t>(n) * sizeof(float);       // p32
-  bytes += static_cast<size_t>(m) * (mode == 0 ? sizeof(double) : sizeof(float));  // u
+  bytes += 6 * static_cast<size_t>(n) * sizeof(double);  // y v w p x0copy
+  bytes += static_cast<size_t>(m) * sizeof(double);     // u
+  bytes += (3 * nblk + 16) * sizeof(int) + 4096 * sizeof(double);                  // flags, err, norm partials
+  bytes += trsv_factor_bytes(n);
   return bytes;
 }
 
-// Runs LSQR from x0 on A R^-1 (mode 0: FP64; mode 1/2: mixed form with FP64
-// residual refinement around FP32 inner iterations).
+size_t trsv_workspace_bytes(int n) {
+  return trsv_factor_bytes(n) + 8 * 256 + ((n + kTrsvB - 1) / kTrsvB + 8) * sizeof(int);
+}
+
+sap_status launch_trsv(sap_ctx *ctx, const double *R, int64_t ldr, int n, int trans, const double *rhs, double *x,
+                       void *work, hipStream_t st) {
+  if (n > kMaxN) return fail(ctx, SAP_EINVAL, "sap_trsv: n > 8192 is not supported");
+  Carve cv(work);
+  int *flags = cv.take<int>((n + kTrsvB - 1) / kTrsvB + 1);
+  int *err = cv.take<int>(1);
+  TrsvFactor f;
+  trsv_factor_carve(f, cv, n);
+  sap_status s = trsv_prepare(ctx, R, ldr, f, st);
+  if (s != SAP_OK) return s;
+  SAP_HIP_TRY(hipMemsetAsync(err, 0, sizeof(int), st));
+  s = trsv_solve(ctx, f, trans == 0, rhs, x, flags, err, st);
+  if (s != SAP_OK) return s;
+  int herr = 0;
+  SAP_HIP_TRY(hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, st));
+  SAP_HIP_TRY(hipStreamSynchronize(st));
+  if (herr) return fail(ctx, SAP_EDEVICE, "sap_trsv: a block wait expired");
+  return SAP_OK;
+}
+
+// Runs LSQR (Alg. 2) from x0 on A R^-1.  mode 0: A in FP64; mode 1: A
+// stored in FP32 (FP64 arithmetic throughout).
 sap_status run_lsqr(sap_ctx *ctx, const sap_problem *prob, const double *R, int64_t ldr, const double *x0,
-                    double tol, int maxiter, int mode, int max_refine, double inner_tol, double *x,
-                    sap_info *info, void *work, hipStream_t s) {
+                    const double *z, double tol, int maxiter, int mode, double *x, sap_info *info, void *work,
+                    hipStream_t s) {
   const int64_t m = prob->m;
   const int n = prob->n;
   if (n > kMaxN) return fail(ctx, SAP_EINVAL, "LSQR: n > 8192 is not supported");
+  const int nblk = (n + kTrsvB - 1) / kTrsvB;
   Carve cv(work);
   LsqrState *st = cv.take<LsqrState>(1);
-  const int pass_mode_main = (mode == 0) ? 0 : 1;
-  const PassPlan plan_main = plan_pass(ctx, pass_mode_main, m, n, prob->lda, prob->A);
-  const PassPlan plan_ref = (mode == 0) ? plan_main : plan_pass(ctx, 2, m, n, prob->lda, prob->A);
-  const int G = plan_main.grid > plan_ref.grid ? plan_main.grid : plan_ref.grid;
-  if (G > max_grid(ctx)) return fail(ctx, SAP_EINVAL, "LSQR: internal grid larger than planned");
+  const PassPlan plan = plan_pass(ctx, mode, m, n, prob->lda, prob->A);
+  if (plan.grid > max_grid(ctx)) return fail(ctx, SAP_EINVAL, "LSQR: internal grid larger than planned");
   double *qpart = cv.take<double>(static_cast<size_t>(max_grid(ctx)) * n);
   double *nrmpart = cv.take<double>(max_grid(ctx));
-  double *q = cv.take<double>(n);
+  double *y = cv.take<double>(n);
   double *v = cv.take<double>(n);
   double *w = cv.take<double>(n);
   double *p = cv.take<double>(n);
   double *xin = cv.take<double>(n);
-  float *p32 = cv.take<float>(n);
-  void *u = (mode == 0) ? static_cast<void *>(cv.take<double>(m)) : static_cast<void *>(cv.take<float>(m));
+  double *u = cv.take<double>(m);
+  int *flags = cv.take<int>(3 * nblk + 2);
+  int *flags_lo = flags, *flags_up = flags + nblk, *flags_x0 = flags + 2 * nblk;
+  int *err = cv.take<int>(4);
+  unsigned int *ticket = reinterpret_cast<unsigned int *>(err + 1);
+  double *normpart = cv.take<double>(4096);
+  TrsvFactor f;
+  trsv_factor_carve(f, cv, n);
 
-  const size_t step_lds = trsv_lds_bytes(n);
-  // x0 may alias x: copy first.
-  copy_f64_kernel<<<(n + 255) / 256, 256, 0, s>>>(x0, xin, n);
-  copy_f64_kernel<<<(n + 255) / 256, 256, 0, s>>>(xin, x, n);
-  lsqr_init_state_kernel<<<1, 64, 0, s>>>(st, mode == 0 ? tol : inner_tol, maxiter, 0);
-  norm_kernel<<<1, 1024, 0, s>>>(prob->b, m, st);
+  sap_status sst = trsv_prepare(ctx, R, ldr, f, s);
+  if (sst != SAP_OK) return sst;
+  SAP_HIP_TRY(hipMemsetAsync(err, 0, 4 * sizeof(int), s));
+  if (z) {
+    // x0 = R^-1 z: the minimiser of ||S b - S A x|| (Alg. 1, initial guess)
+    sst = trsv_solve(ctx, f, true, z, x, flags_x0, err, s);
+    if (sst != SAP_OK) return sst;
+  } else {
+    // x0 may alias x: copy first.
+    copy_f64_kernel<<<(n + 255) / 256, 256, 0, s>>>(x0, xin, n);
+    copy_f64_kernel<<<(n + 255) / 256, 256, 0, s>>>(xin, x, n);
+  }
+  lsqr_init_state_kernel<<<1, 256, 0, s>>>(st, tol, maxiter, flags, 2 * nblk);
+  const int ngrid = static_cast<int>(std::min<int64_t>(256, (m + 1023) / 1024));
+  norm_kernel<<<ngrid, 1024, 0, s>>>(prob->b, m, normpart, ticket, st);
   SAP_HIP_TRY(hipGetLastError());
 
+  // One iteration = pass over A, lower solve (+ v update), upper solve (+ x,
+  // w update and the stopping test).
+  auto iteration = [&](const void *pv, const void *uin) {
+    launch_pass(ctx, plan, prob->A, prob->lda, m, n, pv, uin, u, st, qpart, nrmpart, s);
+    lsqr_lower_kernel<<<nblk, kTrsvThreads, 0, s>>>(f.Rt, n, f.Dlo, qpart, plan.grid, nrmpart, y, v, st, flags_lo,
+                                                    err);
+    lsqr_upper_kernel<<<nblk, kTrsvThreads, 0, s>>>(R, ldr, n, f.Dup, v, p, w, x, st, flags_up, err);
+  };
+
+  // Initialisation: beta_1 u_1 = b - A x0 (the pass with p = x, u_in = b).
+  iteration(x, prob->b);
+  SAP_HIP_TRY(hipGetLastError());
+  // Iterations in batches; one state read per batch.  The upper kernel sets
+  // `done` no later than iteration maxiter, so the batch count is bounded.
   const int batch = 8;
-  int refinements = 0;
+  const int max_batches = maxiter / batch + 2;
   LsqrState hs{};
-  const int max_outer = (mode == 0) ? 1 : (max_refine > 0 ? max_refine : 8) + 1;
-  for (int outer = 0; outer < max_outer; ++outer) {
-    if (outer > 0) {
-      lsqr_init_state_kernel<<<1, 64, 0, s>>>(st, inner_tol, maxiter, hs.total_iters);
-      SAP_HIP_TRY(hipGetLastError());
-    }
-    // Initialisation pass: u_hat_1 = b - A x (mode 2 in the mixed form: FP64
-    // accumulation of the FP32 A; this is the residual refinement pass).
-    const int init_mode = (mode == 0) ? 0 : 2;
-    const PassPlan &pi = (mode == 0) ? plan_main : plan_ref;
-    launch_pass(ctx, pi, prob->A, prob->lda, m, n, x, prob->b, u, st, qpart, nrmpart, s);
-    lsqr_reduce_kernel<<<(n + 63) / 64, 256, 0, s>>>(qpart, nrmpart, pi.grid, n, q, st);
-    lsqr_step_kernel<<<1, kStepThreads, step_lds, s>>>(R, ldr, n, q, v, w, x, p, mode == 0 ? nullptr : p32, st,
-                                                      mode == 0 ? 0.0 : tol);
+  int herr = 0;
+  for (int nbatch = 0;; ++nbatch) {
+    if (nbatch > max_batches) return fail(ctx, SAP_EDEVICE, "LSQR: device never reported completion");
+    for (int k = 0; k < batch; ++k) iteration(p, u);
     SAP_HIP_TRY(hipGetLastError());
-    if (mode != 0) ++refinements;
-    // Iterations in batches; one flag read per batch.  The step kernel sets
-    // `done` no later than iteration maxiter, so the batch count is bounded.
-    const int max_batches = maxiter / batch + 2;
-    for (int nbatch = 0;; ++nbatch) {
-      if (nbatch > max_batches) return fail(ctx, SAP_EDEVICE, "LSQR: device never reported completion");
-      for (int k = 0; k < batch; ++k) {
-        if (mode == 0)
-          launch_pass(ctx, plan_main, prob->A, prob->lda, m, n, p, u, u, st, qpart, nrmpart, s);
-        else
-          launch_pass(ctx, plan_main, prob->A, prob->lda, m, n, p32, u, u, st, qpart, nrmpart, s);
-        lsqr_reduce_kernel<<<(n + 63) / 64, 256, 0, s>>>(qpart, nrmpart, plan_main.grid, n, q, st);
-        lsqr_step_kernel<<<1, kStepThreads, step_lds, s>>>(R, ldr, n, q, v, w, x, p,
-                                                          mode == 0 ? nullptr : p32, st, 0.0);
-      }
-      SAP_HIP_TRY(hipGetLastError());
-      SAP_HIP_TRY(hipMemcpyAsync(&hs, st, sizeof(LsqrState), hipMemcpyDeviceToHost, s));
-      SAP_HIP_TRY(hipStreamSynchronize(s));
-      if (hs.done) break;
-    }
-    if (mode == 0) break;
-    // Mixed form: the inner loop ended.  Converged at the outer level only if
-    // the refinement pass itself said so (done at init with converged set).
-    if (hs.converged && hs.iter == 0) break;
-    if (hs.total_iters >= maxiter) break;
+    SAP_HIP_TRY(hipMemcpyAsync(&hs, st, sizeof(LsqrState), hipMemcpyDeviceToHost, s));
+    SAP_HIP_TRY(hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, s));
+    SAP_HIP_TRY(hipStreamSynchronize(s));
+    if (herr) return fail(ctx, SAP_EDEVICE, "LSQR: a triangular-solve wait expired");
+    if (hs.done) break;
   }
   if (info) {
     info->iters = hs.total_iters;
-    info->refinements = refinements;
     info->resid_est = hs.resid_est;
     info->normar_est = hs.normar_est;
   }
-  if (mode == 0) return hs.converged ? SAP_OK : SAP_NOT_CONVERGED;
-  return (hs.converged && hs.iter == 0) ? SAP_OK : SAP_NOT_CONVERGED;
+  return hs.converged ? SAP_OK : SAP_NOT_CONVERGED;
 }
 
 }  // namespace sap

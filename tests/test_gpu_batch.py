@@ -1,0 +1,102 @@
+"""GPU parity of the batched form (sap_solve_batch): many uneven problems in
+one set of launches.  Problem k's sketch uses Philox stream word k, so the
+oracle reference for problem k is Alg. 1 with the same (seed, stream).  The
+batched passes accumulate in FP64 whatever A's storage type, so the bars are
+the FP64 ones: ||A(x - x_or)|| / ||b|| <= 1e-11 and, where the perturbation
+bound allows (cond <= 1e6 here), ||x - x_or|| / ||x_or|| <= 1e-8."""
+import numpy as np
+import pytest
+
+import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sap():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2506_03070_amd as sap
+    sap.lib()
+    return sap
+
+
+def _batch(count, seed, dtype, m_range=(3000, 40000), n_range=(20, 130), cond_exp=(2, 6)):
+    rng = np.random.default_rng(seed)
+    probs = []
+    for k in range(count):
+        m = int(rng.integers(*m_range))
+        n = int(rng.integers(*n_range))
+        cond = float(10 ** rng.uniform(*cond_exp))
+        p = inputs.make_problem(m, n, kind="colscale", cond=cond, noise=1e-8, seed=seed * 1000 + k, dtype=dtype)
+        probs.append(p)
+    return probs
+
+
+@pytest.mark.parametrize("dtype,count,pad", [(np.float32, 12, 0), (np.float64, 7, 0), (np.float32, 9, 4)])
+def test_batch_parity(sap, orc, dtype, count, pad):
+    import torch
+    print(f"batch dtype={np.dtype(dtype).name} count={count} pad={pad}", flush=True)
+    probs = _batch(count, 17 + count, dtype)
+    As, bs = [], []
+    for p in probs:
+        m, n = p.A.shape
+        if pad:
+            big = np.zeros((m, n + pad), dtype=dtype)
+            big[:, :n] = p.A
+            As.append(torch.from_numpy(big).cuda()[:, :n])
+        else:
+            As.append(torch.from_numpy(np.ascontiguousarray(p.A)).cuda())
+        bs.append(torch.from_numpy(p.b).cuda())
+    ds = [4 * p.A.shape[1] for p in probs]
+    xs, st, infos = sap.sap_solve_batch(As, bs, ds, 8, 99, tol=1e-12, maxiter=300)
+    torch.cuda.synchronize()
+    assert st == sap.SAP_OK, infos
+    for k, p in enumerate(probs):
+        A64 = p.A.astype(np.float64)
+        x_or, io = orc.solve(A64, p.b, ds[k], 8, 99, tol=1e-12, maxiter=300, stream=k)
+        x = xs[k].cpu().numpy()
+        nb = np.linalg.norm(p.b)
+        assert io["status"] == "ok"
+        assert infos[k]["status"] == sap.SAP_OK
+        assert np.linalg.norm(A64 @ (x - x_or)) <= 1e-11 * nb, k
+        assert np.linalg.norm(x - x_or) <= 1e-8 * np.linalg.norm(x_or), k
+
+
+def test_batch_rank_deficient_member(sap, orc):
+    """A rank-deficient problem is reported as such and does not disturb the
+    others."""
+    import torch
+    probs = _batch(4, 5, np.float32)
+    bad = probs[2].A.copy()
+    bad[:, 3] = bad[:, 1]
+    probs[2].A = bad
+    As = [torch.from_numpy(np.ascontiguousarray(p.A)).cuda() for p in probs]
+    bs = [torch.from_numpy(p.b).cuda() for p in probs]
+    ds = [4 * p.A.shape[1] for p in probs]
+    xs, st, infos = sap.sap_solve_batch(As, bs, ds, 8, 7, tol=1e-12, maxiter=300)
+    torch.cuda.synchronize()
+    assert st == sap.SAP_NOT_CONVERGED
+    assert infos[2]["status"] == sap.SAP_RANK_DEFICIENT
+    for k in (0, 1, 3):
+        p = probs[k]
+        x_or, _ = orc.solve(p.A.astype(np.float64), p.b, ds[k], 8, 7, tol=1e-12, maxiter=300, stream=k)
+        assert infos[k]["status"] == sap.SAP_OK
+        assert np.linalg.norm(xs[k].cpu().numpy() - x_or) <= 1e-8 * np.linalg.norm(x_or)
+
+
+def test_batch_matches_single_solves(sap):
+    """A problem solved inside a batch equals the same problem solved alone
+    in a batch of one (same stream word 0), to the solver tolerance."""
+    import torch
+    probs = _batch(5, 9, np.float32)
+    As = [torch.from_numpy(np.ascontiguousarray(p.A)).cuda() for p in probs]
+    bs = [torch.from_numpy(p.b).cuda() for p in probs]
+    ds = [4 * p.A.shape[1] for p in probs]
+    xs, st, _ = sap.sap_solve_batch(As, bs, ds, 8, 3, tol=1e-12, maxiter=300)
+    x1, st1, _ = sap.sap_solve_batch(As[:1], bs[:1], ds[:1], 8, 3, tol=1e-12, maxiter=300)
+    torch.cuda.synchronize()
+    a = xs[0].cpu().numpy()
+    b = x1[0].cpu().numpy()
+    assert np.linalg.norm(a - b) <= 1e-10 * np.linalg.norm(b)

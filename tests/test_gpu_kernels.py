@@ -101,6 +101,8 @@ APPLY_CASES = [
     (40000, 64, 512, 8, "colscale", "f32", "f64", True, 1),
     (100000, 17, 8192, 8, "colscale", "f32", "f32", True, 0),
     (1, 5, 7, 3, "colscale", "f64", "f64", True, 0),
+    (70000, 47, 4000, 8, "svd", "f64", "f64", True, 0),        # config 1's d: 4 row ranges, bucketed
+    (20000, 200, 2600, 8, "colscale", "f32", "f64", True, 0),  # 3 ranges, ragged last tile
 ]
 
 
@@ -113,12 +115,12 @@ def test_apply_parity(sap, orc, m, n, d, zeta, kind, adt, ydt, with_b, pad):
     assert rel <= bound, rel
 
 
-@pytest.mark.parametrize("ydt", ["f64", "f32"])
-def test_apply_integer_bitwise(sap, orc, ydt):
+@pytest.mark.parametrize("ydt,d", [("f64", 700), ("f32", 700), ("f64", 4000), ("f32", 9000)])
+def test_apply_integer_bitwise(sap, orc, ydt, d):
     """Integer A and b: every partial sum is an exact integer in the
     accumulation type, so Y = h * sum is the same bits in any order."""
     import torch
-    m, n, d, zeta = 60000, 31, 700, 8
+    m, n, zeta = 60000, 31, 8
     _note(f"apply-int m={m} n={n} d={d} Y={ydt}")
     p = inputs.make_problem(m, n, kind="integer", seed=9)
     A_np = p.A if ydt == "f64" else p.A.astype(np.float32)
@@ -140,6 +142,29 @@ def test_apply_integer_bitwise(sap, orc, ydt):
         ref = exact.astype(np.float32) * np.float32(orc.sketch_scale(zeta))
         got = Y.cpu().numpy().T
     assert np.array_equal(got, ref)
+
+
+def test_apply_ignores_out_of_range_rows(sap, orc):
+    """A caller-supplied sketch with row indices outside [0, d) must not
+    fault: those nonzeros are ignored."""
+    import torch
+    m, n, d, zeta = 5000, 9, 3000, 4
+    p = inputs.make_problem(m, n, kind="colscale", cond=10.0, seed=4)
+    idx_ref, sign_ref = orc.sketch(8, 0, m, d, zeta)
+    bad = idx_ref.copy()
+    bad[::7, 1] = d + 5
+    bad[::11, 2] = -3
+    Y = sap.sps_apply(torch.from_numpy(bad).cuda(), torch.from_numpy(sign_ref.view(np.int64)).cuda(), d, zeta,
+                      torch.from_numpy(p.A).cuda(), torch.from_numpy(p.b).cuda())
+    torch.cuda.synchronize()
+    keep = (bad >= 0) & (bad < d)
+    s = orc.sign_values(sign_ref, zeta) * keep
+    Ab = np.column_stack([p.A, p.b])
+    ref = np.zeros((d, n + 1))
+    for k in range(zeta):
+        np.add.at(ref, np.where(keep[:, k], bad[:, k], 0), s[:, k:k + 1] * Ab)
+    ref *= orc.sketch_scale(zeta)
+    assert np.linalg.norm(Y.cpu().numpy().T - ref) <= 1e-12 * np.linalg.norm(ref)
 
 
 # ----------------------------------------------------------------- QR -----

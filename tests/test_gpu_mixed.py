@@ -1,0 +1,84 @@
+"""GPU parity of the mixed-precision form: A stored in FP32; the sketch
+accumulated in FP32; QR, triangular solves, recurrences and the LSQR passes
+(which widen each FP32 element) in FP64.  The reference is the FP64 oracle run
+on the FP32-rounded A (exactly representable in FP64), so both sides solve the
+same problem; the bar is the forward error ||x - x_or|| / ||x_or|| <= 1e-8
+(where the least-squares perturbation bound allows it) and the paper's metric
+||A(x - x_or)|| / ||b|| <= 1e-10.  Only the preconditioner differs (FP32
+sketch), which changes the iterates but not the limit."""
+import numpy as np
+import pytest
+
+import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sap():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2506_03070_amd as sap
+    sap.lib()
+    return sap
+
+
+def _dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+MIXED_CASES = [
+    # name, m, n, d, kind, cond, noise
+    ("colscale", 200000, 256, 1024, "colscale", 1e6, 1e-8),
+    ("svd", 60000, 100, 400, "svd", 1e6, 1e-8),
+    ("wide", 120000, 1000, 2000, "colscale", 1e4, 1e-6),
+    ("odd-n", 50000, 77, 308, "colscale", 1e5, 1e-8),
+]
+
+
+@pytest.mark.parametrize("name,m,n,d,kind,cond,noise", MIXED_CASES)
+def test_mixed_solve_parity(sap, orc, name, m, n, d, kind, cond, noise):
+    import torch
+    print(f"mixed {name} m={m} n={n} d={d}", flush=True)
+    p = inputs.make_problem(m, n, kind=kind, cond=cond, noise=noise, seed=m + 11, dtype=np.float32)
+    A64 = p.A.astype(np.float64)
+    seed = 321
+    res = sap.sap_solve(_dev(p.A), _dev(p.b), d, 8, seed, tol=1e-12, maxiter=400, mode=sap.SAP_MODE_MIXED_FP32)
+    torch.cuda.synchronize()
+    x = res.x.cpu().numpy()
+    x_or, info_or = orc.solve(A64, p.b, d, 8, seed, tol=1e-12, maxiter=400)
+    assert info_or["status"] == "ok"
+    assert res.status == sap.SAP_OK, res.info
+    nb = np.linalg.norm(p.b)
+    assert np.linalg.norm(A64 @ (x - x_or)) <= 1e-10 * nb
+    assert np.linalg.norm(x - x_or) <= 1e-8 * np.linalg.norm(x_or)
+
+
+def test_mixed_mode_dtype_checks(sap):
+    p = inputs.make_problem(4000, 10, kind="colscale", cond=10.0, seed=1)
+    with pytest.raises(sap.SapError) as e:
+        sap.sap_solve(_dev(p.A), _dev(p.b), 40, 8, 1, mode=sap.SAP_MODE_MIXED_FP32)  # F64 A
+    assert e.value.status == sap.SAP_EINVAL
+    with pytest.raises(sap.SapError) as e:
+        sap.sap_solve(_dev(p.A.astype(np.float32)), _dev(p.b), 40, 8, 1, mode=7)
+    assert e.value.status == sap.SAP_EINVAL
+
+
+def test_fp32_apply_then_fp64_qr_is_a_good_preconditioner(sap, orc):
+    """The preconditioner only has to be approximate: the FP32 sketch gives an
+    R with cond(A R^-1) within the sketch's own distortion bound."""
+    import torch
+    m, n, d = 40000, 60, 240
+    p = inputs.make_problem(m, n, kind="colscale", cond=1e6, seed=3, dtype=np.float32)
+    idx, sign = sap.sps_generate(m, d, 8, 5)
+    Y = sap.sps_apply(idx, sign, d, 8, _dev(p.A), None, y_dtype=torch.float32)
+    torch.cuda.synchronize()
+    Yh = Y.cpu().numpy().T.astype(np.float64)
+    F, _ = orc.householder_qr(Yh)
+    R = np.triu(F[:n, :n])
+    AM = p.A.astype(np.float64) @ np.linalg.inv(R)
+    sv = np.linalg.svd(AM, compute_uv=False)
+    eta = np.sqrt(n / d)
+    assert sv[0] / sv[-1] <= 2.0 * (1 + eta) / (1 - eta)
