@@ -3,10 +3,16 @@ sketch generation, sketch apply, Householder QR of the sketch, x0, LSQR to
 tolerance) of the FP64 workload m = 2^20, n = 1000, d = 4000, zeta = 8 on one
 MI355X, with A and b resident in HBM before the timed region.
 
-Prints ONE JSON line.  `value` is solves per second; `roofline` reports the
-dominant kernel (the fused LSQR pass over A) from HIP-event timings taken on
-its own stream inside the timed region; `cpu_baseline` times the CPU oracle on
-a bounded row sample of the same workload and projects it to the full size.
+Prints ONE JSON line.  `value` is solves per second of that workload;
+`roofline` reports the dominant kernel (the fused LSQR pass over A) from
+HIP-event timings taken on its own stream inside the timed region;
+`cpu_baseline` times the CPU oracle on a bounded row sample of the same
+workload and projects it to the full size.  `forms` adds the other three
+forms, each against the plain FP64 form on the same problems:
+  * mixed   - one large solve, m = 2^22, n = 4096, d = 2n, A stored in FP32;
+  * batched - 512 uneven FP32 problems in one sap_solve_batch call;
+  * served  - a Poisson request stream (200 req/s) through sap_submit/poll,
+              with p50/p99 latency.
 """
 import argparse
 import json
@@ -32,6 +38,15 @@ def parse():
     ap.add_argument("--n", type=int, default=1000)
     ap.add_argument("--d", type=int, default=4000)
     ap.add_argument("--zeta", type=int, default=8)
+    ap.add_argument("--forms", default="mixed,batched,served",
+                    help="comma list of extra forms to run (mixed, batched, served; empty for none)")
+    ap.add_argument("--mixed-m", type=int, default=1 << 22)
+    ap.add_argument("--mixed-n", type=int, default=4096)
+    ap.add_argument("--batch-count", type=int, default=512)
+    ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--serve-duration", type=float, default=1.5)
+    ap.add_argument("--copy-ref-mib", type=int, default=2048,
+                    help="size of the plain device-to-device copy timed as the achievable-bandwidth reference")
     return ap.parse_args()
 
 
@@ -39,16 +54,13 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(A_dev, b_dev, d, zeta, seed, tol, iters_gpu, rows):
-    """Oracle (plain C, one thread) on the first `rows` rows; per-phase times
-    projected to the full m (generation, apply and each LSQR iteration scale
-    with m; the QR of the d x (n+1) sketch does not), using the GPU's
-    iteration count for the number of iterations."""
-    import numpy as np
+def cpu_baseline(A, b, m, d, zeta, seed, tol, iters_gpu):
+    """Oracle (plain C, one thread) on the first rows of the workload (A, b:
+    host arrays of that sample); per-phase times projected to the full m
+    (generation, apply and each LSQR iteration scale with m; the QR of the
+    d x (n+1) sketch does not), using the GPU's iteration count."""
     import oracle
-    m = A_dev.shape[0]
-    A = A_dev[:rows].cpu().numpy()
-    b = b_dev[:rows].cpu().numpy()
+    rows = A.shape[0]
     t0 = time.perf_counter()
     x, info = oracle.solve(A, b, d, zeta, seed, tol=tol, maxiter=200)
     wall = time.perf_counter() - t0
@@ -60,6 +72,216 @@ def cpu_baseline(A_dev, b_dev, d, zeta, seed, tol, iters_gpu, rows):
                        f"{wall:.1f} s wall, generate {info['t_generate']:.2f} s, apply {info['t_apply']:.2f} s, "
                        f"QR {info['t_qr']:.2f} s, {info['iters']} LSQR iterations {info['t_iterate']:.2f} s; "
                        f"projected to m={m} with {iters_gpu} iterations: {t_full:.1f} s per solve")}
+
+
+def rel(a, b):
+    import torch
+    return (torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b)).item()
+
+
+def widen(A32):
+    """FP64 copy of an FP32 matrix (exact), built in row chunks."""
+    import torch
+    A64 = torch.empty(A32.shape, dtype=torch.float64, device=A32.device)
+    step = 1 << 18
+    for r0 in range(0, A32.shape[0], step):
+        A64[r0:r0 + step] = A32[r0:r0 + step].to(torch.float64)
+    return A64
+
+
+def copy_reference(torch, mib):
+    """Plain device-to-device copy (torch's copy kernel) of `mib` MiB, timed
+    with HIP events: the achievable streaming bandwidth on this GPU, and the
+    known-size kernel that scales the HBM byte counters."""
+    src = torch.empty(mib << 20, dtype=torch.uint8, device="cuda")
+    src.fill_(1)
+    dst = torch.empty_like(src)
+    for _ in range(2):
+        dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 10
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    torch.cuda.empty_cache()
+    return {"bytes_moved": 2 * (mib << 20), "avg_ms": ms, "gbs": 2 * (mib << 20) / (ms * 1e-3) / 1e9}
+
+
+def pass_bytes(m, n, esize):
+    # the fused pass reads A once and u once and writes u once (p, the
+    # per-workgroup partials and the state are < 0.3%)
+    return m * n * esize + 2 * m * 8
+
+
+def apply_bytes(m, n, d, zeta, esize, ysize):
+    # A and b once, the sketch (zeta int32 + one 64-bit sign word per row), Y once
+    return m * n * esize + m * 8 + m * (zeta * 4 + 8) + d * (n + 1) * ysize
+
+
+def form_mixed(args, sap, torch, inputs):
+    """Mixed form (A stored FP32, FP64 arithmetic in the passes) against the
+    FP64 form on the same matrix (its exact FP64 copy)."""
+    m, n = args.mixed_m, args.mixed_n
+    log(f"bench[mixed]: generating m={m} n={n} FP32 A")
+    A32, b, _, meta = inputs.config2_torch("cuda", m=m, n=n)
+    d, zeta, seed, tol, maxiter = meta["d"], meta["zeta"], meta["sketch_seed"], meta["tol"], meta["maxiter"]
+    ctx = sap.default_context(0)
+    x32 = torch.empty(n, dtype=torch.float64, device="cuda")
+    x64 = torch.empty(n, dtype=torch.float64, device="cuda")
+
+    def timed(A, x, mode):
+        sap.sap_solve(A, b, d, zeta, seed, tol=tol, maxiter=maxiter, x=x, mode=mode)  # warm-up
+        torch.cuda.synchronize()
+        ctx.profile(True)
+        ctx.profile_read(sap.PROF_PASS, reset=True)
+        ctx.profile_read(sap.PROF_APPLY, reset=True)
+        t0 = time.perf_counter()
+        r = sap.sap_solve(A, b, d, zeta, seed, tol=tol, maxiter=maxiter, x=x, mode=mode)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        ctx.profile(False)
+        npass, mspass = ctx.profile_read(sap.PROF_PASS)
+        nap, msap = ctx.profile_read(sap.PROF_APPLY)
+        es = A.element_size()
+        pb = pass_bytes(m, n, es)
+        ab = apply_bytes(m, n, d, zeta, es, 4 if mode == sap.SAP_MODE_MIXED_FP32 else 8)
+        return dict(solve_ms=dt * 1e3, status=r.info["status_name"], iters=r.info["iters"],
+                    phases_ms={"generate": r.info["t_generate_ms"], "apply": r.info["t_apply_ms"],
+                               "qr": r.info["t_qr_ms"], "iterate": r.info["t_iterate_ms"]},
+                    pass_gbs=pb / (mspass / max(1, npass) * 1e-3) / 1e9,
+                    sa_gbs=ab / (msap / max(1, nap) * 1e-3) / 1e9)
+
+    log("bench[mixed]: FP32-storage solve")
+    rm = timed(A32, x32, sap.SAP_MODE_MIXED_FP32)
+    log(f"bench[mixed]: {rm}")
+    log("bench[mixed]: widening A to FP64 for the FP64 form")
+    A64 = widen(A32)
+    del A32
+    torch.cuda.empty_cache()
+    r64 = timed(A64, x64, sap.SAP_MODE_FP64)
+    log(f"bench[mixed]: fp64 {r64}")
+    del A64
+    torch.cuda.empty_cache()
+    return {"workload": f"m={m} n={n} d={d} zeta={zeta}, A_ij = g_ij 10^(-6 j/(n-1)) stored FP32, "
+                        f"b = A x + 1e-8 noise, tol {tol}",
+            "mixed": rm, "fp64": r64, "speedup": r64["solve_ms"] / rm["solve_ms"],
+            "rel_diff_x": rel(x32, x64)}
+
+
+def form_batched(args, sap, torch, inputs):
+    """Batched form over uneven FP32 problems against one-at-a-time FP64
+    solves of the same problems."""
+    shapes = inputs.batch_shapes(count=args.batch_count)
+    log(f"bench[batched]: generating {len(shapes)} problems")
+    As, bs = [], []
+    for s in shapes:
+        A, b, _ = inputs.make_problem_torch(s["m"], s["n"], kind="colscale", cond=s["cond"], noise=1e-8,
+                                            seed=s["seed"], device="cuda", dtype=torch.float32)
+        As.append(A)
+        bs.append(b)
+    ds = [s["d"] for s in shapes]
+    seeds = [s["seed"] + 1 for s in shapes]
+    tot_bytes = sum(A.numel() * 4 for A in As)
+    sap.sap_solve_batch(As, bs, ds, 8, seeds, tol=1e-12, maxiter=300)  # warm-up and autotune
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    xs, st, infos = sap.sap_solve_batch(As, bs, ds, 8, seeds, tol=1e-12, maxiter=300)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    n_ok = sum(1 for i in infos if i["status"] == sap.SAP_OK)
+    log(f"bench[batched]: {len(As)} problems in {t_batch * 1e3:.1f} ms ({n_ok} converged)")
+    # FP64 form, one solve after another on exact FP64 copies
+    A64s = [A.to(torch.float64) for A in As]
+    x64s = [torch.empty(A.shape[1], dtype=torch.float64, device="cuda") for A in As]
+    sap.sap_solve(A64s[0], bs[0], ds[0], 8, seeds[0], tol=1e-12, maxiter=300, x=x64s[0])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(len(As)):
+        sap.sap_solve(A64s[k], bs[k], ds[k], 8, seeds[k], tol=1e-12, maxiter=300, x=x64s[k])
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
+    diffs = sorted(rel(xs[k], x64s[k]) for k in range(len(As)))
+    del A64s, As
+    torch.cuda.empty_cache()
+    return {"workload": f"{len(shapes)} problems, m ~ U[5000, 200000], n ~ U{{32..256}}, d = 4n, zeta = 8, "
+                        "FP32 A (column scales, cond log-uniform in [1e2, 1e8]), tol 1e-12",
+            "a_bytes": tot_bytes, "batch_ms": t_batch * 1e3, "solves_per_s": len(shapes) / t_batch,
+            "converged": n_ok, "fp64_sequential_ms": t_seq * 1e3, "fp64_solves_per_s": len(shapes) / t_seq,
+            "speedup": t_seq / t_batch, "rel_diff_x_median": diffs[len(diffs) // 2], "rel_diff_x_max": diffs[-1]}
+
+
+def form_served(args, sap, torch, inputs):
+    """Served form: requests arrive as a Poisson stream and are submitted at
+    their arrival times; latency = submit to finished.  The FP64 form serves
+    the same stream one solve at a time, first come first served."""
+    import numpy as np
+    reqs = inputs.served_stream(rate=args.serve_rate, duration=args.serve_duration)
+    log(f"bench[served]: generating {len(reqs)} requests")
+    probs = []
+    for k, r in enumerate(reqs):
+        A, b, _ = inputs.make_problem_torch(r["m"], r["n"], kind="colscale", cond=1e6, noise=1e-8,
+                                            seed=inputs.config_seed(4) + 13 * k, device="cuda",
+                                            dtype=torch.float32)
+        probs.append((A, b))
+    torch.cuda.synchronize()
+    ctx = sap.Context(0)
+    # warm-up request (not counted)
+    t = sap.sap_submit(probs[0][0], probs[0][1], reqs[0]["d"], 8, 1, tol=1e-12, maxiter=300, ctx=ctx)
+    sap.sap_poll(t, wait=True, ctx=ctx)
+    tickets = []
+    t_start = time.perf_counter()
+    for k, r in enumerate(reqs):
+        delay = t_start + r["t"] - time.perf_counter()
+        if delay > 0:
+            time.sleep(delay)
+        A, b = probs[k]
+        tickets.append(sap.sap_submit(A, b, r["d"], 8, 101 + k, tol=1e-12, maxiter=300, ctx=ctx))
+    lat, xs, statuses = [], [], []
+    for t in tickets:
+        st, info, x = sap.sap_poll(t, wait=True, ctx=ctx)
+        lat.append(info["t_total_ms"])
+        xs.append(x)
+        statuses.append(st)
+    t_end = time.perf_counter()
+    stats = sap.sap_serve_stats(ctx)
+    ctx.close()
+    log(f"bench[served]: {len(reqs)} requests served in {t_end - t_start:.2f} s")
+    # FP64 form, first come first served: solve durations measured back to
+    # back, queueing replayed against the same arrival times
+    A64s = [A.to(torch.float64) for A, _ in probs]
+    x64s = []
+    finish = 0.0
+    lat64 = []
+    for k, r in enumerate(reqs):
+        x64 = torch.empty(r["n"], dtype=torch.float64, device="cuda")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sap.sap_solve(A64s[k], probs[k][1], r["d"], 8, 101 + k, tol=1e-12, maxiter=300, x=x64)
+        torch.cuda.synchronize()
+        dur = time.perf_counter() - t0
+        start = max(r["t"], finish)
+        finish = start + dur
+        lat64.append((finish - r["t"]) * 1e3)
+        x64s.append(x64)
+    diffs = sorted(rel(xs[k], x64s[k]) for k in range(len(reqs)))
+    del A64s, probs
+    torch.cuda.empty_cache()
+
+    def pct(v, q):
+        return float(np.percentile(np.asarray(v), q))
+
+    return {"workload": f"{len(reqs)} requests, Poisson {args.serve_rate:g} req/s, m ~ lognormal(median 1e5, "
+                        "sigma 1) clamped to [8n, 2^21], n in {64,128,256,512}, d = 4n, zeta = 8, FP32 A "
+                        "(column scales, cond 1e6), tol 1e-12",
+            "requests": len(reqs), "ok": sum(1 for s in statuses if s == sap.SAP_OK),
+            "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99), "solves_per_s": len(reqs) / (t_end - t_start),
+            "fp64_fcfs_p50_ms": pct(lat64, 50), "fp64_fcfs_p99_ms": pct(lat64, 99),
+            "fp64_fcfs_solves_per_s": len(reqs) / finish if finish > 0 else None,
+            "rel_diff_x_max": diffs[-1], "serve_stats": stats}
 
 
 def main():
@@ -77,6 +299,9 @@ def main():
     import paper_2506_03070_amd as sap
 
     torch.cuda.set_device(0)
+    copy_ref = copy_reference(torch, args.copy_ref_mib) if args.copy_ref_mib > 0 else None
+    if copy_ref:
+        log(f"bench: copy reference {copy_ref['gbs']:.0f} GB/s")
     m, n, d, zeta = args.m, args.n, args.d, args.zeta
     log(f"bench: generating workload m={m} n={n} d={d} zeta={zeta} (FP64) on the GPU")
     t0 = time.perf_counter()
@@ -117,16 +342,12 @@ def main():
 
     ms_per_step = 1e3 * elapsed / args.steps
     iters = int(np.median([i["iters"] for i in infos]))
-    # algorithmic bytes: the fused pass reads A once and u once and writes u
-    # once (p, the per-workgroup partials and the state are < 0.3%); the apply
-    # reads A, b and the sketch (zeta int32 + one 64-bit sign word per row)
-    # once and writes Y once
-    pass_bytes = m * n * 8 + 2 * m * 8
-    apply_bytes = m * (n + 1) * 8 + m * (zeta * 4 + 8) + d * (n + 1) * 8
+    pb = pass_bytes(m, n, 8)
+    ab = apply_bytes(m, n, d, zeta, 8, 8)
     pass_avg_ms = ms_pass / max(1, n_pass)
     apply_avg_ms = ms_apply / max(1, n_apply)
-    pass_gbs = pass_bytes / (pass_avg_ms * 1e-3) / 1e9
-    apply_gbs = apply_bytes / (apply_avg_ms * 1e-3) / 1e9
+    pass_gbs = pb / (pass_avg_ms * 1e-3) / 1e9
+    apply_gbs = ab / (apply_avg_ms * 1e-3) / 1e9
 
     # Accuracy of the last solve in the paper's metric, via the normal equations
     # residual computed with plain torch (checker only)
@@ -156,19 +377,33 @@ def main():
                    "m": m, "n": n, "d": d, "zeta": zeta, "tol": tol, "precision": "fp64"},
         "roofline": {"bound": "hbm", "kernel": "lsqr_pass_kernel (fused A p / A^T u pass)",
                      "achieved": pass_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": pass_gbs / HBM_PEAK_GBS,
-                     "traffic": None, "bytes_per_launch": pass_bytes, "avg_launch_ms": pass_avg_ms,
+                     "traffic": None, "bytes_per_launch": pb, "avg_launch_ms": pass_avg_ms,
                      "launches": n_pass},
-        "sa": {"kernel": "apply_lds_kernel", "achieved_gbs": apply_gbs, "frac": apply_gbs / HBM_PEAK_GBS,
-               "bytes_per_launch": apply_bytes, "avg_launch_ms": apply_avg_ms, "launches": n_apply},
+        "sa": {"kernel": "apply_strip_kernel", "achieved_gbs": apply_gbs, "frac": apply_gbs / HBM_PEAK_GBS,
+               "bytes_per_launch": ab, "avg_launch_ms": apply_avg_ms, "launches": n_apply},
         "phases_ms": {"generate": med("t_generate_ms"), "apply": med("t_apply_ms"), "qr": med("t_qr_ms"),
                       "iterate": med("t_iterate_ms")},
         "iters": iters,
         "normal_eq_residual_rel": rel_ne,
+        "copy_reference": copy_ref,
         "cpu_baseline": None,
+        "forms": {},
     }
+    rows = min(args.cpu_sample_rows, m)
+    A_sample, b_sample = A[:rows].cpu().numpy(), b[:rows].cpu().numpy()
+    del A, r_vec
+    torch.cuda.empty_cache()
+    for f in [f for f in args.forms.split(",") if f]:
+        fn = {"mixed": form_mixed, "batched": form_batched, "served": form_served}.get(f)
+        if fn is None:
+            log(f"bench: unknown form {f}")
+            continue
+        t0 = time.perf_counter()
+        out["forms"][f] = fn(args, sap, torch, inputs)
+        log(f"bench: form {f} done in {time.perf_counter() - t0:.1f} s")
     if not args.no_cpu_baseline:
         log("bench: timing the CPU oracle on a row sample")
-        out["cpu_baseline"] = cpu_baseline(A, b, d, zeta, seed, tol, iters, args.cpu_sample_rows)
+        out["cpu_baseline"] = cpu_baseline(A_sample, b_sample, m, d, zeta, seed, tol, iters)
     print(json.dumps(out), flush=True)
 
 

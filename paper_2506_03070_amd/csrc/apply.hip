@@ -1,27 +1,28 @@
 // Sketch apply Y = S [A b] on gfx950 (Alg. 1 "form Y = SA"; the paper calls a
 // library sparse-times-dense product, Sec. 3).
 //
-// Design.  A is streamed from HBM once; every nonzero (i, k) of S adds
-// +-A[i, :] into row idx[i][k] of Y.  Y (d x ncols, column-major) is far
-// larger than one CU's LDS, so each workgroup owns a tile
-// Y[r_lo : r_lo + DR, c0 : c0 + 16] in LDS for its whole life:
-//   * 16 columns = one 128-byte piece of a row of A, so the 16 lanes that
-//     serve one nonzero read one line and add into 16 consecutive LDS
-//     doubles; a wave instruction serves 4 nonzeros and touches every bank
-//     equally (no serialisation beyond the minimum for 512 bytes);
-//   * the rows of Y are split into ranges of DR <= 1250 (FP64) rows so the
-//     tile fits in 160 KB of LDS; a counting-sort pre-pass buckets the
-//     nonzeros by range (kept in ascending-i order within each chunk), so a
-//     workgroup walks only its own nonzeros;
-//   * the workgroups of one column tile (all ranges) sit on the same XCD, so
-//     the pieces of A that several ranges need come from that XCD's L2 after
-//     the first touch;
-//   * when there are too few tiles to fill the chip the nonzeros of a range
-//     are split into slices whose partial tiles a second kernel sums in a
-//     fixed order.
+// Design.  Column j of S has zeta nonzeros, so row i of [A b] is added, with
+// sign, into zeta rows of Y.  A is streamed from HBM once; Y (d x ncols,
+// column-major) does not fit in one CU's LDS, so it is cut into column
+// strips:
+//   * a workgroup owns Y[r_lo : r_lo + DR, c0 : c0 + W] in LDS for its whole
+//     life, W the widest power of two (<= 32) with d * W elements in 160 KB,
+//     so normally DR = d and one strip pass reads each element of A once;
+//   * W lanes serve one row of A: they load its W-element piece once and add
+//     it into the zeta target rows with LDS atomics (ds_add), so a wave
+//     instruction serves 64 / W rows; the zeta row indices are read once per
+//     row (same address for the W lanes: one broadcast);
+//   * the strips that share a cache line of A (consecutive strips) run on the
+//     same XCD, so a line fetched from HBM for one strip serves its
+//     neighbours from that XCD's L2;
+//   * when strips alone do not fill the chip, the rows of A are split into
+//     slices whose partial strips a second kernel sums in a fixed order;
+//   * only when even W = 1 does not fit (d > 20000 in FP64) are the rows of
+//     Y split into ranges, each range skipping the nonzeros outside it.
 // The 1/sqrt(zeta) scale is applied once, after summation.
 #include <hip/hip_bf16.h>
 
+#include <algorithm>
 #include <cmath>
 #include <type_traits>
 
@@ -32,13 +33,11 @@ namespace {
 
 constexpr int kApplyThreads = 1024;
 constexpr int kApplyWaves = kApplyThreads / kWave;
-constexpr int kTileCols = 16;                // columns per tile: one 128-byte row piece
-constexpr int kGroups = kWave / kTileCols;   // nonzeros per wave instruction
-constexpr int kUnroll = 8;                   // nonzeros in flight per lane
-constexpr size_t kApplyLdsBytes = 160000;    // gfx950: up to 160 KB of LDS per workgroup
+constexpr size_t kApplyLdsBytes = 160000;  // gfx950: up to 160 KB of LDS per workgroup
 constexpr int kXcds = 8;
-constexpr int kChunkRows = 8192;             // rows of A per bucketing chunk
-constexpr int kMaxRanges = 64;
+constexpr int kUnroll = 8;                 // rows in flight per lane group
+constexpr int kMaxW = 32;
+constexpr int64_t kMinSliceRows = 4096;
 
 template <typename TA, typename TY>
 __device__ __forceinline__ TY load_as(const TA *p) {
@@ -48,156 +47,111 @@ __device__ __forceinline__ TY load_as(const TA *p) {
     return static_cast<TY>(*p);
 }
 
-// ---- bucketing of the nonzeros by row range of Y (counting sort) ----------
-__global__ __launch_bounds__(256) void bucket_count_kernel(const int32_t *__restrict__ idx, int64_t m, int zeta,
-                                                           int d, int dr, int nranges, int *__restrict__ counts) {
-  __shared__ int hist[kMaxRanges];
-  for (int k = threadIdx.x; k < nranges; k += 256) hist[k] = 0;
-  __syncthreads();
-  const int64_t e0 = static_cast<int64_t>(blockIdx.x) * kChunkRows * zeta;
-  const int64_t e1 = min(m * zeta, e0 + static_cast<int64_t>(kChunkRows) * zeta);
-  for (int64_t e = e0 + threadIdx.x; e < e1; e += 256) {
-    const int r = idx[e];
-    if (static_cast<unsigned>(r) < static_cast<unsigned>(d)) atomicAdd(&hist[r / dr], 1);
-  }
-  __syncthreads();
-  for (int k = threadIdx.x; k < nranges; k += 256) counts[static_cast<int64_t>(blockIdx.x) * nranges + k] = hist[k];
-}
-
-// Exclusive offsets: range-major, chunk-minor.  start[range] = first entry
-// of the range; offs[chunk][range] = first slot of that chunk's entries.
-__global__ void bucket_scan_kernel(const int *__restrict__ counts, int nchunks, int nranges, int64_t *__restrict__ offs,
-                                   int64_t *__restrict__ start) {
-  if (threadIdx.x != 0) return;
-  int64_t pos = 0;
-  for (int r = 0; r < nranges; ++r) {
-    start[r] = pos;
-    for (int c = 0; c < nchunks; ++c) {
-      offs[static_cast<int64_t>(c) * nranges + r] = pos;
-      pos += counts[static_cast<int64_t>(c) * nranges + r];
-    }
-  }
-  start[nranges] = pos;
-}
-
-// Entries are (row i, local row | sign << 31).  Within a chunk the slots of a
-// range are claimed through LDS counters, so chunks are in ascending order of
-// i but the order inside a (chunk, range) run is unspecified (the apply adds
-// with LDS atomics, whose order is unspecified anyway).  Row indices outside
-// [0, d) are ignored here and in the count.
-__global__ __launch_bounds__(256) void bucket_scatter_kernel(const int32_t *__restrict__ idx,
-                                                             const uint64_t *__restrict__ sign, int64_t m, int zeta,
-                                                             int d, int dr, int nranges,
-                                                             const int64_t *__restrict__ offs,
-                                                             uint2 *__restrict__ list) {
-  __shared__ unsigned long long cursor[kMaxRanges];
-  for (int k = threadIdx.x; k < nranges; k += 256) cursor[k] = offs[static_cast<int64_t>(blockIdx.x) * nranges + k];
-  __syncthreads();
-  const int64_t e0 = static_cast<int64_t>(blockIdx.x) * kChunkRows * zeta;
-  const int64_t e1 = min(m * zeta, e0 + static_cast<int64_t>(kChunkRows) * zeta);
-  for (int64_t e = e0 + threadIdx.x; e < e1; e += 256) {
-    const int r = idx[e];
-    if (static_cast<unsigned>(r) >= static_cast<unsigned>(d)) continue;
-    const int rg = r / dr;
-    const int64_t i = e / zeta;
-    const int k = static_cast<int>(e - i * zeta);
-    const unsigned s = static_cast<unsigned>((sign[i] >> k) & 1ull);
-    const unsigned long long pos = atomicAdd(&cursor[rg], 1ull);
-    list[pos] = make_uint2(static_cast<unsigned>(i), static_cast<unsigned>(r - rg * dr) | (s << 31));
-  }
-}
-
-// ---- main kernel ---------------------------------------------------------
-// One work item = (column tile, row range of Y, slice of that range's
-// nonzeros).  BUCKETED: nonzeros come from the bucket list; otherwise (a
-// single range) straight from idx/sign in order.
-template <typename TA, typename TY, bool BUCKETED>
-__global__ __launch_bounds__(kApplyThreads) void apply_tile_kernel(
-    const int32_t *__restrict__ idx, const uint64_t *__restrict__ sign, int zeta, const uint2 *__restrict__ list,
-    const int64_t *__restrict__ start, const TA *__restrict__ A, int64_t lda, const double *__restrict__ b,
-    int64_t m, int n, int ncols, int d, int dr, int ntiles, int nranges, int nslices, TY *__restrict__ out,
-    int64_t ldo, int64_t slice_stride, double h, int scale_now) {
+// One work item = (strip, range, slice).
+// FAST (one range, zeta = 8, idx 16-byte aligned): per row two 16-byte index
+// loads, every load of a batch of rows issued before any add, and no
+// branches: a row past the slice end adds zeros, and an index outside [0, d)
+// adds into a spare LDS row that is never written out.  Otherwise the
+// general path loads the indices four at a time and skips indices outside
+// the range.
+template <typename TA, typename TY, int W, bool FAST>
+__global__ __launch_bounds__(kApplyThreads) void apply_strip_kernel(
+    const int32_t *__restrict__ idx, const uint64_t *__restrict__ sign, int zeta, const TA *__restrict__ A,
+    int64_t lda, const double *__restrict__ b, int64_t m, int n, int ncols, int d, int dr, int nstrips,
+    int nranges, int nslices, int64_t rows_per_slice, TY *__restrict__ out, int64_t ldo, int64_t slice_stride,
+    double h, int scale_now) {
   extern __shared__ unsigned char lds_raw[];
   TY *acc = reinterpret_cast<TY *>(lds_raw);
+  constexpr int RPW = kWave / W;  // rows per wave instruction
 
-  // XCD-aware decode: workgroup IDs are dealt round-robin over the 8 XCDs;
-  // give each XCD a contiguous block of work items (range fastest, then
-  // tile, then slice) so that the ranges of a tile share an L2.
-  const int total = ntiles * nranges * nslices;
+  // XCD-aware decode: workgroup IDs are dealt round-robin over the XCDs;
+  // each XCD gets a contiguous block of work items, strip fastest.
+  const int total = nstrips * nranges * nslices;
   const int per_xcd = (total + kXcds - 1) / kXcds;
   const int w = (blockIdx.x % kXcds) * per_xcd + blockIdx.x / kXcds;
   if (w >= total) return;
-  const int range = w % nranges;
-  const int tile = (w / nranges) % ntiles;
-  const int slice = w / (nranges * ntiles);
-  const int c0 = tile * kTileCols;
+  const int strip = w % nstrips;
+  const int range = (w / nstrips) % nranges;
+  const int slice = w / (nstrips * nranges);
+  const int c0 = strip * W;
   const int r_lo = range * dr;
   const int rows_here = min(dr, d - r_lo);
 
-  for (int e = threadIdx.x; e < rows_here * kTileCols; e += kApplyThreads) acc[e] = TY(0);
+  for (int e = threadIdx.x; e < (rows_here + (FAST ? 1 : 0)) * W; e += kApplyThreads) acc[e] = TY(0);
   __syncthreads();
 
-  int64_t e_begin, e_end;
-  if constexpr (BUCKETED) {
-    e_begin = start[range];
-    e_end = start[range + 1];
-  } else {
-    e_begin = 0;
-    e_end = m * zeta;
-  }
-  const int64_t cnt = e_end - e_begin;
-  const int64_t per_slice = (cnt + nslices - 1) / nslices;
-  const int64_t s_begin = e_begin + min(cnt, per_slice * slice);
-  const int64_t s_end = e_begin + min(cnt, per_slice * (slice + 1));
-
+  const int64_t i_begin = static_cast<int64_t>(slice) * rows_per_slice;
+  const int64_t i_end = min(m, i_begin + rows_per_slice);
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-  const int g = lane / kTileCols, c = lane % kTileCols;
+  const int g = lane / W, c = lane % W;
   const int col = c0 + c;
   const bool col_a = col < n;
   const bool col_b = (col == n) && (col < ncols);
-  constexpr int kStride = kApplyWaves * kGroups * kUnroll;  // nonzeros per workgroup round
-  for (int64_t base = s_begin + wave * (kGroups * kUnroll); base < s_end; base += kStride) {
-    TY val[kUnroll];
-    int rloc[kUnroll];
+  constexpr int64_t kStride = static_cast<int64_t>(kApplyWaves) * RPW * kUnroll;
+  for (int64_t base = i_begin + wave * (RPW * kUnroll) + g; base < i_end; base += kStride) {
+    if constexpr (FAST) {
+      TY val[kUnroll];
+      uint32_t sg[kUnroll];
+      int4 ix[kUnroll][2];
 #pragma unroll
-    for (int u = 0; u < kUnroll; ++u) {
-      const int64_t e = base + u * kGroups + g;
-      rloc[u] = -1;
-      val[u] = TY(0);
-      if (e < s_end) {
-        int64_t i;
-        int r;
-        bool plus;
-        if constexpr (BUCKETED) {
-          const uint2 en = list[e];
-          i = en.x;
-          r = static_cast<int>(en.y & 0x7fffffffu);
-          plus = (en.y >> 31) != 0;
-        } else {
-          i = e / zeta;
-          const int k = static_cast<int>(e - i * zeta);
-          r = idx[e];
-          plus = ((sign[i] >> k) & 1ull) != 0;
-        }
+      for (int u = 0; u < kUnroll; ++u) {
+        const int64_t i0 = base + u * RPW;
+        const bool ok = i0 < i_end;
+        const int64_t i = ok ? i0 : i_end - 1;
         TY a = TY(0);
         if (col_a) a = load_as<TA, TY>(A + i * lda + col);
         else if (col_b) a = static_cast<TY>(b[i]);
-        val[u] = plus ? a : -a;
-        rloc[u] = static_cast<unsigned>(r) < static_cast<unsigned>(rows_here) ? r : -1;
+        val[u] = ok ? a : TY(0);
+        sg[u] = static_cast<uint32_t>(sign[i]);
+        const int4 *ip = reinterpret_cast<const int4 *>(idx + i * 8);
+        ix[u][0] = ip[0];
+        ix[u][1] = ip[1];
+      }
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        const int rr[8] = {ix[u][0].x, ix[u][0].y, ix[u][0].z, ix[u][0].w,
+                           ix[u][1].x, ix[u][1].y, ix[u][1].z, ix[u][1].w};
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          const int r = static_cast<unsigned>(rr[k]) < static_cast<unsigned>(d) ? rr[k] : d;
+          const TY v = ((sg[u] >> k) & 1u) ? val[u] : -val[u];
+          atomicAdd(acc + r * W + c, v);
+        }
+      }
+    } else {
+#pragma unroll 2
+      for (int u = 0; u < kUnroll; ++u) {
+        const int64_t i = base + u * RPW;
+        if (i >= i_end) break;
+        TY a = TY(0);
+        if (col_a) a = load_as<TA, TY>(A + i * lda + col);
+        else if (col_b) a = static_cast<TY>(b[i]);
+        const uint64_t sg = sign[i];
+        const int32_t *ri = idx + i * zeta;
+        for (int k0 = 0; k0 < zeta; k0 += 4) {
+          int rr[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) rr[q] = (k0 + q < zeta) ? ri[k0 + q] : -1;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int r = rr[q] - r_lo;
+            if (rr[q] >= 0 && static_cast<unsigned>(r) < static_cast<unsigned>(rows_here)) {
+              const TY v = ((sg >> (k0 + q)) & 1ull) ? a : -a;
+              atomicAdd(acc + r * W + c, v);
+            }
+          }
+        }
       }
     }
-#pragma unroll
-    for (int u = 0; u < kUnroll; ++u)
-      if (rloc[u] >= 0) atomicAdd(acc + rloc[u] * kTileCols + c, val[u]);
   }
   __syncthreads();
 
   const TY scale = scale_now ? TY(h) : TY(1);
   TY *dst = out + static_cast<int64_t>(slice) * slice_stride;
-  for (int e = threadIdx.x; e < rows_here * kTileCols; e += kApplyThreads) {
+  for (int e = threadIdx.x; e < rows_here * W; e += kApplyThreads) {
     const int q = e / rows_here, r = e % rows_here;
     const int cc = c0 + q;
-    if (cc < ncols) dst[(r_lo + r) + static_cast<int64_t>(cc) * ldo] = acc[r * kTileCols + q] * scale;
+    if (cc < ncols) dst[(r_lo + r) + static_cast<int64_t>(cc) * ldo] = acc[r * W + q] * scale;
   }
 }
 
@@ -216,60 +170,63 @@ __global__ __launch_bounds__(256) void apply_reduce_kernel(const TY *__restrict_
 }
 
 struct ApplyPlan {
-  int dr, ntiles, nranges, nslices, nchunks;
-  bool bucketed;
+  int w, dr, nstrips, nranges, nslices;
+  int64_t rows_per_slice;
 };
 
-ApplyPlan make_plan(int num_cus, int64_t m, int zeta, int d, int ncols, size_t esize) {
+ApplyPlan make_plan(int num_cus, int64_t m, int d, int ncols, size_t esize) {
   ApplyPlan p{};
-  const int dr_max = static_cast<int>(kApplyLdsBytes / (esize * kTileCols));
-  p.nranges = (d + dr_max - 1) / dr_max;
-  p.dr = (d + p.nranges - 1) / p.nranges;
-  p.ntiles = (ncols + kTileCols - 1) / kTileCols;
-  p.bucketed = p.nranges > 1;
-  p.nchunks = static_cast<int>((m + kChunkRows - 1) / kChunkRows);
-  const int items = p.ntiles * p.nranges;
-  // One resident workgroup per CU (the tile fills most of the LDS).  Split
-  // the nonzeros of a range into slices only when there are too few items
-  // to fill the chip, keeping at least 64K nonzeros per slice.
+  // columns of a full-height strip (plus one spare row)
+  const size_t fit = kApplyLdsBytes / (esize * (static_cast<size_t>(d) + 1));
+  int w = 1;
+  while (w * 2 <= kMaxW && static_cast<size_t>(w * 2) <= fit) w *= 2;
+  // no wider than the matrix needs
+  while (w > 1 && w / 2 >= ncols) w /= 2;
+  p.w = w;
+  if (fit >= 1) {
+    p.nranges = 1;
+    p.dr = d;
+  } else {
+    const int dr_max = static_cast<int>(kApplyLdsBytes / esize) - 1;  // plus the spare row
+    p.nranges = (d + dr_max - 1) / dr_max;
+    p.dr = (d + p.nranges - 1) / p.nranges;
+  }
+  p.nstrips = (ncols + w - 1) / w;
+  // One resident workgroup per CU when the strip fills the LDS; split the
+  // rows into slices when the strips alone leave CUs idle.
+  const int items = p.nstrips * p.nranges;
   int ns = 1;
   if (items < num_cus) ns = (num_cus + items - 1) / items;
-  const int64_t nnz_per_range = m * zeta / p.nranges;
-  const int64_t max_slices = (nnz_per_range + 65535) / 65536;
-  if (ns > max_slices) ns = static_cast<int>(max_slices < 1 ? 1 : max_slices);
-  p.nslices = ns;
+  const int64_t max_slices = std::max<int64_t>(1, m / kMinSliceRows);
+  if (ns > max_slices) ns = static_cast<int>(max_slices);
+  p.rows_per_slice = (m + ns - 1) / ns;
+  p.nslices = static_cast<int>((m + p.rows_per_slice - 1) / p.rows_per_slice);
+  if (p.nslices < 1) p.nslices = 1;
   return p;
 }
 
-size_t bucket_bytes(const ApplyPlan &p, int64_t m, int zeta) {
-  if (!p.bucketed) return 0;
-  return 4 * 256 + sizeof(uint2) * static_cast<size_t>(m) * zeta +
-         (sizeof(int) + sizeof(int64_t)) * static_cast<size_t>(p.nchunks) * p.nranges +
-         sizeof(int64_t) * (p.nranges + 1);
+template <typename TA, typename TY, int W>
+void launch_strip(const ApplyPlan &p, dim3 grid, size_t lds, hipStream_t st, const sps_sketch *S, const TA *A,
+                  int64_t lda, const double *b, int n, int ncols, TY *out, int64_t ldo, int64_t slice_stride,
+                  double h, int scale_now) {
+  const bool fast = S->zeta == 8 && p.nranges == 1 && (reinterpret_cast<uintptr_t>(S->idx) % 16 == 0);
+  if (fast)
+    apply_strip_kernel<TA, TY, W, true><<<grid, kApplyThreads, lds, st>>>(
+        S->idx, S->sign, S->zeta, A, lda, b, S->m, n, ncols, S->d, p.dr, p.nstrips, p.nranges, p.nslices,
+        p.rows_per_slice, out, ldo, slice_stride, h, scale_now);
+  else
+    apply_strip_kernel<TA, TY, W, false><<<grid, kApplyThreads, lds, st>>>(
+        S->idx, S->sign, S->zeta, A, lda, b, S->m, n, ncols, S->d, p.dr, p.nstrips, p.nranges, p.nslices,
+        p.rows_per_slice, out, ldo, slice_stride, h, scale_now);
 }
 
 template <typename TA, typename TY>
 sap_status apply_typed(sap_ctx *ctx, const sps_sketch *S, const TA *A, int64_t lda, const double *b, int n, TY *Y,
                        int64_t ldy, void *work, hipStream_t st) {
   const int ncols = n + (b != nullptr ? 1 : 0);
-  const ApplyPlan p = make_plan(ctx->num_cus, S->m, S->zeta, S->d, ncols, sizeof(TY));
-  if (p.nranges > kMaxRanges) return fail(ctx, SAP_EINVAL, "sps_apply: d too large");
-  if (p.bucketed && S->m > static_cast<int64_t>(UINT32_MAX)) return fail(ctx, SAP_EINVAL, "sps_apply: m >= 2^32");
+  const ApplyPlan p = make_plan(ctx->num_cus, S->m, S->d, ncols, sizeof(TY));
   const double h = 1.0 / std::sqrt(static_cast<double>(S->zeta));
   Carve cv(work);
-  uint2 *list = nullptr;
-  int64_t *start = nullptr;
-  if (p.bucketed) {
-    list = cv.take<uint2>(static_cast<size_t>(S->m) * S->zeta);
-    int *counts = cv.take<int>(static_cast<size_t>(p.nchunks) * p.nranges);
-    int64_t *offs = cv.take<int64_t>(static_cast<size_t>(p.nchunks) * p.nranges);
-    start = cv.take<int64_t>(p.nranges + 1);
-    bucket_count_kernel<<<p.nchunks, 256, 0, st>>>(S->idx, S->m, S->zeta, S->d, p.dr, p.nranges, counts);
-    bucket_scan_kernel<<<1, 64, 0, st>>>(counts, p.nchunks, p.nranges, offs, start);
-    bucket_scatter_kernel<<<p.nchunks, 256, 0, st>>>(S->idx, S->sign, S->m, S->zeta, S->d, p.dr, p.nranges, offs,
-                                                      list);
-    SAP_HIP_TRY(hipGetLastError());
-  }
   TY *out = Y;
   int64_t ldo = ldy, slice_stride = 0;
   int scale_now = 1;
@@ -279,18 +236,18 @@ sap_status apply_typed(sap_ctx *ctx, const sps_sketch *S, const TA *A, int64_t l
     slice_stride = static_cast<int64_t>(S->d) * ncols;
     scale_now = 0;
   }
-  const int total = p.ntiles * p.nranges * p.nslices;
+  const int total = p.nstrips * p.nranges * p.nslices;
   const int per_xcd = (total + kXcds - 1) / kXcds;
   const dim3 grid(static_cast<unsigned>(per_xcd * kXcds));
-  const size_t lds = static_cast<size_t>(p.dr) * kTileCols * sizeof(TY);
-  if (p.bucketed)
-    apply_tile_kernel<TA, TY, true><<<grid, kApplyThreads, lds, st>>>(
-        S->idx, S->sign, S->zeta, list, start, A, lda, b, S->m, n, ncols, S->d, p.dr, p.ntiles, p.nranges,
-        p.nslices, out, ldo, slice_stride, h, scale_now);
-  else
-    apply_tile_kernel<TA, TY, false><<<grid, kApplyThreads, lds, st>>>(
-        S->idx, S->sign, S->zeta, list, start, A, lda, b, S->m, n, ncols, S->d, p.dr, p.ntiles, p.nranges,
-        p.nslices, out, ldo, slice_stride, h, scale_now);
+  const size_t lds = (static_cast<size_t>(p.dr) + 1) * p.w * sizeof(TY);
+  switch (p.w) {
+    case 1: launch_strip<TA, TY, 1>(p, grid, lds, st, S, A, lda, b, n, ncols, out, ldo, slice_stride, h, scale_now); break;
+    case 2: launch_strip<TA, TY, 2>(p, grid, lds, st, S, A, lda, b, n, ncols, out, ldo, slice_stride, h, scale_now); break;
+    case 4: launch_strip<TA, TY, 4>(p, grid, lds, st, S, A, lda, b, n, ncols, out, ldo, slice_stride, h, scale_now); break;
+    case 8: launch_strip<TA, TY, 8>(p, grid, lds, st, S, A, lda, b, n, ncols, out, ldo, slice_stride, h, scale_now); break;
+    case 16: launch_strip<TA, TY, 16>(p, grid, lds, st, S, A, lda, b, n, ncols, out, ldo, slice_stride, h, scale_now); break;
+    default: launch_strip<TA, TY, 32>(p, grid, lds, st, S, A, lda, b, n, ncols, out, ldo, slice_stride, h, scale_now); break;
+  }
   SAP_HIP_TRY(hipGetLastError());
   if (p.nslices > 1) {
     const int64_t tot = static_cast<int64_t>(S->d) * ncols;
@@ -304,9 +261,10 @@ sap_status apply_typed(sap_ctx *ctx, const sps_sketch *S, const TA *A, int64_t l
 }  // namespace
 
 size_t apply_workspace_bytes(sap_ctx *ctx, int64_t m, int zeta, int d, int ncols, sap_dtype y_type) {
+  (void)zeta;
   const size_t es = (y_type == SAP_F64) ? 8 : 4;
-  const ApplyPlan p = make_plan(ctx->num_cus, m, zeta, d, ncols, es);
-  size_t bytes = 8 * 256 + bucket_bytes(p, m, zeta);
+  const ApplyPlan p = make_plan(ctx->num_cus, m, d, ncols, es);
+  size_t bytes = 8 * 256;
   if (p.nslices > 1) bytes += static_cast<size_t>(p.nslices) * d * ncols * es;
   return bytes;
 }

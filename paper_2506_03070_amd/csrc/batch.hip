@@ -106,38 +106,69 @@ __global__ __launch_bounds__(kBThreads) void batch_apply_kernel(const BatchItem 
   const int c0 = wk.y * kTileColsB;
   const int d = it.d, n = it.n, ncols = it.n + 1, zeta = it.zeta;
   const TA *__restrict__ A = static_cast<const TA *>(it.A);
-  for (int e = threadIdx.x; e < d * kTileColsB; e += kBThreads) acc[e] = TY(0);
+  for (int e = threadIdx.x; e < (d + 1) * kTileColsB; e += kBThreads) acc[e] = TY(0);
   __syncthreads();
+  // One row of [A b] per group of 16 lanes: its 16-column piece is loaded
+  // once and added into the zeta target rows; all loads of a batch of rows
+  // are issued before the adds.
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  constexpr int RPW = kWave / kTileColsB;  // rows per wave instruction
   const int g = lane / kTileColsB, c = lane % kTileColsB;
   const int col = c0 + c;
   const bool col_a = col < n, col_b = col == n;
-  const int64_t nnz = it.m * zeta;
+  const int64_t m = it.m;
   constexpr int U = 8;
-  constexpr int64_t kStride = static_cast<int64_t>(kBWaves) * 4 * U;
-  for (int64_t base = static_cast<int64_t>(wave) * 4 * U; base < nnz; base += kStride) {
-    TY val[U];
-    int rloc[U];
+  constexpr int64_t kStride = static_cast<int64_t>(kBWaves) * RPW * U;
+  const bool fast = zeta == 8 && (reinterpret_cast<uintptr_t>(it.idx) % 16 == 0);
+  for (int64_t base = static_cast<int64_t>(wave) * RPW * U + g; base < m; base += kStride) {
+    if (fast) {
+      TY val[U];
+      uint32_t sg[U];
+      int4 ix[U][2];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int64_t e = base + u * 4 + g;
-      rloc[u] = -1;
-      val[u] = TY(0);
-      if (e < nnz) {
-        const int64_t i = e / zeta;
-        const int k = static_cast<int>(e - i * zeta);
-        const int r = it.idx[e];
-        const bool plus = ((it.sign[i] >> k) & 1ull) != 0;
+      for (int u = 0; u < U; ++u) {
+        const int64_t i0 = base + u * RPW;
+        const bool ok = i0 < m;
+        const int64_t i = ok ? i0 : m - 1;
         TY a = TY(0);
         if (col_a) a = static_cast<TY>(A[i * it.lda + col]);
         else if (col_b) a = static_cast<TY>(it.b[i]);
-        val[u] = plus ? a : -a;
-        rloc[u] = static_cast<unsigned>(r) < static_cast<unsigned>(d) ? r : -1;
+        val[u] = ok ? a : TY(0);
+        sg[u] = static_cast<uint32_t>(it.sign[i]);
+        const int4 *ip = reinterpret_cast<const int4 *>(it.idx + i * 8);
+        ix[u][0] = ip[0];
+        ix[u][1] = ip[1];
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int rr[8] = {ix[u][0].x, ix[u][0].y, ix[u][0].z, ix[u][0].w,
+                           ix[u][1].x, ix[u][1].y, ix[u][1].z, ix[u][1].w};
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          const int r = static_cast<unsigned>(rr[k]) < static_cast<unsigned>(d) ? rr[k] : d;  // spare row
+          atomicAdd(acc + r * kTileColsB + c, ((sg[u] >> k) & 1u) ? val[u] : -val[u]);
+        }
+      }
+    } else {
+      for (int u = 0; u < U; ++u) {
+        const int64_t i = base + u * RPW;
+        if (i >= m) break;
+        TY a = TY(0);
+        if (col_a) a = static_cast<TY>(A[i * it.lda + col]);
+        else if (col_b) a = static_cast<TY>(it.b[i]);
+        const uint64_t sg = it.sign[i];
+        const int32_t *ri = it.idx + i * zeta;
+        for (int k0 = 0; k0 < zeta; k0 += 4) {
+          int rr[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) rr[q] = (k0 + q < zeta) ? ri[k0 + q] : -1;
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            if (static_cast<unsigned>(rr[q]) < static_cast<unsigned>(d))
+              atomicAdd(acc + rr[q] * kTileColsB + c, ((sg >> (k0 + q)) & 1ull) ? a : -a);
+        }
       }
     }
-#pragma unroll
-    for (int u = 0; u < U; ++u)
-      if (rloc[u] >= 0) atomicAdd(acc + rloc[u] * kTileColsB + c, val[u]);
   }
   __syncthreads();
   TY *Ysk = static_cast<TY *>(it.Ysk);
@@ -569,7 +600,7 @@ sap_status setup_items(sap_ctx *ctx, BatchItem *ditems, const std::vector<BatchI
   else batch_generate_kernel<64><<<grid, 256, 0, st>>>(ditems, count, total_cols, dflags + 2);
   const size_t ya = (at == SAP_F32) ? 4 : 8;
   const int per_xcd = (napply + kXcdsB - 1) / kXcdsB;
-  const size_t lds = static_cast<size_t>(d_max) * kTileColsB * ya;
+  const size_t lds = static_cast<size_t>(d_max + 1) * kTileColsB * ya;  // plus a spare row
   if (at == SAP_F32) {
     batch_apply_kernel<float, float><<<per_xcd * kXcdsB, kBThreads, lds, st>>>(ditems, dapply, napply);
     batch_widen_kernel<<<dim3(64, count), 256, 0, st>>>(ditems);
@@ -621,7 +652,7 @@ sap_status run_batch(sap_ctx *ctx, int count, const sap_problem *probs, const sa
     if (q.d < p.n + 1 || q.zeta < 1 || q.zeta > 64 || q.zeta > q.d || q.maxiter < 0 || !(q.tol >= 0.0))
       return fail(ctx, SAP_EINVAL, "sap_solve_batch: bad parameters");
     const size_t es = (at == SAP_F32) ? 4 : 8;
-    if (static_cast<size_t>(q.d) * 16 * es > 160000 || q.d > 4096)
+    if (static_cast<size_t>(q.d + 1) * 16 * es > 160000 || q.d > 4096)
       return fail(ctx, SAP_EINVAL, "sap_solve_batch: d too large for the batched form");
     n_max = std::max(n_max, p.n);
     maxiter_max = std::max(maxiter_max, q.maxiter);
@@ -1197,7 +1228,7 @@ sap_status serve_submit(sap_ctx *ctx, const sap_problem *p, const sap_params *q,
   if (p->n < 1 || p->n > 1024 || p->m < static_cast<int64_t>(p->n) + 1 || p->lda < p->n || p->m > (int64_t(1) << 31))
     return fail(ctx, SAP_EINVAL, "sap_submit: bad problem shape (n <= 1024, m >= n + 1)");
   const size_t es = (p->a_type == SAP_F32) ? 4 : 8;
-  if (q->d < p->n + 1 || q->d > 4096 || static_cast<size_t>(q->d) * 16 * es > 160000 || q->zeta < 1 || q->zeta > 64 ||
+  if (q->d < p->n + 1 || q->d > 4096 || static_cast<size_t>(q->d + 1) * 16 * es > 160000 || q->zeta < 1 || q->zeta > 64 ||
       q->zeta > q->d || q->maxiter < 0 || !(q->tol >= 0.0))
     return fail(ctx, SAP_EINVAL, "sap_submit: bad parameters");
   const size_t bytes = item_bytes(p->m, p->n, q->d, q->zeta, p->a_type);

@@ -61,7 +61,7 @@ __device__ __forceinline__ void lower_epilogue(int n, int G, const double *__res
   if (beta > 0.0) {
     double part = 0.0;
     for (int c = t; c < n; c += kTrsvThreads) {
-      const double vh = y[c] / beta - (init ? 0.0 : beta * v[c]);
+      const double vh = load_coherent(y + c) / beta - (init ? 0.0 : beta * v[c]);
       y[c] = vh;
       part += vh * vh;
     }
@@ -90,7 +90,7 @@ __device__ __forceinline__ void upper_epilogue(int n, const double *p, double *_
   if (init) {
     // beta_1 u_1 = b - A x0, alpha_1 v_1 = M^T A^T u_1, w_1 = M v_1
     if (proceed)
-      for (int c = t; c < n; c += kTrsvThreads) w[c] = p[c];
+      for (int c = t; c < n; c += kTrsvThreads) w[c] = load_coherent(p + c);
     if (t == 0) {
       st->init = 0;
       st->phibar = beta;
@@ -122,7 +122,7 @@ __device__ __forceinline__ void upper_epilogue(int n, const double *p, double *_
   for (int c = t; c < n; c += kTrsvThreads) {
     const double wc = w[c];
     x[c] += fx * wc;
-    if (proceed) w[c] = p[c] - fw * wc;
+    if (proceed) w[c] = load_coherent(p + c) - fw * wc;
   }
   if (t == 0) {
     st->iter += 1;

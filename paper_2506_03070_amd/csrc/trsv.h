@@ -32,10 +32,24 @@ sap_status trsv_solve(sap_ctx *ctx, const TrsvFactor &f, bool upper, const doubl
 
 constexpr int kSpinLimit = 1 << 24;
 
+// Cross-workgroup hand-off without whole-cache maintenance.  The solution
+// entries and the flags are written and read with agent-scope relaxed
+// atomics, which the gfx950 memory model makes coherent across the XCDs
+// per access (no L2 writeback or invalidate).  Ordering: a producer waits
+// until its own entry stores have completed (s_waitcnt vmcnt(0)) before it
+// stores the flag; a consumer issues its entry loads only after its flag
+// load has returned the awaited epoch.
+__device__ __forceinline__ void store_coherent(double *p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double load_coherent(const double *p) {
+  return __hip_atomic_load(const_cast<double *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 __device__ __forceinline__ void wait_flag(const int *flag, int epoch, int *err) {
   if (threadIdx.x == 0) {
     int spins = 0;
-    while (__hip_atomic_load(flag, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < epoch) {
+    while (__hip_atomic_load(const_cast<int *>(flag), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < epoch) {
       __builtin_amdgcn_s_sleep(1);
       if (++spins > kSpinLimit) {
         atomicOr(err, 2);
@@ -44,13 +58,13 @@ __device__ __forceinline__ void wait_flag(const int *flag, int epoch, int *err) 
     }
   }
   __syncthreads();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
 }
 
+// Every wave calls this after its coherent stores; thread 0 then raises the flag.
 __device__ __forceinline__ void publish_flag(int *flag, int epoch) {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   __syncthreads();
-  if (threadIdx.x == 0) __hip_atomic_store(flag, epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  if (threadIdx.x == 0) __hip_atomic_store(flag, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Solve for block b of the chain; rb (LDS, kTrsvB doubles) holds the
@@ -78,7 +92,7 @@ __device__ __forceinline__ void chain_block(const double *__restrict__ M, int64_
 #pragma unroll
     for (int k = 0; k < kTrsvCols; ++k) {
       const int col = j * kTrsvB + g + kTrsvGroups * k;
-      const double zc = col < n ? z[col] : 0.0;
+      const double zc = col < n ? load_coherent(z + col) : 0.0;
       acc += mv[k] * zc;
     }
   }
@@ -107,7 +121,7 @@ __device__ __forceinline__ void chain_block(const double *__restrict__ M, int64_
 #pragma unroll
     for (int q = 0; q < kTrsvGroups; ++q) s += red[q * kTrsvB + t];
     rb[t] = s;
-    if (row < n) z[row] = s;
+    if (row < n) store_coherent(z + row, s);
   }
   publish_flag(&flags[b], epoch);
 }

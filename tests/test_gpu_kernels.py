@@ -168,8 +168,9 @@ def test_apply_ignores_out_of_range_rows(sap, orc):
 
 
 # ----------------------------------------------------------------- QR -----
+# rows > 4096 with cols > 192 takes the two-level (64-column panel, WY trailing update) path
 QR_CASES = [(400, 101), (4000, 1001), (1000, 1000), (5, 3), (700, 1), (2500, 64), (8192, 130), (16384, 40),
-            (513, 100), (1100, 17)]
+            (513, 100), (1100, 17), (8192, 600), (5000, 257), (700, 259), (300, 300), (193, 193)]
 
 
 @pytest.mark.parametrize("rows,cols", QR_CASES)
