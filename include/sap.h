@@ -55,12 +55,14 @@ typedef enum sap_dtype { SAP_F64 = 0, SAP_F32 = 1, SAP_BF16 = 2 } sap_dtype;
 
 /* Precision forms of sap_solve.  FP64: A and every step in double.
  * MIXED_FP32: A stored in FP32 (the problem is the FP32 matrix, whose
- * elements are exact in FP64); the sketch S [A b] is accumulated in FP32 (the
- * preconditioner only has to be approximate), widened to FP64 for the QR;
- * the LSQR passes read the FP32 A and widen each element, so products,
- * accumulation, u, the triangular solves and the recurrences are FP64.  The
+ * elements are exact in FP64).  The sketch apply and the LSQR passes read the
+ * FP32 A and widen each element, so the sketch, the QR, the products and
+ * accumulations, u, the preconditioner and the recurrences are FP64.  The
  * passes, which dominate the run time, move half the bytes of the FP64 form
- * and reach the same FP64 stopping test, with no refinement loop. */
+ * and reach the same FP64 stopping test, with no refinement loop.  (An FP32
+ * sketch is available through sps_apply; it perturbs the preconditioner of an
+ * ill-conditioned A enough to cost extra iterations, so sap_solve does not
+ * use it.) */
 typedef enum sap_mode { SAP_MODE_FP64 = 0, SAP_MODE_MIXED_FP32 = 1 } sap_mode;
 
 typedef struct sap_ctx sap_ctx;

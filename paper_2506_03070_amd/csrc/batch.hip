@@ -362,11 +362,8 @@ __global__ __launch_bounds__(kBThreads) void batch_pass_kernel(const BatchItem *
       for (int j = 0; j < KJ; ++j) {
         const int c = (sub + L * j) * VEC;
         if (rv && vec_ok && c + VEC <= n) {
-          const auto v = *reinterpret_cast<const typename std::conditional<
-              std::is_same<TA, float>::value,
-              typename std::conditional<VEC == 4, float4, float2>::type,
-              typename std::conditional<VEC == 2, double2, double>::type>::type *>(arow + c);
-          const TA *vv = reinterpret_cast<const TA *>(&v);
+          TA vv[VEC];
+          load_stream<TA, VEC>(arow + c, vv);
 #pragma unroll
           for (int e = 0; e < VEC; ++e) a[uu][j][e] = static_cast<double>(vv[e]);
         } else {
@@ -544,7 +541,7 @@ size_t item_bytes(int64_t m, int n, int d, int zeta, sap_dtype at) {
   b += 4 * (256 + sizeof(double) * n);
   b += 256 + sizeof(double) * gmax * n;
   b += 256 + sizeof(double) * gmax;
-  return b + 256;
+  return (b + 256 + 255) / 256 * 256;  // a multiple of 256: consecutive items stay aligned
 }
 
 // Fill the workspace pointers of `it` from memory at `base`.
@@ -668,7 +665,7 @@ sap_status run_batch(sap_ctx *ctx, int count, const sap_problem *probs, const sa
   const bool have_tune = tit != g_tune_rows.end();
   if (have_tune) rows_per_chunk = tit->second;
   std::vector<size_t> need(count);
-  size_t total = 8 * 256 + sizeof(BatchItem) * count;
+  size_t total = 8 * 256 + sizeof(BatchItem) * count + static_cast<size_t>(count) * 256;
   int64_t total_chunks_max = 0;
   for (int k = 0; k < count; ++k) {
     need[k] = item_bytes(probs[k].m, probs[k].n, par[k].d, par[k].zeta, at);

@@ -99,6 +99,22 @@ __device__ __forceinline__ double block_sum(double v, double *scratch, int nwave
 
 // Device-resident LSQR state.  All recurrence scalars stay on the device so
 // that an iteration needs no host round trip.
+// Streaming load of V consecutive elements (16 bytes or fewer) with the
+// nontemporal hint: data read once per pass should not displace what the
+// caches hold for reuse.  On gfx950 a read-only stream reaches ~90% of the
+// HBM peak this way, ~80% with ordinary loads.
+template <typename T, int V>
+__device__ __forceinline__ void load_stream(const T *p, T (&out)[V]) {
+  if constexpr (V == 1) {
+    out[0] = __builtin_nontemporal_load(p);
+  } else {
+    typedef T vec_t __attribute__((ext_vector_type(V)));
+    const vec_t v = __builtin_nontemporal_load(reinterpret_cast<const vec_t *>(p));
+#pragma unroll
+    for (int e = 0; e < V; ++e) out[e] = v[e];
+  }
+}
+
 struct LsqrState {
   double alpha, beta, rhobar, phibar;
   double c_ap, c_u;           // next pass computes u <- c_ap * (A p) + c_u * u

@@ -50,11 +50,6 @@ struct PassTypes<1> {
   using TA = float; using TC = double; using TUI = double; using TUO = double;
 };
 
-template <typename T, int V>
-struct alignas(sizeof(T) * V) VecT {
-  T e[V];
-};
-
 // WC waves split the columns of a row (64*VEC*J columns each); WR = 16/WC
 // row groups share the workgroup.
 template <int MODE, int VEC, int J, int WC>
@@ -106,9 +101,10 @@ __global__ __launch_bounds__(kPassThreads) void lsqr_pass_kernel(
       for (int j = 0; j < J; ++j) {
         const int c = col0 + (j * kWave + lane) * VEC;
         if (rv && c < n) {
-          const VecT<TA, VEC> v = *reinterpret_cast<const VecT<TA, VEC> *>(arow + c);
+          TA v[VEC];
+          load_stream<TA, VEC>(arow + c, v);
 #pragma unroll
-          for (int e = 0; e < VEC; ++e) a[r][j][e] = v.e[e];
+          for (int e = 0; e < VEC; ++e) a[r][j][e] = v[e];
         } else {
 #pragma unroll
           for (int e = 0; e < VEC; ++e) a[r][j][e] = TA(0);
@@ -194,37 +190,205 @@ __global__ __launch_bounds__(kPassThreads) void lsqr_pass_kernel(
 }
 
 // --------------------------------------------------------------------------
-// Kernel 2: y = R^-T q, then v_hat = y/beta - beta v, alpha, v.
-__global__ __launch_bounds__(kTrsvThreads) void lsqr_lower_kernel(
-    const double *__restrict__ Rt, int n, const double *__restrict__ Dlo, const double *__restrict__ qpart, int G,
-    const double *__restrict__ nrmpart, double *y, double *__restrict__ v, LsqrState *st, int *flags, int *err) {
-  __shared__ LowerShared sh;
-  if (st->done) return;
-  const int nblk = (n + kTrsvB - 1) / kTrsvB;
-  const int b = blockIdx.x;
-  const int epoch = st->steps + 1;
-  reduce_q_block(qpart, G, n, b, sh);
-  chain_block<false>(Rt, n, n, Dlo, y, flags, epoch, b, sh.rb, sh.red, err);
-  if (b != nblk - 1) return;
-  lower_epilogue(n, G, nrmpart, y, v, st, sh);
+// Explicit preconditioner M = R^-1 (the paper's choice, Sec. 3.2).  Formed
+// once per solve; each iteration then applies M^T and M as wide GEMVs over
+// the whole GPU instead of two chains of dependent triangular blocks.
+
+// Upper triangle of M (n x n, column-major, ld n) by blocked back
+// substitution of R X = I: for the C columns c of this workgroup (all in
+// diagonal block jb), X_jb = D_jb (the inverted diagonal block) and, for
+// ib = jb-1 .. 0, X_ib = -D_ib sum_{kb > ib} R_{ib,kb} X_kb.  The columns
+// being built live in LDS; R and the D blocks are read from memory.
+template <int C>
+__global__ __launch_bounds__(256) void tri_inverse_kernel(const double *__restrict__ R, int64_t ldr, int n,
+                                                          const double *__restrict__ Dup, double *__restrict__ M) {
+  extern __shared__ unsigned char lds_raw[];
+  double *X = reinterpret_cast<double *>(lds_raw);  // X[k + q * n], q < C
+  __shared__ double Ts[kTrsvB][C + 1];
+  constexpr int G = C < 4 ? C : 4;  // column groups
+  constexpr int CPT = C / G;        // columns per thread
+  const int t = threadIdx.x;
+  const int r = t % kTrsvB, cg = t / kTrsvB;
+  const int c0 = blockIdx.x * C;
+  const int jb = c0 / kTrsvB;
+  const int kend = min(n, (jb + 1) * kTrsvB);
+  for (int ib = jb; ib >= 0; --ib) {
+    const int row = ib * kTrsvB + r;
+    if (ib < jb && cg < G) {
+      double acc[CPT];
+#pragma unroll
+      for (int q = 0; q < CPT; ++q) acc[q] = 0.0;
+      if (row < n) {
+        // eight independent loads of R in flight per thread
+        int k = (ib + 1) * kTrsvB;
+        for (; k + 8 <= kend; k += 8) {
+          double a[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) a[u] = R[row + static_cast<int64_t>(k + u) * ldr];
+#pragma unroll
+          for (int u = 0; u < 8; ++u)
+#pragma unroll
+            for (int q = 0; q < CPT; ++q) acc[q] += a[u] * X[k + u + (cg * CPT + q) * n];
+        }
+        for (; k < kend; ++k) {
+          const double a = R[row + static_cast<int64_t>(k) * ldr];
+#pragma unroll
+          for (int q = 0; q < CPT; ++q) acc[q] += a * X[k + (cg * CPT + q) * n];
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < CPT; ++q) Ts[r][cg * CPT + q] = acc[q];
+    }
+    __syncthreads();
+    const double *D = Dup + static_cast<int64_t>(ib) * kTrsvB * kTrsvB;
+    if (cg < G) {
+#pragma unroll
+      for (int q = 0; q < CPT; ++q) {
+        const int ql = cg * CPT + q;
+        const int c = c0 + ql;
+        double x = 0.0;
+        if (ib == jb) {
+          x = D[r + (c - jb * kTrsvB) * kTrsvB];
+        } else {
+          for (int qq = 0; qq < kTrsvB; ++qq) x -= D[r + qq * kTrsvB] * Ts[qq][ql];
+        }
+        if (row < n && c < n) X[row + ql * n] = x;
+      }
+    }
+    __syncthreads();
+  }
+  // write the columns out (rows 0 .. end of block jb; the rest of M's column
+  // lies below the diagonal and is never read)
+  for (int e = t; e < kend * C; e += 256) {
+    const int k = e % kend, ql = e / kend;
+    const int c = c0 + ql;
+    if (c < n) M[k + static_cast<int64_t>(c) * n] = X[k + ql * n];
+  }
 }
 
-// Kernel 3: p = R^-1 v, then the plane rotation and the x, w updates.
-__global__ __launch_bounds__(kTrsvThreads) void lsqr_upper_kernel(
-    const double *__restrict__ R, int64_t ldr, int n, const double *__restrict__ Dup, const double *__restrict__ v,
-    double *p, double *__restrict__ w, double *__restrict__ x, LsqrState *st, int *flags, int *err) {
-  __shared__ LowerShared sh;
+__global__ __launch_bounds__(256) void inverse_transpose_kernel(const double *__restrict__ M, int n,
+                                                                double *__restrict__ Mt) {
+  __shared__ double tile[32][33];
+  trsv_transpose_tile(M, n, n, static_cast<int>(blockIdx.x), static_cast<int>(blockIdx.y), Mt, tile);
+}
+
+// q = sum over the pass partials, in two fixed-order levels: this kernel sums
+// slice s (kQSlice consecutive partials) for 64 columns; the GEMV kernels sum
+// the slices.
+constexpr int kQSlice = 64;
+__global__ __launch_bounds__(256) void q_slices_kernel(const double *__restrict__ qpart, int G, int n,
+                                                       double *__restrict__ qs) {
+  __shared__ double red[4][64];
+  const int t = threadIdx.x;
+  const int cl = t % 64, sub = t / 64;
+  const int c = blockIdx.x * 64 + cl;
+  const int g0 = blockIdx.y * kQSlice;
+  const int g1 = min(G, g0 + kQSlice);
+  double s = 0.0;
+  if (c < n)
+    for (int g = g0 + sub; g < g1; g += 4) s += qpart[static_cast<int64_t>(g) * n + c];
+  red[sub][cl] = s;
+  __syncthreads();
+  if (sub == 0 && c < n) qs[static_cast<int64_t>(blockIdx.y) * n + c] = red[0][cl] + red[1][cl] + red[2][cl] + red[3][cl];
+}
+
+// beta = ||u_hat|| from the pass partials (fixed order, every workgroup the same).
+__device__ __forceinline__ double beta_from_partials(const double *__restrict__ nrmpart, int G, double *scr) {
+  double bsq = 0.0;
+  for (int g = threadIdx.x; g < G; g += 1024) bsq += nrmpart[g];
+  return sqrt(wg_sum(bsq, scr));
+}
+
+// v_hat = M^T q / beta - beta v (Alg. 2 in the App. D.4.1 order); one wave per
+// entry j (column j of M, rows 0..j); per-workgroup partials of ||v_hat||^2.
+__global__ __launch_bounds__(1024) void lsqr_mtq_kernel(const double *__restrict__ M, int n,
+                                                        const double *__restrict__ qs, int nslices,
+                                                        const double *__restrict__ nrmpart, int G,
+                                                        const double *__restrict__ v, double *__restrict__ vh,
+                                                        double *__restrict__ vpart, const LsqrState *st) {
+  __shared__ double scr[16];
+  __shared__ double q[kMaxN];
+  __shared__ double wsum[16];
   if (st->done) return;
-  const int nblk = (n + kTrsvB - 1) / kTrsvB;
-  const int b = nblk - 1 - static_cast<int>(blockIdx.x);
-  const int epoch = st->steps + 1;
-  if (threadIdx.x < kTrsvB) {
-    const int row = b * kTrsvB + threadIdx.x;
-    sh.rb[threadIdx.x] = row < n ? v[row] : 0.0;
+  const double beta = beta_from_partials(nrmpart, G, scr);
+  const int t = threadIdx.x;
+  for (int c = t; c < n; c += 1024) {
+    double a = 0.0;
+    for (int s = 0; s < nslices; ++s) a += qs[static_cast<int64_t>(s) * n + c];
+    q[c] = a;
   }
   __syncthreads();
-  chain_block<true>(R, ldr, n, Dup, p, flags, epoch, b, sh.rb, sh.red, err);
-  if (b != 0) return;
+  const int lane = t & (kWave - 1), wave = t / kWave;
+  const int j = blockIdx.x * 16 + wave;
+  double sq = 0.0;
+  if (j < n) {
+    const double *__restrict__ col = M + static_cast<int64_t>(j) * n;
+    double acc = 0.0;
+    for (int k = lane; k <= j; k += kWave) acc += col[k] * q[k];
+    acc = wave_sum_u(acc);
+    const double vhj = beta > 0.0 ? acc / beta - (st->init ? 0.0 : beta * v[j]) : 0.0;
+    if (lane == 0) vh[j] = vhj;
+    sq = vhj * vhj;
+  }
+  if (lane == 0) wsum[wave] = sq;
+  __syncthreads();
+  if (t == 0) {
+    double a = 0.0;
+    for (int w = 0; w < 16; ++w) a += wsum[w];
+    vpart[blockIdx.x] = a;
+  }
+}
+
+// alpha = ||v_hat||, v = v_hat / alpha, p = M v; one wave per entry r (row r
+// of M = column r of M^T, rows r..n-1).  Workgroup 0 records beta, alpha.
+__global__ __launch_bounds__(1024) void lsqr_mv_kernel(const double *__restrict__ Mt, int n,
+                                                       const double *__restrict__ vh, const double *__restrict__ vpart,
+                                                       int nvpart, const double *__restrict__ nrmpart, int G,
+                                                       double *__restrict__ v, double *__restrict__ p,
+                                                       LsqrState *st) {
+  __shared__ double scr[16];
+  __shared__ double vs[kMaxN];
+  if (st->done) return;
+  const double beta = beta_from_partials(nrmpart, G, scr);
+  const int t = threadIdx.x;
+  double asq = 0.0;
+  for (int k = t; k < nvpart; k += 1024) asq += vpart[k];
+  const double alpha = beta > 0.0 ? sqrt(wg_sum(asq, scr)) : 0.0;
+  const bool proceed = beta > 0.0 && alpha > 0.0;
+  if (!proceed) {
+    if (blockIdx.x == 0 && t == 0) {
+      st->beta_new = beta;
+      st->alpha_new = alpha;
+      st->proceed = 0;
+    }
+    return;
+  }
+  const double ia = 1.0 / alpha;
+  for (int c = t; c < n; c += 1024) vs[c] = vh[c] * ia;
+  __syncthreads();
+  const int lane = t & (kWave - 1), wave = t / kWave;
+  const int rr = blockIdx.x * 16 + wave;
+  if (rr < n) {
+    const double *__restrict__ col = Mt + static_cast<int64_t>(rr) * n;
+    double acc = 0.0;
+    for (int k = rr + lane; k < n; k += kWave) acc += col[k] * vs[k];
+    acc = wave_sum_u(acc);
+    if (lane == 0) {
+      p[rr] = acc;
+      v[rr] = vs[rr];
+    }
+  }
+  if (blockIdx.x == 0 && t == 0) {
+    st->beta_new = beta;
+    st->alpha_new = alpha;
+    st->proceed = 1;
+  }
+}
+
+// Plane rotation, x and w updates, stopping test (one workgroup).
+__global__ __launch_bounds__(kTrsvThreads) void lsqr_update_kernel(const double *p, double *__restrict__ w,
+                                                                   double *__restrict__ x, int n, LsqrState *st) {
+  if (st->done) return;
   upper_epilogue(n, p, w, x, st, nullptr);
 }
 
@@ -400,9 +564,12 @@ size_t lsqr_workspace_bytes(sap_ctx *ctx, int64_t m, int n) {
   size_t bytes = 256 * 32;                                // alignment slack
   bytes += sizeof(LsqrState);
   bytes += G * n * sizeof(double) + G * sizeof(double);  // partials
-  bytes += 6 * static_cast<size_t>(n) * sizeof(double);  // y v w p x0copy
+  bytes += 6 * static_cast<size_t>(n) * sizeof(double);  // v w p x0copy (+1 spare)
   bytes += static_cast<size_t>(m) * sizeof(double);     // u
   bytes += (3 * nblk + 16) * sizeof(int) + 4096 * sizeof(double);                  // flags, err, norm partials
+  bytes += 2 * static_cast<size_t>(n) * n * sizeof(double);                        // M = R^-1 and M^T
+  bytes += (static_cast<size_t>((G + kQSlice - 1) / kQSlice) + 2) * n * sizeof(double);  // q slices, v_hat
+  bytes += static_cast<size_t>((n + 15) / 16 + 1) * sizeof(double);                // ||v_hat||^2 partials
   bytes += trsv_factor_bytes(n);
   return bytes;
 }
@@ -446,17 +613,23 @@ sap_status run_lsqr(sap_ctx *ctx, const sap_problem *prob, const double *R, int6
   if (plan.grid > max_grid(ctx)) return fail(ctx, SAP_EINVAL, "LSQR: internal grid larger than planned");
   double *qpart = cv.take<double>(static_cast<size_t>(max_grid(ctx)) * n);
   double *nrmpart = cv.take<double>(max_grid(ctx));
-  double *y = cv.take<double>(n);
   double *v = cv.take<double>(n);
   double *w = cv.take<double>(n);
   double *p = cv.take<double>(n);
   double *xin = cv.take<double>(n);
   double *u = cv.take<double>(m);
   int *flags = cv.take<int>(3 * nblk + 2);
-  int *flags_lo = flags, *flags_up = flags + nblk, *flags_x0 = flags + 2 * nblk;
+  int *flags_x0 = flags + 2 * nblk;
   int *err = cv.take<int>(4);
   unsigned int *ticket = reinterpret_cast<unsigned int *>(err + 1);
   double *normpart = cv.take<double>(4096);
+  const int nslices = (max_grid(ctx) + kQSlice - 1) / kQSlice;
+  double *M = cv.take<double>(static_cast<size_t>(n) * n);
+  double *Mt = cv.take<double>(static_cast<size_t>(n) * n);
+  double *qs = cv.take<double>(static_cast<size_t>(nslices) * n);
+  double *vh = cv.take<double>(n);
+  const int ngemv = (n + 15) / 16;
+  double *vpart = cv.take<double>(ngemv);
   TrsvFactor f;
   trsv_factor_carve(f, cv, n);
 
@@ -472,18 +645,36 @@ sap_status run_lsqr(sap_ctx *ctx, const sap_problem *prob, const double *R, int6
     copy_f64_kernel<<<(n + 255) / 256, 256, 0, s>>>(x0, xin, n);
     copy_f64_kernel<<<(n + 255) / 256, 256, 0, s>>>(xin, x, n);
   }
+  // M = R^-1 and its transpose (the columns a workgroup builds sit in LDS)
+  {
+    const unsigned nt = static_cast<unsigned>((n + 31) / 32);
+    if (n <= 1170)
+      tri_inverse_kernel<16><<<(n + 15) / 16, 256, 16 * static_cast<size_t>(n) * 8, s>>>(R, ldr, n, f.Dup, M);
+    else if (n <= 2340)
+      tri_inverse_kernel<8><<<(n + 7) / 8, 256, 8 * static_cast<size_t>(n) * 8, s>>>(R, ldr, n, f.Dup, M);
+    else if (n <= 4680)
+      tri_inverse_kernel<4><<<(n + 3) / 4, 256, 4 * static_cast<size_t>(n) * 8, s>>>(R, ldr, n, f.Dup, M);
+    else
+      tri_inverse_kernel<2><<<(n + 1) / 2, 256, 2 * static_cast<size_t>(n) * 8, s>>>(R, ldr, n, f.Dup, M);
+    inverse_transpose_kernel<<<dim3(nt, nt), 256, 0, s>>>(M, n, Mt);
+    SAP_HIP_TRY(hipGetLastError());
+  }
   lsqr_init_state_kernel<<<1, 256, 0, s>>>(st, tol, maxiter, flags, 2 * nblk);
   const int ngrid = static_cast<int>(std::min<int64_t>(256, (m + 1023) / 1024));
   norm_kernel<<<ngrid, 1024, 0, s>>>(prob->b, m, normpart, ticket, st);
   SAP_HIP_TRY(hipGetLastError());
 
-  // One iteration = pass over A, lower solve (+ v update), upper solve (+ x,
-  // w update and the stopping test).
+  // One iteration = pass over A; q from the pass partials; v_hat = M^T q /
+  // beta - beta v; alpha, v, p = M v; rotation, x and w updates and the
+  // stopping test.
+  const int G = plan.grid;
+  const int qsl = (G + kQSlice - 1) / kQSlice;
   auto iteration = [&](const void *pv, const void *uin) {
     launch_pass(ctx, plan, prob->A, prob->lda, m, n, pv, uin, u, st, qpart, nrmpart, s);
-    lsqr_lower_kernel<<<nblk, kTrsvThreads, 0, s>>>(f.Rt, n, f.Dlo, qpart, plan.grid, nrmpart, y, v, st, flags_lo,
-                                                    err);
-    lsqr_upper_kernel<<<nblk, kTrsvThreads, 0, s>>>(R, ldr, n, f.Dup, v, p, w, x, st, flags_up, err);
+    q_slices_kernel<<<dim3((n + 63) / 64, qsl), 256, 0, s>>>(qpart, G, n, qs);
+    lsqr_mtq_kernel<<<ngemv, 1024, 0, s>>>(M, n, qs, qsl, nrmpart, G, v, vh, vpart, st);
+    lsqr_mv_kernel<<<ngemv, 1024, 0, s>>>(Mt, n, vh, vpart, ngemv, nrmpart, G, v, p, st);
+    lsqr_update_kernel<<<1, kTrsvThreads, 0, s>>>(p, w, x, n, st);
   };
 
   // Initialisation: beta_1 u_1 = b - A x0 (the pass with p = x, u_in = b).
