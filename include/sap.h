@@ -193,10 +193,10 @@ sap_status sap_lsqr(sap_ctx *ctx, const sap_problem *prob, const double *R, int6
  * problem has met its own stopping test or its maxiter.  probs, params, x and
  * info are host arrays of `count` entries; x[k] is a device pointer to n_k
  * doubles.  All problems share one A dtype (F32 or F64); each has its own m,
- * n, d, zeta, seed, tol and maxiter (mode is ignored).  The sketch of problem k uses Philox stream word k.  The passes
- * over A accumulate in FP64 whatever A's storage type.  Limits: n <= 1024,
- * d <= 4096 and (d + 1) * 16 * sizeof(A element) <= 160000 (the sketch tile of a
- * workgroup lives in LDS), m < 2^31.  Blocking.  Returns SAP_OK when every
+ * n, d, zeta, seed, tol and maxiter (mode is ignored).  The sketch of
+ * problem k uses Philox stream word k.  The sketch apply and the passes over
+ * A compute in FP64 whatever A's storage type.  Limits: n <= 1024,
+ * d <= 4096 (a strip of the sketch lives in LDS), m < 2^31.  Blocking.  Returns SAP_OK when every
  * problem converged, SAP_NOT_CONVERGED when some did not or were rank
  * deficient (per-problem status in info[k].status); SAP_EINVAL, SAP_ENOMEM,
  * SAP_EDEVICE as for sap_solve. */

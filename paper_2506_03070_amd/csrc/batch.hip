@@ -54,8 +54,7 @@ struct BatchItem {
   int64_t col_base;  // prefix of m over the problems (sketch columns)
   int32_t *idx;
   uint64_t *sign;
-  void *Ysk;         // sketch accumulator (FP32 or FP64), d x (n+1)
-  double *Y;         // FP64 sketch for the QR, d x (n+1)
+  double *Y;         // FP64 sketch, d x (n+1), factored in place
   double *tau, *T0, *T1;
   double *Rt, *Dup, *Dlo;
   int *flags;        // 3 * nblk: lower, upper, x0
@@ -73,7 +72,7 @@ using namespace qr_dev;
 
 constexpr int kBThreads = 1024;
 constexpr int kBWaves = kBThreads / kWave;
-constexpr int kTileColsB = 16;
+constexpr size_t kBatchLds = 160000;  // LDS bytes for the sketch strip of one workgroup
 constexpr int kXcdsB = 8;
 
 // ---- generate --------------------------------------------------------------
@@ -93,9 +92,13 @@ __global__ __launch_bounds__(256) void batch_generate_kernel(const BatchItem *__
 }
 
 // ---- apply -----------------------------------------------------------------
-template <typename TA, typename TY>
+// Work item = (problem, strip of W columns); the strip of Y (d + 1 spare
+// rows by W columns) is accumulated in FP64 in LDS.
+template <typename TA, int W>
 __global__ __launch_bounds__(kBThreads) void batch_apply_kernel(const BatchItem *__restrict__ items,
                                                                 const int2 *__restrict__ work, int nwork) {
+  using TY = double;
+  constexpr int kTileColsB = W;
   extern __shared__ unsigned char lds_raw[];
   TY *acc = reinterpret_cast<TY *>(lds_raw);
   const int per_xcd = (nwork + kXcdsB - 1) / kXcdsB;
@@ -171,21 +174,13 @@ __global__ __launch_bounds__(kBThreads) void batch_apply_kernel(const BatchItem 
     }
   }
   __syncthreads();
-  TY *Ysk = static_cast<TY *>(it.Ysk);
+  double *Y = it.Y;
   const TY hs = static_cast<TY>(it.h);
   for (int e = threadIdx.x; e < d * kTileColsB; e += kBThreads) {
     const int q = e / d, r = e % d;
     const int cc = c0 + q;
-    if (cc < ncols) Ysk[r + static_cast<int64_t>(cc) * d] = acc[r * kTileColsB + q] * hs;
+    if (cc < ncols) Y[r + static_cast<int64_t>(cc) * d] = acc[r * kTileColsB + q] * hs;
   }
-}
-
-__global__ __launch_bounds__(256) void batch_widen_kernel(const BatchItem *__restrict__ items) {
-  const BatchItem &it = items[blockIdx.y];
-  const int64_t tot = static_cast<int64_t>(it.d) * (it.n + 1);
-  const float *src = static_cast<const float *>(it.Ysk);
-  for (int64_t e = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; e < tot; e += static_cast<int64_t>(gridDim.x) * 256)
-    it.Y[e] = static_cast<double>(src[e]);
 }
 
 // ---- QR ----------------------------------------------------------------------
@@ -314,10 +309,13 @@ __global__ __launch_bounds__(kTrsvThreads) void batch_x0_kernel(const BatchItem 
 // at most 64, chosen per problem), so a wavefront handles 64/L rows at once.
 // u <- c_ap (A p) + c_u u_in with FP64 accumulation; q += u_i A[i, :].
 // At the initialisation step (st->init) the pass reads u_in = b and p = x.
-template <typename TA, int VEC, int KJ>
+// p sits in LDS (read per element), q in registers; the waves' q partials
+// are combined through one LDS vector in wave order.
+template <typename TA, int VEC, int KJ, int U>
 __global__ __launch_bounds__(kBThreads) void batch_pass_kernel(const BatchItem *__restrict__ items,
                                                                const int2 *__restrict__ work, int nwork, int tune) {
-  __shared__ double qsh[kBWaves][64 * VEC * KJ];
+  __shared__ double psh[64 * VEC * KJ];
+  __shared__ double qacc[64 * VEC * KJ];
   __shared__ double nsh[kBWaves];
   const int2 wk = work[blockIdx.x];
   const BatchItem &it = items[wk.x];
@@ -338,21 +336,22 @@ __global__ __launch_bounds__(kBThreads) void batch_pass_kernel(const BatchItem *
   const int64_t lda = it.lda;
   const bool vec_ok = (VEC > 1);
 
-  double preg[KJ][VEC], q[KJ][VEC];
+  for (int c = threadIdx.x; c < 64 * VEC * KJ; c += kBThreads) {
+    psh[c] = c < n ? pv[c] : 0.0;
+    qacc[c] = 0.0;
+  }
+  __syncthreads();
+  double q[KJ][VEC];
 #pragma unroll
   for (int j = 0; j < KJ; ++j)
 #pragma unroll
-    for (int e = 0; e < VEC; ++e) {
-      const int c = (sub + L * j) * VEC + e;
-      preg[j][e] = c < n ? pv[c] : 0.0;
-      q[j][e] = 0.0;
-    }
+    for (int e = 0; e < VEC; ++e) q[j][e] = 0.0;
   const int64_t r0 = static_cast<int64_t>(wk.y) * it.rows_per_chunk;
   const int64_t r1 = min(it.m, r0 + it.rows_per_chunk);
   double nrm = 0.0;
-  constexpr int U = 2;
   for (int64_t base = r0 + static_cast<int64_t>(wave) * RS * U; base < r1; base += static_cast<int64_t>(kBWaves) * RS * U) {
-    double a[U][KJ][VEC];
+    TA a[U][KJ][VEC];
+    double ui[U];
 #pragma unroll
     for (int uu = 0; uu < U; ++uu) {
       const int64_t row = base + uu * RS + slot;
@@ -362,15 +361,13 @@ __global__ __launch_bounds__(kBThreads) void batch_pass_kernel(const BatchItem *
       for (int j = 0; j < KJ; ++j) {
         const int c = (sub + L * j) * VEC;
         if (rv && vec_ok && c + VEC <= n) {
-          TA vv[VEC];
-          load_stream<TA, VEC>(arow + c, vv);
-#pragma unroll
-          for (int e = 0; e < VEC; ++e) a[uu][j][e] = static_cast<double>(vv[e]);
+          load_stream<TA, VEC>(arow + c, a[uu][j]);
         } else {
 #pragma unroll
-          for (int e = 0; e < VEC; ++e) a[uu][j][e] = (rv && c + e < n) ? static_cast<double>(arow[c + e]) : 0.0;
+          for (int e = 0; e < VEC; ++e) a[uu][j][e] = (rv && c + e < n) ? __builtin_nontemporal_load(arow + c + e) : TA(0);
         }
       }
+      ui[uu] = rv ? uin[row] : 0.0;
     }
 #pragma unroll
     for (int uu = 0; uu < U; ++uu) {
@@ -379,14 +376,14 @@ __global__ __launch_bounds__(kBThreads) void batch_pass_kernel(const BatchItem *
 #pragma unroll
       for (int j = 0; j < KJ; ++j)
 #pragma unroll
-        for (int e = 0; e < VEC; ++e) s += a[uu][j][e] * preg[j][e];
+        for (int e = 0; e < VEC; ++e) s += static_cast<double>(a[uu][j][e]) * psh[(sub + L * j) * VEC + e];
       for (int off = L >> 1; off >= 1; off >>= 1) s += __shfl_xor(s, off, kWave);
       if (row < r1) {
-        const double uh = c_ap * s + c_u * uin[row];
+        const double uh = c_ap * s + c_u * ui[uu];
 #pragma unroll
         for (int j = 0; j < KJ; ++j)
 #pragma unroll
-          for (int e = 0; e < VEC; ++e) q[j][e] += uh * a[uu][j][e];
+          for (int e = 0; e < VEC; ++e) q[j][e] += uh * static_cast<double>(a[uu][j][e]);
         if (sub == 0) {
           if (!tune) uout[row] = uh;
           nrm += uh * uh;
@@ -403,21 +400,19 @@ __global__ __launch_bounds__(kBThreads) void batch_pass_kernel(const BatchItem *
       for (int off = L; off < kWave; off <<= 1) v += __shfl_xor(v, off, kWave);
       q[j][e] = v;
     }
-  if (slot == 0) {
-#pragma unroll
-    for (int j = 0; j < KJ; ++j)
-#pragma unroll
-      for (int e = 0; e < VEC; ++e) qsh[wave][(sub + L * j) * VEC + e] = q[j][e];
-  }
   nrm = wave_sum(nrm);
   if (lane == 0) nsh[wave] = nrm;
-  __syncthreads();
-  double *qdst = it.qpart + static_cast<int64_t>(wk.y) * n;
-  for (int c = threadIdx.x; c < n; c += kBThreads) {
-    double s = 0.0;
-    for (int w = 0; w < kBWaves; ++w) s += qsh[w][c];
-    qdst[c] = s;
+  for (int w = 0; w < kBWaves; ++w) {
+    if (wave == w && slot == 0) {
+#pragma unroll
+      for (int j = 0; j < KJ; ++j)
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) qacc[(sub + L * j) * VEC + e] += q[j][e];
+    }
+    __syncthreads();
   }
+  double *qdst = it.qpart + static_cast<int64_t>(wk.y) * n;
+  for (int c = threadIdx.x; c < n; c += kBThreads) qdst[c] = qacc[c];
   if (threadIdx.x == 0) {
     double s = 0.0;
     for (int w = 0; w < kBWaves; ++w) s += nsh[w];
@@ -489,21 +484,24 @@ struct PassChoice {
   int vec, kj;
 };
 
+// E = KJ * VEC elements of a row per lane: 8 while the widest problem has
+// at most 512 columns, else 16; a problem of n columns puts L = n/E lanes
+// (rounded up to a power of two) on a row, so a wavefront works on 64/L rows
+// at once.
+// U = row groups in flight per lane, as many as the registers allow without
+// spilling (the per-element loads of an unaligned row each need an address).
 template <typename TA>
 PassChoice pick_batch_pass(int n_max, bool aligned) {
   constexpr int vmax = 16 / static_cast<int>(sizeof(TA));
-  const int vec = aligned ? vmax : 1;
-  const int per = 64 * vec;
-  const int kj = (n_max + per - 1) / per;
-  if (vec == 1) {
-    if (kj <= 1) return {reinterpret_cast<const void *>(&batch_pass_kernel<TA, 1, 1>), 1, 1};
-    if (kj <= 2) return {reinterpret_cast<const void *>(&batch_pass_kernel<TA, 1, 2>), 1, 2};
-    if (kj <= 4) return {reinterpret_cast<const void *>(&batch_pass_kernel<TA, 1, 4>), 1, 4};
-    return {reinterpret_cast<const void *>(&batch_pass_kernel<TA, 1, 16>), 1, 16};
+  constexpr bool f32 = sizeof(TA) == 4;
+  if (n_max <= 512) {
+    if (aligned)
+      return {reinterpret_cast<const void *>(&batch_pass_kernel<TA, vmax, 8 / vmax, f32 ? 4 : 2>), vmax, 8 / vmax};
+    return {reinterpret_cast<const void *>(&batch_pass_kernel<TA, 1, 8, 2>), 1, 8};
   }
-  if (kj <= 1) return {reinterpret_cast<const void *>(&batch_pass_kernel<TA, vmax, 1>), vmax, 1};
-  if (kj <= 2) return {reinterpret_cast<const void *>(&batch_pass_kernel<TA, vmax, 2>), vmax, 2};
-  return {reinterpret_cast<const void *>(&batch_pass_kernel<TA, vmax, 4>), vmax, 4};
+  if (aligned)
+    return {reinterpret_cast<const void *>(&batch_pass_kernel<TA, vmax, 16 / vmax, f32 ? 2 : 1>), vmax, 16 / vmax};
+  return {reinterpret_cast<const void *>(&batch_pass_kernel<TA, 1, 16, 1>), 1, 16};
 }
 
 void launch_pass_fn(const void *fn, const BatchItem *items, const int2 *work, int nwork, int tune, hipStream_t st) {
@@ -519,19 +517,26 @@ void launch_pass_fn(const void *fn, const BatchItem *items, const int2 *work, in
 // ----------------------------------------------------------------------------
 // Shared pieces of the batched and served forms.
 
+// Strip width of the batched sketch apply: the widest power of two (4..32)
+// whose FP64 strip of d_max + 1 rows fits in the LDS budget.
+int batch_apply_width(int d_max) {
+  int w = 32;
+  while (w > 4 && static_cast<size_t>(d_max + 1) * w * sizeof(double) > kBatchLds) w /= 2;
+  return w;
+}
+
 // Bytes of one problem's workspace (rows_per_chunk >= kMinRowsPerChunk).
 constexpr int64_t kMinRowsPerChunk = 1024;
 
 size_t item_bytes(int64_t m, int n, int d, int zeta, sap_dtype at) {
-  const size_t ya = (at == SAP_F32) ? 4 : 8;
+  (void)at;
   const int nc = n + 1;
   const int nblk = (n + kTrsvB - 1) / kTrsvB;
   const int64_t gmax = (m + kMinRowsPerChunk - 1) / kMinRowsPerChunk;
   size_t b = 0;
   b += 256 + sizeof(int32_t) * m * zeta;
   b += 256 + sizeof(uint64_t) * m;
-  b += 256 + ya * d * nc;
-  b += (at == SAP_F32 ? 256 + sizeof(double) * d * nc : 0);
+  b += 256 + sizeof(double) * d * nc;
   b += 3 * (256 + sizeof(double) * 256);
   b += 256 + sizeof(double) * n * n;
   b += 2 * (256 + sizeof(double) * nblk * kTrsvB * kTrsvB);
@@ -552,9 +557,8 @@ void carve_item(BatchItem &it, void *base, sap_dtype at, int64_t rows_per_chunk)
   it.nblk = (n + kTrsvB - 1) / kTrsvB;
   it.idx = cv.take<int32_t>(static_cast<size_t>(m) * it.zeta);
   it.sign = cv.take<uint64_t>(m);
-  it.Ysk = (at == SAP_F32) ? static_cast<void *>(cv.take<float>(static_cast<size_t>(d) * nc))
-                           : static_cast<void *>(cv.take<double>(static_cast<size_t>(d) * nc));
-  it.Y = (at == SAP_F32) ? cv.take<double>(static_cast<size_t>(d) * nc) : static_cast<double *>(it.Ysk);
+  (void)at;
+  it.Y = cv.take<double>(static_cast<size_t>(d) * nc);
   it.tau = cv.take<double>(256);
   it.T0 = cv.take<double>(256);
   it.T1 = cv.take<double>(256);
@@ -595,14 +599,24 @@ sap_status setup_items(sap_ctx *ctx, BatchItem *ditems, const std::vector<BatchI
   else if (zeta_max <= 16) batch_generate_kernel<16><<<grid, 256, 0, st>>>(ditems, count, total_cols, dflags + 2);
   else if (zeta_max <= 32) batch_generate_kernel<32><<<grid, 256, 0, st>>>(ditems, count, total_cols, dflags + 2);
   else batch_generate_kernel<64><<<grid, 256, 0, st>>>(ditems, count, total_cols, dflags + 2);
-  const size_t ya = (at == SAP_F32) ? 4 : 8;
   const int per_xcd = (napply + kXcdsB - 1) / kXcdsB;
-  const size_t lds = static_cast<size_t>(d_max + 1) * kTileColsB * ya;  // plus a spare row
+  const int w = batch_apply_width(d_max);
+  const size_t lds = static_cast<size_t>(d_max + 1) * w * sizeof(double);  // plus a spare row
+  const dim3 ag(static_cast<unsigned>(per_xcd * kXcdsB));
   if (at == SAP_F32) {
-    batch_apply_kernel<float, float><<<per_xcd * kXcdsB, kBThreads, lds, st>>>(ditems, dapply, napply);
-    batch_widen_kernel<<<dim3(64, count), 256, 0, st>>>(ditems);
+    switch (w) {
+      case 32: batch_apply_kernel<float, 32><<<ag, kBThreads, lds, st>>>(ditems, dapply, napply); break;
+      case 16: batch_apply_kernel<float, 16><<<ag, kBThreads, lds, st>>>(ditems, dapply, napply); break;
+      case 8: batch_apply_kernel<float, 8><<<ag, kBThreads, lds, st>>>(ditems, dapply, napply); break;
+      default: batch_apply_kernel<float, 4><<<ag, kBThreads, lds, st>>>(ditems, dapply, napply); break;
+    }
   } else {
-    batch_apply_kernel<double, double><<<per_xcd * kXcdsB, kBThreads, lds, st>>>(ditems, dapply, napply);
+    switch (w) {
+      case 32: batch_apply_kernel<double, 32><<<ag, kBThreads, lds, st>>>(ditems, dapply, napply); break;
+      case 16: batch_apply_kernel<double, 16><<<ag, kBThreads, lds, st>>>(ditems, dapply, napply); break;
+      case 8: batch_apply_kernel<double, 8><<<ag, kBThreads, lds, st>>>(ditems, dapply, napply); break;
+      default: batch_apply_kernel<double, 4><<<ag, kBThreads, lds, st>>>(ditems, dapply, napply); break;
+    }
   }
   SAP_HIP_TRY(hipGetLastError());
   const int sh = (d_max + kPanelThreads - 1) / kPanelThreads;
@@ -649,8 +663,7 @@ sap_status run_batch(sap_ctx *ctx, int count, const sap_problem *probs, const sa
     if (q.d < p.n + 1 || q.zeta < 1 || q.zeta > 64 || q.zeta > q.d || q.maxiter < 0 || !(q.tol >= 0.0))
       return fail(ctx, SAP_EINVAL, "sap_solve_batch: bad parameters");
     const size_t es = (at == SAP_F32) ? 4 : 8;
-    if (static_cast<size_t>(q.d + 1) * 16 * es > 160000 || q.d > 4096)
-      return fail(ctx, SAP_EINVAL, "sap_solve_batch: d too large for the batched form");
+    if (q.d > 4096) return fail(ctx, SAP_EINVAL, "sap_solve_batch: d > 4096 is not supported by the batched form");
     n_max = std::max(n_max, p.n);
     maxiter_max = std::max(maxiter_max, q.maxiter);
     const int vm = 16 / static_cast<int>(es);
@@ -672,7 +685,10 @@ sap_status run_batch(sap_ctx *ctx, int count, const sap_problem *probs, const sa
     total += need[k];
     total_chunks_max += (probs[k].m + kMinRowsPerChunk - 1) / kMinRowsPerChunk;
   }
-  const int tiles_max = (n_max + 1 + 15) / 16;
+  int d_max = 0;
+  for (int k = 0; k < count; ++k) d_max = std::max(d_max, par[k].d);
+  const int aw = batch_apply_width(d_max);
+  const int tiles_max = (n_max + 1 + aw - 1) / aw;
   total += 256 + sizeof(int2) * (total_chunks_max + 16);
   total += 256 + sizeof(int2) * (static_cast<size_t>(count) * tiles_max + 16);
   sap_status s = ensure_workspace(ctx, total, user_stream);
@@ -710,7 +726,7 @@ sap_status run_batch(sap_ctx *ctx, int count, const sap_problem *probs, const sa
   // work tables
   std::vector<int2> apply_work;
   for (int k = 0; k < count; ++k) {
-    const int tiles = (items[k].n + 1 + 15) / 16;
+    const int tiles = (items[k].n + 1 + aw - 1) / aw;
     for (int t = 0; t < tiles; ++t) apply_work.push_back(make_int2(k, t));
   }
   auto pass_table = [&](int64_t rpc_) {
@@ -997,13 +1013,16 @@ hipError_t serve_round(Server *S, std::vector<ServeRequest *> &fresh) {
     std::vector<BatchItem> items(fresh.size());
     std::vector<int2> apply_work;
     int64_t col_base = 0;
+    int d_max = 0;
+    for (ServeRequest *r : fresh) d_max = std::max(d_max, r->item.d);
+    const int aw = batch_apply_width(d_max);
     for (size_t k = 0; k < fresh.size(); ++k) {
       ServeRequest *r = fresh[k];
       BatchItem &it = r->item;
       it.col_base = col_base;
       col_base += it.m;
       items[k] = it;
-      const int tiles = (it.n + 1 + 15) / 16;
+      const int tiles = (it.n + 1 + aw - 1) / aw;
       for (int t = 0; t < tiles; ++t) apply_work.push_back(make_int2(static_cast<int>(k), t));
     }
     if (static_cast<int>(apply_work.size()) > kServeMaxApply) return hipErrorInvalidValue;
@@ -1224,8 +1243,7 @@ sap_status serve_submit(sap_ctx *ctx, const sap_problem *p, const sap_params *q,
   if (!p->A || !p->b) return fail(ctx, SAP_EINVAL, "sap_submit: NULL device pointer");
   if (p->n < 1 || p->n > 1024 || p->m < static_cast<int64_t>(p->n) + 1 || p->lda < p->n || p->m > (int64_t(1) << 31))
     return fail(ctx, SAP_EINVAL, "sap_submit: bad problem shape (n <= 1024, m >= n + 1)");
-  const size_t es = (p->a_type == SAP_F32) ? 4 : 8;
-  if (q->d < p->n + 1 || q->d > 4096 || static_cast<size_t>(q->d + 1) * 16 * es > 160000 || q->zeta < 1 || q->zeta > 64 ||
+  if (q->d < p->n + 1 || q->d > 4096 || q->zeta < 1 || q->zeta > 64 ||
       q->zeta > q->d || q->maxiter < 0 || !(q->tol >= 0.0))
     return fail(ctx, SAP_EINVAL, "sap_submit: bad parameters");
   const size_t bytes = item_bytes(p->m, p->n, q->d, q->zeta, p->a_type);
