@@ -133,14 +133,16 @@ def form_mixed(args, sap, torch, inputs):
     x32 = torch.empty(n, dtype=torch.float64, device="cuda")
     x64 = torch.empty(n, dtype=torch.float64, device="cuda")
 
-    def timed(A, x, mode):
-        sap.sap_solve(A, b, d, zeta, seed, tol=tol, maxiter=maxiter, x=x, mode=mode)  # warm-up
+    def timed(A, x, mode, tol_=None):
+        tol_ = tol if tol_ is None else tol_
+        mx = maxiter if mode != sap.SAP_MODE_MIXED_FP32_REFINE else 4 * maxiter
+        sap.sap_solve(A, b, d, zeta, seed, tol=tol_, maxiter=mx, x=x, mode=mode)  # warm-up
         torch.cuda.synchronize()
         ctx.profile(True)
         ctx.profile_read(sap.PROF_PASS, reset=True)
         ctx.profile_read(sap.PROF_APPLY, reset=True)
         t0 = time.perf_counter()
-        r = sap.sap_solve(A, b, d, zeta, seed, tol=tol, maxiter=maxiter, x=x, mode=mode)
+        r = sap.sap_solve(A, b, d, zeta, seed, tol=tol_, maxiter=mx, x=x, mode=mode)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         ctx.profile(False)
@@ -150,14 +152,20 @@ def form_mixed(args, sap, torch, inputs):
         pb = pass_bytes(m, n, es)
         ab = apply_bytes(m, n, d, zeta, es, 8)
         return dict(solve_ms=dt * 1e3, status=r.info["status_name"], iters=r.info["iters"],
+                    refinements=r.info["refinements"], tol=tol_,
                     phases_ms={"generate": r.info["t_generate_ms"], "apply": r.info["t_apply_ms"],
                                "qr": r.info["t_qr_ms"], "iterate": r.info["t_iterate_ms"]},
-                    pass_gbs=pb / (mspass / max(1, min(npass, r.info["iters"] + 1)) * 1e-3) / 1e9,
+                    pass_gbs=pb / (mspass / max(1, min(npass, r.info["iters"] + max(1, r.info["refinements"])))
+                                   * 1e-3) / 1e9,
                     sa_gbs=ab / (msap / max(1, nap) * 1e-3) / 1e9)
 
     log("bench[mixed]: FP32-storage solve")
     rm = timed(A32, x32, sap.SAP_MODE_MIXED_FP32)
     log(f"bench[mixed]: {rm}")
+    log("bench[mixed]: FP32 refinement form to a 1e-8 relative correction")
+    xr = torch.empty(n, dtype=torch.float64, device="cuda")
+    rr = timed(A32, xr, sap.SAP_MODE_MIXED_FP32_REFINE, tol_=1e-8)
+    log(f"bench[mixed]: refine {rr}")
     log("bench[mixed]: widening A to FP64 for the FP64 form")
     A64 = widen(A32)
     del A32
@@ -169,7 +177,8 @@ def form_mixed(args, sap, torch, inputs):
     return {"workload": f"m={m} n={n} d={d} zeta={zeta}, A_ij = g_ij 10^(-6 j/(n-1)) stored FP32, "
                         f"b = A x + 1e-8 noise, tol {tol}",
             "mixed": rm, "fp64": r64, "speedup": r64["solve_ms"] / rm["solve_ms"],
-            "rel_diff_x": rel(x32, x64)}
+            "rel_diff_x": rel(x32, x64),
+            "refine": rr, "refine_speedup": r64["solve_ms"] / rr["solve_ms"], "refine_rel_diff_x": rel(xr, x64)}
 
 
 def form_batched(args, sap, torch, inputs):

@@ -63,7 +63,23 @@ typedef enum sap_dtype { SAP_F64 = 0, SAP_F32 = 1, SAP_BF16 = 2 } sap_dtype;
  * sketch is available through sps_apply; it perturbs the preconditioner of an
  * ill-conditioned A enough to cost extra iterations, so sap_solve does not
  * use it.) */
-typedef enum sap_mode { SAP_MODE_FP64 = 0, SAP_MODE_MIXED_FP32 = 1 } sap_mode;
+/* MIXED_FP32_REFINE: A stored in FP32; iterative refinement: each outer
+ * step forms r = b - A x with FP64 accumulation, solves min ||r - A delta||
+ * by preconditioned LSQR whose products, accumulations and u are FP32, until
+ * that problem's normal-equation residual has dropped by 1e-6 or reached FP32
+ * resolution, and sets x += delta.  It stops with SAP_OK when
+ * ||delta|| <= tol ||x|| (tol is the target relative error of x, e.g. 1e-8;
+ * the error left is much smaller than that last correction), and with
+ * SAP_NOT_CONVERGED when a correction is no smaller than the previous one
+ * (the FP32 representation of r, about 2^-24 ||r|| / sigma_min(A) in x, is
+ * reached) or after max_refine steps.  The sketch, QR and preconditioner are
+ * FP64 as in MIXED_FP32, which reaches the FP64 stopping test and is usually
+ * faster. */
+typedef enum sap_mode {
+    SAP_MODE_FP64 = 0,
+    SAP_MODE_MIXED_FP32 = 1,
+    SAP_MODE_MIXED_FP32_REFINE = 2
+} sap_mode;
 
 typedef struct sap_ctx sap_ctx;
 
@@ -152,13 +168,15 @@ typedef struct sap_params {
     int32_t zeta;       /* sketch nonzeros per column, 1..min(d, 64) */
     uint64_t seed;      /* sketch seed (stream word is 0 for sap_solve) */
     double tol;         /* LSQR stopping tolerance (see below), e.g. 1e-12 */
-    int32_t maxiter;    /* LSQR iteration cap */
+    int32_t maxiter;    /* LSQR iteration cap (summed over refinements) */
     int32_t mode;       /* sap_mode */
+    int32_t max_refine; /* MIXED_FP32_REFINE: outer steps cap (0 = 10) */
 } sap_params;
 
 typedef struct sap_info {
     int32_t status;      /* final sap_status of the solve */
-    int32_t iters;       /* LSQR iterations */
+    int32_t iters;       /* LSQR iterations (summed over refinements) */
+    int32_t refinements; /* MIXED_FP32_REFINE: residual refinement steps */
     double resid_est;    /* estimate of ||b - A x|| */
     double normar_est;   /* estimate of ||(A M)^T (b - A x)|| */
     double t_generate_ms, t_apply_ms, t_qr_ms, t_iterate_ms; /* phase times */

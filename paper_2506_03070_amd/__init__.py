@@ -17,7 +17,7 @@ SAP_OK, SAP_EINVAL, SAP_ENOMEM, SAP_RANK_DEFICIENT, SAP_NOT_CONVERGED, SAP_PENDI
 STATUS_NAMES = {0: "SAP_OK", 1: "SAP_EINVAL", 2: "SAP_ENOMEM", 3: "SAP_RANK_DEFICIENT",
                 4: "SAP_NOT_CONVERGED", 5: "SAP_PENDING", 6: "SAP_EDEVICE", 7: "SAP_ECANCELED"}
 SAP_F64, SAP_F32, SAP_BF16 = 0, 1, 2
-SAP_MODE_FP64, SAP_MODE_MIXED_FP32 = 0, 1
+SAP_MODE_FP64, SAP_MODE_MIXED_FP32, SAP_MODE_MIXED_FP32_REFINE = 0, 1, 2
 
 # Every symbol the header declares (checked by the CPU test suite).
 EXPORTS = ["sap_create", "sap_destroy", "sap_last_error", "sap_status_string", "sps_generate",
@@ -44,11 +44,11 @@ class SapProblem(ctypes.Structure):
 
 class SapParams(ctypes.Structure):
     _fields_ = [("d", _i32), ("zeta", _i32), ("seed", _u64), ("tol", _f64), ("maxiter", _i32),
-                ("mode", _i32)]
+                ("mode", _i32), ("max_refine", _i32)]
 
 
 class SapInfo(ctypes.Structure):
-    _fields_ = [("status", _i32), ("iters", _i32), ("resid_est", _f64), ("normar_est", _f64), ("t_generate_ms", _f64),
+    _fields_ = [("status", _i32), ("iters", _i32), ("refinements", _i32), ("resid_est", _f64), ("normar_est", _f64), ("t_generate_ms", _f64),
                 ("t_apply_ms", _f64), ("t_qr_ms", _f64), ("t_iterate_ms", _f64),
                 ("t_queue_ms", _f64), ("t_total_ms", _f64)]
 
@@ -274,14 +274,14 @@ class SolveResult:
 
 
 def sap_solve(A, b, d, zeta=8, seed=1, tol=1e-12, maxiter=200, mode=None, ctx=None, x=None,
-              allow_not_converged=True):
+              allow_not_converged=True, max_refine=0):
     """min ||b - A x|| by sketch-and-precondition (Alg. 1) with LSQR (Alg. 2)."""
     torch = _torch()
     ctx = ctx or default_context()
     if mode is None:
         mode = SAP_MODE_FP64 if A.dtype == torch.float64 else SAP_MODE_MIXED_FP32
     prob = _problem(A, b)
-    par = SapParams(d, zeta, seed, tol, maxiter, mode)
+    par = SapParams(d, zeta, seed, tol, maxiter, mode, max_refine)
     x = x if x is not None else torch.empty(A.shape[1], dtype=torch.float64, device=A.device)
     info = SapInfo()
     st = lib().sap_solve(ctx.handle, ctypes.byref(prob), ctypes.byref(par), _dev(x, torch.float64, "x"),
@@ -316,7 +316,7 @@ def sap_solve_batch(As, bs, ds, zetas=8, seeds=1, tol=1e-12, maxiter=200, ctx=No
     seeds = seeds if isinstance(seeds, (list, tuple)) else [seeds] * count
     ds = ds if isinstance(ds, (list, tuple)) else [ds] * count
     probs = (SapProblem * count)(*[_problem(A, b) for A, b in zip(As, bs)])
-    pars = (SapParams * count)(*[SapParams(int(d), int(z), int(s), tol, maxiter, 0)
+    pars = (SapParams * count)(*[SapParams(int(d), int(z), int(s), tol, maxiter, 0, 0)
                                  for d, z, s in zip(ds, zetas, seeds)])
     xs = xs or [torch.empty(A.shape[1], dtype=torch.float64, device=A.device) for A in As]
     xptrs = (_vp * count)(*[_vp(_dev(xx, torch.float64, "x")) for xx in xs])
@@ -344,7 +344,7 @@ def sap_submit(A, b, d, zeta=8, seed=1, tol=1e-12, maxiter=200, ctx=None, x=None
     ctx = ctx or default_context()
     x = x if x is not None else torch.empty(A.shape[1], dtype=torch.float64, device=A.device)
     prob = _problem(A, b)
-    par = SapParams(int(d), int(zeta), int(seed), float(tol), int(maxiter), 0)
+    par = SapParams(int(d), int(zeta), int(seed), float(tol), int(maxiter), 0, 0)
     ticket = _u64(0)
     st = lib().sap_submit(ctx.handle, ctypes.byref(prob), ctypes.byref(par), _vp(_dev(x, torch.float64, "x")),
                           ctypes.byref(ticket), _vp(_stream()))

@@ -296,7 +296,8 @@ sap_status sap_lsqr(sap_ctx *ctx, const sap_problem *prob, const double *R, int6
   SAP_HIP_TRY(hipEventCreate(&e0));
   SAP_HIP_TRY(hipEventCreate(&e1));
   SAP_HIP_TRY(hipEventRecord(e0, st));
-  s = run_lsqr(ctx, prob, R, ldr, x0, nullptr, tol, maxiter, prob->a_type == SAP_F32 ? 1 : 0, x, info, ctx->ws, st);
+  s = run_lsqr(ctx, prob, R, ldr, x0, nullptr, tol, maxiter, prob->a_type == SAP_F32 ? 1 : 0, 0, x, info, ctx->ws,
+               st);
   (void)hipEventRecord(e1, st);
   (void)hipEventSynchronize(e1);
   prof_resolve(ctx);
@@ -334,8 +335,9 @@ sap_status sap_solve(sap_ctx *ctx, const sap_problem *prob, const sap_params *pa
   const int mode = par->mode;
   if (mode == SAP_MODE_FP64) {
     if (prob->a_type != SAP_F64) return fail(ctx, SAP_EINVAL, "sap_solve: FP64 mode needs an F64 A");
-  } else if (mode == SAP_MODE_MIXED_FP32) {
-    if (prob->a_type != SAP_F32) return fail(ctx, SAP_EINVAL, "sap_solve: mixed mode needs an F32 A");
+  } else if (mode == SAP_MODE_MIXED_FP32 || mode == SAP_MODE_MIXED_FP32_REFINE) {
+    if (prob->a_type != SAP_F32) return fail(ctx, SAP_EINVAL, "sap_solve: mixed modes need an F32 A");
+    if (par->max_refine < 0) return fail(ctx, SAP_EINVAL, "sap_solve: max_refine must be >= 0");
   } else {
     return fail(ctx, SAP_EINVAL, "sap_solve: unsupported mode");
   }
@@ -405,10 +407,10 @@ sap_status sap_solve(sap_ctx *ctx, const sap_problem *prob, const sap_params *pa
     return fail(ctx, SAP_RANK_DEFICIENT, "sap_solve: R is numerically singular (A rank deficient)");
   }
   // x0 = R^-1 (Q^T S b)[0:n]: column n of the factored sketch.
-  const int lsqr_mode = (mode == SAP_MODE_FP64) ? 0 : 1;
+  const int lsqr_mode = (mode == SAP_MODE_FP64) ? 0 : (mode == SAP_MODE_MIXED_FP32 ? 1 : 2);
   sap_info li{};
-  s = run_lsqr(ctx, prob, Y, d, nullptr, Y + static_cast<int64_t>(n) * d, par->tol, par->maxiter, lsqr_mode, x,
-               &li, work, st);
+  s = run_lsqr(ctx, prob, Y, d, nullptr, Y + static_cast<int64_t>(n) * d, par->tol, par->maxiter, lsqr_mode,
+               par->max_refine, x, &li, work, st);
   if (s != SAP_OK && s != SAP_NOT_CONVERGED) return s;
   SAP_HIP_TRY(hipEventRecord(ev[4], st));
   SAP_HIP_TRY(hipEventSynchronize(ev[4]));

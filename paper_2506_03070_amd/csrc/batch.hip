@@ -284,6 +284,7 @@ __global__ __launch_bounds__(1024) void batch_init_kernel(const BatchItem *__res
     st->proceed = 0;
     st->total_iters = 0;
     st->steps = 0;
+    st->rel = 0;
   }
 }
 

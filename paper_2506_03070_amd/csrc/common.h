@@ -127,6 +127,10 @@ struct LsqrState {
   int32_t total_iters;   // iterations done
   int32_t proceed;       // alpha_{t+1} > 0 and beta_{t+1} > 0
   int32_t steps;         // completed lower/upper solve pairs (flag epoch)
+  int32_t rel;           // 1: phibar is tested against beta_1 of this run (inner solves)
+  int32_t pad;
+  double normref;        // scale of the phibar test: ||b||, or beta_1 when rel
+  double normar0;        // ||(A M)^T r|| at the initialisation step (rel runs)
 };
 
 }  // namespace sap
@@ -207,11 +211,12 @@ sap_status launch_trsv(sap_ctx *ctx, const double *R, int64_t ldr, int n, int tr
 
 // LSQR driver (lsqr.hip).  When z is non-null, x0 is ignored and the initial
 // guess is R^-1 z (the sketch-and-solve solution of Alg. 1).
-// mode 0: A in FP64; mode 1: A stored in FP32 (FP64 arithmetic).
+// mode 0: A in FP64; mode 1: A stored in FP32 (FP64 arithmetic); mode 2: A
+// stored in FP32, FP64 residual refinement around FP32 inner solves.
 size_t lsqr_workspace_bytes(sap_ctx *ctx, int64_t m, int n);
 sap_status run_lsqr(sap_ctx *ctx, const sap_problem *prob, const double *R, int64_t ldr,
-                    const double *x0, const double *z, double tol, int maxiter, int mode, double *x,
-                    sap_info *info, void *work, hipStream_t st);
+                    const double *x0, const double *z, double tol, int maxiter, int mode, int max_refine,
+                    double *x, sap_info *info, void *work, hipStream_t st);
 
 // Served form (batch.hip).
 sap_status serve_start(sap_ctx *ctx, size_t arena_bytes, int max_slots);

@@ -37,8 +37,11 @@ constexpr int kMaxN = 8192;
 
 // --------------------------------------------------------------------------
 // Fused pass.  MODE 0: A in FP64.  MODE 1: A stored in FP32 (the mixed
-// form).  In both, p, the accumulation and u are FP64: an FP32 element is
-// widened exactly, so the pass reads half the bytes for the same arithmetic.
+// form): p, the accumulation and u are FP64, an FP32 element is widened
+// exactly, so the pass reads half the bytes for the same arithmetic.
+// The refinement form uses two more: MODE 2, the inner iterations, with p,
+// the accumulation and u in FP32; MODE 3, the residual pass r = b - A x with
+// FP64 accumulation, whose u output (the inner right-hand side) is FP32.
 template <int MODE>
 struct PassTypes;
 template <>
@@ -48,6 +51,14 @@ struct PassTypes<0> {
 template <>
 struct PassTypes<1> {
   using TA = float; using TC = double; using TUI = double; using TUO = double;
+};
+template <>
+struct PassTypes<2> {
+  using TA = float; using TC = float; using TUI = float; using TUO = float;
+};
+template <>
+struct PassTypes<3> {
+  using TA = float; using TC = double; using TUI = double; using TUO = float;
 };
 
 // WC waves split the columns of a row (64*VEC*J columns each); WR = 16/WC
@@ -345,7 +356,7 @@ __global__ __launch_bounds__(1024) void lsqr_mv_kernel(const double *__restrict_
                                                        const double *__restrict__ vh, const double *__restrict__ vpart,
                                                        int nvpart, const double *__restrict__ nrmpart, int G,
                                                        double *__restrict__ v, double *__restrict__ p,
-                                                       LsqrState *st) {
+                                                       float *__restrict__ p32, LsqrState *st) {
   __shared__ double scr[16];
   __shared__ double vs[kMaxN];
   if (st->done) return;
@@ -375,6 +386,7 @@ __global__ __launch_bounds__(1024) void lsqr_mv_kernel(const double *__restrict_
     acc = wave_sum_u(acc);
     if (lane == 0) {
       p[rr] = acc;
+      if (p32) p32[rr] = static_cast<float>(acc);
       v[rr] = vs[rr];
     }
   }
@@ -393,7 +405,8 @@ __global__ __launch_bounds__(kTrsvThreads) void lsqr_update_kernel(const double 
 }
 
 // Fresh state for an LSQR run; clears the chain flags of the two solves.
-__global__ void lsqr_init_state_kernel(LsqrState *st, double tol, int maxiter, int *flags, int nflags) {
+__global__ void lsqr_init_state_kernel(LsqrState *st, double tol, int maxiter, int *flags, int nflags,
+                                       int total_iters, int rel) {
   for (int i = threadIdx.x; i < nflags; i += blockDim.x) flags[i] = 0;
   if (threadIdx.x != 0) return;
   st->alpha = st->beta = st->rhobar = st->phibar = 0.0;
@@ -408,8 +421,9 @@ __global__ void lsqr_init_state_kernel(LsqrState *st, double tol, int maxiter, i
   st->converged = 0;
   st->init = 1;
   st->proceed = 0;
-  st->total_iters = 0;
+  st->total_iters = total_iters;
   st->steps = 0;
+  st->rel = rel;
 }
 
 // ||b|| into st->normb: per-workgroup partial sums, then a fixed-order sum
@@ -534,7 +548,9 @@ int max_grid(sap_ctx *ctx) { return ctx->num_cus * 2; }
 PassPlan plan_pass(sap_ctx *ctx, int mode, int64_t m, int n, int64_t lda, const void *A) {
   const void *fn;
   if (mode == 0) fn = pick_pass<0>(choose_pass<0>(n, lda, A));
-  else fn = pick_pass<1>(choose_pass<1>(n, lda, A));
+  else if (mode == 1) fn = pick_pass<1>(choose_pass<1>(n, lda, A));
+  else if (mode == 2) fn = pick_pass<2>(choose_pass<2>(n, lda, A));
+  else fn = pick_pass<3>(choose_pass<3>(n, lda, A));
   int64_t grid = static_cast<int64_t>(ctx->num_cus) * std::min(2, occupancy(fn));
   const int64_t min_rows = 64;
   if (grid * min_rows > m) grid = (m + min_rows - 1) / min_rows;
@@ -570,6 +586,7 @@ size_t lsqr_workspace_bytes(sap_ctx *ctx, int64_t m, int n) {
   bytes += 2 * static_cast<size_t>(n) * n * sizeof(double);                        // M = R^-1 and M^T
   bytes += (static_cast<size_t>((G + kQSlice - 1) / kQSlice) + 2) * n * sizeof(double);  // q slices, v_hat
   bytes += static_cast<size_t>((n + 15) / 16 + 1) * sizeof(double);                // ||v_hat||^2 partials
+  bytes += static_cast<size_t>(n) * (sizeof(float) + sizeof(double)) + 2 * sizeof(double);  // p32, xprev, norms
   bytes += trsv_factor_bytes(n);
   return bytes;
 }
@@ -598,26 +615,60 @@ sap_status launch_trsv(sap_ctx *ctx, const double *R, int64_t ldr, int n, int tr
   return SAP_OK;
 }
 
+namespace {
+
+// out[0] = ||x - xprev||, out[1] = ||x|| (fixed-order sums, one workgroup).
+__global__ __launch_bounds__(1024) void delta_norm_kernel(const double *__restrict__ x, const double *__restrict__ xprev,
+                                                          int n, double *__restrict__ out) {
+  __shared__ double scr[16];
+  double a = 0.0, b = 0.0;
+  for (int c = threadIdx.x; c < n; c += 1024) {
+    const double dx = x[c] - xprev[c];
+    a += dx * dx;
+    b += x[c] * x[c];
+  }
+  a = wg_sum(a, scr);
+  b = wg_sum(b, scr);
+  if (threadIdx.x == 0) {
+    out[0] = sqrt(a);
+    out[1] = sqrt(b);
+  }
+}
+
+}  // namespace
+
 // Runs LSQR (Alg. 2) from x0 on A R^-1.  mode 0: A in FP64; mode 1: A
-// stored in FP32 (FP64 arithmetic throughout).
+// stored in FP32, FP64 arithmetic throughout; mode 2: A stored in FP32,
+// residual refinement: each outer step forms r = b - A x with FP64
+// accumulation and solves min ||r - A delta|| by LSQR with FP32 products,
+// accumulation and u until that problem's normal-equation residual has
+// dropped by kInnerReduction or reached FP32 resolution; x += delta.  The
+// refinement stops when ||delta|| <= tol ||x|| (the inner reduction makes
+// the remaining error much smaller than the last correction), and gives up
+// when a correction is no smaller than the one before (the FP32 inner solves
+// cannot resolve the remaining error) or after max_refine steps.
 sap_status run_lsqr(sap_ctx *ctx, const sap_problem *prob, const double *R, int64_t ldr, const double *x0,
-                    const double *z, double tol, int maxiter, int mode, double *x, sap_info *info, void *work,
-                    hipStream_t s) {
+                    const double *z, double tol, int maxiter, int mode, int max_refine, double *x, sap_info *info,
+                    void *work, hipStream_t s) {
+  constexpr double kInnerTol = 0x1p-23;  // FP32 resolution of the inner test
   const int64_t m = prob->m;
   const int n = prob->n;
   if (n > kMaxN) return fail(ctx, SAP_EINVAL, "LSQR: n > 8192 is not supported");
+  const bool refine = mode == 2;
   const int nblk = (n + kTrsvB - 1) / kTrsvB;
   Carve cv(work);
   LsqrState *st = cv.take<LsqrState>(1);
-  const PassPlan plan = plan_pass(ctx, mode, m, n, prob->lda, prob->A);
-  if (plan.grid > max_grid(ctx)) return fail(ctx, SAP_EINVAL, "LSQR: internal grid larger than planned");
+  const PassPlan plan = plan_pass(ctx, refine ? 2 : mode, m, n, prob->lda, prob->A);
+  const PassPlan plan_res = refine ? plan_pass(ctx, 3, m, n, prob->lda, prob->A) : plan;
+  if (plan.grid > max_grid(ctx) || plan_res.grid > max_grid(ctx))
+    return fail(ctx, SAP_EINVAL, "LSQR: internal grid larger than planned");
   double *qpart = cv.take<double>(static_cast<size_t>(max_grid(ctx)) * n);
   double *nrmpart = cv.take<double>(max_grid(ctx));
   double *v = cv.take<double>(n);
   double *w = cv.take<double>(n);
   double *p = cv.take<double>(n);
   double *xin = cv.take<double>(n);
-  double *u = cv.take<double>(m);
+  double *u = cv.take<double>(m);  // FP32 values in the refinement form
   int *flags = cv.take<int>(3 * nblk + 2);
   int *flags_x0 = flags + 2 * nblk;
   int *err = cv.take<int>(4);
@@ -630,6 +681,9 @@ sap_status run_lsqr(sap_ctx *ctx, const sap_problem *prob, const double *R, int6
   double *vh = cv.take<double>(n);
   const int ngemv = (n + 15) / 16;
   double *vpart = cv.take<double>(ngemv);
+  float *p32 = cv.take<float>(n);
+  double *xprev = cv.take<double>(n);
+  double *dnorm = cv.take<double>(2);
   TrsvFactor f;
   trsv_factor_carve(f, cv, n);
 
@@ -659,7 +713,8 @@ sap_status run_lsqr(sap_ctx *ctx, const sap_problem *prob, const double *R, int6
     inverse_transpose_kernel<<<dim3(nt, nt), 256, 0, s>>>(M, n, Mt);
     SAP_HIP_TRY(hipGetLastError());
   }
-  lsqr_init_state_kernel<<<1, 256, 0, s>>>(st, tol, maxiter, flags, 2 * nblk);
+  lsqr_init_state_kernel<<<1, 256, 0, s>>>(st, refine ? kInnerTol : tol, maxiter, flags, 2 * nblk, 0,
+                                           refine ? 1 : 0);
   const int ngrid = static_cast<int>(std::min<int64_t>(256, (m + 1023) / 1024));
   norm_kernel<<<ngrid, 1024, 0, s>>>(prob->b, m, normpart, ticket, st);
   SAP_HIP_TRY(hipGetLastError());
@@ -667,41 +722,77 @@ sap_status run_lsqr(sap_ctx *ctx, const sap_problem *prob, const double *R, int6
   // One iteration = pass over A; q from the pass partials; v_hat = M^T q /
   // beta - beta v; alpha, v, p = M v; rotation, x and w updates and the
   // stopping test.
-  const int G = plan.grid;
-  const int qsl = (G + kQSlice - 1) / kQSlice;
-  auto iteration = [&](const void *pv, const void *uin) {
-    launch_pass(ctx, plan, prob->A, prob->lda, m, n, pv, uin, u, st, qpart, nrmpart, s);
+  auto iteration = [&](const PassPlan &pl, const void *pv, const void *uin) {
+    const int G = pl.grid;
+    const int qsl = (G + kQSlice - 1) / kQSlice;
+    launch_pass(ctx, pl, prob->A, prob->lda, m, n, pv, uin, u, st, qpart, nrmpart, s);
     q_slices_kernel<<<dim3((n + 63) / 64, qsl), 256, 0, s>>>(qpart, G, n, qs);
     lsqr_mtq_kernel<<<ngemv, 1024, 0, s>>>(M, n, qs, qsl, nrmpart, G, v, vh, vpart, st);
-    lsqr_mv_kernel<<<ngemv, 1024, 0, s>>>(Mt, n, vh, vpart, ngemv, nrmpart, G, v, p, st);
+    lsqr_mv_kernel<<<ngemv, 1024, 0, s>>>(Mt, n, vh, vpart, ngemv, nrmpart, G, v, p, refine ? p32 : nullptr, st);
     lsqr_update_kernel<<<1, kTrsvThreads, 0, s>>>(p, w, x, n, st);
   };
 
-  // Initialisation: beta_1 u_1 = b - A x0 (the pass with p = x, u_in = b).
-  iteration(x, prob->b);
-  SAP_HIP_TRY(hipGetLastError());
-  // Iterations in batches; one state read per batch.  The upper kernel sets
-  // `done` no later than iteration maxiter, so the batch count is bounded.
   const int batch = 8;
-  const int max_batches = maxiter / batch + 2;
   LsqrState hs{};
   int herr = 0;
-  for (int nbatch = 0;; ++nbatch) {
-    if (nbatch > max_batches) return fail(ctx, SAP_EDEVICE, "LSQR: device never reported completion");
-    for (int k = 0; k < batch; ++k) iteration(p, u);
+  int refinements = 0;
+  bool converged = false;
+  double prev_delta = INFINITY;
+  const int max_outer = refine ? (max_refine > 0 ? max_refine : 10) : 1;
+  for (int outer = 0; outer < max_outer; ++outer) {
+    if (outer > 0)
+      lsqr_init_state_kernel<<<1, 256, 0, s>>>(st, kInnerTol, maxiter, flags, 0, hs.total_iters, 1);
+    if (refine) copy_f64_kernel<<<(n + 255) / 256, 256, 0, s>>>(x, xprev, n);
+    // Initialisation: beta_1 u_1 = b - A x (the pass with p = x, u_in = b);
+    // in the refinement form this is the FP64-accumulated residual pass.
+    iteration(plan_res, x, prob->b);
     SAP_HIP_TRY(hipGetLastError());
-    SAP_HIP_TRY(hipMemcpyAsync(&hs, st, sizeof(LsqrState), hipMemcpyDeviceToHost, s));
-    SAP_HIP_TRY(hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, s));
+    if (refine) {
+      ++refinements;
+      SAP_HIP_TRY(hipMemcpyAsync(&hs, st, sizeof(LsqrState), hipMemcpyDeviceToHost, s));
+      SAP_HIP_TRY(hipStreamSynchronize(s));
+      if (hs.done) {  // breakdown: r or (A M)^T r is exactly zero, x is the solution
+        converged = true;
+        break;
+      }
+      if (hs.total_iters >= maxiter) break;
+    }
+    // Iterations in batches; one state read per batch.  The update kernel
+    // sets `done` no later than iteration maxiter, so the batch count is
+    // bounded.
+    const int max_batches = maxiter / batch + 2;
+    for (int nbatch = 0;; ++nbatch) {
+      if (nbatch > max_batches) return fail(ctx, SAP_EDEVICE, "LSQR: device never reported completion");
+      for (int k = 0; k < batch; ++k) iteration(plan, refine ? static_cast<const void *>(p32) : p, u);
+      SAP_HIP_TRY(hipGetLastError());
+      SAP_HIP_TRY(hipMemcpyAsync(&hs, st, sizeof(LsqrState), hipMemcpyDeviceToHost, s));
+      SAP_HIP_TRY(hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, s));
+      SAP_HIP_TRY(hipStreamSynchronize(s));
+      if (herr) return fail(ctx, SAP_EDEVICE, "LSQR: a triangular-solve wait expired");
+      if (hs.done) break;
+    }
+    if (!refine) {
+      converged = hs.converged != 0;
+      break;
+    }
+    delta_norm_kernel<<<1, 1024, 0, s>>>(x, xprev, n, dnorm);
+    double hd[2] = {0.0, 0.0};
+    SAP_HIP_TRY(hipMemcpyAsync(hd, dnorm, sizeof(hd), hipMemcpyDeviceToHost, s));
     SAP_HIP_TRY(hipStreamSynchronize(s));
-    if (herr) return fail(ctx, SAP_EDEVICE, "LSQR: a triangular-solve wait expired");
-    if (hs.done) break;
+    if (hd[0] <= tol * hd[1]) {
+      converged = true;
+      break;
+    }
+    if (hd[0] >= prev_delta || hs.total_iters >= maxiter) break;  // stagnated, or out of iterations
+    prev_delta = hd[0];
   }
   if (info) {
     info->iters = hs.total_iters;
+    info->refinements = refinements;
     info->resid_est = hs.resid_est;
     info->normar_est = hs.normar_est;
   }
-  return hs.converged ? SAP_OK : SAP_NOT_CONVERGED;
+  return converged ? SAP_OK : SAP_NOT_CONVERGED;
 }
 
 }  // namespace sap

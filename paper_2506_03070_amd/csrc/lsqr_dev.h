@@ -8,6 +8,8 @@
 
 namespace sap {
 
+constexpr double kInnerReduction = 1e-6;
+
 // Sum over a 1024-thread workgroup, result in every thread (two barriers).
 __device__ __forceinline__ double wg_sum(double v, double *scratch) {
   v = wave_sum_u(v);
@@ -103,6 +105,8 @@ __device__ __forceinline__ void upper_epilogue(int n, const double *p, double *_
       st->c_u = beta > 0.0 ? -alpha / beta : 0.0;
       bool stop = !proceed || st->maxiter <= st->total_iters;
       bool conv = !proceed;
+      st->normref = st->rel ? beta : st->normb;
+      st->normar0 = alpha * beta;
       st->converged = conv ? 1 : 0;
       st->done = stop ? 1 : 0;
       st->steps += 1;
@@ -135,7 +139,10 @@ __device__ __forceinline__ void upper_epilogue(int n, const double *p, double *_
     st->c_u = beta > 0.0 ? -alpha / beta : 0.0;
     st->resid_est = phibar;
     st->normar_est = phibar * alpha * fabs(cs);
-    const bool conv = !proceed || alpha * fabs(cs) <= st->tol || phibar <= st->tol * st->normb;
+    // Inner solves of the refinement form (rel) also stop once the normal-
+    // equation residual of their own problem has dropped by kInnerReduction.
+    const bool conv = !proceed || alpha * fabs(cs) <= st->tol || phibar <= st->tol * st->normref ||
+                      (st->rel && phibar * alpha * fabs(cs) <= kInnerReduction * st->normar0);
     st->converged = conv ? 1 : 0;
     const bool stop = conv || st->total_iters >= st->maxiter;
     st->done = stop ? 1 : 0;

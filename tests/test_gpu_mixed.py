@@ -56,6 +56,39 @@ def test_mixed_solve_parity(sap, orc, name, m, n, d, kind, cond, noise):
     assert np.linalg.norm(x - x_or) <= 1e-8 * np.linalg.norm(x_or)
 
 
+REFINE_CASES = [
+    # name, m, n, d, kind, cond, noise
+    ("colscale", 200000, 256, 1024, "colscale", 1e6, 1e-8),
+    ("svd", 60000, 100, 400, "svd", 1e6, 1e-8),
+    ("odd-n", 50000, 77, 308, "colscale", 1e5, 1e-5),
+]
+
+
+@pytest.mark.parametrize("name,m,n,d,kind,cond,noise", REFINE_CASES)
+def test_refine_solve_parity(sap, orc, name, m, n, d, kind, cond, noise):
+    """Residual refinement around FP32 inner solves to the target relative
+    error 1e-8, against the FP64 oracle on the same FP32 A: forward error
+    ||x - x_or|| <= 1e-8 ||x_or|| and ||A (x - x_or)|| <= 1e-10 ||b||.  The
+    cases keep the form's floor, the FP32 rounding of r seen through the
+    least-squares solution (~2^-24 ||r|| sqrt(n/m) / sigma_min relative to
+    ||x||), well below 1e-8: at noise 1e-3 the odd-n case would sit near it."""
+    import torch
+    print(f"refine {name} m={m} n={n} d={d}", flush=True)
+    p = inputs.make_problem(m, n, kind=kind, cond=cond, noise=noise, seed=m + 29, dtype=np.float32)
+    A64 = p.A.astype(np.float64)
+    seed = 77
+    res = sap.sap_solve(_dev(p.A), _dev(p.b), d, 8, seed, tol=1e-8, maxiter=1000,
+                        mode=sap.SAP_MODE_MIXED_FP32_REFINE, max_refine=12)
+    torch.cuda.synchronize()
+    assert res.status == sap.SAP_OK, res.info
+    assert res.info["refinements"] >= 1
+    x = res.x.cpu().numpy()
+    x_or, info_or = orc.solve(A64, p.b, d, 8, seed, tol=1e-12, maxiter=400)
+    assert info_or["status"] == "ok"
+    assert np.linalg.norm(x - x_or) <= 1e-8 * np.linalg.norm(x_or)
+    assert np.linalg.norm(A64 @ (x - x_or)) <= 1e-10 * np.linalg.norm(p.b)
+
+
 def test_mixed_mode_dtype_checks(sap):
     p = inputs.make_problem(4000, 10, kind="colscale", cond=10.0, seed=1)
     with pytest.raises(sap.SapError) as e:
@@ -63,6 +96,13 @@ def test_mixed_mode_dtype_checks(sap):
     assert e.value.status == sap.SAP_EINVAL
     with pytest.raises(sap.SapError) as e:
         sap.sap_solve(_dev(p.A.astype(np.float32)), _dev(p.b), 40, 8, 1, mode=7)
+    assert e.value.status == sap.SAP_EINVAL
+    with pytest.raises(sap.SapError) as e:
+        sap.sap_solve(_dev(p.A), _dev(p.b), 40, 8, 1, mode=sap.SAP_MODE_MIXED_FP32_REFINE)  # F64 A
+    assert e.value.status == sap.SAP_EINVAL
+    with pytest.raises(sap.SapError) as e:
+        sap.sap_solve(_dev(p.A.astype(np.float32)), _dev(p.b), 40, 8, 1, mode=sap.SAP_MODE_MIXED_FP32_REFINE,
+                      max_refine=-1)
     assert e.value.status == sap.SAP_EINVAL
 
 
