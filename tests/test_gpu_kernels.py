@@ -144,6 +144,27 @@ def test_apply_integer_bitwise(sap, orc, ydt, d):
     assert np.array_equal(got, ref)
 
 
+@pytest.mark.parametrize("ydt", ["f64", "f32"])
+def test_apply_bf16_input(sap, orc, ydt):
+    """BF16 A (the reduced-precision input variant): the oracle on the
+    BF16-rounded values, which are exact in FP64."""
+    import torch
+    m, n, d, zeta = 30000, 70, 280, 8
+    _note(f"apply-bf16 m={m} n={n} d={d} Y={ydt}")
+    p = inputs.make_problem(m, n, kind="colscale", cond=1e3, seed=41)
+    A_bf = torch.from_numpy(p.A).to(torch.bfloat16)
+    A_ref = A_bf.to(torch.float64).numpy()
+    idx_ref, sign_ref = orc.sketch(77, 0, m, d, zeta)
+    ydtype = torch.float64 if ydt == "f64" else torch.float32
+    Y = sap.sps_apply(torch.from_numpy(idx_ref).cuda(), torch.from_numpy(sign_ref.view(np.int64)).cuda(), d, zeta,
+                      A_bf.cuda(), torch.from_numpy(p.b).cuda(), y_dtype=ydtype)
+    torch.cuda.synchronize()
+    Yg = Y.cpu().numpy().T.astype(np.float64)
+    Yo = orc.apply_sparse(idx_ref, sign_ref, A_ref, p.b, d, zeta)
+    tol = 1e-12 if ydt == "f64" else 1e-5
+    assert np.linalg.norm(Yg - Yo) <= tol * np.linalg.norm(Yo)
+
+
 def test_apply_ignores_out_of_range_rows(sap, orc):
     """A caller-supplied sketch with row indices outside [0, d) must not
     fault: those nonzeros are ignored."""

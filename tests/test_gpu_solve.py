@@ -64,6 +64,27 @@ def test_lsqr_parity(sap, orc, m, n, d, cond, noise):
     assert abs(res.info["iters"] - info_or["iters"]) <= 2
 
 
+@pytest.mark.parametrize("m,n,d,cond,noise", [(20000, 100, 400, 1e6, 1e-8), (30000, 300, 1200, 1e4, 1e-4)])
+def test_lsqr_fp32_storage_parity(sap, orc, m, n, d, cond, noise):
+    """sap_lsqr with A stored in FP32 computes in FP64: the oracle on the
+    FP32-rounded A (exact in FP64) is the reference, at the FP64 bar."""
+    import torch
+    _note(f"lsqr-f32 m={m} n={n} d={d}")
+    p = inputs.make_problem(m, n, kind="svd", cond=cond, noise=noise, seed=m + 3 * n, dtype=np.float32)
+    A64 = p.A.astype(np.float64)
+    idx, sign = orc.sketch(9, 0, m, d, 8)
+    Y = orc.apply_sparse(idx, sign, A64, p.b, d, 8)
+    F, _ = orc.householder_qr(Y)
+    R = np.triu(F[:n, :n])
+    x0 = orc.backsub(R, F[:n, n])
+    x_or, info_or = orc.lsqr(A64, p.b, R, x0, tol=1e-12, maxiter=300)
+    res = sap.sap_lsqr(_dev(p.A), _dev(p.b), _dev(np.ascontiguousarray(F[:n, :n].T)), _dev(x0), tol=1e-12,
+                       maxiter=300)
+    torch.cuda.synchronize()
+    assert res.status == sap.SAP_OK and info_or["converged"]
+    assert np.linalg.norm(A64 @ (res.x.cpu().numpy() - x_or)) <= 1e-12 * np.linalg.norm(p.b)
+
+
 def test_lsqr_maxiter_and_zero(sap, orc):
     import torch
     p = inputs.make_problem(4000, 20, kind="svd", cond=1e4, noise=1e-3, seed=1)
