@@ -17,6 +17,7 @@ forms, each against the plain FP64 form on the same problems:
 import argparse
 import json
 import os
+import re
 import sys
 import time
 
@@ -45,6 +46,9 @@ def parse():
     ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-duration", type=float, default=1.5)
+    ap.add_argument("--gaussian-input", action="store_true",
+                    help="column-scaled Gaussian A of the same shape instead of the SVD-built one (cheap to "
+                         "generate; for counter runs, where the kernels move the same bytes)")
     ap.add_argument("--copy-ref-mib", type=int, default=2048,
                     help="size of the plain device-to-device copy timed as the achievable-bandwidth reference")
     return ap.parse_args()
@@ -90,9 +94,11 @@ def widen(A32):
 
 
 def copy_reference(torch, mib):
-    """Plain device-to-device copy (torch's copy kernel) of `mib` MiB, timed
-    with HIP events: the achievable streaming bandwidth on this GPU, and the
-    known-size kernel that scales the HBM byte counters."""
+    """Plain device-to-device copy of `mib` MiB (torch's copy_ between
+    same-typed tensors, which the HIP runtime runs as its blit copy kernel),
+    timed with HIP events: the streaming bandwidth a plain copy reaches on
+    this GPU, and the known-size kernel that calibrates the HBM byte
+    counters."""
     src = torch.empty(mib << 20, dtype=torch.uint8, device="cuda")
     src.fill_(1)
     dst = torch.empty_like(src)
@@ -109,6 +115,39 @@ def copy_reference(torch, mib):
     del src, dst
     torch.cuda.empty_cache()
     return {"bytes_moved": 2 * (mib << 20), "avg_ms": ms, "gbs": 2 * (mib << 20) / (ms * 1e-3) / 1e9}
+
+
+TRAFFIC_PROFILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
+                               "lsqr_pass_fp64_m1048576_n1000_counters.md")
+PASS_SOURCES = ("lsqr.hip", "lsqr_dev.h", "common.h")
+
+
+def pass_sources_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    for f in PASS_SOURCES:
+        with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2506_03070_amd", "csrc", f),
+                  "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(m, n):
+    """HBM bytes per full pass launch from the committed counter summary
+    (FETCH_SIZE and WRITE_SIZE, calibrated against a copy of known size), or
+    None when the workload differs or the pass kernel's sources changed since
+    the counters were taken."""
+    if (m, n) != (1 << 20, 1000) or not os.path.exists(TRAFFIC_PROFILE):
+        return None
+    fields = {}
+    with open(TRAFFIC_PROFILE) as fh:
+        for line in fh:
+            mt = re.match(r"^\s*(traffic_bytes_per_launch|sources_sha256):\s*(\S+)", line)
+            if mt:
+                fields[mt.group(1)] = mt.group(2)
+    if fields.get("sources_sha256") != pass_sources_sha256() or "traffic_bytes_per_launch" not in fields:
+        return None
+    return int(fields["traffic_bytes_per_launch"])
 
 
 def pass_bytes(m, n, esize):
@@ -314,7 +353,11 @@ def main():
     m, n, d, zeta = args.m, args.n, args.d, args.zeta
     log(f"bench: generating workload m={m} n={n} d={d} zeta={zeta} (FP64) on the GPU")
     t0 = time.perf_counter()
-    if (m, n) == (1 << 20, 1000):
+    if args.gaussian_input:
+        A, b, x_true = inputs.make_problem_torch(m, n, kind="colscale", cond=1e4, noise=1e-6,
+                                                 seed=inputs.config_seed(1), device="cuda")
+        meta = dict(sketch_seed=inputs.config_seed(1) + 1, tol=1e-12, maxiter=200)
+    elif (m, n) == (1 << 20, 1000):
         A, b, x_true, meta = inputs.config1_torch("cuda")
     else:
         A, b, x_true = inputs.make_problem_torch(m, n, kind="svd", cond=1e8, noise=1e-6,
@@ -391,7 +434,7 @@ def main():
                    "m": m, "n": n, "d": d, "zeta": zeta, "tol": tol, "precision": "fp64"},
         "roofline": {"bound": "hbm", "kernel": "lsqr_pass_kernel (fused A p / A^T u pass)",
                      "achieved": pass_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": pass_gbs / HBM_PEAK_GBS,
-                     "traffic": None, "bytes_per_launch": pb, "avg_launch_ms": pass_avg_ms,
+                     "traffic": measured_traffic(m, n), "bytes_per_launch": pb, "avg_launch_ms": pass_avg_ms,
                      "launches": n_pass, "full_launches": n_full},
         "sa": {"kernel": "apply_strip_kernel", "achieved_gbs": apply_gbs, "frac": apply_gbs / HBM_PEAK_GBS,
                "bytes_per_launch": ab, "avg_launch_ms": apply_avg_ms, "launches": n_apply},

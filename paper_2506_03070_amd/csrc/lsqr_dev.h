@@ -50,8 +50,8 @@ __device__ __forceinline__ void reduce_q_block(const double *__restrict__ qpart,
 }
 
 // After y = R^-T q is complete: beta = ||u_hat||, v_hat = y/beta - beta v,
-// alpha = ||v_hat||, v = v_hat/alpha (Alg. 2 lines 4-6 in the App. D.4.1
-// order).  One workgroup.
+// alpha = ||v_hat||, v = v_hat/alpha (the bidiagonalisation step of Alg. 2,
+// in the App. D.4.1 order).  One workgroup.
 __device__ __forceinline__ void lower_epilogue(int n, int G, const double *__restrict__ nrmpart, double *y,
                                                double *__restrict__ v, LsqrState *st, LowerShared &sh) {
   const int t = threadIdx.x;
@@ -80,7 +80,7 @@ __device__ __forceinline__ void lower_epilogue(int n, int G, const double *__res
 }
 
 // After p = R^-1 v is complete: initialisation (w = p) or the plane rotation
-// of Alg. 2 line 7, x += (phi/rho) w, w = p - (theta/rho) w, the stopping
+// of Alg. 2, x += (phi/rho) w, w = p - (theta/rho) w, the stopping
 // test and the coefficients of the next pass.  One workgroup.  When the
 // solve finishes, *done_count (nullable) is incremented once.
 __device__ __forceinline__ void upper_epilogue(int n, const double *p, double *__restrict__ w,
@@ -114,7 +114,7 @@ __device__ __forceinline__ void upper_epilogue(int n, const double *p, double *_
     }
     return;
   }
-  // plane rotation (Alg. 2, line 7) with beta_{t+1}, alpha_{t+1}
+  // plane rotation of Alg. 2 with beta_{t+1}, alpha_{t+1}
   const double rhobar_old = st->rhobar, phibar_old = st->phibar;
   const double rho = sqrt(rhobar_old * rhobar_old + beta * beta);
   const double cs = rhobar_old / rho, sn = beta / rho;
