@@ -63,12 +63,21 @@ struct PassTypes<3> {
 
 // WC waves split the columns of a row (64*VEC*J columns each); WR = 16/WC
 // row groups share the workgroup.
+//
+// Row distribution: workgroup g first takes rows [g S, (g+1) S) (S =
+// rows_per_wg, a whole number of steps); the rows from dyn_begin = grid S to
+// m are claimed in chunks of `chunk` rows from the counter dyn[0], so that
+// workgroups on faster XCDs take more of the tail (the eight XCDs finish a
+// static split up to ~7% apart).  The last workgroup to finish resets
+// dyn[0..1] to zero for the next launch; they must be zero before the first.
+// The rows a workgroup sums into its partials then depend on timing, so q
+// and ||u||^2 are reproducible to rounding only.
 template <int MODE, int VEC, int J, int WC>
 __global__ __launch_bounds__(kPassThreads) void lsqr_pass_kernel(
     const typename PassTypes<MODE>::TA *__restrict__ A, int64_t lda, int64_t m, int n,
     const typename PassTypes<MODE>::TC *__restrict__ p, const typename PassTypes<MODE>::TUI *u_in,
     typename PassTypes<MODE>::TUO *u_out, const LsqrState *__restrict__ st, double *__restrict__ qpart,
-    double *__restrict__ nrmpart, int64_t rows_per_wg) {
+    double *__restrict__ nrmpart, int64_t rows_per_wg, int64_t dyn_begin, int chunk, unsigned int *dyn) {
   using TA = typename PassTypes<MODE>::TA;
   using TC = typename PassTypes<MODE>::TC;
   constexpr int WR = kPassWaves / WC;
@@ -96,10 +105,12 @@ __global__ __launch_bounds__(kPassThreads) void lsqr_pass_kernel(
       q[j][e] = TC(0);
     }
 
-  const int64_t i_begin = static_cast<int64_t>(blockIdx.x) * rows_per_wg;
-  const int64_t i_end = min(m, i_begin + rows_per_wg);
-  const int64_t nsteps = i_end > i_begin ? (i_end - i_begin + WR * R - 1) / (WR * R) : 0;
+  __shared__ unsigned int next_chunk[2];
   double nrm = 0.0;
+  // rows [i_begin, i_end), WR * R per step; for WC > 1 the caller separates
+  // two calls by a barrier (the exchange buffer parity restarts)
+  auto rows = [&](int64_t i_begin, int64_t i_end) {
+  const int64_t nsteps = i_end > i_begin ? (i_end - i_begin + WR * R - 1) / (WR * R) : 0;
   for (int64_t step = 0; step < nsteps; ++step) {
     const int64_t base = i_begin + step * (WR * R) + wr * R;
     TA a[R][J][VEC];
@@ -163,6 +174,27 @@ __global__ __launch_bounds__(kPassThreads) void lsqr_pass_kernel(
       }
     }
   }
+  };
+
+  // The static range first, then claimed chunks.  One thread claims; each
+  // claim is issued before the range in hand is processed and published at
+  // the barrier that ends it (the first before the static range).
+  const bool dynamic = dyn_begin < m;
+  unsigned int claim = 0;
+  if (dynamic && threadIdx.x == 0) claim = atomicAdd(dyn, 1u);
+  const int64_t s_begin = static_cast<int64_t>(blockIdx.x) * rows_per_wg;
+  int64_t r0 = s_begin, r1 = min(min(m, dyn_begin), s_begin + rows_per_wg);
+  for (int it = 0;; ++it) {
+    if (it > 0 && threadIdx.x == 0) claim = atomicAdd(dyn, 1u);
+    rows(r0, r1);
+    if (!dynamic) break;
+    if (threadIdx.x == 0) next_chunk[it & 1] = claim;
+    __syncthreads();
+    // the same LDS word in every lane: keep the range in scalar registers
+    r0 = dyn_begin + static_cast<int64_t>(__builtin_amdgcn_readfirstlane(next_chunk[it & 1])) * chunk;
+    if (r0 >= m) break;
+    r1 = min(m, r0 + chunk);
+  }
 
   // Per-workgroup partials: q (row groups combined in a fixed order through
   // LDS) and ||u||^2.
@@ -197,6 +229,12 @@ __global__ __launch_bounds__(kPassThreads) void lsqr_pass_kernel(
     double s = 0.0;
     for (int w = 0; w < kPassWaves; ++w) s += nbuf[w];
     nrmpart[blockIdx.x] = s;
+    // every claim of this workgroup has returned (its value was used), so
+    // the last workgroup here sees no further claims
+    if (dynamic && atomicAdd(dyn + 1, 1u) == gridDim.x - 1) {
+      atomicExch(dyn, 0u);
+      atomicExch(dyn + 1, 0u);
+    }
   }
 }
 
@@ -406,9 +444,11 @@ __global__ __launch_bounds__(kTrsvThreads) void lsqr_update_kernel(const double 
 
 // Fresh state for an LSQR run; clears the chain flags of the two solves.
 __global__ void lsqr_init_state_kernel(LsqrState *st, double tol, int maxiter, int *flags, int nflags,
-                                       int total_iters, int rel) {
+                                       int total_iters, int rel, unsigned int *dyn) {
   for (int i = threadIdx.x; i < nflags; i += blockDim.x) flags[i] = 0;
   if (threadIdx.x != 0) return;
+  __hip_atomic_store(dyn, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(dyn + 1, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   st->alpha = st->beta = st->rhobar = st->phibar = 0.0;
   st->alpha_new = st->beta_new = 0.0;
   st->c_ap = -1.0;
@@ -540,32 +580,52 @@ int occupancy(const void *fn) {
 struct PassPlan {
   const void *fn;
   int grid;
-  int64_t rows_per_wg;
+  int64_t rows_per_wg;  // static rows per workgroup
+  int64_t dyn_begin;    // first row of the dynamically claimed tail
+  int chunk;            // rows per claim
 };
 
 int max_grid(sap_ctx *ctx) { return ctx->num_cus * 2; }
 
+// Rows one step of the kernel pick_pass returns for c covers: WR = 16 / WC
+// row groups of R rows (J as pick_vec resolves it).
+int rows_per_step(const PassCfg &c) {
+  const int jmax = std::min(16 / c.vec, 8);
+  const int j = c.wc == 1 ? (c.j == 2 || c.j == 4 ? c.j : jmax) : jmax;
+  const int jv = j * c.vec;
+  const int r = jv >= 16 ? 1 : std::min(4, 16 / jv);
+  return (kPassWaves / c.wc) * r;
+}
+
+// Share of the rows assigned statically (the rest is claimed in chunks).
+constexpr double kStaticShare = 0.875;
+constexpr int kStepsPerChunk = 4;
+
 PassPlan plan_pass(sap_ctx *ctx, int mode, int64_t m, int n, int64_t lda, const void *A) {
   const void *fn;
-  if (mode == 0) fn = pick_pass<0>(choose_pass<0>(n, lda, A));
-  else if (mode == 1) fn = pick_pass<1>(choose_pass<1>(n, lda, A));
-  else if (mode == 2) fn = pick_pass<2>(choose_pass<2>(n, lda, A));
-  else fn = pick_pass<3>(choose_pass<3>(n, lda, A));
+  PassCfg c;
+  if (mode == 0) { c = choose_pass<0>(n, lda, A); fn = pick_pass<0>(c); }
+  else if (mode == 1) { c = choose_pass<1>(n, lda, A); fn = pick_pass<1>(c); }
+  else if (mode == 2) { c = choose_pass<2>(n, lda, A); fn = pick_pass<2>(c); }
+  else { c = choose_pass<3>(n, lda, A); fn = pick_pass<3>(c); }
   int64_t grid = static_cast<int64_t>(ctx->num_cus) * std::min(2, occupancy(fn));
   const int64_t min_rows = 64;
   if (grid * min_rows > m) grid = (m + min_rows - 1) / min_rows;
   if (grid < 1) grid = 1;
-  return PassPlan{fn, static_cast<int>(grid), (m + grid - 1) / grid};
+  const int64_t step = rows_per_step(c);
+  const int64_t per_wg = static_cast<int64_t>(kStaticShare * static_cast<double>(m) / static_cast<double>(grid)) /
+                         step * step;
+  return PassPlan{fn, static_cast<int>(grid), per_wg, grid * per_wg, static_cast<int>(step * kStepsPerChunk)};
 }
 
 void launch_pass(sap_ctx *ctx, const PassPlan &pl, const void *A, int64_t lda, int64_t m, int n, const void *p,
                  const void *u_in, void *u_out, const LsqrState *st, double *qpart, double *nrmpart,
-                 hipStream_t s) {
-  int64_t lda_ = lda, m_ = m, rows = pl.rows_per_wg;
-  int n_ = n;
+                 unsigned int *dyn, hipStream_t s) {
+  int64_t lda_ = lda, m_ = m, rows = pl.rows_per_wg, dyn_begin = pl.dyn_begin;
+  int n_ = n, chunk = pl.chunk;
   const void *A_ = A, *p_ = p, *ui = u_in, *st_ = st;
-  void *uo = u_out, *qp = qpart, *np = nrmpart;
-  void *args[] = {&A_, &lda_, &m_, &n_, &p_, &ui, &uo, &st_, &qp, &np, &rows};
+  void *uo = u_out, *qp = qpart, *np = nrmpart, *dy = dyn;
+  void *args[] = {&A_, &lda_, &m_, &n_, &p_, &ui, &uo, &st_, &qp, &np, &rows, &dyn_begin, &chunk, &dy};
   hipEvent_t pb = prof_begin(ctx, s);
   const hipError_t e = hipLaunchKernel(pl.fn, dim3(pl.grid), dim3(kPassThreads), args, 0, s);
   if (e != hipSuccess) (void)e;  // reported by the hipGetLastError check after the batch
@@ -583,6 +643,7 @@ size_t lsqr_workspace_bytes(sap_ctx *ctx, int64_t m, int n) {
   bytes += 6 * static_cast<size_t>(n) * sizeof(double);  // v w p x0copy (+1 spare)
   bytes += static_cast<size_t>(m) * sizeof(double);     // u
   bytes += (3 * nblk + 16) * sizeof(int) + 4096 * sizeof(double);                  // flags, err, norm partials
+  bytes += 2 * sizeof(unsigned int);                                               // pass claim counters
   bytes += 2 * static_cast<size_t>(n) * n * sizeof(double);                        // M = R^-1 and M^T
   bytes += (static_cast<size_t>((G + kQSlice - 1) / kQSlice) + 2) * n * sizeof(double);  // q slices, v_hat
   bytes += static_cast<size_t>((n + 15) / 16 + 1) * sizeof(double);                // ||v_hat||^2 partials
@@ -673,6 +734,7 @@ sap_status run_lsqr(sap_ctx *ctx, const sap_problem *prob, const double *R, int6
   int *flags_x0 = flags + 2 * nblk;
   int *err = cv.take<int>(4);
   unsigned int *ticket = reinterpret_cast<unsigned int *>(err + 1);
+  unsigned int *dyn = cv.take<unsigned int>(2);  // pass row-claim counters
   double *normpart = cv.take<double>(4096);
   const int nslices = (max_grid(ctx) + kQSlice - 1) / kQSlice;
   double *M = cv.take<double>(static_cast<size_t>(n) * n);
@@ -714,7 +776,7 @@ sap_status run_lsqr(sap_ctx *ctx, const sap_problem *prob, const double *R, int6
     SAP_HIP_TRY(hipGetLastError());
   }
   lsqr_init_state_kernel<<<1, 256, 0, s>>>(st, refine ? kInnerTol : tol, maxiter, flags, 2 * nblk, 0,
-                                           refine ? 1 : 0);
+                                           refine ? 1 : 0, dyn);
   const int ngrid = static_cast<int>(std::min<int64_t>(256, (m + 1023) / 1024));
   norm_kernel<<<ngrid, 1024, 0, s>>>(prob->b, m, normpart, ticket, st);
   SAP_HIP_TRY(hipGetLastError());
@@ -725,7 +787,7 @@ sap_status run_lsqr(sap_ctx *ctx, const sap_problem *prob, const double *R, int6
   auto iteration = [&](const PassPlan &pl, const void *pv, const void *uin) {
     const int G = pl.grid;
     const int qsl = (G + kQSlice - 1) / kQSlice;
-    launch_pass(ctx, pl, prob->A, prob->lda, m, n, pv, uin, u, st, qpart, nrmpart, s);
+    launch_pass(ctx, pl, prob->A, prob->lda, m, n, pv, uin, u, st, qpart, nrmpart, dyn, s);
     q_slices_kernel<<<dim3((n + 63) / 64, qsl), 256, 0, s>>>(qpart, G, n, qs);
     lsqr_mtq_kernel<<<ngemv, 1024, 0, s>>>(M, n, qs, qsl, nrmpart, G, v, vh, vpart, st);
     lsqr_mv_kernel<<<ngemv, 1024, 0, s>>>(Mt, n, vh, vpart, ngemv, nrmpart, G, v, p, refine ? p32 : nullptr, st);
@@ -741,7 +803,7 @@ sap_status run_lsqr(sap_ctx *ctx, const sap_problem *prob, const double *R, int6
   const int max_outer = refine ? (max_refine > 0 ? max_refine : 10) : 1;
   for (int outer = 0; outer < max_outer; ++outer) {
     if (outer > 0)
-      lsqr_init_state_kernel<<<1, 256, 0, s>>>(st, kInnerTol, maxiter, flags, 0, hs.total_iters, 1);
+      lsqr_init_state_kernel<<<1, 256, 0, s>>>(st, kInnerTol, maxiter, flags, 0, hs.total_iters, 1, dyn);
     if (refine) copy_f64_kernel<<<(n + 255) / 256, 256, 0, s>>>(x, xprev, n);
     // Initialisation: beta_1 u_1 = b - A x (the pass with p = x, u_in = b);
     // in the refinement form this is the FP64-accumulated residual pass.

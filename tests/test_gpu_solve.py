@@ -172,8 +172,9 @@ def test_solve_errors(sap):
 
 
 def test_solve_deterministic(sap):
-    """Fixed reduction orders everywhere except the LDS sketch-apply adds:
-    repeated solves agree to the solver tolerance and the sketch bit for bit."""
+    """Fixed reduction orders everywhere except the LDS sketch-apply adds and
+    the rows each workgroup of the LSQR pass claims at run time: repeated
+    solves agree to the solver tolerance."""
     import torch
     p = inputs.make_problem(20000, 64, kind="svd", cond=1e6, noise=1e-6, seed=5)
     r1 = sap.sap_solve(_dev(p.A), _dev(p.b), 256, 8, 3)
