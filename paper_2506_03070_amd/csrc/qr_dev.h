@@ -21,42 +21,77 @@ __device__ __forceinline__ double vval(int r, int k, double y) {
 // Shared state of the panel factorisation and the block-reflector apply (LDS).
 template <int NB>
 struct PanelShared {
-  double red[kPanelWaves][NB * NB + 1];
-  double bc[2];
-  double Ts[NB][NB];
-  double gdot[NB * NB];
+  double red[kPanelWaves][NB * NB + 1];  // per-wave partials of W = V^T C
   double W2[NB][NB];
+  double cred[2][kPanelWaves][NB];       // per-wave partials of one panel column, by column parity
+  double ctot[2][2 * NB];                // its totals (0..NB-1) and row J of the panel (NB..2NB-1)
+  double G[NB][NB];                      // G[J][q] = v_q^T v_J (q < J), for T
+  double tauv[NB];
+  double Tl[NB * NB];                    // T of the panel being applied
 };
 
 // Rows: thread t holds panel-relative rows lr = t + 512 s - roff (s < S);
 // rows with lr < 0 lie above the panel (they belong to R) and only ride along.
 
 // Column J of the panel: reflector, update of columns J+1.. of the panel,
-// column J of T.  J is a template parameter so that every register index of
-// the panel P is static (no scratch).
+// and what column J of T needs (tau_J, V_{<J}^T v_J, kept in LDS).  One batched
+// workgroup reduction per column: with a = column J below the diagonal,
+// alpha its diagonal entry and v = [1; a / (alpha - beta)], every quantity
+// the column needs follows from a^T a and a^T (column x) for all x and from
+// row J of the panel: v^T (column x) = P[J][x] + (a^T column x) / (alpha - beta).
+// J is a template parameter so that every register index of the panel P is
+// static (no scratch).
 template <int S, int NB, int J>
 __device__ __forceinline__ void panel_column(double (&P)[S][NB], PanelShared<NB> &sh, int nb, int dr, int roff,
                                              int k0, double *__restrict__ tau) {
+  constexpr int B = J & 1;  // LDS buffers alternate between columns: one barrier fewer
   const int t = threadIdx.x;
   const int lane = t & (kWave - 1), wave = t / kWave;
-  // --- norm of the part below the diagonal ---
-  double part = 0.0;
+  // Straight-line code: masks instead of per-row branches (the column is
+  // latency-bound, and every branch costs exec-mask bookkeeping).
+  double acc[NB];
+#pragma unroll
+  for (int x = 0; x < NB; ++x) acc[x] = 0.0;
 #pragma unroll
   for (int s = 0; s < S; ++s) {
     const int lr = t + kPanelThreads * s - roff;
-    if (lr > J && lr < dr) part += P[s][J] * P[s][J];
+    const double a = (lr > J && lr < dr) ? P[s][J] : 0.0;
+#pragma unroll
+    for (int x = 0; x < NB; ++x) acc[x] += a * P[s][x];
   }
-  part = wave_sum_u(part);
-  __syncthreads();  // previous readers of red/bc are done
-  if (lane == 0) sh.red[wave][0] = part;
+  // row J of the panel sits in one register row of one thread
+  const int jrow = J + roff;  // uniform
+  if (J < dr && jrow < S * kPanelThreads && t == (jrow & (kPanelThreads - 1))) {
+    const int so = jrow / kPanelThreads;
 #pragma unroll
-  for (int s = 0; s < S; ++s)
-    if (t + kPanelThreads * s - roff == J) sh.bc[0] = P[s][J];  // alpha
+    for (int s = 0; s < S; ++s)
+      if (s == so) {
+#pragma unroll
+        for (int x = 0; x < NB; ++x) sh.ctot[B][NB + x] = P[s][x];
+      }
+  }
+#pragma unroll
+  for (int x = 0; x < NB; ++x) acc[x] = wave_sum_u(acc[x]);
+  if (lane == 0) {
+#pragma unroll
+    for (int x = 0; x < NB; ++x) sh.cred[B][wave][x] = acc[x];
+  }
   __syncthreads();
-  double sq = 0.0;
+  if (t < NB) {
+    double s_ = 0.0;
+    for (int w = 0; w < kPanelWaves; ++w) s_ += sh.cred[B][w][t];
+    sh.ctot[B][t] = s_;
+  }
+  __syncthreads();
+  const bool has_row = J < dr;  // uniform; a panel shorter than J+1 rows has no row J
+  double tot[NB], row[NB];
 #pragma unroll
-  for (int w = 0; w < kPanelWaves; ++w) sq += sh.red[w][0];
-  const double alpha = sh.bc[0];
+  for (int x = 0; x < NB; ++x) {
+    tot[x] = sh.ctot[B][x];
+    row[x] = has_row ? sh.ctot[B][NB + x] : 0.0;
+  }
+  const double alpha = row[J];
+  const double sq = tot[J];
   double tj, beta, scale;
   if (sq == 0.0) {
     tj = 0.0;
@@ -68,60 +103,33 @@ __device__ __forceinline__ void panel_column(double (&P)[S][NB], PanelShared<NB>
     tj = (beta - alpha) / beta;
     scale = 1.0 / (alpha - beta);
   }
-#pragma unroll
-  for (int s = 0; s < S; ++s) {
-    const int lr = t + kPanelThreads * s - roff;
-    if (lr > J && lr < dr) P[s][J] *= scale;
-    if (lr == J) P[s][J] = beta;
-  }
-  // --- dot_x = v_J^T (column x) for every x != J (x > J: update weights,
-  //     x < J: V_{<J}^T v_J for the T factor) ---
-  double dots[NB];
+  // dots[x] = v^T (column x): x > J weights the update of column x, x < J
+  // gives V_{<J}^T v for the T factor
+  double dots[NB], wgt[NB];
 #pragma unroll
   for (int x = 0; x < NB; ++x) {
-    double acc = 0.0;
-    if (x != J) {
-#pragma unroll
-      for (int s = 0; s < S; ++s) {
-        const int lr = t + kPanelThreads * s - roff;
-        if (lr > J && lr < dr) acc += P[s][J] * P[s][x];
-        else if (lr == J) acc += P[s][x];
-      }
-    }
-    dots[x] = wave_sum_u(acc);
+    dots[x] = x == J ? 0.0 : row[x] + scale * tot[x];
+    wgt[x] = (x > J && x < nb) ? tj * dots[x] : 0.0;
   }
-  __syncthreads();
-  if (lane == 0) {
-#pragma unroll
-    for (int x = 0; x < NB; ++x) sh.red[wave][x] = dots[x];
-  }
-  __syncthreads();
-  if (t < NB) {
-    double s_ = 0.0;
-    for (int w = 0; w < kPanelWaves; ++w) s_ += sh.red[w][t];
-    sh.gdot[t] = s_;
-  }
-  __syncthreads();
-#pragma unroll
-  for (int x = 0; x < NB; ++x) dots[x] = sh.gdot[x];
-  // --- apply H_J to the columns right of J inside the panel ---
+  // column J becomes v below the diagonal and beta on it; H_J = I - tj v v^T
+  // is applied to the panel columns right of J (v = 0 outside the panel rows
+  // from J on, where the subtraction leaves the value unchanged)
 #pragma unroll
   for (int s = 0; s < S; ++s) {
     const int lr = t + kPanelThreads * s - roff;
-    const double v = (lr > J && lr < dr) ? P[s][J] : (lr == J ? 1.0 : 0.0);
+    const bool below = lr > J && lr < dr;
+    const bool diag = lr == J;
+    const double v = below ? P[s][J] * scale : (diag ? 1.0 : 0.0);
+    P[s][J] = below ? v : (diag ? beta : P[s][J]);
 #pragma unroll
-    for (int x = J + 1; x < NB; ++x)
-      if (x < nb) P[s][x] -= tj * dots[x] * v;
+    for (int x = J + 1; x < NB; ++x) P[s][x] -= wgt[x] * v;
   }
-  // --- T(:, J) = [-tau_J T(0:J,0:J) V_{<J}^T v_J ; tau_J] (dlarft) ---
+  // LDS only: a global store here would hold up the next column, since a
+  // workgroup barrier waits for the wave's outstanding memory operations
   if (t == 0) {
-    for (int l = 0; l < J; ++l) {
-      double acc = 0.0;
-      for (int q = l; q < J; ++q) acc += sh.Ts[l][q] * sh.gdot[q];
-      sh.Ts[l][J] = -tj * acc;
-    }
-    sh.Ts[J][J] = tj;
-    tau[k0 + J] = tj;
+    sh.tauv[J] = tj;
+#pragma unroll
+    for (int q = 0; q < J; ++q) sh.G[J][q] = dots[q];
   }
 }
 
@@ -137,39 +145,64 @@ __device__ __forceinline__ void panel_columns(double (&P)[S][NB], PanelShared<NB
 }
 
 // Factor the panel held in P (columns k0 .. k0+nb-1, rows from k0); writes
-// tau and T (column-major NB x NB).
+// tau and T (column-major NB x NB).  T follows the dlarft recurrence
+// T(0:J, J) = -tau_J T(0:J, 0:J) V_{<J}^T v_J, T(J, J) = tau_J once all
+// columns are done: row l of T depends only on its own earlier entries, so
+// thread l builds row l.  Ends without a barrier (the tau and T stores stay
+// in flight); a caller that reuses `sh` afterwards synchronises first.
 template <int S, int NB>
 __device__ __forceinline__ void factor_panel(double (&P)[S][NB], PanelShared<NB> &sh, int nb, int dr, int roff,
                                              int k0, double *__restrict__ tau, double *__restrict__ Tout) {
   const int t = threadIdx.x;
+  __syncthreads();  // earlier users of the shared buffers are done
+  if (t < NB * NB) sh.G[t / NB][t % NB] = 0.0;
+  if (t < NB) sh.tauv[t] = 0.0;
+  panel_columns<S, NB, 0>(P, sh, nb, dr, roff, k0, tau);  // its first barrier orders the zeroing
   __syncthreads();
-  if (t < NB * NB) sh.Ts[t / NB][t % NB] = 0.0;
-  panel_columns<S, NB, 0>(P, sh, nb, dr, roff, k0, tau);
-  __syncthreads();
-  if (t < NB * NB) Tout[t] = sh.Ts[t % NB][t / NB];
+  if (t < NB) {
+    const int l = t;
+    double row[NB];
+#pragma unroll
+    for (int J = 0; J < NB; ++J) {
+      double a = 0.0;
+#pragma unroll
+      for (int q = 0; q < J; ++q)
+        if (q >= l) a += row[q] * sh.G[J][q];
+      row[J] = J < l ? 0.0 : (J == l ? sh.tauv[J] : -sh.tauv[J] * a);
+      Tout[l + J * NB] = row[J];
+    }
+    if (l < nb) tau[k0 + l] = sh.tauv[l];
+  }
 }
 
 // C <- (I - V T^T V^T) C for the block C[S][NB] (rows from k0), where V are
 // the nbp Householder vectors stored in columns k0.. of Y (unit diagonal
 // implicit) and T the panel's triangular factor (column-major NB x NB).
+// Writes `sh` before its first barrier: no other use of `sh` may be pending.
 template <int S, int NB>
 __device__ __forceinline__ void apply_panel_qt(const double *__restrict__ Y, int64_t ldy, int dr, int k0, int nbp,
                                                const double *__restrict__ T, double (&C)[S][NB], int ncb,
                                                PanelShared<NB> &sh) {
+  if (nbp <= 0 || dr <= 0) return;  // uniform: no reflectors, nothing to apply
   const int t = threadIdx.x;
   const int lane = t & (kWave - 1), wave = t / kWave;
   const double *__restrict__ vb = Y + k0 + static_cast<int64_t>(k0) * ldy;
+  const double tload = t < NB * NB ? T[t] : 0.0;  // in flight with the V loads
+  // Every load is issued unconditionally from an in-range address (row and
+  // column clamped, dr >= 1 and nbp >= 1) and masked afterwards: no branch
+  // separates the loads.
   double V[S][NB];
 #pragma unroll
   for (int s = 0; s < S; ++s) {
-    const unsigned lr = static_cast<unsigned>(t + kPanelThreads * s);
+    const int lr = t + kPanelThreads * s;
+    const int rr = min(lr, dr - 1);
 #pragma unroll
     for (int i = 0; i < NB; ++i) {
-      double v = 0.0;
-      if (i < nbp && lr < static_cast<unsigned>(dr)) v = vval(static_cast<int>(lr), i, lr > static_cast<unsigned>(i) ? vb[static_cast<int64_t>(i) * ldy + lr] : 0.0);
-      V[s][i] = v;
+      const double y = vb[static_cast<int64_t>(min(i, nbp - 1)) * ldy + rr];
+      V[s][i] = (i < nbp && lr < dr) ? vval(lr, i, y) : 0.0;
     }
   }
+  if (t < NB * NB) sh.Tl[t] = tload;
   // W = V^T C  (NB x NB values, each a workgroup-wide sum)
   __syncthreads();
 #pragma unroll
@@ -183,17 +216,16 @@ __device__ __forceinline__ void apply_panel_qt(const double *__restrict__ Y, int
       if (lane == 0) sh.red[wave][i * NB + c] = acc;
     }
   __syncthreads();
-  if (t < NB * NB) {
-    double s_ = 0.0;
-    for (int w = 0; w < kPanelWaves; ++w) s_ += sh.red[w][t];
-    sh.gdot[t] = s_;  // W[i][c] at i*NB + c
-  }
-  __syncthreads();
-  // W2 = T^T W: W2[i][c] = sum_{l <= i} T[l][i] W[l][c]
+  // W2 = T^T W: W2[i][c] = sum_{l <= i} T[l][i] W[l][c], each W[l][c] summed
+  // over the waves by the thread that needs it (no separate pass for W)
   if (t < NB * NB) {
     const int i = t / NB, c = t % NB;
     double s_ = 0.0;
-    for (int l = 0; l <= i && l < nbp; ++l) s_ += T[l + i * NB] * sh.gdot[l * NB + c];
+    for (int l = 0; l <= i && l < nbp; ++l) {
+      double wlc = 0.0;
+      for (int w = 0; w < kPanelWaves; ++w) wlc += sh.red[w][l * NB + c];
+      s_ += sh.Tl[l + i * NB] * wlc;
+    }
     sh.W2[i][c] = (i < nbp && c < ncb) ? s_ : 0.0;
   }
   __syncthreads();
@@ -208,16 +240,28 @@ __device__ __forceinline__ void apply_panel_qt(const double *__restrict__ Y, int
     }
 }
 
+// Loads rows r0 .. r0+dr-1 of columns c0 .. c0+ncb-1.  Addresses are
+// clamped into the block, so the loads need no branches and no select waits
+// for their data: a slot outside the block (row >= dr or column >= ncb) holds
+// a copy of an entry inside it.  Every user masks those slots: the apply
+// weights them by V = 0 and W2 = 0, the panel factorisation by its row and
+// column masks, and store_block does not write them.
 template <int S, int NB>
 __device__ __forceinline__ void load_block(const double *__restrict__ Y, int64_t ldy, int r0, int dr, int c0, int ncb,
                                            double (&C)[S][NB]) {
+  if (dr <= 0 || ncb <= 0) {  // uniform
+#pragma unroll
+    for (int s = 0; s < S; ++s)
+#pragma unroll
+      for (int c = 0; c < NB; ++c) C[s][c] = 0.0;
+    return;
+  }
   const double *__restrict__ base = Y + r0 + static_cast<int64_t>(c0) * ldy;
 #pragma unroll
   for (int s = 0; s < S; ++s) {
-    const unsigned lr = static_cast<unsigned>(threadIdx.x + kPanelThreads * s);
+    const int rr = min(static_cast<int>(threadIdx.x) + kPanelThreads * s, dr - 1);
 #pragma unroll
-    for (int c = 0; c < NB; ++c)
-      C[s][c] = (lr < static_cast<unsigned>(dr) && c < ncb) ? base[static_cast<int64_t>(c) * ldy + lr] : 0.0;
+    for (int c = 0; c < NB; ++c) C[s][c] = base[static_cast<int64_t>(min(c, ncb - 1)) * ldy + rr];
   }
 }
 
