@@ -244,75 +244,94 @@ __global__ __launch_bounds__(kPassThreads) void lsqr_pass_kernel(
 // the whole GPU instead of two chains of dependent triangular blocks.
 
 // Upper triangle of M (n x n, column-major, ld n) by blocked back
-// substitution of R X = I: for the C columns c of this workgroup (all in
+// substitution of R X = I: for the C columns of this workgroup (all in
 // diagonal block jb), X_jb = D_jb (the inverted diagonal block) and, for
 // ib = jb-1 .. 0, X_ib = -D_ib sum_{kb > ib} R_{ib,kb} X_kb.  The columns
-// being built live in LDS; R and the D blocks are read from memory.
+// being built live in LDS.  Each step is a 64 x K x C product followed by a
+// 64 x 64 x C one; the K terms are split over the 16 waves (lane = row of the
+// block, eight loads of R in flight per lane), so a step costs a few load
+// latencies instead of K / 8 of them; partial sums are combined in a fixed
+// order.  LDS: C n doubles of X and 16 * 64 * C partials.
+constexpr int kInvThreads = 1024;
+constexpr int kInvWaves = kInvThreads / kWave;
+
 template <int C>
-__global__ __launch_bounds__(256) void tri_inverse_kernel(const double *__restrict__ R, int64_t ldr, int n,
-                                                          const double *__restrict__ Dup, double *__restrict__ M) {
+__global__ __launch_bounds__(kInvThreads) void tri_inverse_kernel(const double *__restrict__ R, int64_t ldr, int n,
+                                                                  const double *__restrict__ Dup,
+                                                                  double *__restrict__ M) {
   extern __shared__ unsigned char lds_raw[];
-  double *X = reinterpret_cast<double *>(lds_raw);  // X[k + q * n], q < C
-  __shared__ double Ts[kTrsvB][C + 1];
-  constexpr int G = C < 4 ? C : 4;  // column groups
-  constexpr int CPT = C / G;        // columns per thread
+  double *X = reinterpret_cast<double *>(lds_raw);  // X[k + q n], q < C
+  double *red = X + static_cast<size_t>(C) * n;     // red[(w 64 + r) C + q]; the w = 0 slots then hold the sums
   const int t = threadIdx.x;
-  const int r = t % kTrsvB, cg = t / kTrsvB;
-  const int c0 = blockIdx.x * C;
+  const int lane = t & (kWave - 1), w = t / kWave;
+  const int c0 = static_cast<int>(blockIdx.x) * C;
   const int jb = c0 / kTrsvB;
   const int kend = min(n, (jb + 1) * kTrsvB);
-  for (int ib = jb; ib >= 0; --ib) {
-    const int row = ib * kTrsvB + r;
-    if (ib < jb && cg < G) {
-      double acc[CPT];
+  if (t < kWave * C) {  // X_jb = D_jb (columns of this workgroup)
+    const int q = t / kWave, row = jb * kTrsvB + lane;
+    const double *D = Dup + static_cast<int64_t>(jb) * kTrsvB * kTrsvB;
+    if (row < n) X[row + q * n] = c0 + q < n ? D[lane + (c0 + q - jb * kTrsvB) * kTrsvB] : 0.0;
+  }
+  __syncthreads();
+  for (int ib = jb - 1; ib >= 0; --ib) {
+    const int row = ib * kTrsvB + lane;  // a full block: ib < jb
+    const int k0 = (ib + 1) * kTrsvB;
+    const int per = (kend - k0 + kInvWaves - 1) / kInvWaves;
+    const int ka = min(kend, k0 + w * per), kb = min(kend, ka + per);
+    double acc[C];
 #pragma unroll
-      for (int q = 0; q < CPT; ++q) acc[q] = 0.0;
-      if (row < n) {
-        // eight independent loads of R in flight per thread
-        int k = (ib + 1) * kTrsvB;
-        for (; k + 8 <= kend; k += 8) {
-          double a[8];
+    for (int q = 0; q < C; ++q) acc[q] = 0.0;
+    int k = ka;
+    for (; k + 8 <= kb; k += 8) {
+      double a[8];
 #pragma unroll
-          for (int u = 0; u < 8; ++u) a[u] = R[row + static_cast<int64_t>(k + u) * ldr];
+      for (int u = 0; u < 8; ++u) a[u] = R[row + static_cast<int64_t>(k + u) * ldr];
 #pragma unroll
-          for (int u = 0; u < 8; ++u)
+      for (int u = 0; u < 8; ++u)
 #pragma unroll
-            for (int q = 0; q < CPT; ++q) acc[q] += a[u] * X[k + u + (cg * CPT + q) * n];
-        }
-        for (; k < kend; ++k) {
-          const double a = R[row + static_cast<int64_t>(k) * ldr];
+        for (int q = 0; q < C; ++q) acc[q] += a[u] * X[k + u + q * n];
+    }
+    for (; k < kb; ++k) {
+      const double a = R[row + static_cast<int64_t>(k) * ldr];
 #pragma unroll
-          for (int q = 0; q < CPT; ++q) acc[q] += a * X[k + (cg * CPT + q) * n];
-        }
-      }
+      for (int q = 0; q < C; ++q) acc[q] += a * X[k + q * n];
+    }
 #pragma unroll
-      for (int q = 0; q < CPT; ++q) Ts[r][cg * CPT + q] = acc[q];
+    for (int q = 0; q < C; ++q) red[(w * kWave + lane) * C + q] = acc[q];
+    __syncthreads();
+    if (t < kWave * C) {  // thread (r = lane, q = wave): sum over the waves, into the w = 0 slot
+      const int q = w;
+      double sum = 0.0;
+      for (int ww = 0; ww < kInvWaves; ++ww) sum += red[(ww * kWave + lane) * C + q];
+      red[lane * C + q] = sum;
     }
     __syncthreads();
-    const double *D = Dup + static_cast<int64_t>(ib) * kTrsvB * kTrsvB;
-    if (cg < G) {
-#pragma unroll
-      for (int q = 0; q < CPT; ++q) {
-        const int ql = cg * CPT + q;
-        const int c = c0 + ql;
-        double x = 0.0;
-        if (ib == jb) {
-          x = D[r + (c - jb * kTrsvB) * kTrsvB];
-        } else {
-          for (int qq = 0; qq < kTrsvB; ++qq) x -= D[r + qq * kTrsvB] * Ts[qq][ql];
-        }
-        if (row < n && c < n) X[row + ql * n] = x;
-      }
+    if (t < kWave * C) {  // X_ib = -D_ib T
+      const int q = w;
+      const double *D = Dup + static_cast<int64_t>(ib) * kTrsvB * kTrsvB;
+      double x = 0.0;
+#pragma unroll 16
+      for (int qq = 0; qq < kTrsvB; ++qq) x -= D[lane + qq * kTrsvB] * red[qq * C + q];
+      X[row + q * n] = c0 + q < n ? x : 0.0;
     }
     __syncthreads();
   }
   // write the columns out (rows 0 .. end of block jb; the rest of M's column
   // lies below the diagonal and is never read)
-  for (int e = t; e < kend * C; e += 256) {
+  for (int e = t; e < kend * C; e += kInvThreads) {
     const int k = e % kend, ql = e / kend;
     const int c = c0 + ql;
     if (c < n) M[k + static_cast<int64_t>(c) * n] = X[k + ql * n];
   }
+}
+
+// Columns per workgroup for M = R^-1: as many as fit in LDS (160 KiB per
+// workgroup on gfx950, 1 KiB kept spare), at most 8.
+int tri_inverse_cols(int n) {
+  for (int c = 8; c > 1; c >>= 1)
+    if (static_cast<size_t>(c) * (static_cast<size_t>(n) + kInvWaves * kWave) * sizeof(double) <= 159 * 1024)
+      return c;
+  return 1;
 }
 
 __global__ __launch_bounds__(256) void inverse_transpose_kernel(const double *__restrict__ M, int n,
@@ -764,14 +783,15 @@ sap_status run_lsqr(sap_ctx *ctx, const sap_problem *prob, const double *R, int6
   // M = R^-1 and its transpose (the columns a workgroup builds sit in LDS)
   {
     const unsigned nt = static_cast<unsigned>((n + 31) / 32);
-    if (n <= 1170)
-      tri_inverse_kernel<16><<<(n + 15) / 16, 256, 16 * static_cast<size_t>(n) * 8, s>>>(R, ldr, n, f.Dup, M);
-    else if (n <= 2340)
-      tri_inverse_kernel<8><<<(n + 7) / 8, 256, 8 * static_cast<size_t>(n) * 8, s>>>(R, ldr, n, f.Dup, M);
-    else if (n <= 4680)
-      tri_inverse_kernel<4><<<(n + 3) / 4, 256, 4 * static_cast<size_t>(n) * 8, s>>>(R, ldr, n, f.Dup, M);
-    else
-      tri_inverse_kernel<2><<<(n + 1) / 2, 256, 2 * static_cast<size_t>(n) * 8, s>>>(R, ldr, n, f.Dup, M);
+    const int ci = tri_inverse_cols(n);
+    const size_t lds = static_cast<size_t>(ci) * (static_cast<size_t>(n) + kInvWaves * kWave) * sizeof(double);
+    const unsigned gi = static_cast<unsigned>((n + ci - 1) / ci);
+    switch (ci) {
+      case 8: tri_inverse_kernel<8><<<gi, kInvThreads, lds, s>>>(R, ldr, n, f.Dup, M); break;
+      case 4: tri_inverse_kernel<4><<<gi, kInvThreads, lds, s>>>(R, ldr, n, f.Dup, M); break;
+      case 2: tri_inverse_kernel<2><<<gi, kInvThreads, lds, s>>>(R, ldr, n, f.Dup, M); break;
+      default: tri_inverse_kernel<1><<<gi, kInvThreads, lds, s>>>(R, ldr, n, f.Dup, M); break;
+    }
     inverse_transpose_kernel<<<dim3(nt, nt), 256, 0, s>>>(M, n, Mt);
     SAP_HIP_TRY(hipGetLastError());
   }
