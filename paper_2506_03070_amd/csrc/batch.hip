@@ -538,7 +538,8 @@ size_t item_bytes(int64_t m, int n, int d, int zeta, sap_dtype at) {
   b += 256 + sizeof(int32_t) * m * zeta;
   b += 256 + sizeof(uint64_t) * m;
   b += 256 + sizeof(double) * d * nc;
-  b += 3 * (256 + sizeof(double) * 256);
+  b += 256 + sizeof(double) * nc;             // tau, one per column
+  b += 2 * (256 + sizeof(double) * 256);      // T of two panels (NB x NB <= 256)
   b += 256 + sizeof(double) * n * n;
   b += 2 * (256 + sizeof(double) * nblk * kTrsvB * kTrsvB);
   b += 256 + sizeof(int) * 3 * nblk;
@@ -560,7 +561,7 @@ void carve_item(BatchItem &it, void *base, sap_dtype at, int64_t rows_per_chunk)
   it.sign = cv.take<uint64_t>(m);
   (void)at;
   it.Y = cv.take<double>(static_cast<size_t>(d) * nc);
-  it.tau = cv.take<double>(256);
+  it.tau = cv.take<double>(nc);
   it.T0 = cv.take<double>(256);
   it.T1 = cv.take<double>(256);
   it.Rt = cv.take<double>(static_cast<size_t>(n) * n);

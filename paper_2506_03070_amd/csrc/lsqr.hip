@@ -616,13 +616,18 @@ int rows_per_step(const PassCfg &c) {
   return (kPassWaves / c.wc) * r;
 }
 
-// Share of the rows assigned statically (the rest is claimed in chunks).
+// Share of the rows assigned statically (the rest is claimed in chunks),
+// for passes over at least kDynamicMinBytes of A; shorter passes split the
+// rows statically (the XCD imbalance is a few microseconds there, less than
+// the claims cost).
 constexpr double kStaticShare = 0.875;
 constexpr int kStepsPerChunk = 4;
+constexpr double kDynamicMinBytes = 512.0 * 1024 * 1024;
 
 PassPlan plan_pass(sap_ctx *ctx, int mode, int64_t m, int n, int64_t lda, const void *A) {
   const void *fn;
   PassCfg c;
+  const double a_bytes = static_cast<double>(m) * n * (mode == 0 ? 8.0 : 4.0);
   if (mode == 0) { c = choose_pass<0>(n, lda, A); fn = pick_pass<0>(c); }
   else if (mode == 1) { c = choose_pass<1>(n, lda, A); fn = pick_pass<1>(c); }
   else if (mode == 2) { c = choose_pass<2>(n, lda, A); fn = pick_pass<2>(c); }
@@ -632,6 +637,7 @@ PassPlan plan_pass(sap_ctx *ctx, int mode, int64_t m, int n, int64_t lda, const 
   if (grid * min_rows > m) grid = (m + min_rows - 1) / min_rows;
   if (grid < 1) grid = 1;
   const int64_t step = rows_per_step(c);
+  if (a_bytes < kDynamicMinBytes) return PassPlan{fn, static_cast<int>(grid), (m + grid - 1) / grid, m, 0};
   const int64_t per_wg = static_cast<int64_t>(kStaticShare * static_cast<double>(m) / static_cast<double>(grid)) /
                          step * step;
   return PassPlan{fn, static_cast<int>(grid), per_wg, grid * per_wg, static_cast<int>(step * kStepsPerChunk)};

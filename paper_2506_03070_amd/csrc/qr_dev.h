@@ -49,26 +49,25 @@ __device__ __forceinline__ void panel_column(double (&P)[S][NB], PanelShared<NB>
   const int lane = t & (kWave - 1), wave = t / kWave;
   // Straight-line code: masks instead of per-row branches (the column is
   // latency-bound, and every branch costs exec-mask bookkeeping).
-  double acc[NB];
+  double acc[NB], rowv[NB];
 #pragma unroll
-  for (int x = 0; x < NB; ++x) acc[x] = 0.0;
+  for (int x = 0; x < NB; ++x) acc[x] = rowv[x] = 0.0;
+  bool has_j = false;  // this thread holds row J of the panel (one thread does)
 #pragma unroll
   for (int s = 0; s < S; ++s) {
     const int lr = t + kPanelThreads * s - roff;
     const double a = (lr > J && lr < dr) ? P[s][J] : 0.0;
+    const bool hit = lr == J && lr < dr;
+    has_j = has_j || hit;
 #pragma unroll
-    for (int x = 0; x < NB; ++x) acc[x] += a * P[s][x];
+    for (int x = 0; x < NB; ++x) {
+      acc[x] += a * P[s][x];
+      rowv[x] = hit ? P[s][x] : rowv[x];  // selects with static indices only
+    }
   }
-  // row J of the panel sits in one register row of one thread
-  const int jrow = J + roff;  // uniform
-  if (J < dr && jrow < S * kPanelThreads && t == (jrow & (kPanelThreads - 1))) {
-    const int so = jrow / kPanelThreads;
+  if (has_j) {
 #pragma unroll
-    for (int s = 0; s < S; ++s)
-      if (s == so) {
-#pragma unroll
-        for (int x = 0; x < NB; ++x) sh.ctot[B][NB + x] = P[s][x];
-      }
+    for (int x = 0; x < NB; ++x) sh.ctot[B][NB + x] = rowv[x];
   }
 #pragma unroll
   for (int x = 0; x < NB; ++x) acc[x] = wave_sum_u(acc[x]);

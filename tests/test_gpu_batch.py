@@ -100,3 +100,31 @@ def test_batch_matches_single_solves(sap):
     a = xs[0].cpu().numpy()
     b = x1[0].cpu().numpy()
     assert np.linalg.norm(a - b) <= 1e-10 * np.linalg.norm(b)
+
+
+def test_batch_wide_problems_iterations(sap, orc):
+    """Problems with more than 256 columns (every Householder scalar of the
+    sketch's QR stored, n + 1 of them): the batched solve matches the oracle
+    with the same (seed, stream) in the solution and in the iteration count
+    to within one (a corrupted panel T factor shows up as a weaker
+    preconditioner, i.e. several extra iterations, before it shows in x)."""
+    import torch
+    rng = np.random.default_rng(41)
+    probs = []
+    for k, n in enumerate((300, 420, 513)):
+        m = int(rng.integers(8000, 11000))
+        probs.append(inputs.make_problem(m, n, kind="colscale", cond=1e4, noise=1e-8, seed=4100 + k,
+                                         dtype=np.float64))
+    print("wide batch: n = 300, 420, 513", flush=True)
+    As = [torch.from_numpy(np.ascontiguousarray(p.A)).cuda() for p in probs]
+    bs = [torch.from_numpy(p.b).cuda() for p in probs]
+    ds = [4 * p.A.shape[1] for p in probs]
+    xs, st, infos = sap.sap_solve_batch(As, bs, ds, 8, 5, tol=1e-12, maxiter=300)
+    torch.cuda.synchronize()
+    assert st == sap.SAP_OK, infos
+    for k, p in enumerate(probs):
+        x_or, io = orc.solve(p.A, p.b, ds[k], 8, 5, tol=1e-12, maxiter=300, stream=k)
+        x = xs[k].cpu().numpy()
+        assert io["status"] == "ok"
+        assert abs(infos[k]["iters"] - io["iters"]) <= 1, (k, infos[k]["iters"], io["iters"])
+        assert np.linalg.norm(p.A @ (x - x_or)) <= 1e-11 * np.linalg.norm(p.b), k
