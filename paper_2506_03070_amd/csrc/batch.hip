@@ -969,19 +969,28 @@ struct Server {
   bool at_set = false;
   Arena arena;
   void *arena_mem = nullptr;
-  hipStream_t st = nullptr;
+  hipStream_t st = nullptr;        // iterations of the active requests
+  hipStream_t st_setup = nullptr;  // setup of newly admitted requests, overlapping the iterations
   int max_slots = 0;
   int iters_per_round = 8;
   BatchItem *d_active = nullptr, *d_new = nullptr;
   int2 *d_pass = nullptr, *d_apply = nullptr;
-  int *d_flags = nullptr, *d_done = nullptr;
+  int *d_flags = nullptr, *d_flags_setup = nullptr, *d_done = nullptr;
   void *scratch = nullptr;
   int64_t n_submitted = 0, n_completed = 0, n_rejected = 0;
 };
 
 namespace {
 
-constexpr int64_t kServeRowsPerChunk = 4096;
+// Rows per pass work item of a served request: about 2 MB of A per item
+// (power of two in [1024, 8192] rows), so that the few requests a round holds
+// still spread over the whole GPU in even pieces.
+int64_t serve_rows_per_chunk(int n, sap_dtype at) {
+  const int64_t row_bytes = static_cast<int64_t>(n) * (at == SAP_F32 ? 4 : 8);
+  int64_t r = 1024;
+  while (r < 8192 && 2 * r * row_bytes <= (int64_t(2) << 20)) r *= 2;
+  return r;
+}
 constexpr int kServeMaxChunks = 1 << 20;
 constexpr int kServeMaxApply = 1 << 18;
 
@@ -1006,13 +1015,18 @@ void serve_fail_all(Server *S, const std::string &msg, std::vector<ServeRequest 
   S->cv_done.notify_all();
 }
 
+// One round: the setup of the newly admitted requests (one batched launch
+// sequence on the setup stream) overlaps 8 iterations of the active ones on
+// the iteration stream; finished requests retire, and the new ones join the
+// active set for the next round.
 hipError_t serve_round(Server *S, std::vector<ServeRequest *> &fresh) {
-  hipStream_t st = S->st;
+  hipStream_t st = S->st, ss = S->st_setup;
   const sap_dtype at = S->at;
   hipError_t e;
-  // setup of the newly admitted requests as one batch
+  // ---- setup of the newly admitted requests (enqueued only) ----
+  std::vector<BatchItem> new_items(fresh.size());
+  int setup_flags[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   if (!fresh.empty()) {
-    std::vector<BatchItem> items(fresh.size());
     std::vector<int2> apply_work;
     int64_t col_base = 0;
     int d_max = 0;
@@ -1023,69 +1037,60 @@ hipError_t serve_round(Server *S, std::vector<ServeRequest *> &fresh) {
       BatchItem &it = r->item;
       it.col_base = col_base;
       col_base += it.m;
-      items[k] = it;
+      new_items[k] = it;
       const int tiles = (it.n + 1 + aw - 1) / aw;
       for (int t = 0; t < tiles; ++t) apply_work.push_back(make_int2(static_cast<int>(k), t));
     }
     if (static_cast<int>(apply_work.size()) > kServeMaxApply) return hipErrorInvalidValue;
     for (ServeRequest *r : fresh)
-      if ((e = hipStreamWaitEvent(st, r->ready, 0)) != hipSuccess) return e;
-    if ((e = hipMemsetAsync(S->d_flags, 0, 8 * sizeof(int), st)) != hipSuccess) return e;
-    if ((e = hipMemcpyAsync(S->d_new, items.data(), sizeof(BatchItem) * items.size(), hipMemcpyHostToDevice, st)) != hipSuccess) return e;
-    if ((e = hipMemcpyAsync(S->d_apply, apply_work.data(), sizeof(int2) * apply_work.size(), hipMemcpyHostToDevice, st)) != hipSuccess) return e;
-    if (setup_items(S->ctx, S->d_new, items, S->d_apply, static_cast<int>(apply_work.size()), S->d_flags, at, st) != SAP_OK)
+      if ((e = hipStreamWaitEvent(ss, r->ready, 0)) != hipSuccess) return e;
+    if ((e = hipMemsetAsync(S->d_flags_setup, 0, 8 * sizeof(int), ss)) != hipSuccess) return e;
+    if ((e = hipMemcpyAsync(S->d_new, new_items.data(), sizeof(BatchItem) * new_items.size(), hipMemcpyHostToDevice, ss)) != hipSuccess) return e;
+    if ((e = hipMemcpyAsync(S->d_apply, apply_work.data(), sizeof(int2) * apply_work.size(), hipMemcpyHostToDevice, ss)) != hipSuccess) return e;
+    if (setup_items(S->ctx, S->d_new, new_items, S->d_apply, static_cast<int>(apply_work.size()), S->d_flags_setup, at, ss) != SAP_OK)
       return hipErrorLaunchFailure;
     // the rank test wrote its flag into the device copy of each item
-    if ((e = hipMemcpyAsync(items.data(), S->d_new, sizeof(BatchItem) * items.size(), hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
-    int hf[8];
-    if ((e = hipMemcpyAsync(hf, S->d_flags, sizeof(hf), hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
-    if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
-    if (hf[0] || hf[2]) return hipErrorLaunchFailure;
-    std::lock_guard<std::mutex> lk(S->mu);
-    for (size_t k = 0; k < fresh.size(); ++k) {
-      (void)hipEventDestroy(fresh[k]->ready);
-      fresh[k]->ready = nullptr;
-      fresh[k]->item = items[k];
-      S->active.push_back(fresh[k]);
-    }
-    fresh.clear();
+    if ((e = hipMemcpyAsync(new_items.data(), S->d_new, sizeof(BatchItem) * new_items.size(), hipMemcpyDeviceToHost, ss)) != hipSuccess) return e;
+    if ((e = hipMemcpyAsync(setup_flags, S->d_flags_setup, sizeof(setup_flags), hipMemcpyDeviceToHost, ss)) != hipSuccess) return e;
   }
+  // ---- iterations of the active requests ----
   std::vector<ServeRequest *> act;
   {
     std::lock_guard<std::mutex> lk(S->mu);
     act = S->active;
   }
-  if (act.empty()) return hipSuccess;
   const int count = static_cast<int>(act.size());
-  std::vector<BatchItem> items(count);
-  std::vector<int2> pass_work;
-  int n_max = 0;
-  bool aligned = true;
-  const int vm = (at == SAP_F32) ? 4 : 2;
-  for (int k = 0; k < count; ++k) {
-    items[k] = act[k]->item;
-    n_max = std::max(n_max, items[k].n);
-    if (reinterpret_cast<uintptr_t>(items[k].A) % 16 != 0 || items[k].lda % vm != 0) aligned = false;
-    for (int g = 0; g < items[k].G; ++g) pass_work.push_back(make_int2(k, g));
+  std::vector<int> done(count), hflags(8, 0);
+  if (count > 0) {
+    std::vector<BatchItem> items(count);
+    std::vector<int2> pass_work;
+    int n_max = 0;
+    bool aligned = true;
+    const int vm = (at == SAP_F32) ? 4 : 2;
+    for (int k = 0; k < count; ++k) {
+      items[k] = act[k]->item;
+      n_max = std::max(n_max, items[k].n);
+      if (reinterpret_cast<uintptr_t>(items[k].A) % 16 != 0 || items[k].lda % vm != 0) aligned = false;
+      for (int g = 0; g < items[k].G; ++g) pass_work.push_back(make_int2(k, g));
+    }
+    if (static_cast<int>(pass_work.size()) > kServeMaxChunks) return hipErrorInvalidValue;
+    if ((e = hipMemcpyAsync(S->d_active, items.data(), sizeof(BatchItem) * count, hipMemcpyHostToDevice, st)) != hipSuccess) return e;
+    if ((e = hipMemcpyAsync(S->d_pass, pass_work.data(), sizeof(int2) * pass_work.size(), hipMemcpyHostToDevice, st)) != hipSuccess) return e;
+    const PassChoice pc = (at == SAP_F32) ? pick_batch_pass<float>(n_max, aligned) : pick_batch_pass<double>(n_max, aligned);
+    const int nblk_max = (n_max + kTrsvB - 1) / kTrsvB;
+    for (int k = 0; k < S->iters_per_round; ++k) {
+      launch_pass_fn(pc.fn, S->d_active, S->d_pass, static_cast<int>(pass_work.size()), 0, st);
+      batch_lower_kernel<<<dim3(nblk_max, count), kTrsvThreads, 0, st>>>(S->d_active, S->d_flags);
+      batch_upper_kernel<<<dim3(nblk_max, count), kTrsvThreads, 0, st>>>(S->d_active, S->d_flags, S->d_flags + 1);
+    }
+    serve_done_kernel<<<(count + 255) / 256, 256, 0, st>>>(S->d_active, count, S->d_done);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = hipMemcpyAsync(done.data(), S->d_done, sizeof(int) * count, hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
+    if ((e = hipMemcpyAsync(hflags.data(), S->d_flags, sizeof(int) * 8, hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
+    if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+    if (hflags[0] || hflags[2]) return hipErrorLaunchFailure;
   }
-  if (static_cast<int>(pass_work.size()) > kServeMaxChunks) return hipErrorInvalidValue;
-  if ((e = hipMemcpyAsync(S->d_active, items.data(), sizeof(BatchItem) * count, hipMemcpyHostToDevice, st)) != hipSuccess) return e;
-  if ((e = hipMemcpyAsync(S->d_pass, pass_work.data(), sizeof(int2) * pass_work.size(), hipMemcpyHostToDevice, st)) != hipSuccess) return e;
-  const PassChoice pc = (at == SAP_F32) ? pick_batch_pass<float>(n_max, aligned) : pick_batch_pass<double>(n_max, aligned);
-  const int nblk_max = (n_max + kTrsvB - 1) / kTrsvB;
-  for (int k = 0; k < S->iters_per_round; ++k) {
-    launch_pass_fn(pc.fn, S->d_active, S->d_pass, static_cast<int>(pass_work.size()), 0, st);
-    batch_lower_kernel<<<dim3(nblk_max, count), kTrsvThreads, 0, st>>>(S->d_active, S->d_flags);
-    batch_upper_kernel<<<dim3(nblk_max, count), kTrsvThreads, 0, st>>>(S->d_active, S->d_flags, S->d_flags + 1);
-  }
-  serve_done_kernel<<<(count + 255) / 256, 256, 0, st>>>(S->d_active, count, S->d_done);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  std::vector<int> done(count), hflags(8);
-  if ((e = hipMemcpyAsync(done.data(), S->d_done, sizeof(int) * count, hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
-  if ((e = hipMemcpyAsync(hflags.data(), S->d_flags, sizeof(int) * 8, hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
-  if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
-  if (hflags[0] || hflags[2]) return hipErrorLaunchFailure;
-  // retire finished (or cancelled) requests
+  // ---- retire finished (or cancelled) requests ----
   std::vector<ServeRequest *> finished;
   for (int k = 0; k < count; ++k) {
     ServeRequest *r = act[k];
@@ -1096,36 +1101,51 @@ hipError_t serve_round(Server *S, std::vector<ServeRequest *> &fresh) {
     }
     if (done[k] || cancel) finished.push_back(r);
   }
-  if (finished.empty()) return hipSuccess;
-  std::vector<LsqrState> states(finished.size());
-  for (size_t k = 0; k < finished.size(); ++k) {
-    if ((e = hipMemcpyAsync(&states[k], finished[k]->item.st, sizeof(LsqrState), hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
+  if (!finished.empty()) {
+    std::vector<LsqrState> states(finished.size());
+    for (size_t k = 0; k < finished.size(); ++k) {
+      if ((e = hipMemcpyAsync(&states[k], finished[k]->item.st, sizeof(LsqrState), hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
+    }
+    if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+    const auto now = std::chrono::steady_clock::now();
+    std::lock_guard<std::mutex> lk(S->mu);
+    for (size_t k = 0; k < finished.size(); ++k) {
+      ServeRequest *r = finished[k];
+      sap_status stt;
+      if (r->cancel) stt = SAP_ECANCELED;
+      else if (r->item.rank_deficient) stt = SAP_RANK_DEFICIENT;
+      else stt = states[k].converged ? SAP_OK : SAP_NOT_CONVERGED;
+      r->status = stt;
+      r->t_done = now;
+      std::memset(&r->info, 0, sizeof(r->info));
+      r->info.status = stt;
+      r->info.iters = states[k].total_iters;
+      r->info.resid_est = states[k].resid_est;
+      r->info.normar_est = states[k].normar_est;
+      r->info.t_queue_ms = std::chrono::duration<double, std::milli>(r->t_admit - r->t_submit).count();
+      r->info.t_total_ms = std::chrono::duration<double, std::milli>(r->t_done - r->t_submit).count();
+      r->state = 2;
+      S->arena.release(r->offset, r->bytes);
+      S->active.erase(std::find(S->active.begin(), S->active.end(), r));
+      S->n_completed += 1;
+    }
+    S->cv_done.notify_all();
+    S->cv.notify_all();
   }
-  if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
-  const auto now = std::chrono::steady_clock::now();
-  std::lock_guard<std::mutex> lk(S->mu);
-  for (size_t k = 0; k < finished.size(); ++k) {
-    ServeRequest *r = finished[k];
-    sap_status stt;
-    if (r->cancel) stt = SAP_ECANCELED;
-    else if (r->item.rank_deficient) stt = SAP_RANK_DEFICIENT;
-    else stt = states[k].converged ? SAP_OK : SAP_NOT_CONVERGED;
-    r->status = stt;
-    r->t_done = now;
-    std::memset(&r->info, 0, sizeof(r->info));
-    r->info.status = stt;
-    r->info.iters = states[k].total_iters;
-    r->info.resid_est = states[k].resid_est;
-    r->info.normar_est = states[k].normar_est;
-    r->info.t_queue_ms = std::chrono::duration<double, std::milli>(r->t_admit - r->t_submit).count();
-    r->info.t_total_ms = std::chrono::duration<double, std::milli>(r->t_done - r->t_submit).count();
-    r->state = 2;
-    S->arena.release(r->offset, r->bytes);
-    S->active.erase(std::find(S->active.begin(), S->active.end(), r));
-    S->n_completed += 1;
+  // ---- the new requests join the active set ----
+  if (!fresh.empty()) {
+    if ((e = hipStreamSynchronize(ss)) != hipSuccess) return e;
+    if (setup_flags[0] || setup_flags[2]) return hipErrorLaunchFailure;
+    std::lock_guard<std::mutex> lk(S->mu);
+    for (size_t k = 0; k < fresh.size(); ++k) {
+      (void)hipEventDestroy(fresh[k]->ready);
+      fresh[k]->ready = nullptr;
+      fresh[k]->item = new_items[k];
+      S->active.push_back(fresh[k]);
+    }
+    fresh.clear();
+    S->cv.notify_all();
   }
-  S->cv_done.notify_all();
-  S->cv.notify_all();
   return hipSuccess;
 }
 
@@ -1160,7 +1180,7 @@ void serve_loop(Server *S) {
         r->offset = off;
         r->state = 1;
         r->t_admit = now;
-        carve_item(r->item, S->arena.base + off, S->at, kServeRowsPerChunk);
+        carve_item(r->item, S->arena.base + off, S->at, serve_rows_per_chunk(r->item.n, S->at));
         S->queued.pop_front();
         fresh.push_back(r);
       }
@@ -1188,7 +1208,9 @@ void serve_destroy(sap_ctx *ctx) {
   for (auto &kv : S->reqs)
     if (kv.second->ready) (void)hipEventDestroy(kv.second->ready);
   if (S->st) (void)hipStreamSynchronize(S->st);
+  if (S->st_setup) (void)hipStreamSynchronize(S->st_setup);
   if (S->st) (void)hipStreamDestroy(S->st);
+  if (S->st_setup) (void)hipStreamDestroy(S->st_setup);
   if (S->arena_mem) (void)hipFree(S->arena_mem);
   if (S->scratch) (void)hipFree(S->scratch);
   delete S;
@@ -1210,7 +1232,7 @@ sap_status serve_start(sap_ctx *ctx, size_t arena_bytes, int max_slots) {
   }
   S->arena.init(S->arena_mem, arena_bytes);
   const size_t scratch = 8 * 256 + 2 * sizeof(BatchItem) * max_slots + sizeof(int2) * (kServeMaxChunks + kServeMaxApply) +
-                         sizeof(int) * (8 + max_slots);
+                         sizeof(int) * (16 + max_slots);
   if (hipMalloc(&S->scratch, scratch) != hipSuccess) {
     (void)hipGetLastError();
     (void)hipFree(S->arena_mem);
@@ -1218,12 +1240,14 @@ sap_status serve_start(sap_ctx *ctx, size_t arena_bytes, int max_slots) {
   }
   Carve cv(S->scratch);
   S->d_flags = cv.take<int>(8);
+  S->d_flags_setup = cv.take<int>(8);
   S->d_done = cv.take<int>(max_slots);
   S->d_active = cv.take<BatchItem>(max_slots);
   S->d_new = cv.take<BatchItem>(max_slots);
   S->d_pass = cv.take<int2>(kServeMaxChunks);
   S->d_apply = cv.take<int2>(kServeMaxApply);
   SAP_HIP_TRY(hipStreamCreateWithFlags(&S->st, hipStreamNonBlocking));
+  SAP_HIP_TRY(hipStreamCreateWithFlags(&S->st_setup, hipStreamNonBlocking));
   ctx->server = S.release();
   ctx->server->th = std::thread(serve_loop, ctx->server);
   return SAP_OK;
