@@ -24,40 +24,38 @@ namespace {
 
 using namespace qr_dev;
 
-// The first panel (columns 0 .. nb-1).
-template <int S, int NB>
-__global__ __launch_bounds__(kPanelThreads) void qr_first_panel_kernel(double *__restrict__ Y, int64_t ldy, int d,
-                                                                       int nb, double *__restrict__ tau,
-                                                                       double *__restrict__ Tout) {
-  __shared__ PanelShared<NB> sh;
+// The first panel (columns 0 .. nb-1).  TH threads, S rows each.
+template <int S, int NB, int TH>
+__global__ __launch_bounds__(TH) void qr_first_panel_kernel(double *__restrict__ Y, int64_t ldy, int d, int nb,
+                                                            double *__restrict__ tau, double *__restrict__ Tout) {
+  __shared__ PanelShared<NB, TH> sh;
   double P[S][NB];
-  load_block<S, NB>(Y, ldy, 0, d, 0, nb, P);
+  load_block<S, NB, TH>(Y, ldy, 0, d, 0, nb, P);
   factor_panel<S, NB>(P, sh, nb, d, 0, 0, tau, Tout);
-  store_block<S, NB>(Y, ldy, 0, d, 0, nb, P);
+  store_block<S, NB, TH>(Y, ldy, 0, d, 0, nb, P);
 }
 
 // One step of the right-looking factorisation: every workgroup applies
 // Q_k^T (panel k = columns k0 .. k0+nb-1) to its block of NB trailing
 // columns; workgroup 0's block is panel k+1, which it then factors at once
 // (look-ahead) into Tnext.
-template <int S, int NB>
-__global__ __launch_bounds__(kPanelThreads) void qr_step_kernel(double *__restrict__ Y, int64_t ldy, int d, int ncols,
-                                                                int k0, int nb, const double *__restrict__ Tcur,
-                                                                double *__restrict__ Tnext,
-                                                                double *__restrict__ tau) {
-  __shared__ PanelShared<NB> sh;
+template <int S, int NB, int TH>
+__global__ __launch_bounds__(TH) void qr_step_kernel(double *__restrict__ Y, int64_t ldy, int d, int ncols, int k0,
+                                                     int nb, const double *__restrict__ Tcur,
+                                                     double *__restrict__ Tnext, double *__restrict__ tau) {
+  __shared__ PanelShared<NB, TH> sh;
   const int c0 = k0 + nb + static_cast<int>(blockIdx.x) * NB;
   const int ncb = min(NB, ncols - c0);
   const int dr = d - k0;
   double C[S][NB];
-  load_block<S, NB>(Y, ldy, k0, dr, c0, ncb, C);
+  load_block<S, NB, TH>(Y, ldy, k0, dr, c0, ncb, C);
   apply_panel_qt<S, NB>(Y, ldy, dr, k0, nb, Tcur, C, ncb, sh);
   if (blockIdx.x == 0) {
     // panel k+1 starts at row and column k1 = c0; rows k0..k1-1 ride along
     const int k1 = c0;
     factor_panel<S, NB>(C, sh, ncb, d - k1, k1 - k0, k1, tau, Tnext);
   }
-  store_block<S, NB>(Y, ldy, k0, dr, c0, ncb, C);
+  store_block<S, NB, TH>(Y, ldy, k0, dr, c0, ncb, C);
 }
 
 // Rank test on R's diagonal: deficient when min |R_kk| <= d * 2^-53 * max |R_kk|.
@@ -263,37 +261,20 @@ __global__ __launch_bounds__(kWyThreads) void qr_wy_update_kernel(double *__rest
   }
 }
 
-struct QrShape {
-  int s;   // rows per thread (512 threads)
-  int nb;  // panel width = trailing block width
-};
-
-QrShape qr_shape(int rows) {
-  // The register blocks (S * NB doubles per thread, twice: V and C) must fit
-  // in the 256 VGPRs a 512-thread workgroup leaves each lane: S * NB <= 32.
-  const int s = (rows + kPanelThreads - 1) / kPanelThreads;
-  if (s <= 1) return {1, 8};
-  if (s <= 2) return {2, 8};
-  if (s <= 4) return {4, 8};
-  if (s <= 8) return {8, 4};
-  if (s <= 16) return {16, 2};
-  return {32, 1};
-}
-
-template <int S, int NB>
+template <int S, int NB, int TH>
 sap_status qr_run(sap_ctx *ctx, double *Y, int64_t ldy, int rows, int cols, double *tau, void *work,
                   hipStream_t st) {
   Carve cv(work);
   double *T[2] = {cv.take<double>(NB * NB), cv.take<double>(NB * NB)};
   const int kmax = rows < cols ? rows : cols;
   int nb = kmax < NB ? kmax : NB;
-  qr_first_panel_kernel<S, NB><<<1, kPanelThreads, 0, st>>>(Y, ldy, rows, nb, tau, T[0]);
+  qr_first_panel_kernel<S, NB, TH><<<1, TH, 0, st>>>(Y, ldy, rows, nb, tau, T[0]);
   SAP_HIP_TRY(hipGetLastError());
   int cur = 0;
   for (int k0 = 0; k0 + nb < cols; k0 += NB) {
     const int trailing = cols - (k0 + nb);
     const int nblocks = (trailing + NB - 1) / NB;
-    qr_step_kernel<S, NB><<<nblocks, kPanelThreads, 0, st>>>(Y, ldy, rows, cols, k0, nb, T[cur], T[1 - cur], tau);
+    qr_step_kernel<S, NB, TH><<<nblocks, TH, 0, st>>>(Y, ldy, rows, cols, k0, nb, T[cur], T[1 - cur], tau);
     SAP_HIP_TRY(hipGetLastError());
     cur ^= 1;
     nb = (cols - (k0 + NB)) < NB ? (cols - (k0 + NB)) : NB;
@@ -305,16 +286,17 @@ constexpr size_t kUnblockedBytes = 4 * 256 + 2 * sizeof(double) * 16 * 16;
 
 sap_status qr_unblocked(sap_ctx *ctx, double *Y, int64_t ldy, int rows, int cols, double *tau, void *work,
                         hipStream_t st) {
-  const QrShape sh = qr_shape(rows);
-  switch (sh.s) {
-    case 1: return qr_run<1, 8>(ctx, Y, ldy, rows, cols, tau, work, st);
-    case 2: return qr_run<2, 8>(ctx, Y, ldy, rows, cols, tau, work, st);
-    case 4: return qr_run<4, 8>(ctx, Y, ldy, rows, cols, tau, work, st);
-    case 8: return qr_run<8, 4>(ctx, Y, ldy, rows, cols, tau, work, st);
-    case 16: return qr_run<16, 2>(ctx, Y, ldy, rows, cols, tau, work, st);
-    default: break;
-  }
-  if (rows <= 32 * kPanelThreads) return qr_run<32, 1>(ctx, Y, ldy, rows, cols, tau, work, st);
+  // S rows per thread, NB columns per step, TH threads: the register blocks
+  // (S * NB doubles per thread, twice: V and C) must fit in the 256 VGPRs a
+  // lane keeps at 512 threads.  (1024-thread steps, S halved, measured ~20%
+  // slower at 4000 x 1001: the steps are bound by barriers and cross-wave
+  // sums, which more waves lengthen.)
+  if (rows <= 512) return qr_run<1, 8, 512>(ctx, Y, ldy, rows, cols, tau, work, st);
+  if (rows <= 1024) return qr_run<2, 8, 512>(ctx, Y, ldy, rows, cols, tau, work, st);
+  if (rows <= 2048) return qr_run<4, 8, 512>(ctx, Y, ldy, rows, cols, tau, work, st);
+  if (rows <= 4096) return qr_run<8, 4, 512>(ctx, Y, ldy, rows, cols, tau, work, st);
+  if (rows <= 8192) return qr_run<16, 2, 512>(ctx, Y, ldy, rows, cols, tau, work, st);
+  if (rows <= 16384) return qr_run<32, 1, 512>(ctx, Y, ldy, rows, cols, tau, work, st);
   return fail(ctx, SAP_EINVAL, "sap_qr: more than 16384 rows is not supported");
 }
 

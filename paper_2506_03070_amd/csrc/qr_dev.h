@@ -19,18 +19,19 @@ __device__ __forceinline__ double vval(int r, int k, double y) {
 }
 
 // Shared state of the panel factorisation and the block-reflector apply (LDS).
-template <int NB>
+// TH: threads of the workgroup (512 or 1024); thread t holds rows t + TH s.
+template <int NB, int TH = kPanelThreads>
 struct PanelShared {
-  double red[kPanelWaves][NB * NB + 1];  // per-wave partials of W = V^T C
+  double red[TH / kWave][NB * NB + 1];  // per-wave partials of W = V^T C
   double W2[NB][NB];
-  double cred[2][kPanelWaves][NB];       // per-wave partials of one panel column, by column parity
+  double cred[2][TH / kWave][NB];       // per-wave partials of one panel column, by column parity
   double ctot[2][2 * NB];                // its totals (0..NB-1) and row J of the panel (NB..2NB-1)
   double G[NB][NB];                      // G[J][q] = v_q^T v_J (q < J), for T
   double tauv[NB];
   double Tl[NB * NB];                    // T of the panel being applied
 };
 
-// Rows: thread t holds panel-relative rows lr = t + 512 s - roff (s < S);
+// Rows: thread t holds panel-relative rows lr = t + TH s - roff (s < S);
 // rows with lr < 0 lie above the panel (they belong to R) and only ride along.
 
 // Column J of the panel: reflector, update of columns J+1.. of the panel,
@@ -41,8 +42,8 @@ struct PanelShared {
 // row J of the panel: v^T (column x) = P[J][x] + (a^T column x) / (alpha - beta).
 // J is a template parameter so that every register index of the panel P is
 // static (no scratch).
-template <int S, int NB, int J>
-__device__ __forceinline__ void panel_column(double (&P)[S][NB], PanelShared<NB> &sh, int nb, int dr, int roff,
+template <int S, int NB, int J, int TH>
+__device__ __forceinline__ void panel_column(double (&P)[S][NB], PanelShared<NB, TH> &sh, int nb, int dr, int roff,
                                              int k0, double *__restrict__ tau) {
   constexpr int B = J & 1;  // LDS buffers alternate between columns: one barrier fewer
   const int t = threadIdx.x;
@@ -55,7 +56,7 @@ __device__ __forceinline__ void panel_column(double (&P)[S][NB], PanelShared<NB>
   bool has_j = false;  // this thread holds row J of the panel (one thread does)
 #pragma unroll
   for (int s = 0; s < S; ++s) {
-    const int lr = t + kPanelThreads * s - roff;
+    const int lr = t + TH * s - roff;
     const double a = (lr > J && lr < dr) ? P[s][J] : 0.0;
     const bool hit = lr == J && lr < dr;
     has_j = has_j || hit;
@@ -78,7 +79,7 @@ __device__ __forceinline__ void panel_column(double (&P)[S][NB], PanelShared<NB>
   __syncthreads();
   if (t < NB) {
     double s_ = 0.0;
-    for (int w = 0; w < kPanelWaves; ++w) s_ += sh.cred[B][w][t];
+    for (int w = 0; w < (TH / kWave); ++w) s_ += sh.cred[B][w][t];
     sh.ctot[B][t] = s_;
   }
   __syncthreads();
@@ -115,7 +116,7 @@ __device__ __forceinline__ void panel_column(double (&P)[S][NB], PanelShared<NB>
   // from J on, where the subtraction leaves the value unchanged)
 #pragma unroll
   for (int s = 0; s < S; ++s) {
-    const int lr = t + kPanelThreads * s - roff;
+    const int lr = t + TH * s - roff;
     const bool below = lr > J && lr < dr;
     const bool diag = lr == J;
     const double v = below ? P[s][J] * scale : (diag ? 1.0 : 0.0);
@@ -132,13 +133,13 @@ __device__ __forceinline__ void panel_column(double (&P)[S][NB], PanelShared<NB>
   }
 }
 
-template <int S, int NB, int J>
-__device__ __forceinline__ void panel_columns(double (&P)[S][NB], PanelShared<NB> &sh, int nb, int dr, int roff,
+template <int S, int NB, int J, int TH>
+__device__ __forceinline__ void panel_columns(double (&P)[S][NB], PanelShared<NB, TH> &sh, int nb, int dr, int roff,
                                               int k0, double *__restrict__ tau) {
   if constexpr (J < NB) {
     if (J < nb) {  // nb is uniform: every thread reaches the same barriers
-      panel_column<S, NB, J>(P, sh, nb, dr, roff, k0, tau);
-      panel_columns<S, NB, J + 1>(P, sh, nb, dr, roff, k0, tau);
+      panel_column<S, NB, J, TH>(P, sh, nb, dr, roff, k0, tau);
+      panel_columns<S, NB, J + 1, TH>(P, sh, nb, dr, roff, k0, tau);
     }
   }
 }
@@ -149,14 +150,14 @@ __device__ __forceinline__ void panel_columns(double (&P)[S][NB], PanelShared<NB
 // columns are done: row l of T depends only on its own earlier entries, so
 // thread l builds row l.  Ends without a barrier (the tau and T stores stay
 // in flight); a caller that reuses `sh` afterwards synchronises first.
-template <int S, int NB>
-__device__ __forceinline__ void factor_panel(double (&P)[S][NB], PanelShared<NB> &sh, int nb, int dr, int roff,
+template <int S, int NB, int TH>
+__device__ __forceinline__ void factor_panel(double (&P)[S][NB], PanelShared<NB, TH> &sh, int nb, int dr, int roff,
                                              int k0, double *__restrict__ tau, double *__restrict__ Tout) {
   const int t = threadIdx.x;
   __syncthreads();  // earlier users of the shared buffers are done
   if (t < NB * NB) sh.G[t / NB][t % NB] = 0.0;
   if (t < NB) sh.tauv[t] = 0.0;
-  panel_columns<S, NB, 0>(P, sh, nb, dr, roff, k0, tau);  // its first barrier orders the zeroing
+  panel_columns<S, NB, 0, TH>(P, sh, nb, dr, roff, k0, tau);  // its first barrier orders the zeroing
   __syncthreads();
   if (t < NB) {
     const int l = t;
@@ -178,10 +179,10 @@ __device__ __forceinline__ void factor_panel(double (&P)[S][NB], PanelShared<NB>
 // the nbp Householder vectors stored in columns k0.. of Y (unit diagonal
 // implicit) and T the panel's triangular factor (column-major NB x NB).
 // Writes `sh` before its first barrier: no other use of `sh` may be pending.
-template <int S, int NB>
+template <int S, int NB, int TH>
 __device__ __forceinline__ void apply_panel_qt(const double *__restrict__ Y, int64_t ldy, int dr, int k0, int nbp,
                                                const double *__restrict__ T, double (&C)[S][NB], int ncb,
-                                               PanelShared<NB> &sh) {
+                                               PanelShared<NB, TH> &sh) {
   if (nbp <= 0 || dr <= 0) return;  // uniform: no reflectors, nothing to apply
   const int t = threadIdx.x;
   const int lane = t & (kWave - 1), wave = t / kWave;
@@ -193,7 +194,7 @@ __device__ __forceinline__ void apply_panel_qt(const double *__restrict__ Y, int
   double V[S][NB];
 #pragma unroll
   for (int s = 0; s < S; ++s) {
-    const int lr = t + kPanelThreads * s;
+    const int lr = t + TH * s;
     const int rr = min(lr, dr - 1);
 #pragma unroll
     for (int i = 0; i < NB; ++i) {
@@ -222,7 +223,7 @@ __device__ __forceinline__ void apply_panel_qt(const double *__restrict__ Y, int
     double s_ = 0.0;
     for (int l = 0; l <= i && l < nbp; ++l) {
       double wlc = 0.0;
-      for (int w = 0; w < kPanelWaves; ++w) wlc += sh.red[w][l * NB + c];
+      for (int w = 0; w < (TH / kWave); ++w) wlc += sh.red[w][l * NB + c];
       s_ += sh.Tl[l + i * NB] * wlc;
     }
     sh.W2[i][c] = (i < nbp && c < ncb) ? s_ : 0.0;
@@ -245,7 +246,7 @@ __device__ __forceinline__ void apply_panel_qt(const double *__restrict__ Y, int
 // a copy of an entry inside it.  Every user masks those slots: the apply
 // weights them by V = 0 and W2 = 0, the panel factorisation by its row and
 // column masks, and store_block does not write them.
-template <int S, int NB>
+template <int S, int NB, int TH = kPanelThreads>
 __device__ __forceinline__ void load_block(const double *__restrict__ Y, int64_t ldy, int r0, int dr, int c0, int ncb,
                                            double (&C)[S][NB]) {
   if (dr <= 0 || ncb <= 0) {  // uniform
@@ -258,19 +259,19 @@ __device__ __forceinline__ void load_block(const double *__restrict__ Y, int64_t
   const double *__restrict__ base = Y + r0 + static_cast<int64_t>(c0) * ldy;
 #pragma unroll
   for (int s = 0; s < S; ++s) {
-    const int rr = min(static_cast<int>(threadIdx.x) + kPanelThreads * s, dr - 1);
+    const int rr = min(static_cast<int>(threadIdx.x) + TH * s, dr - 1);
 #pragma unroll
     for (int c = 0; c < NB; ++c) C[s][c] = base[static_cast<int64_t>(min(c, ncb - 1)) * ldy + rr];
   }
 }
 
-template <int S, int NB>
+template <int S, int NB, int TH = kPanelThreads>
 __device__ __forceinline__ void store_block(double *__restrict__ Y, int64_t ldy, int r0, int dr, int c0, int ncb,
                                             const double (&C)[S][NB]) {
   double *__restrict__ base = Y + r0 + static_cast<int64_t>(c0) * ldy;
 #pragma unroll
   for (int s = 0; s < S; ++s) {
-    const unsigned lr = static_cast<unsigned>(threadIdx.x + kPanelThreads * s);
+    const unsigned lr = static_cast<unsigned>(threadIdx.x + TH * s);
     if (lr < static_cast<unsigned>(dr)) {
 #pragma unroll
       for (int c = 0; c < NB; ++c)
