@@ -305,6 +305,46 @@ __global__ __launch_bounds__(kTrsvThreads) void batch_x0_kernel(const BatchItem 
   chain_block<true>(it.Y, it.d, n, it.Dup, it.x, it.flags + 2 * it.nblk, 1, b, sh.rb, sh.red, err);
 }
 
+// ---- repacking of unaligned rows -------------------------------------------
+// A problem whose rows do not start on 16-byte boundaries (lda not a multiple
+// of 16 / element size, or A itself unaligned) can only be read element by
+// element.  Before the solve its rows are copied once into a buffer with
+// lda_pad = n rounded up to 16 bytes, so that every pass reads it with
+// 16-byte loads; the columns past n are never read.
+struct RepackJob {
+  const void *src;
+  int64_t lda_src;
+  void *dst;
+  int64_t lda_dst;
+  int64_t m;
+  int32_t n, pad;
+};
+constexpr int kRepackRows = 256;  // rows per work item
+
+template <typename TA>
+__global__ __launch_bounds__(256) void batch_repack_kernel(const RepackJob *__restrict__ jobs,
+                                                           const int2 *__restrict__ work) {
+  constexpr int V = 16 / static_cast<int>(sizeof(TA));
+  typedef TA vec_t __attribute__((ext_vector_type(V)));
+  const int2 wk = work[blockIdx.x];
+  const RepackJob &jb = jobs[wk.x];
+  const TA *__restrict__ src = static_cast<const TA *>(jb.src);
+  TA *__restrict__ dst = static_cast<TA *>(jb.dst);
+  const int n = jb.n;
+  const int nv = (n + V - 1) / V;  // vectors per row
+  const int64_t r0 = static_cast<int64_t>(wk.y) * kRepackRows;
+  const int64_t r1 = min(jb.m, r0 + kRepackRows);
+  const int64_t total = (r1 - r0) * nv;
+  for (int64_t e = threadIdx.x; e < total; e += 256) {
+    const int64_t row = r0 + e / nv;
+    const int c = static_cast<int>(e % nv) * V;
+    vec_t v;
+#pragma unroll
+    for (int q = 0; q < V; ++q) v[q] = c + q < n ? src[row * jb.lda_src + c + q] : TA(0);
+    *reinterpret_cast<vec_t *>(dst + row * jb.lda_dst + c) = v;
+  }
+}
+
 // ---- LSQR iteration -----------------------------------------------------------
 // Packed pass: L lanes serve one row (L = the power of two covering n/VEC,
 // at most 64, chosen per problem), so a wavefront handles 64/L rows at once.
@@ -673,6 +713,23 @@ sap_status run_batch(sap_ctx *ctx, int count, const sap_problem *probs, const sa
   }
   if (n_max > 1024) return fail(ctx, SAP_EINVAL, "sap_solve_batch: n > 1024 is not supported");
 
+  // ---- unaligned rows: repack into 16-byte-aligned rows when memory allows ----
+  const size_t es_a = (at == SAP_F32) ? 4 : 8;
+  const int vm_a = 16 / static_cast<int>(es_a);
+  std::vector<int> repack_idx;   // problems to repack
+  size_t repack_bytes = 0;
+  int64_t repack_chunks = 0;
+  if (!aligned) {
+    for (int k = 0; k < count; ++k) {
+      const sap_problem &p = probs[k];
+      if (reinterpret_cast<uintptr_t>(p.A) % 16 == 0 && p.lda % vm_a == 0) continue;
+      const int64_t ldp = (p.n + vm_a - 1) / vm_a * vm_a;
+      repack_idx.push_back(k);
+      repack_bytes += 256 + static_cast<size_t>(p.m) * ldp * es_a;
+      repack_chunks += (p.m + kRepackRows - 1) / kRepackRows;
+    }
+  }
+
   // ---- workspace layout ---------------------------------------------------------
   const BatchTuneKey key{static_cast<int>(at), (n_max + 63) / 64, count};
   int64_t rows_per_chunk = 4096;
@@ -693,6 +750,11 @@ sap_status run_batch(sap_ctx *ctx, int count, const sap_problem *probs, const sa
   const int tiles_max = (n_max + 1 + aw - 1) / aw;
   total += 256 + sizeof(int2) * (total_chunks_max + 16);
   total += 256 + sizeof(int2) * (static_cast<size_t>(count) * tiles_max + 16);
+  const size_t repack_total = repack_idx.empty() ? 0
+                                                 : repack_bytes + 2 * 256 + sizeof(RepackJob) * repack_idx.size() +
+                                                       sizeof(int2) * static_cast<size_t>(repack_chunks);
+  const bool repack = !repack_idx.empty() && total + repack_total <= ctx->budget;
+  if (repack) total += repack_total;
   sap_status s = ensure_workspace(ctx, total, user_stream);
   if (s != SAP_OK) return s;
   Carve cv(ctx->ws);
@@ -724,6 +786,32 @@ sap_status run_batch(sap_ctx *ctx, int count, const sap_problem *probs, const sa
   }
   int2 *dpass = cv.take<int2>(total_chunks_max + 16);
   int2 *dapply = cv.take<int2>(static_cast<size_t>(count) * tiles_max + 16);
+  std::vector<RepackJob> jobs;
+  std::vector<int2> repack_work;
+  RepackJob *djobs = nullptr;
+  int2 *drepack = nullptr;
+  if (repack) {
+    djobs = cv.take<RepackJob>(repack_idx.size());
+    drepack = cv.take<int2>(static_cast<size_t>(repack_chunks));
+    for (int k : repack_idx) {
+      BatchItem &it = items[k];
+      const int64_t ldp = (it.n + vm_a - 1) / vm_a * vm_a;
+      RepackJob jb{};
+      jb.src = it.A;
+      jb.lda_src = it.lda;
+      jb.dst = cv.take<char>(static_cast<size_t>(it.m) * ldp * es_a);
+      jb.lda_dst = ldp;
+      jb.m = it.m;
+      jb.n = it.n;
+      const int j = static_cast<int>(jobs.size());
+      for (int64_t c = 0; c < (it.m + kRepackRows - 1) / kRepackRows; ++c)
+        repack_work.push_back(make_int2(j, static_cast<int>(c)));
+      jobs.push_back(jb);
+      it.A = jb.dst;  // the solve reads the repacked rows
+      it.lda = ldp;
+    }
+    aligned = true;
+  }
 
   // work tables
   std::vector<int2> apply_work;
@@ -754,6 +842,15 @@ sap_status run_batch(sap_ctx *ctx, int count, const sap_problem *probs, const sa
   (void)hipEventDestroy(ev_in);
 
   SAP_HIP_TRY(hipMemsetAsync(dflags, 0, 8 * sizeof(int), st));
+  if (repack) {
+    SAP_HIP_TRY(hipMemcpyAsync(djobs, jobs.data(), sizeof(RepackJob) * jobs.size(), hipMemcpyHostToDevice, st));
+    SAP_HIP_TRY(hipMemcpyAsync(drepack, repack_work.data(), sizeof(int2) * repack_work.size(), hipMemcpyHostToDevice, st));
+    if (at == SAP_F32)
+      batch_repack_kernel<float><<<static_cast<unsigned>(repack_work.size()), 256, 0, st>>>(djobs, drepack);
+    else
+      batch_repack_kernel<double><<<static_cast<unsigned>(repack_work.size()), 256, 0, st>>>(djobs, drepack);
+    SAP_HIP_TRY(hipGetLastError());
+  }
   SAP_HIP_TRY(hipMemcpyAsync(ditems, items.data(), sizeof(BatchItem) * count, hipMemcpyHostToDevice, st));
   SAP_HIP_TRY(hipMemcpyAsync(dapply, apply_work.data(), sizeof(int2) * apply_work.size(), hipMemcpyHostToDevice, st));
   s = setup_items(ctx, ditems, items, dapply, static_cast<int>(apply_work.size()), dflags, at, st);
