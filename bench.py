@@ -9,7 +9,8 @@ HIP-event timings taken on its own stream inside the timed region;
 `cpu_baseline` times the CPU oracle on a bounded row sample of the same
 workload and projects it to the full size.  `forms` adds the other three
 forms, each against the plain FP64 form on the same problems:
-  * mixed   - one large solve, m = 2^22, n = 4096, d = 2n, A stored in FP32;
+  * mixed   - one large solve, m = 2^22, n = 4096, d = 2n, A stored in FP32 (FP64
+              arithmetic; FP32 refinement; BF16-input sketch with refinement);
   * batched - 512 uneven FP32 problems in one sap_solve_batch call;
   * served  - a Poisson request stream (200 req/s) through sap_submit/poll,
               with p50/p99 latency.
@@ -174,7 +175,7 @@ def form_mixed(args, sap, torch, inputs):
 
     def timed(A, x, mode, tol_=None):
         tol_ = tol if tol_ is None else tol_
-        mx = maxiter if mode != sap.SAP_MODE_MIXED_FP32_REFINE else 4 * maxiter
+        mx = maxiter if mode not in (sap.SAP_MODE_MIXED_FP32_REFINE, sap.SAP_MODE_MIXED_BF16SA) else 4 * maxiter
         sap.sap_solve(A, b, d, zeta, seed, tol=tol_, maxiter=mx, x=x, mode=mode)  # warm-up
         torch.cuda.synchronize()
         ctx.profile(True)
@@ -189,7 +190,7 @@ def form_mixed(args, sap, torch, inputs):
         nap, msap = ctx.profile_read(sap.PROF_APPLY)
         es = A.element_size()
         pb = pass_bytes(m, n, es)
-        ab = apply_bytes(m, n, d, zeta, es, 8)
+        ab = apply_bytes(m, n, d, zeta, 2 if mode == sap.SAP_MODE_MIXED_BF16SA else es, 8)
         return dict(solve_ms=dt * 1e3, status=r.info["status_name"], iters=r.info["iters"],
                     refinements=r.info["refinements"], tol=tol_,
                     phases_ms={"generate": r.info["t_generate_ms"], "apply": r.info["t_apply_ms"],
@@ -205,6 +206,10 @@ def form_mixed(args, sap, torch, inputs):
     xr = torch.empty(n, dtype=torch.float64, device="cuda")
     rr = timed(A32, xr, sap.SAP_MODE_MIXED_FP32_REFINE, tol_=1e-8)
     log(f"bench[mixed]: refine {rr}")
+    log("bench[mixed]: BF16-input sketch with the refinement form, to a 1e-8 relative correction")
+    xb = torch.empty(n, dtype=torch.float64, device="cuda")
+    rb = timed(A32, xb, sap.SAP_MODE_MIXED_BF16SA, tol_=1e-8)
+    log(f"bench[mixed]: bf16sa {rb}")
     log("bench[mixed]: widening A to FP64 for the FP64 form")
     A64 = widen(A32)
     del A32
@@ -217,7 +222,8 @@ def form_mixed(args, sap, torch, inputs):
                         f"b = A x + 1e-8 noise, tol {tol}",
             "mixed": rm, "fp64": r64, "speedup": r64["solve_ms"] / rm["solve_ms"],
             "rel_diff_x": rel(x32, x64),
-            "refine": rr, "refine_speedup": r64["solve_ms"] / rr["solve_ms"], "refine_rel_diff_x": rel(xr, x64)}
+            "refine": rr, "refine_speedup": r64["solve_ms"] / rr["solve_ms"], "refine_rel_diff_x": rel(xr, x64),
+            "bf16sa": rb, "bf16sa_speedup": r64["solve_ms"] / rb["solve_ms"], "bf16sa_rel_diff_x": rel(xb, x64)}
 
 
 def form_batched(args, sap, torch, inputs):

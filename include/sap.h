@@ -75,10 +75,23 @@ typedef enum sap_dtype { SAP_F64 = 0, SAP_F32 = 1, SAP_BF16 = 2 } sap_dtype;
  * reached) or after max_refine steps.  The sketch, QR and preconditioner are
  * FP64 as in MIXED_FP32, which reaches the FP64 stopping test and is usually
  * faster. */
+/* MIXED_BF16SA: A stored in FP32; the sketch is applied to a BF16 copy of A
+ * (round to nearest even, made by the library in its workspace: m * n * 2
+ * more bytes, counted in t_apply_ms) with FP64 accumulation, since the
+ * preconditioner only has to be approximate (Sec. 3.2: LSQR on A R^-1
+ * converges to the solution for any invertible R); the iterations are those
+ * of MIXED_FP32_REFINE, with the same tol semantics.  BF16 keeps 8 bits of
+ * each entry: a relative perturbation of up to 2^-9 per entry of A.  Where
+ * A's ill-conditioning is column scaling (which commutes with entrywise
+ * relative rounding) the convergence rate stays that of the sketch, but the
+ * sketch-and-solve initial guess is then only ~2^-9 accurate, which costs
+ * extra iterations on near-consistent problems; otherwise the preconditioner
+ * itself degrades. */
 typedef enum sap_mode {
     SAP_MODE_FP64 = 0,
     SAP_MODE_MIXED_FP32 = 1,
-    SAP_MODE_MIXED_FP32_REFINE = 2
+    SAP_MODE_MIXED_FP32_REFINE = 2,
+    SAP_MODE_MIXED_BF16SA = 3
 } sap_mode;
 
 typedef struct sap_ctx sap_ctx;
@@ -159,7 +172,7 @@ typedef struct sap_problem {
     int32_t n;          /* columns of A, n >= 1 */
     const void *A;      /* device, row-major m x n, lda >= n */
     int64_t lda;
-    sap_dtype a_type;   /* F64 for SAP_MODE_FP64, F32 for SAP_MODE_MIXED_FP32 */
+    sap_dtype a_type;   /* F64 for SAP_MODE_FP64, F32 for the mixed modes */
     const double *b;    /* device, m doubles */
 } sap_problem;
 

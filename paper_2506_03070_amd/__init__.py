@@ -17,7 +17,7 @@ SAP_OK, SAP_EINVAL, SAP_ENOMEM, SAP_RANK_DEFICIENT, SAP_NOT_CONVERGED, SAP_PENDI
 STATUS_NAMES = {0: "SAP_OK", 1: "SAP_EINVAL", 2: "SAP_ENOMEM", 3: "SAP_RANK_DEFICIENT",
                 4: "SAP_NOT_CONVERGED", 5: "SAP_PENDING", 6: "SAP_EDEVICE", 7: "SAP_ECANCELED"}
 SAP_F64, SAP_F32, SAP_BF16 = 0, 1, 2
-SAP_MODE_FP64, SAP_MODE_MIXED_FP32, SAP_MODE_MIXED_FP32_REFINE = 0, 1, 2
+SAP_MODE_FP64, SAP_MODE_MIXED_FP32, SAP_MODE_MIXED_FP32_REFINE, SAP_MODE_MIXED_BF16SA = 0, 1, 2, 3
 
 # Every symbol the header declares (checked by the CPU test suite).
 EXPORTS = ["sap_create", "sap_destroy", "sap_last_error", "sap_status_string", "sps_generate",

@@ -1,5 +1,8 @@
 // C ABI entry points (declared in include/sap.h): argument validation,
 // workspace management and the orchestration of Alg. 1 on one stream.
+#include <hip/hip_bf16.h>
+
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -115,6 +118,20 @@ __global__ __launch_bounds__(256) void finite_check_kernel(const double *__restr
   for (int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; i < m; i += stride)
     bad |= !isfinite(b[i]);
   if (bad) atomicOr(flag, 1);
+}
+
+// BF16 copy of an FP32 row-major matrix (round to nearest even), rows of
+// ldo elements (ldo a multiple of 8: 16-byte rows).  The BF16-input sketch
+// mode applies S to this copy.
+__global__ __launch_bounds__(256) void to_bf16_kernel(const float *__restrict__ A, int64_t lda, int64_t m, int n,
+                                                      __hip_bfloat16 *__restrict__ out, int64_t ldo) {
+  const int64_t total = m * ldo;
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * 256;
+  for (int64_t e = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; e < total; e += stride) {
+    const int64_t i = e / ldo;
+    const int j = static_cast<int>(e - i * ldo);
+    out[e] = __float2bfloat16(j < n ? A[i * lda + j] : 0.0f);
+  }
 }
 
 sap_status check_sketch(sap_ctx *ctx, const sps_sketch *S) {
@@ -335,7 +352,7 @@ sap_status sap_solve(sap_ctx *ctx, const sap_problem *prob, const sap_params *pa
   const int mode = par->mode;
   if (mode == SAP_MODE_FP64) {
     if (prob->a_type != SAP_F64) return fail(ctx, SAP_EINVAL, "sap_solve: FP64 mode needs an F64 A");
-  } else if (mode == SAP_MODE_MIXED_FP32 || mode == SAP_MODE_MIXED_FP32_REFINE) {
+  } else if (mode == SAP_MODE_MIXED_FP32 || mode == SAP_MODE_MIXED_FP32_REFINE || mode == SAP_MODE_MIXED_BF16SA) {
     if (prob->a_type != SAP_F32) return fail(ctx, SAP_EINVAL, "sap_solve: mixed modes need an F32 A");
     if (par->max_refine < 0) return fail(ctx, SAP_EINVAL, "sap_solve: max_refine must be >= 0");
   } else {
@@ -358,7 +375,10 @@ sap_status sap_solve(sap_ctx *ctx, const sap_problem *prob, const sap_params *pa
   const size_t bytes_lsqr = lsqr_workspace_bytes(ctx, m, n);
   size_t scratch = bytes_apply > bytes_qr ? bytes_apply : bytes_qr;
   scratch = scratch > bytes_lsqr ? scratch : bytes_lsqr;
-  const size_t total = 8 * 256 + bytes_flags + bytes_idx + bytes_sign + bytes_Y + bytes_tau + scratch;
+  const bool bf16sa = mode == SAP_MODE_MIXED_BF16SA;
+  const int64_t ld_bf = (static_cast<int64_t>(n) + 7) / 8 * 8;
+  const size_t bytes_bf = bf16sa ? static_cast<size_t>(m) * ld_bf * sizeof(__hip_bfloat16) : 0;
+  const size_t total = 9 * 256 + bytes_flags + bytes_idx + bytes_sign + bytes_Y + bytes_tau + bytes_bf + scratch;
   s = ensure_workspace(ctx, total, st);
   if (s != SAP_OK) return s;
   Carve cv(ctx->ws);
@@ -367,6 +387,7 @@ sap_status sap_solve(sap_ctx *ctx, const sap_problem *prob, const sap_params *pa
   uint64_t *sign = cv.take<uint64_t>(static_cast<size_t>(m));
   double *Y = cv.take<double>(static_cast<size_t>(d) * nc);
   double *tau = cv.take<double>(nc);
+  __hip_bfloat16 *Abf = bf16sa ? cv.take<__hip_bfloat16>(static_cast<size_t>(m) * ld_bf) : nullptr;
   void *work = cv.take<char>(scratch);
 
   if (info) std::memset(info, 0, sizeof(*info));
@@ -387,8 +408,15 @@ sap_status sap_solve(sap_ctx *ctx, const sap_problem *prob, const sap_params *pa
   s = launch_generate(ctx, &S, &flags->gen_error, st);
   if (s != SAP_OK) return s;
   SAP_HIP_TRY(hipEventRecord(ev[1], st));
+  if (bf16sa) {  // the BF16 copy is part of the apply phase's cost
+    const int64_t tot = m * ld_bf;
+    const unsigned g = static_cast<unsigned>(std::min<int64_t>((tot + 255) / 256, int64_t(ctx->num_cus) * 16));
+    to_bf16_kernel<<<g, 256, 0, st>>>(static_cast<const float *>(prob->A), prob->lda, m, n, Abf, ld_bf);
+    SAP_HIP_TRY(hipGetLastError());
+  }
   hipEvent_t pb_apply = prof_begin(ctx, st);
-  s = launch_apply(ctx, &S, prob->A, prob->lda, prob->a_type, prob->b, n, Y, d, y_type, work, st);
+  s = bf16sa ? launch_apply(ctx, &S, Abf, ld_bf, SAP_BF16, prob->b, n, Y, d, y_type, work, st)
+             : launch_apply(ctx, &S, prob->A, prob->lda, prob->a_type, prob->b, n, Y, d, y_type, work, st);
   if (s != SAP_OK) return s;
   prof_end(ctx, kProfApply, pb_apply, st);
   SAP_HIP_TRY(hipEventRecord(ev[2], st));
@@ -407,6 +435,7 @@ sap_status sap_solve(sap_ctx *ctx, const sap_problem *prob, const sap_params *pa
     return fail(ctx, SAP_RANK_DEFICIENT, "sap_solve: R is numerically singular (A rank deficient)");
   }
   // x0 = R^-1 (Q^T S b)[0:n]: column n of the factored sketch.
+  // MIXED_BF16SA iterates as MIXED_FP32_REFINE (FP32 passes, FP64 refinement)
   const int lsqr_mode = (mode == SAP_MODE_FP64) ? 0 : (mode == SAP_MODE_MIXED_FP32 ? 1 : 2);
   sap_info li{};
   s = run_lsqr(ctx, prob, Y, d, nullptr, Y + static_cast<int64_t>(n) * d, par->tol, par->maxiter, lsqr_mode,

@@ -89,6 +89,36 @@ def test_refine_solve_parity(sap, orc, name, m, n, d, kind, cond, noise):
     assert np.linalg.norm(A64 @ (x - x_or)) <= 1e-10 * np.linalg.norm(p.b)
 
 
+@pytest.mark.parametrize("name,m,n,d,kind,cond,noise", REFINE_CASES[:1] + REFINE_CASES[2:])
+def test_bf16_sketch_solve_parity(sap, orc, name, m, n, d, kind, cond, noise):
+    """BF16-input sketch (MIXED_BF16SA): the sketch of a BF16 copy of A only
+    preconditions, so the refined solution meets the same bars as the
+    refinement form against the FP64 oracle on the FP32 A.  The cases are
+    column-scaled (their ill-conditioning commutes with the entrywise BF16
+    rounding), so the convergence rate stays that of the sketch, about
+    sqrt(n/d) = 1/2 per iteration.  What the BF16 sketch loses is the
+    sketch-and-solve initial guess: accurate to ~2^-9 instead of to the
+    problem's small residual, which costs up to log2(2^-9 / 1e-8) ~ 18 more
+    iterations than the FP32-input refinement form; the bound allows 24."""
+    import torch
+    print(f"bf16 sketch {name} m={m} n={n} d={d}", flush=True)
+    p = inputs.make_problem(m, n, kind=kind, cond=cond, noise=noise, seed=m + 29, dtype=np.float32)
+    A64 = p.A.astype(np.float64)
+    seed = 77
+    res = sap.sap_solve(_dev(p.A), _dev(p.b), d, 8, seed, tol=1e-8, maxiter=1000,
+                        mode=sap.SAP_MODE_MIXED_BF16SA, max_refine=12)
+    ref = sap.sap_solve(_dev(p.A), _dev(p.b), d, 8, seed, tol=1e-8, maxiter=1000,
+                        mode=sap.SAP_MODE_MIXED_FP32_REFINE, max_refine=12)
+    torch.cuda.synchronize()
+    assert res.status == sap.SAP_OK, res.info
+    assert res.info["iters"] <= ref.info["iters"] + 24, (res.info["iters"], ref.info["iters"])
+    x = res.x.cpu().numpy()
+    x_or, info_or = orc.solve(A64, p.b, d, 8, seed, tol=1e-12, maxiter=400)
+    assert info_or["status"] == "ok"
+    assert np.linalg.norm(x - x_or) <= 1e-8 * np.linalg.norm(x_or)
+    assert np.linalg.norm(A64 @ (x - x_or)) <= 1e-10 * np.linalg.norm(p.b)
+
+
 def test_mixed_mode_dtype_checks(sap):
     p = inputs.make_problem(4000, 10, kind="colscale", cond=10.0, seed=1)
     with pytest.raises(sap.SapError) as e:
@@ -99,6 +129,9 @@ def test_mixed_mode_dtype_checks(sap):
     assert e.value.status == sap.SAP_EINVAL
     with pytest.raises(sap.SapError) as e:
         sap.sap_solve(_dev(p.A), _dev(p.b), 40, 8, 1, mode=sap.SAP_MODE_MIXED_FP32_REFINE)  # F64 A
+    assert e.value.status == sap.SAP_EINVAL
+    with pytest.raises(sap.SapError) as e:
+        sap.sap_solve(_dev(p.A), _dev(p.b), 40, 8, 1, mode=sap.SAP_MODE_MIXED_BF16SA)  # F64 A
     assert e.value.status == sap.SAP_EINVAL
     with pytest.raises(sap.SapError) as e:
         sap.sap_solve(_dev(p.A.astype(np.float32)), _dev(p.b), 40, 8, 1, mode=sap.SAP_MODE_MIXED_FP32_REFINE,
