@@ -116,6 +116,13 @@ SOLVE_CASES = [
     ("tiny", 40, 3, 12, 2, "svd", 10.0, 1e-3, False),
     ("sparse", 50000, 120, 480, 8, "sparse_sign", 1.0, 1e-2, False),
     ("odd-n", 25000, 333, 1337, 8, "svd", 1e5, 1e-6, False),
+    # degenerate shapes the method allows: the smallest problem (m = 2, n = 1,
+    # d = 2, one nonzero per column), the smallest sketch (d = n + 1, slow
+    # rate sqrt(n/d) ~ 1), and a dense sign sketch (zeta = d: every column of
+    # S holds every row, generation needs the most redraw rounds)
+    ("min-m", 2, 1, 2, 1, "svd", 10.0, 1e-3, False),
+    ("d-eq-n-plus-1", 5000, 40, 41, 8, "svd", 10.0, 1e-3, False),
+    ("zeta-eq-d", 3000, 10, 16, 16, "colscale", 10.0, 1e-3, False),
 ]
 
 
@@ -137,9 +144,11 @@ def test_solve_parity(sap, orc, name, m, n, d, zeta, kind, cond, noise, row_scal
     assert res.status == sap.SAP_OK, res.info
     assert info_or["status"] == "ok"
     assert np.linalg.norm(p.A @ (x - x_or)) <= 1e-12 * nb
-    if name in ("config0", "tiny", "wide-d", "sparse"):
+    if name in ("config0", "tiny", "wide-d", "sparse", "min-m", "d-eq-n-plus-1", "zeta-eq-d"):
         assert np.linalg.norm(x - x_or) <= 1e-8 * np.linalg.norm(x_or)
-    assert abs(res.info["iters"] - info_or["iters"]) <= 2
+    # the stopping iteration moves with rounding where the rate is close to 1
+    # (d = n + 1: ~80 iterations), by a few percent of the count
+    assert abs(res.info["iters"] - info_or["iters"]) <= max(2, 0.05 * info_or["iters"])
 
 
 def test_solve_errors(sap):
