@@ -55,18 +55,33 @@ __device__ __forceinline__ float readlane(float v, int src) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
 }
 
+// DPP move restricted to the rows in ROWMASK; lanes of the other rows read 0.
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ double dpp_mov_rows(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROWMASK, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROWMASK, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ float dpp_mov_rows(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROWMASK, 0xF, false));
+}
+
 // Sum over the 64 lanes of a wavefront returned as a wave-uniform value.
 // Within each row of 16 lanes: quad_perm [1,0,3,2], quad_perm [2,3,0,1],
-// row_half_mirror, row_mirror leave the row sum in every lane; the four row
-// sums are then combined from lanes 0, 16, 32, 48.  Fixed order, so the
-// result is deterministic.  Every lane of the wave must be active.
+// row_half_mirror, row_mirror leave the row sum in every lane; row_bcast:15
+// into rows 1 and 3 then row_bcast:31 into rows 2 and 3 accumulate the four
+// row sums into row 3, and lane 63 is read.  Fixed order, so the result is
+// deterministic.  Every lane of the wave must be active.
 template <typename T>
 __device__ __forceinline__ T wave_sum_u(T v) {
   v += dpp_mov<0xB1>(v);
   v += dpp_mov<0x4E>(v);
   v += dpp_mov<0x141>(v);
   v += dpp_mov<0x140>(v);
-  return (readlane(v, 0) + readlane(v, 16)) + (readlane(v, 32) + readlane(v, 48));
+  v += dpp_mov_rows<0x142, 0xA>(v);
+  v += dpp_mov_rows<0x143, 0xC>(v);
+  return readlane(v, 63);
 }
 
 // Broadcast a double held by lane `src` (wave-uniform) to all lanes.
