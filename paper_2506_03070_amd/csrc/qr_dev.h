@@ -50,25 +50,41 @@ __device__ __forceinline__ void panel_column(double (&P)[S][NB], PanelShared<NB,
   const int lane = t & (kWave - 1), wave = t / kWave;
   // Straight-line code: masks instead of per-row branches (the column is
   // latency-bound, and every branch costs exec-mask bookkeeping).
-  double acc[NB], rowv[NB];
+  double acc[NB];
 #pragma unroll
-  for (int x = 0; x < NB; ++x) acc[x] = rowv[x] = 0.0;
-  bool has_j = false;  // this thread holds row J of the panel (one thread does)
+  for (int x = 0; x < NB; ++x) acc[x] = 0.0;
 #pragma unroll
   for (int s = 0; s < S; ++s) {
     const int lr = t + TH * s - roff;
     const double a = (lr > J && lr < dr) ? P[s][J] : 0.0;
-    const bool hit = lr == J && lr < dr;
-    has_j = has_j || hit;
 #pragma unroll
-    for (int x = 0; x < NB; ++x) {
-      acc[x] += a * P[s][x];
-      rowv[x] = hit ? P[s][x] : rowv[x];  // selects with static indices only
-    }
+    for (int x = 0; x < NB; ++x) acc[x] += a * P[s][x];
   }
-  if (has_j) {
+  // row J of the panel is held by one thread: in its register row 0 whenever
+  // J + roff < TH (every caller: roff <= NB), else found by selects with
+  // static indices only
+  if (J + roff < TH) {  // uniform
+    if (J < dr && t == J + roff) {
 #pragma unroll
-    for (int x = 0; x < NB; ++x) sh.ctot[B][NB + x] = rowv[x];
+      for (int x = 0; x < NB; ++x) sh.ctot[B][NB + x] = P[0][x];
+    }
+  } else {
+    double rowv[NB];
+    bool has_j = false;
+#pragma unroll
+    for (int x = 0; x < NB; ++x) rowv[x] = 0.0;
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const int lr = t + TH * s - roff;
+      const bool hit = lr == J && lr < dr;
+      has_j = has_j || hit;
+#pragma unroll
+      for (int x = 0; x < NB; ++x) rowv[x] = hit ? P[s][x] : rowv[x];
+    }
+    if (has_j) {
+#pragma unroll
+      for (int x = 0; x < NB; ++x) sh.ctot[B][NB + x] = rowv[x];
+    }
   }
 #pragma unroll
   for (int x = 0; x < NB; ++x) acc[x] = wave_sum_u(acc[x]);
