@@ -31,7 +31,7 @@
 namespace sap {
 namespace {
 
-constexpr int kPassThreads = 1024;
+constexpr int kPassThreads = 512;
 constexpr int kPassWaves = kPassThreads / kWave;
 constexpr int kMaxN = 8192;
 
@@ -61,7 +61,7 @@ struct PassTypes<3> {
   using TA = float; using TC = double; using TUI = double; using TUO = float;
 };
 
-// WC waves split the columns of a row (64*VEC*J columns each); WR = 16/WC
+// WC waves split the columns of a row (64*VEC*J columns each); WR = kPassWaves/WC
 // row groups share the workgroup.
 //
 // Row distribution: workgroup g first takes rows [g S, (g+1) S) (S =
@@ -111,9 +111,8 @@ __global__ __launch_bounds__(kPassThreads) void lsqr_pass_kernel(
   // two calls by a barrier (the exchange buffer parity restarts)
   auto rows = [&](int64_t i_begin, int64_t i_end) {
   const int64_t nsteps = i_end > i_begin ? (i_end - i_begin + WR * R - 1) / (WR * R) : 0;
-  for (int64_t step = 0; step < nsteps; ++step) {
+  auto load_step = [&](int64_t step, TA (&a)[R][J][VEC]) {
     const int64_t base = i_begin + step * (WR * R) + wr * R;
-    TA a[R][J][VEC];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const int64_t row = base + r;
@@ -133,6 +132,9 @@ __global__ __launch_bounds__(kPassThreads) void lsqr_pass_kernel(
         }
       }
     }
+  };
+  auto compute_step = [&](int64_t step, TA (&a)[R][J][VEC]) {
+    const int64_t base = i_begin + step * (WR * R) + wr * R;
     TC dot[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -172,6 +174,18 @@ __global__ __launch_bounds__(kPassThreads) void lsqr_pass_kernel(
           nrm += static_cast<double>(uh) * static_cast<double>(uh);
         }
       }
+    }
+  };
+  // two steps in flight per wave: the loads of step s+1 are issued before
+  // step s is reduced (512-thread workgroups leave the registers for it)
+  TA a0[R][J][VEC], a1[R][J][VEC];
+  if (nsteps > 0) load_step(0, a0);
+  for (int64_t step = 0; step < nsteps; step += 2) {
+    if (step + 1 < nsteps) load_step(step + 1, a1);
+    compute_step(step, a0);
+    if (step + 1 < nsteps) {
+      if (step + 2 < nsteps) load_step(step + 2, a0);
+      compute_step(step + 1, a1);
     }
   }
   };
@@ -530,8 +544,9 @@ PassCfg choose_pass(int n, int64_t lda, const void *A) {
   const int vmax = 16 / static_cast<int>(sizeof(TA));
   const bool aligned = (reinterpret_cast<uintptr_t>(A) % 16 == 0) && (lda % vmax == 0) && (n % vmax == 0);
   PassCfg c{aligned ? vmax : 1, 2, 1};
-  // at most 16 elements of a row per lane (A values, p and q live in registers)
-  const int jmax = std::min(8, 16 / c.vec);
+  // at most 16 elements of a row per lane (A values, p and q live in
+  // registers); at most kPassWaves waves across a row (n <= 8192 needs 8)
+  const int jmax = 16 / c.vec;
   const int per_j = kWave * c.vec;
   const int need = (n + per_j - 1) / per_j;  // J * WC needed
   if (need <= jmax) {
@@ -558,18 +573,28 @@ const void *pick_wc(int wc) {
   switch (wc) {
     case 2: return pass_fn<MODE, VEC, J, 2>();
     case 4: return pass_fn<MODE, VEC, J, 4>();
-    case 8: return pass_fn<MODE, VEC, J, 8>();
-    default: return pass_fn<MODE, VEC, J, 16>();
+    default: return pass_fn<MODE, VEC, J, 8>();  // kPassWaves
   }
+}
+
+// J that pick_vec instantiates for c (the host mirror of its choice).
+int pass_j(const PassCfg &c) {
+  const int jmax = 16 / c.vec;
+  if (c.wc > 1) return jmax;
+  if (c.j == 2 || c.j == 4 || (c.j == 8 && jmax >= 8)) return c.j;
+  return jmax;
 }
 
 template <int MODE, int VEC>
 const void *pick_vec(const PassCfg &c) {
-  constexpr int JMAX = (16 / VEC) < 8 ? (16 / VEC) : 8;
+  constexpr int JMAX = 16 / VEC;
   if (c.wc == 1) {
-    switch (c.j) {
+    switch (pass_j(c)) {
       case 2: return pass_fn<MODE, VEC, 2, 1>();
       case 4: return pass_fn<MODE, VEC, 4, 1>();
+      case 8:
+        if constexpr (JMAX >= 8) return pass_fn<MODE, VEC, 8, 1>();
+        [[fallthrough]];
       default: return pass_fn<MODE, VEC, JMAX, 1>();
     }
   }
@@ -606,12 +631,10 @@ struct PassPlan {
 
 int max_grid(sap_ctx *ctx) { return ctx->num_cus * 2; }
 
-// Rows one step of the kernel pick_pass returns for c covers: WR = 16 / WC
-// row groups of R rows (J as pick_vec resolves it).
+// Rows one step of the kernel pick_pass returns for c covers: WR =
+// kPassWaves / WC row groups of R rows.
 int rows_per_step(const PassCfg &c) {
-  const int jmax = std::min(16 / c.vec, 8);
-  const int j = c.wc == 1 ? (c.j == 2 || c.j == 4 ? c.j : jmax) : jmax;
-  const int jv = j * c.vec;
+  const int jv = pass_j(c) * c.vec;
   const int r = jv >= 16 ? 1 : std::min(4, 16 / jv);
   return (kPassWaves / c.wc) * r;
 }

@@ -192,3 +192,34 @@ def test_solve_deterministic(sap):
     x2 = r2.x.cpu().numpy()
     torch.cuda.synchronize()
     assert np.linalg.norm(p.A @ (x1 - x2)) <= 1e-13 * np.linalg.norm(p.b)
+
+
+def test_unaligned_wide_rows(sap):
+    """n = 4099 in FP64: an odd row length, so the pass reads rows element by
+    element, 16 per lane, with all 8 waves of a workgroup across a row (the
+    widest element-wise case).  The same matrix stored with lda = n and
+    with lda = n + 1 gives the same solution to rounding, and both meet the
+    normal-equation bar ||A^T r|| <= 1e-11 ||A||_F (||A||_F ||x|| + ||b||)."""
+    import torch
+    m, n, d = 20000, 4099, 8200
+    _note(f"unaligned wide rows m={m} n={n} d={d}")
+    g = torch.Generator(device="cuda")
+    g.manual_seed(4099)
+    A = torch.randn(m, n, generator=g, device="cuda", dtype=torch.float64)
+    A *= torch.logspace(0, -3, n, device="cuda", dtype=torch.float64)[None, :]
+    b = torch.randn(m, generator=g, device="cuda", dtype=torch.float64)
+    Ap = torch.zeros(m, n + 1, device="cuda", dtype=torch.float64)
+    Ap[:, :n] = A
+    Aview = Ap[:, :n]  # lda = n + 1
+    r1 = sap.sap_solve(A, b, d, 8, 5, tol=1e-12, maxiter=300)
+    r2 = sap.sap_solve(Aview, b, d, 8, 5, tol=1e-12, maxiter=300)
+    torch.cuda.synchronize()
+    assert r1.status == sap.SAP_OK and r2.status == sap.SAP_OK, (r1.info, r2.info)
+    x1, x2 = r1.x, r2.x
+    assert float(torch.linalg.vector_norm(x1 - x2)) <= 1e-9 * float(torch.linalg.vector_norm(x2))
+    fro = float(torch.linalg.matrix_norm(A))
+    for x in (x1, x2):
+        r = b - A @ x
+        eta = float(torch.linalg.vector_norm(A.T @ r)) / (fro * (fro * float(torch.linalg.vector_norm(x)) +
+                                                                 float(torch.linalg.vector_norm(b))))
+        assert eta <= 1e-11, eta
