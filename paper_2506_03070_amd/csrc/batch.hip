@@ -352,12 +352,20 @@ __global__ __launch_bounds__(256) void batch_repack_kernel(const RepackJob *__re
 // At the initialisation step (st->init) the pass reads u_in = b and p = x.
 // p sits in LDS (read per element), q in registers; the waves' q partials
 // are combined through one LDS vector in wave order.
-template <typename TA, int VEC, int KJ, int U>
-__global__ __launch_bounds__(kBThreads) void batch_pass_kernel(const BatchItem *__restrict__ items,
-                                                               const int2 *__restrict__ work, int nwork, int tune) {
+// PF: 512-thread workgroups with two row groups in flight per wave (the next
+// group's loads issued before the current one is reduced); otherwise 1024
+// threads and one group at a time.  The served form, whose rounds hold a few
+// large requests, uses PF; the batched form, many small problems, the other
+// (more waves to cover the per-row shuffles).
+template <typename TA, int VEC, int KJ, int U, bool PF>
+__global__ __launch_bounds__(PF ? 512 : kBThreads) void batch_pass_kernel(const BatchItem *__restrict__ items,
+                                                                          const int2 *__restrict__ work, int nwork,
+                                                                          int tune) {
+  constexpr int TH = PF ? 512 : kBThreads;
+  constexpr int NW = TH / kWave;
   __shared__ double psh[64 * VEC * KJ];
   __shared__ double qacc[64 * VEC * KJ];
-  __shared__ double nsh[kBWaves];
+  __shared__ double nsh[NW];
   const int2 wk = work[blockIdx.x];
   const BatchItem &it = items[wk.x];
   const LsqrState *st = it.st;
@@ -377,7 +385,7 @@ __global__ __launch_bounds__(kBThreads) void batch_pass_kernel(const BatchItem *
   const int64_t lda = it.lda;
   const bool vec_ok = (VEC > 1);
 
-  for (int c = threadIdx.x; c < 64 * VEC * KJ; c += kBThreads) {
+  for (int c = threadIdx.x; c < 64 * VEC * KJ; c += TH) {
     psh[c] = c < n ? pv[c] : 0.0;
     qacc[c] = 0.0;
   }
@@ -390,9 +398,8 @@ __global__ __launch_bounds__(kBThreads) void batch_pass_kernel(const BatchItem *
   const int64_t r0 = static_cast<int64_t>(wk.y) * it.rows_per_chunk;
   const int64_t r1 = min(it.m, r0 + it.rows_per_chunk);
   double nrm = 0.0;
-  for (int64_t base = r0 + static_cast<int64_t>(wave) * RS * U; base < r1; base += static_cast<int64_t>(kBWaves) * RS * U) {
-    TA a[U][KJ][VEC];
-    double ui[U];
+  const int64_t gstride = static_cast<int64_t>(NW) * RS * U;
+  auto load_group = [&](int64_t base, TA (&a)[U][KJ][VEC], double (&ui)[U]) {
 #pragma unroll
     for (int uu = 0; uu < U; ++uu) {
       const int64_t row = base + uu * RS + slot;
@@ -410,6 +417,8 @@ __global__ __launch_bounds__(kBThreads) void batch_pass_kernel(const BatchItem *
       }
       ui[uu] = rv ? uin[row] : 0.0;
     }
+  };
+  auto compute_group = [&](int64_t base, TA (&a)[U][KJ][VEC], double (&ui)[U]) {
 #pragma unroll
     for (int uu = 0; uu < U; ++uu) {
       const int64_t row = base + uu * RS + slot;
@@ -431,6 +440,27 @@ __global__ __launch_bounds__(kBThreads) void batch_pass_kernel(const BatchItem *
         }
       }
     }
+  };
+  int64_t base = r0 + static_cast<int64_t>(wave) * RS * U;
+  if constexpr (PF) {
+    TA a0[U][KJ][VEC], a1[U][KJ][VEC];
+    double u0[U], u1[U];
+    if (base < r1) load_group(base, a0, u0);
+    for (; base < r1; base += 2 * gstride) {
+      if (base + gstride < r1) load_group(base + gstride, a1, u1);
+      compute_group(base, a0, u0);
+      if (base + gstride < r1) {
+        if (base + 2 * gstride < r1) load_group(base + 2 * gstride, a0, u0);
+        compute_group(base + gstride, a1, u1);
+      }
+    }
+  } else {
+    for (; base < r1; base += gstride) {
+      TA a[U][KJ][VEC];
+      double ui[U];
+      load_group(base, a, ui);
+      compute_group(base, a, ui);
+    }
   }
   // combine the row slots of the wavefront (lanes with equal `sub`), then waves
 #pragma unroll
@@ -443,7 +473,7 @@ __global__ __launch_bounds__(kBThreads) void batch_pass_kernel(const BatchItem *
     }
   nrm = wave_sum(nrm);
   if (lane == 0) nsh[wave] = nrm;
-  for (int w = 0; w < kBWaves; ++w) {
+  for (int w = 0; w < NW; ++w) {
     if (wave == w && slot == 0) {
 #pragma unroll
       for (int j = 0; j < KJ; ++j)
@@ -453,10 +483,10 @@ __global__ __launch_bounds__(kBThreads) void batch_pass_kernel(const BatchItem *
     __syncthreads();
   }
   double *qdst = it.qpart + static_cast<int64_t>(wk.y) * n;
-  for (int c = threadIdx.x; c < n; c += kBThreads) qdst[c] = qacc[c];
+  for (int c = threadIdx.x; c < n; c += TH) qdst[c] = qacc[c];
   if (threadIdx.x == 0) {
     double s = 0.0;
-    for (int w = 0; w < kBWaves; ++w) s += nsh[w];
+    for (int w = 0; w < NW; ++w) s += nsh[w];
     it.nrmpart[wk.y] = s;
   }
 }
@@ -523,6 +553,7 @@ void launch_batch_qr(const BatchItem *items, int count, int max_cols, hipStream_
 struct PassChoice {
   const void *fn;
   int vec, kj;
+  int threads;
 };
 
 // E = KJ * VEC elements of a row per lane: 8 while the widest problem has
@@ -532,25 +563,30 @@ struct PassChoice {
 // U = row groups in flight per lane, as many as the registers allow without
 // spilling (the per-element loads of an unaligned row each need an address).
 template <typename TA>
-PassChoice pick_batch_pass(int n_max, bool aligned) {
+PassChoice pick_batch_pass(int n_max, bool aligned, bool pf) {
   constexpr int vmax = 16 / static_cast<int>(sizeof(TA));
   constexpr bool f32 = sizeof(TA) == 4;
+  auto fn = [](auto kernel) { return reinterpret_cast<const void *>(kernel); };
+  const int th = pf ? 512 : kBThreads;
   if (n_max <= 512) {
     if (aligned)
-      return {reinterpret_cast<const void *>(&batch_pass_kernel<TA, vmax, 8 / vmax, f32 ? 4 : 2>), vmax, 8 / vmax};
-    return {reinterpret_cast<const void *>(&batch_pass_kernel<TA, 1, 8, 2>), 1, 8};
+      return {pf ? fn(&batch_pass_kernel<TA, vmax, 8 / vmax, f32 ? 4 : 2, true>)
+                 : fn(&batch_pass_kernel<TA, vmax, 8 / vmax, f32 ? 4 : 2, false>), vmax, 8 / vmax, th};
+    return {pf ? fn(&batch_pass_kernel<TA, 1, 8, 2, true>) : fn(&batch_pass_kernel<TA, 1, 8, 2, false>), 1, 8, th};
   }
   if (aligned)
-    return {reinterpret_cast<const void *>(&batch_pass_kernel<TA, vmax, 16 / vmax, f32 ? 2 : 1>), vmax, 16 / vmax};
-  return {reinterpret_cast<const void *>(&batch_pass_kernel<TA, 1, 16, 1>), 1, 16};
+    return {pf ? fn(&batch_pass_kernel<TA, vmax, 16 / vmax, f32 ? 2 : 1, true>)
+               : fn(&batch_pass_kernel<TA, vmax, 16 / vmax, f32 ? 2 : 1, false>), vmax, 16 / vmax, th};
+  return {pf ? fn(&batch_pass_kernel<TA, 1, 16, 1, true>) : fn(&batch_pass_kernel<TA, 1, 16, 1, false>), 1, 16, th};
 }
 
-void launch_pass_fn(const void *fn, const BatchItem *items, const int2 *work, int nwork, int tune, hipStream_t st) {
+void launch_pass_fn(const PassChoice &pc, const BatchItem *items, const int2 *work, int nwork, int tune,
+                    hipStream_t st) {
   const BatchItem *it_ = items;
   const int2 *w_ = work;
   int nw = nwork, tn = tune;
   void *args[] = {&it_, &w_, &nw, &tn};
-  (void)hipLaunchKernel(fn, dim3(nwork), dim3(kBThreads), args, 0, st);
+  (void)hipLaunchKernel(pc.fn, dim3(nwork), dim3(pc.threads), args, 0, st);
 }
 
 }  // namespace
@@ -863,7 +899,8 @@ sap_status run_batch(sap_ctx *ctx, int count, const sap_problem *probs, const sa
   SAP_HIP_TRY(hipStreamSynchronize(st));
 
   // ---- autotune the pass chunking once per batch shape ----
-  const PassChoice pc = (at == SAP_F32) ? pick_batch_pass<float>(n_max, aligned) : pick_batch_pass<double>(n_max, aligned);
+  const PassChoice pc = (at == SAP_F32) ? pick_batch_pass<float>(n_max, aligned, false)
+                                         : pick_batch_pass<double>(n_max, aligned, false);
   if (!have_tune) {
     const int64_t cands[] = {2048, 4096, 8192, 16384};
     float best_ms = 1e30f;
@@ -883,7 +920,7 @@ sap_status run_batch(sap_ctx *ctx, int count, const sap_problem *probs, const sa
       float ms_best = 1e30f;
       for (int rep = 0; rep < 2; ++rep) {
         SAP_HIP_TRY(hipEventRecord(e0, st));
-        launch_pass_fn(pc.fn, ditems, dpass, static_cast<int>(wt.size()), 1, st);
+        launch_pass_fn(pc, ditems, dpass, static_cast<int>(wt.size()), 1, st);
         SAP_HIP_TRY(hipEventRecord(e1, st));
         SAP_HIP_TRY(hipEventSynchronize(e1));
         float ms = 0.f;
@@ -915,7 +952,7 @@ sap_status run_batch(sap_ctx *ctx, int count, const sap_problem *probs, const sa
   hipGraphExec_t gexec = nullptr;
   SAP_HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
   for (int k = 0; k < kIterPerGraph; ++k) {
-    launch_pass_fn(pc.fn, ditems, dpass, npass, 0, st);
+    launch_pass_fn(pc, ditems, dpass, npass, 0, st);
     batch_lower_kernel<<<dim3(nblk_max, count), kTrsvThreads, 0, st>>>(ditems, dflags);
     batch_upper_kernel<<<dim3(nblk_max, count), kTrsvThreads, 0, st>>>(ditems, dflags, dflags + 1);
   }
@@ -1173,10 +1210,11 @@ hipError_t serve_round(Server *S, std::vector<ServeRequest *> &fresh) {
     if (static_cast<int>(pass_work.size()) > kServeMaxChunks) return hipErrorInvalidValue;
     if ((e = hipMemcpyAsync(S->d_active, items.data(), sizeof(BatchItem) * count, hipMemcpyHostToDevice, st)) != hipSuccess) return e;
     if ((e = hipMemcpyAsync(S->d_pass, pass_work.data(), sizeof(int2) * pass_work.size(), hipMemcpyHostToDevice, st)) != hipSuccess) return e;
-    const PassChoice pc = (at == SAP_F32) ? pick_batch_pass<float>(n_max, aligned) : pick_batch_pass<double>(n_max, aligned);
+    const PassChoice pc = (at == SAP_F32) ? pick_batch_pass<float>(n_max, aligned, true)
+                                           : pick_batch_pass<double>(n_max, aligned, true);
     const int nblk_max = (n_max + kTrsvB - 1) / kTrsvB;
     for (int k = 0; k < S->iters_per_round; ++k) {
-      launch_pass_fn(pc.fn, S->d_active, S->d_pass, static_cast<int>(pass_work.size()), 0, st);
+      launch_pass_fn(pc, S->d_active, S->d_pass, static_cast<int>(pass_work.size()), 0, st);
       batch_lower_kernel<<<dim3(nblk_max, count), kTrsvThreads, 0, st>>>(S->d_active, S->d_flags);
       batch_upper_kernel<<<dim3(nblk_max, count), kTrsvThreads, 0, st>>>(S->d_active, S->d_flags, S->d_flags + 1);
     }
