@@ -689,7 +689,7 @@ size_t lsqr_workspace_bytes(sap_ctx *ctx, int64_t m, int n) {
   bytes += sizeof(LsqrState);
   bytes += G * n * sizeof(double) + G * sizeof(double);  // partials
   bytes += 6 * static_cast<size_t>(n) * sizeof(double);  // v w p x0copy (+1 spare)
-  bytes += static_cast<size_t>(m) * sizeof(double);     // u
+  bytes += 2 * static_cast<size_t>(m) * sizeof(double);  // u, two buffers
   bytes += (3 * nblk + 16) * sizeof(int) + 4096 * sizeof(double);                  // flags, err, norm partials
   bytes += 2 * sizeof(unsigned int);                                               // pass claim counters
   bytes += 2 * static_cast<size_t>(n) * n * sizeof(double);                        // M = R^-1 and M^T
@@ -777,7 +777,12 @@ sap_status run_lsqr(sap_ctx *ctx, const sap_problem *prob, const double *R, int6
   double *w = cv.take<double>(n);
   double *p = cv.take<double>(n);
   double *xin = cv.take<double>(n);
-  double *u = cv.take<double>(m);  // FP32 values in the refinement form
+  // u alternates between two buffers: with several waves across a row
+  // (n > 1024), every wave of the row reads u_in[i] while one of them writes
+  // u_out[i], so a pass must not update u in place.  FP32 values in the
+  // refinement form.
+  double *ubuf[2] = {cv.take<double>(m), cv.take<double>(m)};
+  int ucur = 0;  // ubuf[ucur] holds the current u
   int *flags = cv.take<int>(3 * nblk + 2);
   int *flags_x0 = flags + 2 * nblk;
   int *err = cv.take<int>(4);
@@ -836,7 +841,8 @@ sap_status run_lsqr(sap_ctx *ctx, const sap_problem *prob, const double *R, int6
   auto iteration = [&](const PassPlan &pl, const void *pv, const void *uin) {
     const int G = pl.grid;
     const int qsl = (G + kQSlice - 1) / kQSlice;
-    launch_pass(ctx, pl, prob->A, prob->lda, m, n, pv, uin, u, st, qpart, nrmpart, dyn, s);
+    launch_pass(ctx, pl, prob->A, prob->lda, m, n, pv, uin, ubuf[ucur ^ 1], st, qpart, nrmpart, dyn, s);
+    ucur ^= 1;
     q_slices_kernel<<<dim3((n + 63) / 64, qsl), 256, 0, s>>>(qpart, G, n, qs);
     lsqr_mtq_kernel<<<ngemv, 1024, 0, s>>>(M, n, qs, qsl, nrmpart, G, v, vh, vpart, st);
     lsqr_mv_kernel<<<ngemv, 1024, 0, s>>>(Mt, n, vh, vpart, ngemv, nrmpart, G, v, p, refine ? p32 : nullptr, st);
@@ -874,7 +880,7 @@ sap_status run_lsqr(sap_ctx *ctx, const sap_problem *prob, const double *R, int6
     const int max_batches = maxiter / batch + 2;
     for (int nbatch = 0;; ++nbatch) {
       if (nbatch > max_batches) return fail(ctx, SAP_EDEVICE, "LSQR: device never reported completion");
-      for (int k = 0; k < batch; ++k) iteration(plan, refine ? static_cast<const void *>(p32) : p, u);
+      for (int k = 0; k < batch; ++k) iteration(plan, refine ? static_cast<const void *>(p32) : p, ubuf[ucur]);
       SAP_HIP_TRY(hipGetLastError());
       SAP_HIP_TRY(hipMemcpyAsync(&hs, st, sizeof(LsqrState), hipMemcpyDeviceToHost, s));
       SAP_HIP_TRY(hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, s));
