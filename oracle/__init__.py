@@ -76,6 +76,12 @@ def lib():
         L.orc_solve.argtypes = [_i64, _i32, _vp, _i64, _vp, _i32, _i32, _u64, _u64, _f64, _i32, _vp, _vp,
                                 _vp, ctypes.POINTER(SolveInfo)]
         L.orc_direct_solve.argtypes = [_i64, _i32, _vp, _i64, _vp, _vp]
+        L.orc_lambert_w0.argtypes = [_f64]
+        L.orc_lambert_w0.restype = _f64
+        L.orc_embedding_dim.argtypes = [_i64, _i32, _f64, _f64]
+        L.orc_embedding_dim.restype = _f64
+        L.orc_iteration_estimate.argtypes = [_i32, _i32, _f64]
+        L.orc_iteration_estimate.restype = _f64
         _lib = L
     return _lib
 
@@ -301,3 +307,18 @@ def direct_solve(A, b):
     x = np.zeros(n)
     lib().orc_direct_solve(m, n, _p(A), n, _p(_f64c(b)), _p(x))
     return x
+
+
+def lambert_w0(z):
+    """Principal branch of the Lambert W function for z >= 0 (Sec. 4.3)."""
+    return lib().orc_lambert_w0(float(z))
+
+
+def embedding_dim(m, n, eps, cost_ratio=1.0):
+    """Real d of eq. (4.2), iteration cost weighted by cost_ratio."""
+    return lib().orc_embedding_dim(int(m), int(n), float(eps), float(cost_ratio))
+
+
+def iteration_estimate(n, d, eps):
+    """Real t with (n/d)^(t/2) = eps (eq. (4.1))."""
+    return lib().orc_iteration_estimate(int(n), int(d), float(eps))

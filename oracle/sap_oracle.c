@@ -554,3 +554,40 @@ void orc_direct_solve(int64_t m, int32_t n, const double *A, int64_t lda, const 
     free(W);
     free(tau);
 }
+
+/* ------------------------------------------------------------------------
+ * Embedding dimension (Sec. 4.3).
+ *
+ * orc_lambert_w0: the principal branch W(z) for z >= 0, the w >= 0 with
+ * w e^w = z, found by bisection (w e^w is increasing for w >= 0; the bracket
+ * [0, max(1, ln(1 + z))] holds the root because w e^w >= z at w = ln(1 + z)
+ * when z >= e, and at w = 1 when z < e).  Slow and plain on purpose.
+ */
+double orc_lambert_w0(double z)
+{
+    if (!(z >= 0.0)) return NAN;
+    double lo = 0.0, hi = log1p(z);
+    if (hi < 1.0) hi = 1.0;
+    for (int it = 0; it < 200; ++it) {
+        double mid = 0.5 * (lo + hi);
+        if (mid * exp(mid) < z) lo = mid; else hi = mid;
+    }
+    return 0.5 * (lo + hi);
+}
+
+/* Eq. (4.2): d = n exp(W(-m log(eps) / n^2)), the d at which the iteration
+ * cost (log eps / log(n/d)) m n equals the QR cost d n^2.  cost_ratio scales
+ * the iteration side (time per unit of m n over time per unit of d n^2); the
+ * paper's form is cost_ratio = 1.  Returns the real d, before any rounding. */
+double orc_embedding_dim(int64_t m, int32_t n, double eps, double cost_ratio)
+{
+    double z = cost_ratio * (-(double)m * log(eps)) / ((double)n * (double)n);
+    return (double)n * exp(orc_lambert_w0(z));
+}
+
+/* Eq. (4.1): after t iterations the error is about (n/d)^(t/2); the t at
+ * which that reaches eps, as a real number. */
+double orc_iteration_estimate(int32_t n, int32_t d, double eps)
+{
+    return 2.0 * log(eps) / log((double)n / (double)d);
+}
