@@ -47,6 +47,8 @@ def parse():
     ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-duration", type=float, default=1.5)
+    ap.add_argument("--no-adaptive-d", action="store_true",
+                    help="skip the solve at the embedding dimension of eq. (4.2)")
     ap.add_argument("--gaussian-input", action="store_true",
                     help="column-scaled Gaussian A of the same shape instead of the SVD-built one (cheap to "
                          "generate; for counter runs, where the kernels move the same bytes)")
@@ -338,6 +340,35 @@ def form_served(args, sap, torch, inputs):
             "rel_diff_x_max": diffs[-1], "serve_stats": stats}
 
 
+def adaptive_d(sap, torch, A, b, x, m, n, d, zeta, seed, tol, maxiter, pass_ms, qr_ms, fixed_ms, fixed_iters):
+    """The same problem at the embedding dimension of eq. (4.2) (Sec. 4.3),
+    with the iteration and QR costs weighted by this run's measurements: time
+    per unit of m n (one pass) over time per unit of d n^2 (the QR at d).
+    Reported beside the fixed-d solve; the headline value stays the fixed d."""
+    ratio = (pass_ms / (m * n)) / (qr_ms / (d * n * n))
+    d_ad = sap.sap_embedding_dim(m, n, tol, ratio)
+    log(f"bench: adaptive d = {d_ad} (cost ratio {ratio:.3f}; paper form {sap.sap_embedding_dim(m, n, tol)})")
+    sap.sap_solve(A, b, d_ad, zeta, seed, tol=tol, maxiter=maxiter, x=x)  # warm-up
+    torch.cuda.synchronize()
+    times, infos = [], []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        r = sap.sap_solve(A, b, d_ad, zeta, seed, tol=tol, maxiter=maxiter, x=x)
+        torch.cuda.synchronize()
+        times.append((time.perf_counter() - t0) * 1e3)
+        infos.append(r.info)
+    k = sorted(range(len(times)), key=times.__getitem__)[len(times) // 2]
+    i = infos[k]
+    return {"rule": "eq. (4.2) with measured cost ratio", "cost_ratio": ratio, "d": d_ad,
+            "d_paper_form": sap.sap_embedding_dim(m, n, tol), "status": i["status_name"],
+            "iters": i["iters"], "iters_estimate": sap.sap_iteration_estimate(n, d_ad, tol),
+            "solve_ms_median": times[k],
+            "phases_ms": {"generate": i["t_generate_ms"], "apply": i["t_apply_ms"], "qr": i["t_qr_ms"],
+                          "iterate": i["t_iterate_ms"]},
+            "fixed_d": d, "fixed_iters": fixed_iters, "fixed_iters_estimate": sap.sap_iteration_estimate(n, d, tol),
+            "fixed_solve_ms": fixed_ms, "speedup_vs_fixed": fixed_ms / times[k]}
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -452,6 +483,9 @@ def main():
         "cpu_baseline": None,
         "forms": {},
     }
+    if not args.no_adaptive_d:
+        out["embedding_dim"] = adaptive_d(sap, torch, A, b, x, m, n, d, zeta, seed, tol, maxiter,
+                                          pass_avg_ms, med("t_qr_ms"), ms_per_step, iters)
     rows = min(args.cpu_sample_rows, m)
     A_sample, b_sample = A[:rows].cpu().numpy(), b[:rows].cpu().numpy()
     del A, r_vec

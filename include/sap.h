@@ -286,6 +286,27 @@ sap_status sap_cancel(sap_ctx *ctx, uint64_t ticket);
 sap_status sap_serve_stats(sap_ctx *ctx, int64_t *stats);
 
 /* ------------------------------------------------------------------------
+ * Embedding dimension (Sec. 4.3).  Host-only: no device work, no context,
+ * callable before sap_create and without a GPU.
+ *
+ * sap_embedding_dim: the d of eq. (4.2), d = n exp(W(-r m log(eps) / n^2))
+ * with W the principal branch of the Lambert W function: the d at which the
+ * iteration work (log eps / log(n/d)) m n, weighted by r = cost_ratio, equals
+ * the QR work d n^2.  cost_ratio is the time per unit of iteration work
+ * (one m x n pass over A) divided by the time per unit of QR work; the
+ * paper's form is 1.  The real d is rounded up and clamped to
+ * [n + 1, min(m, INT32_MAX)].  *d receives the result.
+ * Errors: SAP_EINVAL (d null, n < 1, m <= n, eps outside (0, 1), cost_ratio
+ * not finite and positive, or the argument of W not finite); *d is then
+ * untouched.
+ * ---------------------------------------------------------------------- */
+sap_status sap_embedding_dim(int64_t m, int32_t n, double eps, double cost_ratio, int32_t *d);
+/* sap_iteration_estimate: the iterations after which the rate estimate of
+ * eq. (4.1), (n/d)^(t/2), reaches eps: t = ceil(2 log eps / log(n/d)).
+ * Errors: SAP_EINVAL (iters null, n < 1, d <= n, eps outside (0, 1)). */
+sap_status sap_iteration_estimate(int32_t n, int32_t d, double eps, int32_t *iters);
+
+/* ------------------------------------------------------------------------
  * Kernel timing (measurement support).  When enabled, the library brackets
  * every launch of its two bandwidth-bound kernels with HIP events on the
  * stream it launches them on, and accumulates their durations:

@@ -23,7 +23,7 @@ SAP_MODE_FP64, SAP_MODE_MIXED_FP32, SAP_MODE_MIXED_FP32_REFINE, SAP_MODE_MIXED_B
 EXPORTS = ["sap_create", "sap_destroy", "sap_last_error", "sap_status_string", "sps_generate",
            "sps_apply", "sap_qr", "sap_trsv", "sap_solve", "sap_lsqr", "sap_profile_enable",
            "sap_profile_read", "sap_solve_batch", "sap_serve_start", "sap_submit", "sap_poll",
-           "sap_cancel", "sap_serve_stats"]
+           "sap_cancel", "sap_serve_stats", "sap_embedding_dim", "sap_iteration_estimate"]
 PROF_PASS, PROF_APPLY = 0, 1
 
 _vp = ctypes.c_void_p
@@ -115,6 +115,10 @@ def lib():
         L.sap_profile_enable.restype = ctypes.c_int
         L.sap_profile_read.argtypes = [_vp, _i32, ctypes.POINTER(_i64), ctypes.POINTER(_f64), ctypes.c_int]
         L.sap_profile_read.restype = ctypes.c_int
+        L.sap_embedding_dim.argtypes = [_i64, _i32, _f64, _f64, ctypes.POINTER(_i32)]
+        L.sap_embedding_dim.restype = ctypes.c_int
+        L.sap_iteration_estimate.argtypes = [_i32, _i32, _f64, ctypes.POINTER(_i32)]
+        L.sap_iteration_estimate.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -378,3 +382,21 @@ def sap_serve_stats(ctx=None):
     ctx.check(lib().sap_serve_stats(ctx.handle, out))
     return dict(zip(SERVE_STATS, list(out)))
 
+
+
+def sap_embedding_dim(m, n, eps, cost_ratio=1.0):
+    """d from eq. (4.2) (Sec. 4.3); host-only, no context or GPU needed."""
+    d = _i32(0)
+    st = lib().sap_embedding_dim(int(m), int(n), float(eps), float(cost_ratio), ctypes.byref(d))
+    if st != SAP_OK:
+        raise SapError(st, "sap_embedding_dim: invalid arguments")
+    return d.value
+
+
+def sap_iteration_estimate(n, d, eps):
+    """Iterations for the eq. (4.1) rate estimate to reach eps; host-only."""
+    t = _i32(0)
+    st = lib().sap_iteration_estimate(int(n), int(d), float(eps), ctypes.byref(t))
+    if st != SAP_OK:
+        raise SapError(st, "sap_iteration_estimate: invalid arguments")
+    return t.value

@@ -223,3 +223,31 @@ def test_unaligned_wide_rows(sap):
         eta = float(torch.linalg.vector_norm(A.T @ r)) / (fro * (fro * float(torch.linalg.vector_norm(x)) +
                                                                  float(torch.linalg.vector_norm(b))))
         assert eta <= 1e-11, eta
+
+
+def test_adaptive_embedding_dim_solve(sap, orc):
+    """A solve at the d that eq. (4.2) picks (Sec. 4.3): parity with the
+    oracle at the same d, and the iteration count against the rate estimate
+    of eq. (4.1): no more than twice the estimate, and fewer iterations than
+    the same problem at d = 4n."""
+    import torch
+    m, n, eps = 60000, 60, 1e-12
+    d = sap.sap_embedding_dim(m, n, eps)
+    assert abs(d - orc.embedding_dim(m, n, eps)) <= 1.0
+    est = sap.sap_iteration_estimate(n, d, eps)
+    _note(f"solve adaptive d m={m} n={n} d={d} estimate={est}")
+    p = inputs.make_problem(m, n, kind="svd", cond=1e6, noise=1e-6, seed=6060)
+    res = sap.sap_solve(_dev(p.A), _dev(p.b), d, 8, 5, tol=eps, maxiter=300)
+    torch.cuda.synchronize()
+    x = res.x.cpu().numpy()
+    x_or, info_or = orc.solve(p.A, p.b, d, 8, 5, tol=eps, maxiter=300)
+    assert res.status == sap.SAP_OK, res.info
+    assert info_or["status"] == "ok"
+    nb = np.linalg.norm(p.b)
+    assert np.linalg.norm(p.A @ (x - x_or)) <= 1e-12 * nb
+    assert abs(res.info["iters"] - info_or["iters"]) <= max(2, 0.05 * info_or["iters"])
+    assert res.info["iters"] <= 2 * est
+    fixed = sap.sap_solve(_dev(p.A), _dev(p.b), 4 * n, 8, 5, tol=eps, maxiter=300)
+    torch.cuda.synchronize()
+    assert fixed.status == sap.SAP_OK
+    assert res.info["iters"] < fixed.info["iters"], (res.info["iters"], fixed.info["iters"])
