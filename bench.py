@@ -359,7 +359,21 @@ def adaptive_d(sap, torch, A, b, x, m, n, d, zeta, seed, tol, maxiter, pass_ms, 
         infos.append(r.info)
     k = sorted(range(len(times)), key=times.__getitem__)[len(times) // 2]
     i = infos[k]
-    return {"rule": "eq. (4.2) with measured cost ratio", "cost_ratio": ratio, "d": d_ad,
+    # total time against d on the same problem (the trade-off of Sec. 4.3:
+    # fewer iterations, dearer QR and, here, a dearer apply)
+    sweep = []
+    for f in (2, 3, 4, 6, 8, 12):
+        dk = min(f * n, m)
+        sap.sap_solve(A, b, dk, zeta, seed, tol=tol, maxiter=maxiter, x=x)  # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = sap.sap_solve(A, b, dk, zeta, seed, tol=tol, maxiter=maxiter, x=x)
+        torch.cuda.synchronize()
+        sweep.append({"d": dk, "iters": r.info["iters"], "iters_estimate": sap.sap_iteration_estimate(n, dk, tol),
+                      "solve_ms": (time.perf_counter() - t0) * 1e3, "apply_ms": r.info["t_apply_ms"],
+                      "qr_ms": r.info["t_qr_ms"], "iterate_ms": r.info["t_iterate_ms"]})
+        log(f"bench: d = {dk}: {sweep[-1]['solve_ms']:.1f} ms, {r.info['iters']} iterations")
+    return {"sweep": sweep,"rule": "eq. (4.2) with measured cost ratio", "cost_ratio": ratio, "d": d_ad,
             "d_paper_form": sap.sap_embedding_dim(m, n, tol), "status": i["status_name"],
             "iters": i["iters"], "iters_estimate": sap.sap_iteration_estimate(n, d_ad, tol),
             "solve_ms_median": times[k],
