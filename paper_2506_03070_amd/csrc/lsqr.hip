@@ -61,6 +61,16 @@ struct PassTypes<3> {
   using TA = float; using TC = double; using TUI = double; using TUO = float;
 };
 
+// Rows of a row group per step: 16 / (J VEC) for short rows (at most 4), one
+// row for rows of 16 or more elements per lane, except that FP32 storage with
+// FP64 arithmetic (modes 1 and 3) then takes two rows: as many bytes in
+// flight per wave as the FP64 pass at the same occupancy, which the FP64
+// accumulators set (FP32 pass over 2^22 x 4096: 5.8 -> 6.8 TB/s).
+__host__ __device__ constexpr int pass_rows(int mode, int jv) {
+  if (jv >= 16) return (mode == 1 || mode == 3) ? 2 : 1;
+  return 16 / jv > 4 ? 4 : 16 / jv;
+}
+
 // WC waves split the columns of a row (64*VEC*J columns each); WR = kPassWaves/WC
 // row groups share the workgroup.
 //
@@ -81,7 +91,7 @@ __global__ __launch_bounds__(kPassThreads) void lsqr_pass_kernel(
   using TA = typename PassTypes<MODE>::TA;
   using TC = typename PassTypes<MODE>::TC;
   constexpr int WR = kPassWaves / WC;
-  constexpr int R = (J * VEC >= 16) ? 1 : (16 / (J * VEC) > 4 ? 4 : 16 / (J * VEC));
+  constexpr int R = pass_rows(MODE, J * VEC);
   constexpr int COLS = kWave * VEC * J;  // columns per wave
   __shared__ double xch[WC > 1 ? 2 : 1][WC > 1 ? WR : 1][R][WC];
   __shared__ double qbuf[WR > 1 ? WC * COLS : 1];
@@ -633,10 +643,8 @@ int max_grid(sap_ctx *ctx) { return ctx->num_cus * 2; }
 
 // Rows one step of the kernel pick_pass returns for c covers: WR =
 // kPassWaves / WC row groups of R rows.
-int rows_per_step(const PassCfg &c) {
-  const int jv = pass_j(c) * c.vec;
-  const int r = jv >= 16 ? 1 : std::min(4, 16 / jv);
-  return (kPassWaves / c.wc) * r;
+int rows_per_step(int mode, const PassCfg &c) {
+  return (kPassWaves / c.wc) * pass_rows(mode, pass_j(c) * c.vec);
 }
 
 // Share of the rows assigned statically (the rest is claimed in chunks),
@@ -659,7 +667,7 @@ PassPlan plan_pass(sap_ctx *ctx, int mode, int64_t m, int n, int64_t lda, const 
   const int64_t min_rows = 64;
   if (grid * min_rows > m) grid = (m + min_rows - 1) / min_rows;
   if (grid < 1) grid = 1;
-  const int64_t step = rows_per_step(c);
+  const int64_t step = rows_per_step(mode, c);
   if (a_bytes < kDynamicMinBytes) return PassPlan{fn, static_cast<int>(grid), (m + grid - 1) / grid, m, 0};
   const int64_t per_wg = static_cast<int64_t>(kStaticShare * static_cast<double>(m) / static_cast<double>(grid)) /
                          step * step;
