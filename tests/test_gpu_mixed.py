@@ -1,11 +1,14 @@
-"""GPU parity of the mixed-precision form: A stored in FP32; the sketch
-accumulated in FP32; QR, triangular solves, recurrences and the LSQR passes
-(which widen each FP32 element) in FP64.  The reference is the FP64 oracle run
-on the FP32-rounded A (exactly representable in FP64), so both sides solve the
-same problem; the bar is the forward error ||x - x_or|| / ||x_or|| <= 1e-8
-(where the least-squares perturbation bound allows it) and the paper's metric
-||A(x - x_or)|| / ||b|| <= 1e-10.  Only the preconditioner differs (FP32
-sketch), which changes the iterates but not the limit."""
+"""GPU parity of the mixed-precision forms: A stored in FP32; the sketch of
+the FP32 values accumulated in FP64; QR, triangular solves, recurrences and
+the passes of MIXED_FP32 (which widen each FP32 element) in FP64; FP32 inner
+passes in the refinement forms; a BF16 copy of A for the MIXED_BF16SA sketch.
+The reference is the FP64 oracle run on the FP32-rounded A (exactly
+representable in FP64), so both sides solve the same problem; the bar is the
+forward error ||x - x_or|| / ||x_or|| <= 1e-8 (where the least-squares
+perturbation bound allows it) and the paper's metric
+||A(x - x_or)|| / ||b|| <= 1e-10.  Where the forms round differently from the
+oracle (FP32 inner solves, the BF16 sketch) the iterates differ but not the
+limit."""
 import numpy as np
 import pytest
 
