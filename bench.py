@@ -27,6 +27,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "solve time & SA/GEMV GB/s, mixed vs FP64 at rel-err 1e-8; p50/p99 solve latency"
 HBM_PEAK_GBS = 8000.0
+FP64_PEAK_GFLOPS = 78600.0  # MI355X dense FP64 (vector and matrix)
 
 
 def parse():
@@ -157,6 +158,11 @@ def pass_bytes(m, n, esize):
     # the fused pass reads A once and u once and writes u once (p, the
     # per-workgroup partials and the state are < 0.3%)
     return m * n * esize + 2 * m * 8
+
+
+def qr_flops(d, nc):
+    # Householder QR of a d x nc matrix: 2 d nc^2 - 2 nc^3 / 3
+    return 2.0 * d * nc * nc - 2.0 * nc ** 3 / 3.0
 
 
 def apply_bytes(m, n, d, zeta, esize, ysize):
@@ -488,7 +494,11 @@ def main():
                      "traffic": measured_traffic(m, n), "bytes_per_launch": pb, "avg_launch_ms": pass_avg_ms,
                      "launches": n_pass, "full_launches": n_full},
         "sa": {"kernel": "apply_strip_kernel", "achieved_gbs": apply_gbs, "frac": apply_gbs / HBM_PEAK_GBS,
-               "bytes_per_launch": ab, "avg_launch_ms": apply_avg_ms, "launches": n_apply},
+               "bytes_per_launch": ab, "avg_launch_ms": apply_avg_ms, "launches": n_apply,
+               "a_only_gbs": m * n * 8 / (apply_avg_ms * 1e-3) / 1e9},
+        "qr": {"flops": qr_flops(d, n + 1), "ms": med("t_qr_ms"),
+               "gflops": qr_flops(d, n + 1) / (med("t_qr_ms") * 1e-3) / 1e9,
+               "frac_fp64": qr_flops(d, n + 1) / (med("t_qr_ms") * 1e-3) / 1e9 / FP64_PEAK_GFLOPS},
         "phases_ms": {"generate": med("t_generate_ms"), "apply": med("t_apply_ms"), "qr": med("t_qr_ms"),
                       "iterate": med("t_iterate_ms")},
         "iters": iters,
