@@ -33,7 +33,7 @@ FP64_PEAK_GFLOPS = 78600.0  # MI355X dense FP64 (vector and matrix)
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-rows", type=int, default=1 << 16)
@@ -439,8 +439,11 @@ def main():
     infos = []
     torch.cuda.synchronize()
     t_start = time.perf_counter()
+    step_ms = []
     for k in range(args.steps):
-        r = sap.sap_solve(A, b, d, zeta, seed, tol=tol, maxiter=maxiter, x=x)
+        t_k = time.perf_counter()
+        r = sap.sap_solve(A, b, d, zeta, seed, tol=tol, maxiter=maxiter, x=x)  # returns when x is final
+        step_ms.append((time.perf_counter() - t_k) * 1e3)
         infos.append(r.info)
         log(f"bench: step {k}: {r.info['status_name']} iters={r.info['iters']}")
     torch.cuda.synchronize()
@@ -502,6 +505,9 @@ def main():
         "phases_ms": {"generate": med("t_generate_ms"), "apply": med("t_apply_ms"), "qr": med("t_qr_ms"),
                       "iterate": med("t_iterate_ms")},
         "iters": iters,
+        # per-solve statistics in the paper's form (median, 5-95% range), over the timed steps
+        "solve_ms": {"runs": len(step_ms), "median": float(np.median(step_ms)),
+                     "p5": float(np.percentile(step_ms, 5)), "p95": float(np.percentile(step_ms, 95))},
         "normal_eq_residual_rel": rel_ne,
         "copy_reference": copy_ref,
         "cpu_baseline": None,
