@@ -54,9 +54,12 @@ __device__ __forceinline__ TY load_as(const TA *p) {
 // adds into a spare LDS row that is never written out.  Otherwise the
 // general path loads the indices four at a time and skips indices outside
 // the range.
-template <typename TA, typename TY, int W, bool FAST>
+// C16 (with FAST): the row indices come from a 16-bit copy (idx16, 8 per row,
+// one 16-byte load), for sketches that many strips re-read.
+template <typename TA, typename TY, int W, bool FAST, bool C16>
 __global__ __launch_bounds__(kApplyThreads) void apply_strip_kernel(
-    const int32_t *__restrict__ idx, const uint64_t *__restrict__ sign, int zeta, const TA *__restrict__ A,
+    const int32_t *__restrict__ idx, const uint16_t *__restrict__ idx16, const uint64_t *__restrict__ sign,
+    int zeta, const TA *__restrict__ A,
     int64_t lda, const double *__restrict__ b, int64_t m, int n, int ncols, int d, int dr, int nstrips,
     int nranges, int nslices, int64_t rows_per_slice, TY *__restrict__ out, int64_t ldo, int64_t slice_stride,
     double h, int scale_now) {
@@ -103,9 +106,17 @@ __global__ __launch_bounds__(kApplyThreads) void apply_strip_kernel(
         else if (col_b) a = static_cast<TY>(b[i]);
         val[u] = ok ? a : TY(0);
         sg[u] = static_cast<uint32_t>(sign[i]);
-        const int4 *ip = reinterpret_cast<const int4 *>(idx + i * 8);
-        ix[u][0] = ip[0];
-        ix[u][1] = ip[1];
+        if constexpr (C16) {
+          const int4 v = *reinterpret_cast<const int4 *>(idx16 + i * 8);
+          ix[u][0] = make_int4(v.x & 0xFFFF, static_cast<unsigned>(v.x) >> 16, v.y & 0xFFFF,
+                               static_cast<unsigned>(v.y) >> 16);
+          ix[u][1] = make_int4(v.z & 0xFFFF, static_cast<unsigned>(v.z) >> 16, v.w & 0xFFFF,
+                               static_cast<unsigned>(v.w) >> 16);
+        } else {
+          const int4 *ip = reinterpret_cast<const int4 *>(idx + i * 8);
+          ix[u][0] = ip[0];
+          ix[u][1] = ip[1];
+        }
       }
 #pragma unroll
       for (int u = 0; u < kUnroll; ++u) {
@@ -169,6 +180,20 @@ __global__ __launch_bounds__(256) void apply_reduce_kernel(const TY *__restrict_
   Y[r + static_cast<int64_t>(c) * ldy] = s * TY(h);
 }
 
+// 16-bit copy of the row indices (zeta = 8, d <= 65535); an index outside
+// [0, d) becomes 65535 (>= d), which the apply adds into its spare row.
+__global__ __launch_bounds__(256) void idx16_kernel(const int32_t *__restrict__ idx, int64_t count, int d,
+                                                    uint16_t *__restrict__ out) {
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  if (e >= count) return;
+  const int32_t v = idx[e];
+  out[e] = static_cast<uint16_t>(v >= 0 && v < d ? v : 65535);
+}
+
+// The strips re-read every row's indices and sign word (40 bytes); past this
+// many bytes of such re-reads the 16-bit copy (24 bytes a row) pays for itself.
+constexpr double kCompactMinRereadBytes = 32e9;
+
 struct ApplyPlan {
   int w, dr, nstrips, nranges, nslices;
   int64_t rows_per_slice;
@@ -205,18 +230,27 @@ ApplyPlan make_plan(int num_cus, int64_t m, int d, int ncols, size_t esize) {
   return p;
 }
 
+bool use_compact(const ApplyPlan &p, int64_t m, int zeta, int d) {
+  return zeta == 8 && p.nranges == 1 && d <= 65535 &&
+         static_cast<double>(p.nstrips) * static_cast<double>(m) * 40.0 >= kCompactMinRereadBytes;
+}
+
 template <typename TA, typename TY, int W>
 void launch_strip(const ApplyPlan &p, dim3 grid, size_t lds, hipStream_t st, const sps_sketch *S, const TA *A,
                   int64_t lda, const double *b, int n, int ncols, TY *out, int64_t ldo, int64_t slice_stride,
-                  double h, int scale_now) {
+                  double h, int scale_now, const uint16_t *idx16) {
   const bool fast = S->zeta == 8 && p.nranges == 1 && (reinterpret_cast<uintptr_t>(S->idx) % 16 == 0);
-  if (fast)
-    apply_strip_kernel<TA, TY, W, true><<<grid, kApplyThreads, lds, st>>>(
-        S->idx, S->sign, S->zeta, A, lda, b, S->m, n, ncols, S->d, p.dr, p.nstrips, p.nranges, p.nslices,
+  if (fast && idx16 != nullptr)
+    apply_strip_kernel<TA, TY, W, true, true><<<grid, kApplyThreads, lds, st>>>(
+        S->idx, idx16, S->sign, S->zeta, A, lda, b, S->m, n, ncols, S->d, p.dr, p.nstrips, p.nranges, p.nslices,
+        p.rows_per_slice, out, ldo, slice_stride, h, scale_now);
+  else if (fast)
+    apply_strip_kernel<TA, TY, W, true, false><<<grid, kApplyThreads, lds, st>>>(
+        S->idx, nullptr, S->sign, S->zeta, A, lda, b, S->m, n, ncols, S->d, p.dr, p.nstrips, p.nranges, p.nslices,
         p.rows_per_slice, out, ldo, slice_stride, h, scale_now);
   else
-    apply_strip_kernel<TA, TY, W, false><<<grid, kApplyThreads, lds, st>>>(
-        S->idx, S->sign, S->zeta, A, lda, b, S->m, n, ncols, S->d, p.dr, p.nstrips, p.nranges, p.nslices,
+    apply_strip_kernel<TA, TY, W, false, false><<<grid, kApplyThreads, lds, st>>>(
+        S->idx, nullptr, S->sign, S->zeta, A, lda, b, S->m, n, ncols, S->d, p.dr, p.nstrips, p.nranges, p.nslices,
         p.rows_per_slice, out, ldo, slice_stride, h, scale_now);
 }
 
@@ -236,17 +270,25 @@ sap_status apply_typed(sap_ctx *ctx, const sps_sketch *S, const TA *A, int64_t l
     slice_stride = static_cast<int64_t>(S->d) * ncols;
     scale_now = 0;
   }
+  const uint16_t *idx16 = nullptr;
+  if (use_compact(p, S->m, S->zeta, S->d)) {
+    uint16_t *c = cv.take<uint16_t>(static_cast<size_t>(S->m) * 8);
+    const int64_t count = S->m * 8;
+    idx16_kernel<<<static_cast<unsigned>((count + 255) / 256), 256, 0, st>>>(S->idx, count, S->d, c);
+    SAP_HIP_TRY(hipGetLastError());
+    idx16 = c;
+  }
   const int total = p.nstrips * p.nranges * p.nslices;
   const int per_xcd = (total + kXcds - 1) / kXcds;
   const dim3 grid(static_cast<unsigned>(per_xcd * kXcds));
   const size_t lds = (static_cast<size_t>(p.dr) + 1) * p.w * sizeof(TY);
   switch (p.w) {
-    case 1: launch_strip<TA, TY, 1>(p, grid, lds, st, S, A, lda, b, n, ncols, out, ldo, slice_stride, h, scale_now); break;
-    case 2: launch_strip<TA, TY, 2>(p, grid, lds, st, S, A, lda, b, n, ncols, out, ldo, slice_stride, h, scale_now); break;
-    case 4: launch_strip<TA, TY, 4>(p, grid, lds, st, S, A, lda, b, n, ncols, out, ldo, slice_stride, h, scale_now); break;
-    case 8: launch_strip<TA, TY, 8>(p, grid, lds, st, S, A, lda, b, n, ncols, out, ldo, slice_stride, h, scale_now); break;
-    case 16: launch_strip<TA, TY, 16>(p, grid, lds, st, S, A, lda, b, n, ncols, out, ldo, slice_stride, h, scale_now); break;
-    default: launch_strip<TA, TY, 32>(p, grid, lds, st, S, A, lda, b, n, ncols, out, ldo, slice_stride, h, scale_now); break;
+    case 1: launch_strip<TA, TY, 1>(p, grid, lds, st, S, A, lda, b, n, ncols, out, ldo, slice_stride, h, scale_now, idx16); break;
+    case 2: launch_strip<TA, TY, 2>(p, grid, lds, st, S, A, lda, b, n, ncols, out, ldo, slice_stride, h, scale_now, idx16); break;
+    case 4: launch_strip<TA, TY, 4>(p, grid, lds, st, S, A, lda, b, n, ncols, out, ldo, slice_stride, h, scale_now, idx16); break;
+    case 8: launch_strip<TA, TY, 8>(p, grid, lds, st, S, A, lda, b, n, ncols, out, ldo, slice_stride, h, scale_now, idx16); break;
+    case 16: launch_strip<TA, TY, 16>(p, grid, lds, st, S, A, lda, b, n, ncols, out, ldo, slice_stride, h, scale_now, idx16); break;
+    default: launch_strip<TA, TY, 32>(p, grid, lds, st, S, A, lda, b, n, ncols, out, ldo, slice_stride, h, scale_now, idx16); break;
   }
   SAP_HIP_TRY(hipGetLastError());
   if (p.nslices > 1) {
@@ -261,11 +303,11 @@ sap_status apply_typed(sap_ctx *ctx, const sps_sketch *S, const TA *A, int64_t l
 }  // namespace
 
 size_t apply_workspace_bytes(sap_ctx *ctx, int64_t m, int zeta, int d, int ncols, sap_dtype y_type) {
-  (void)zeta;
   const size_t es = (y_type == SAP_F64) ? 8 : 4;
   const ApplyPlan p = make_plan(ctx->num_cus, m, d, ncols, es);
   size_t bytes = 8 * 256;
   if (p.nslices > 1) bytes += static_cast<size_t>(p.nslices) * d * ncols * es;
+  if (use_compact(p, m, zeta, d)) bytes += static_cast<size_t>(m) * 8 * sizeof(uint16_t) + 256;
   return bytes;
 }
 

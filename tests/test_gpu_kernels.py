@@ -247,3 +247,29 @@ def test_trsv_parity(sap, orc, n):
     tol = 50 * kappa * 2.0 ** -53 * np.sqrt(n)
     assert np.linalg.norm(x - xo) <= tol * np.linalg.norm(xo)
     assert np.linalg.norm(y - yo) <= tol * np.linalg.norm(yo)
+
+
+def test_apply_compact_index_path(sap, orc):
+    """A sketch re-read by many strips (here 1024 strips of 2 FP64 columns over
+    800000 rows, 33 GB of index re-reads) is applied from a 16-bit copy of its
+    row indices.  Integer A and b keep every sum exact, so sampled columns of Y
+    must equal the exact integer sums times 1/sqrt(zeta) bit for bit."""
+    import torch
+    m, n, d, zeta = 800000, 2047, 8192, 8
+    _note(f"apply-compact m={m} n={n} d={d}")
+    g = torch.Generator(device="cuda")
+    g.manual_seed(812)
+    A = torch.randint(-8, 9, (m, n), generator=g, device="cuda", dtype=torch.int32).to(torch.float32)
+    b = torch.randint(-8, 9, (m,), generator=g, device="cuda", dtype=torch.int32).to(torch.float64)
+    idx_ref, sign_ref = orc.sketch(2024, 0, m, d, zeta)
+    Y = sap.sps_apply(torch.from_numpy(idx_ref).cuda(), torch.from_numpy(sign_ref.view(np.int64)).cuda(), d,
+                      zeta, A, b, y_dtype=torch.float64)
+    torch.cuda.synchronize()
+    cols = [0, 1, 2, 3, 1000, 1001, 2045, 2046]
+    Ab = np.column_stack([A[:, cols].cpu().numpy().astype(np.int64), b.cpu().numpy().astype(np.int64)])
+    s = orc.sign_values(sign_ref, zeta).astype(np.int64)
+    exact = np.zeros((d, len(cols) + 1), dtype=np.int64)
+    for k in range(zeta):
+        np.add.at(exact, idx_ref[:, k], s[:, k:k + 1] * Ab)
+    got = Y.cpu().numpy().T[:, cols + [n]]
+    assert np.array_equal(got, exact.astype(np.float64) * orc.sketch_scale(zeta))
