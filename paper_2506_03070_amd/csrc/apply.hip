@@ -192,7 +192,7 @@ __global__ __launch_bounds__(256) void idx16_kernel(const int32_t *__restrict__ 
 
 // The strips re-read every row's indices and sign word (40 bytes); past this
 // many bytes of such re-reads the 16-bit copy (24 bytes a row) pays for itself.
-constexpr double kCompactMinRereadBytes = 32e9;
+constexpr double kCompactMinRereadBytes = 16e9;
 
 struct ApplyPlan {
   int w, dr, nstrips, nranges, nslices;
