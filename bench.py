@@ -53,6 +53,11 @@ def parse():
     ap.add_argument("--gaussian-input", action="store_true",
                     help="column-scaled Gaussian A of the same shape instead of the SVD-built one (cheap to "
                          "generate; for counter runs, where the kernels move the same bytes)")
+    ap.add_argument("--kernel", choices=["apply"], default=None,
+                    help="time one kernel alone instead of the solve (for profiler runs): 'apply' times "
+                         "sps_apply (Y = S [A b]) on an --m x --n matrix of --a-dtype into a --y-dtype Y")
+    ap.add_argument("--a-dtype", choices=["f64", "f32", "bf16"], default="f64")
+    ap.add_argument("--y-dtype", choices=["f64", "f32"], default="f64")
     ap.add_argument("--copy-ref-mib", type=int, default=2048,
                     help="size of the plain device-to-device copy timed as the achievable-bandwidth reference")
     return ap.parse_args()
@@ -389,6 +394,37 @@ def adaptive_d(sap, torch, A, b, x, m, n, d, zeta, seed, tol, maxiter, pass_ms, 
             "fixed_solve_ms": fixed_ms, "speedup_vs_fixed": fixed_ms / times[k]}
 
 
+def kernel_apply(args, sap, torch, inputs):
+    """sps_apply alone: warm-up, then --steps applies timed with events on
+    the current stream (the stream the library launches on).  One JSON line."""
+    m, n, d, zeta = args.m, args.n, args.d, args.zeta
+    ta = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16}[args.a_dtype]
+    ty = {"f64": torch.float64, "f32": torch.float32}[args.y_dtype]
+    log(f"bench[apply]: m={m} n={n} d={d} zeta={zeta} A {args.a_dtype} Y {args.y_dtype}")
+    # a copy of known size in the same process calibrates the HBM byte counters
+    copy_ref = copy_reference(torch, args.copy_ref_mib) if args.copy_ref_mib > 0 else None
+    A, b, _ = inputs.make_problem_torch(m, n, kind="colscale", cond=1e6, noise=1e-6, seed=inputs.config_seed(1),
+                                        device="cuda", dtype=ta)
+    idx, sign = sap.sps_generate(m, d, zeta, inputs.config_seed(1) + 1)
+    Y = sap.sps_apply(idx, sign, d, zeta, A, b, y_dtype=ty)
+    for _ in range(args.warmup):
+        sap.sps_apply(idx, sign, d, zeta, A, b, y_dtype=ty, Y=Y)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        sap.sps_apply(idx, sign, d, zeta, A, b, y_dtype=ty, Y=Y)
+    e1.record()
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    ab = apply_bytes(m, n, d, zeta, A.element_size(), Y.element_size())
+    print(json.dumps({"kernel": "apply", "m": m, "n": n, "d": d, "zeta": zeta, "a_dtype": args.a_dtype,
+                      "y_dtype": args.y_dtype, "steps": args.steps, "avg_ms": ms, "bytes": ab,
+                      "gbs": ab / (ms * 1e-3) / 1e9, "frac": ab / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                      "a_only_gbs": m * n * A.element_size() / (ms * 1e-3) / 1e9, "copy_reference": copy_ref}),
+          flush=True)
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -404,6 +440,9 @@ def main():
     import paper_2506_03070_amd as sap
 
     torch.cuda.set_device(0)
+    if args.kernel == "apply":
+        kernel_apply(args, sap, torch, inputs)
+        return
     copy_ref = copy_reference(torch, args.copy_ref_mib) if args.copy_ref_mib > 0 else None
     if copy_ref:
         log(f"bench: copy reference {copy_ref['gbs']:.0f} GB/s")

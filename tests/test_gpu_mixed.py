@@ -192,3 +192,41 @@ def test_refine_repeatable_wide_rows(sap):
         print(f"rep {rep}: iters {counts[-1][0]} refinements {counts[-1][1]} rel {rel:.2e}", flush=True)
         assert rel <= 1e-8
     assert len(set(counts)) == 1, counts
+
+
+def test_wide_rows_refine_and_mixed_parity(sap, orc):
+    """n = 2100 FP32 rows against the oracle: the passes then run four waves
+    across a row (the FP32 inner pass and the FP64-accumulating residual pass
+    of the refinement form, and the FP64-arithmetic pass of MIXED_FP32), the
+    explicit inverse of R takes its 2-level blocked path, and A (2^16 x 2100,
+    525 MiB of FP32) is past the size at which the pass claims the last eighth
+    of its rows from a device counter.  One oracle solve (FP64 on the
+    FP32-rounded A) is the reference for both forms; d = 2n, the ratio of the
+    2^22 x 4096 workload.  Bars: forward error <= 1e-8 and the metric
+    ||A(x - x_or)|| <= 1e-10 ||b|| (perturbation bound ~1e-10 here)."""
+    import torch
+    m, n, d = 1 << 16, 2100, 4200
+    print(f"wide refine+mixed m={m} n={n} d={d}", flush=True)
+    p = inputs.make_problem(m, n, kind="colscale", cond=1e5, noise=1e-8, seed=m + 29, dtype=np.float32)
+    A64 = p.A.astype(np.float64)
+    seed = 77
+    A, b = _dev(p.A), _dev(p.b)
+    ref = sap.sap_solve(A, b, d, 8, seed, tol=1e-8, maxiter=1000, mode=sap.SAP_MODE_MIXED_FP32_REFINE,
+                        max_refine=12)
+    mix = sap.sap_solve(A, b, d, 8, seed, tol=1e-12, maxiter=400, mode=sap.SAP_MODE_MIXED_FP32)
+    torch.cuda.synchronize()
+    assert ref.status == sap.SAP_OK, ref.info
+    assert mix.status == sap.SAP_OK, mix.info
+    print(f"  refine: iters {ref.info['iters']} refinements {ref.info['refinements']}; "
+          f"mixed: iters {mix.info['iters']}", flush=True)
+    x_or, info_or = orc.solve(A64, p.b, d, 8, seed, tol=1e-12, maxiter=400)
+    assert info_or["status"] == "ok"
+    nb, nx = np.linalg.norm(p.b), np.linalg.norm(x_or)
+    for name, r in (("refine", ref), ("mixed", mix)):
+        x = r.x.cpu().numpy()
+        fwd = np.linalg.norm(x - x_or) / nx
+        met = np.linalg.norm(A64 @ (x - x_or)) / nb
+        print(f"  {name}: forward {fwd:.2e} metric {met:.2e}", flush=True)
+        assert fwd <= 1e-8, (name, fwd)
+        assert met <= 1e-10, (name, met)
+    assert abs(mix.info["iters"] - info_or["iters"]) <= max(2, 0.05 * info_or["iters"])

@@ -85,6 +85,33 @@ def test_lsqr_fp32_storage_parity(sap, orc, m, n, d, cond, noise):
     assert np.linalg.norm(A64 @ (res.x.cpu().numpy() - x_or)) <= 1e-12 * np.linalg.norm(p.b)
 
 
+def test_lsqr_wide_inverse_parity(sap, orc):
+    """n = 4100: the explicit inverse M = R^-1 is built two columns per
+    workgroup (the LDS holds no more at this width), as for the 2^22 x 4096
+    workload.  R comes from LAPACK's QR of an oracle sketch of A (d = 2n);
+    it is an input here, the same on both sides, and the iterations of the
+    GPU (explicit inverse) and of the oracle (triangular solves, Alg. 2) are
+    compared at the FP64 bar."""
+    import torch
+    m, n, d = 16384, 4100, 8200
+    _note(f"lsqr wide inverse m={m} n={n} d={d}")
+    p = inputs.make_problem(m, n, kind="colscale", cond=1e4, noise=1e-6, seed=4100)
+    idx, sign = orc.sketch(11, 0, m, d, 8)
+    Y = orc.apply_sparse(idx, sign, p.A, None, d, 8)
+    R = np.linalg.qr(Y, mode="r")
+    x0 = np.zeros(n)
+    x_or, info_or = orc.lsqr(p.A, p.b, R, x0, tol=1e-12, maxiter=400)
+    res = sap.sap_lsqr(_dev(p.A), _dev(p.b), _dev(np.ascontiguousarray(R.T)), _dev(x0), tol=1e-12, maxiter=400)
+    torch.cuda.synchronize()
+    x = res.x.cpu().numpy()
+    assert res.status == sap.SAP_OK and info_or["converged"], res.info
+    _note(f"  iterations {res.info['iters']} (oracle {info_or['iters']}), "
+          f"forward {np.linalg.norm(x - x_or) / np.linalg.norm(x_or):.2e}")
+    assert np.linalg.norm(p.A @ (x - x_or)) <= 1e-12 * np.linalg.norm(p.b)
+    assert np.linalg.norm(x - x_or) <= 1e-8 * np.linalg.norm(x_or)
+    assert abs(res.info["iters"] - info_or["iters"]) <= 2
+
+
 def test_lsqr_maxiter_and_zero(sap, orc):
     import torch
     p = inputs.make_problem(4000, 20, kind="svd", cond=1e4, noise=1e-3, seed=1)
@@ -144,11 +171,40 @@ def test_solve_parity(sap, orc, name, m, n, d, zeta, kind, cond, noise, row_scal
     assert res.status == sap.SAP_OK, res.info
     assert info_or["status"] == "ok"
     assert np.linalg.norm(p.A @ (x - x_or)) <= 1e-12 * nb
-    if name in ("config0", "tiny", "wide-d", "sparse", "min-m", "d-eq-n-plus-1", "zeta-eq-d"):
-        assert np.linalg.norm(x - x_or) <= 1e-8 * np.linalg.norm(x_or)
+    fwd = np.linalg.norm(x - x_or) / np.linalg.norm(x_or)
+    _note(f"  forward error {fwd:.2e}, iterations {res.info['iters']} (oracle {info_or['iters']})")
+    # The forward bar 1e-8 holds wherever the least-squares perturbation bound
+    # kappa u + kappa^2 u ||r|| / (||A|| ||x||) allows it, which it does for
+    # every case here.  "lev" is the 1e8-conditioned case with small noise:
+    # bound 1.2e-8, and two correct FP64 solvers (the oracle at other sketch
+    # seeds, LAPACK's lstsq) differ from the oracle by 1.4e-9 to 1.7e-9 on it.
+    assert fwd <= 1e-8, fwd
     # the stopping iteration moves with rounding where the rate is close to 1
     # (d = n + 1: ~80 iterations), by a few percent of the count
     assert abs(res.info["iters"] - info_or["iters"]) <= max(2, 0.05 * info_or["iters"])
+
+
+def test_solve_claimed_tail_parity(sap, orc):
+    """An FP64 solve whose A (2^18 x 300, 629 MB) is past the size at which
+    the LSQR pass claims the last eighth of its rows in chunks from a device
+    counter (timing-dependent row ownership): against the oracle at the
+    paper's metric and the forward bar (bound ~1e-10 here)."""
+    import torch
+    m, n, d = 1 << 18, 300, 1200
+    _note(f"solve claimed-tail m={m} n={n} d={d} ({m * n * 8 / 2**20:.0f} MiB)")
+    p = inputs.make_problem(m, n, kind="svd", cond=1e6, noise=1e-8, seed=7)
+    res = sap.sap_solve(_dev(p.A), _dev(p.b), d, 8, 5, tol=1e-12, maxiter=300)
+    torch.cuda.synchronize()
+    x = res.x.cpu().numpy()
+    x_or, info_or = orc.solve(p.A, p.b, d, 8, 5, tol=1e-12, maxiter=300)
+    assert res.status == sap.SAP_OK, res.info
+    assert info_or["status"] == "ok"
+    nb = np.linalg.norm(p.b)
+    fwd = np.linalg.norm(x - x_or) / np.linalg.norm(x_or)
+    _note(f"  forward error {fwd:.2e}, iterations {res.info['iters']} (oracle {info_or['iters']})")
+    assert np.linalg.norm(p.A @ (x - x_or)) <= 1e-12 * nb
+    assert fwd <= 1e-8
+    assert abs(res.info["iters"] - info_or["iters"]) <= 2
 
 
 def test_solve_errors(sap):
