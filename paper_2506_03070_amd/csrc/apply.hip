@@ -184,10 +184,11 @@ __global__ __launch_bounds__(256) void apply_reduce_kernel(const TY *__restrict_
 // [0, d) becomes 65535 (>= d), which the apply adds into its spare row.
 __global__ __launch_bounds__(256) void idx16_kernel(const int32_t *__restrict__ idx, int64_t count, int d,
                                                     uint16_t *__restrict__ out) {
-  const int64_t e = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
-  if (e >= count) return;
-  const int32_t v = idx[e];
-  out[e] = static_cast<uint16_t>(v >= 0 && v < d ? v : 65535);
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * 256;
+  for (int64_t e = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; e < count; e += stride) {
+    const int32_t v = idx[e];
+    out[e] = static_cast<uint16_t>(v >= 0 && v < d ? v : 65535);
+  }
 }
 
 // The strips re-read every row's indices and sign word (40 bytes); past this
@@ -239,8 +240,10 @@ template <typename TA, typename TY, int W>
 void launch_strip(const ApplyPlan &p, dim3 grid, size_t lds, hipStream_t st, const sps_sketch *S, const TA *A,
                   int64_t lda, const double *b, int n, int ncols, TY *out, int64_t ldo, int64_t slice_stride,
                   double h, int scale_now, const uint16_t *idx16) {
+  // The 16-bit copy is read with 16-byte loads whatever S->idx's alignment
+  // (the copy is 256-byte aligned); the 32-bit indices only when S->idx is.
   const bool fast = S->zeta == 8 && p.nranges == 1 && (reinterpret_cast<uintptr_t>(S->idx) % 16 == 0);
-  if (fast && idx16 != nullptr)
+  if (S->zeta == 8 && p.nranges == 1 && idx16 != nullptr)
     apply_strip_kernel<TA, TY, W, true, true><<<grid, kApplyThreads, lds, st>>>(
         S->idx, idx16, S->sign, S->zeta, A, lda, b, S->m, n, ncols, S->d, p.dr, p.nstrips, p.nranges, p.nslices,
         p.rows_per_slice, out, ldo, slice_stride, h, scale_now);
@@ -274,7 +277,8 @@ sap_status apply_typed(sap_ctx *ctx, const sps_sketch *S, const TA *A, int64_t l
   if (use_compact(p, S->m, S->zeta, S->d)) {
     uint16_t *c = cv.take<uint16_t>(static_cast<size_t>(S->m) * 8);
     const int64_t count = S->m * 8;
-    idx16_kernel<<<static_cast<unsigned>((count + 255) / 256), 256, 0, st>>>(S->idx, count, S->d, c);
+    const unsigned g = static_cast<unsigned>(std::min<int64_t>((count + 255) / 256, int64_t(ctx->num_cus) * 16));
+    idx16_kernel<<<g, 256, 0, st>>>(S->idx, count, S->d, c);
     SAP_HIP_TRY(hipGetLastError());
     idx16 = c;
   }

@@ -103,6 +103,10 @@ APPLY_CASES = [
     (1, 5, 7, 3, "colscale", "f64", "f64", True, 0),
     (70000, 47, 4000, 8, "svd", "f64", "f64", True, 0),        # config 1's d: 4 row ranges, bucketed
     (20000, 200, 2600, 8, "colscale", "f32", "f64", True, 0),  # 3 ranges, ragged last tile
+    (30000, 1000, 4000, 8, "colscale", "f64", "f64", True, 0),  # 2^20 x 1000 workload's columns: 8 groups
+    (20000, 4096, 8192, 8, "colscale", "f32", "f64", True, 0),  # 2^22 x 4096 workload's columns and d
+    (20000, 20, 40000, 8, "colscale", "f64", "f64", True, 0),   # d beyond one LDS strip: two row ranges
+    (12000, 300, 1200, 64, "colscale", "f64", "f64", True, 0),  # zeta = 64: one sign bit per nonzero
 ]
 
 
@@ -163,6 +167,23 @@ def test_apply_bf16_input(sap, orc, ydt):
     Yo = orc.apply_sparse(idx_ref, sign_ref, A_ref, p.b, d, zeta)
     tol = 1e-12 if ydt == "f64" else 1e-5
     assert np.linalg.norm(Yg - Yo) <= tol * np.linalg.norm(Yo)
+
+
+def test_apply_bf16_wide(sap, orc):
+    """BF16 A, 512 columns: full 4-column strips of BF16 input into FP64 Y."""
+    import torch
+    m, n, d, zeta = 30000, 512, 2048, 8
+    _note(f"apply-bf16 wide m={m} n={n} d={d}")
+    p = inputs.make_problem(m, n, kind="colscale", cond=1e3, seed=43)
+    A_bf = torch.from_numpy(p.A).to(torch.bfloat16)
+    A_ref = A_bf.to(torch.float64).numpy()
+    idx_ref, sign_ref = orc.sketch(78, 0, m, d, zeta)
+    Y = sap.sps_apply(torch.from_numpy(idx_ref).cuda(), torch.from_numpy(sign_ref.view(np.int64)).cuda(), d, zeta,
+                      A_bf.cuda(), torch.from_numpy(p.b).cuda(), y_dtype=torch.float64)
+    torch.cuda.synchronize()
+    Yg = Y.cpu().numpy().T
+    Yo = orc.apply_sparse(idx_ref, sign_ref, A_ref, p.b, d, zeta)
+    assert np.linalg.norm(Yg - Yo) <= 1e-12 * np.linalg.norm(Yo)
 
 
 def test_apply_ignores_out_of_range_rows(sap, orc):
