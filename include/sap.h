@@ -145,6 +145,21 @@ sap_status sps_apply(sap_ctx *ctx, const sps_sketch *S, const void *A, int64_t l
                      sap_dtype a_type, const double *b, int32_t n, void *Y, int64_t ldy,
                      sap_dtype y_type, void *stream);
 
+/* sps_apply without any allocation, for callers that cannot allocate device
+ * memory (code being captured into a HIP graph, tight serving loops, hosts
+ * that forbid hipMalloc).  Same arguments, result and errors as sps_apply;
+ * its partial sums live in a static device buffer of 128 MiB that the
+ * library holds on every GPU it runs on until the process ends (looked up
+ * once at sap_create).  It calls no hipMalloc, hipFree or other allocating
+ * routine.  Errors: those of sps_apply, and SAP_ENOMEM when this apply
+ * needs more than the static buffer (sap_last_error gives the size needed;
+ * the 2^20 x 1000, d = 4000 apply needs 64 MB).  Every call on a GPU uses
+ * that GPU's one buffer: calls that overlap in time on one GPU (on
+ * different streams, or from different contexts) race and must be
+ * serialised by the caller.  Asynchronous on `stream`. */
+sap_status sps_apply_noalloc(sap_ctx *ctx, const sps_sketch *S, const void *A, int64_t lda, sap_dtype a_type,
+                             const double *b, int32_t n, void *Y, int64_t ldy, sap_dtype y_type, void *stream);
+
 /* Householder QR of Y (Alg. 1, "factor Q, R = QR(Y)"), in place, FP64.
  * Y: device, column-major rows x cols (ldy >= rows), rows >= cols.  On return
  * the upper triangle holds R and the strict lower part the Householder

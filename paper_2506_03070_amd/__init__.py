@@ -21,7 +21,7 @@ SAP_MODE_FP64, SAP_MODE_MIXED_FP32, SAP_MODE_MIXED_FP32_REFINE, SAP_MODE_MIXED_B
 
 # Every symbol the header declares (checked by the CPU test suite).
 EXPORTS = ["sap_create", "sap_destroy", "sap_last_error", "sap_status_string", "sps_generate",
-           "sps_apply", "sap_qr", "sap_trsv", "sap_solve", "sap_lsqr", "sap_profile_enable",
+           "sps_apply", "sps_apply_noalloc", "sap_qr", "sap_trsv", "sap_solve", "sap_lsqr", "sap_profile_enable",
            "sap_profile_read", "sap_solve_batch", "sap_serve_start", "sap_submit", "sap_poll",
            "sap_cancel", "sap_serve_stats", "sap_embedding_dim", "sap_iteration_estimate"]
 PROF_PASS, PROF_APPLY = 0, 1
@@ -87,6 +87,8 @@ def lib():
         L.sps_apply.argtypes = [_vp, ctypes.POINTER(SpsSketch), _vp, _i64, ctypes.c_int, _vp, _i32, _vp,
                                 _i64, ctypes.c_int, _vp]
         L.sps_apply.restype = ctypes.c_int
+        L.sps_apply_noalloc.argtypes = L.sps_apply.argtypes
+        L.sps_apply_noalloc.restype = ctypes.c_int
         L.sap_qr.argtypes = [_vp, _vp, _i64, _i32, _i32, _vp, _vp]
         L.sap_qr.restype = ctypes.c_int
         L.sap_trsv.argtypes = [_vp, _vp, _i64, _i32, _i32, _vp, _vp, _vp]
@@ -237,6 +239,23 @@ def sps_apply(idx, sign, d, zeta, A, b=None, y_dtype=None, ctx=None, seed=0, str
     bptr = _dev(b, torch.float64, "b") if b is not None else None
     ctx.check(lib().sps_apply(ctx.handle, ctypes.byref(S), _dev(A, name="A"), _ld(A), _dtype_code(A),
                               bptr, n, _dev(Y, y_dtype, "Y"), _ld(Y), _dtype_code(Y), _vp(_stream())))
+    return Y
+
+
+def sps_apply_noalloc(idx, sign, d, zeta, A, b=None, y_dtype=None, ctx=None, seed=0, stream_id=0, Y=None):
+    """sps_apply through the allocation-free entry point (partial sums in the
+    library's static device buffer).  Same arguments and result layout as
+    sps_apply."""
+    torch = _torch()
+    ctx = ctx or default_context()
+    m, n = A.shape
+    y_dtype = y_dtype or (torch.float64 if A.dtype == torch.float64 else torch.float32)
+    ncols = n + (1 if b is not None else 0)
+    Y = Y if Y is not None else torch.empty((ncols, d), dtype=y_dtype, device=A.device)
+    S = _sketch_struct(m, d, zeta, seed, stream_id, idx, sign)
+    bptr = _dev(b, torch.float64, "b") if b is not None else None
+    ctx.check(lib().sps_apply_noalloc(ctx.handle, ctypes.byref(S), _dev(A, name="A"), _ld(A), _dtype_code(A),
+                                      bptr, n, _dev(Y, y_dtype, "Y"), _ld(Y), _dtype_code(Y), _vp(_stream())))
     return Y
 
 

@@ -185,6 +185,10 @@ sap_status sap_create(sap_ctx **out, int device, size_t hbm_budget) {
     return SAP_EDEVICE;
   }
   ctx->budget = hbm_budget ? hbm_budget : static_cast<size_t>(0.9 * static_cast<double>(free_b));
+  if (apply_scratch_init(ctx) != SAP_OK) {
+    delete ctx;
+    return SAP_EDEVICE;
+  }
   *out = ctx;
   return SAP_OK;
 }
@@ -256,6 +260,30 @@ sap_status sps_apply(sap_ctx *ctx, const sps_sketch *S, const void *A, int64_t l
   s = launch_apply(ctx, S, A, lda, a_type, b, n, Y, ldy, y_type, ctx->ws, st);
   prof_end(ctx, kProfApply, pb, st);
   return s;
+}
+
+sap_status sps_apply_noalloc(sap_ctx *ctx, const sps_sketch *S, const void *A, int64_t lda, sap_dtype a_type,
+                             const double *b, int32_t n, void *Y, int64_t ldy, sap_dtype y_type, void *stream) {
+  if (!ctx) return SAP_EINVAL;
+  sap_status s = check_sketch(ctx, S);
+  if (s != SAP_OK) return s;
+  if (!A || !Y) return fail(ctx, SAP_EINVAL, "sps_apply_noalloc: A and Y must be device pointers");
+  if (n < 1) return fail(ctx, SAP_EINVAL, "sps_apply_noalloc: n must be >= 1");
+  if (lda < n) return fail(ctx, SAP_EINVAL, "sps_apply_noalloc: lda must be >= n");
+  if (ldy < S->d) return fail(ctx, SAP_EINVAL, "sps_apply_noalloc: ldy must be >= d");
+  if (a_type != SAP_F64 && a_type != SAP_F32 && a_type != SAP_BF16)
+    return fail(ctx, SAP_EINVAL, "sps_apply_noalloc: a_type must be F64, F32 or BF16");
+  if (y_type != SAP_F64 && y_type != SAP_F32)
+    return fail(ctx, SAP_EINVAL, "sps_apply_noalloc: y_type must be F64 or F32");
+  const int ncols = n + (b ? 1 : 0);
+  const size_t need = apply_workspace_bytes(ctx, S->m, S->zeta, S->d, ncols, y_type);
+  if (ctx->apply_scratch == nullptr || need > ctx->apply_scratch_bytes)
+    return fail(ctx, SAP_ENOMEM, "sps_apply_noalloc: this apply needs " + std::to_string(need) +
+                                     " bytes of scratch, more than the static buffer's " +
+                                     std::to_string(ctx->apply_scratch_bytes));
+  SAP_HIP_TRY(hipSetDevice(ctx->device));
+  return launch_apply(ctx, S, A, lda, a_type, b, n, Y, ldy, y_type, ctx->apply_scratch,
+                      static_cast<hipStream_t>(stream));
 }
 
 sap_status sap_qr(sap_ctx *ctx, double *Y, int64_t ldy, int32_t rows, int32_t cols, double *tau, void *stream) {

@@ -306,6 +306,23 @@ sap_status apply_typed(sap_ctx *ctx, const sps_sketch *S, const TA *A, int64_t l
 
 }  // namespace
 
+// Scratch of sps_apply_noalloc: a file-scope device array, one copy per GPU
+// the library runs on, held until the process ends.  Host code never uses
+// its name as an address (on the host it names a stand-in, not device
+// memory): apply_scratch_init looks up this device's copy once and the
+// context keeps that address.
+static __device__ __align__(256) unsigned char g_apply_scratch[kNoAllocScratchBytes];
+
+sap_status apply_scratch_init(sap_ctx *ctx) {
+  void *p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(g_apply_scratch));
+  if (e != hipSuccess) return hip_fail(ctx, e, "hipGetSymbolAddress(apply scratch)");
+  if (p == nullptr) return fail(ctx, SAP_EDEVICE, "apply scratch: no device address");
+  ctx->apply_scratch = p;
+  ctx->apply_scratch_bytes = kNoAllocScratchBytes;
+  return SAP_OK;
+}
+
 size_t apply_workspace_bytes(sap_ctx *ctx, int64_t m, int zeta, int d, int ncols, sap_dtype y_type) {
   const size_t es = (y_type == SAP_F64) ? 8 : 4;
   const ApplyPlan p = make_plan(ctx->num_cus, m, d, ncols, es);

@@ -162,6 +162,10 @@ struct sap_ctx {
 
   void *ws = nullptr;
   size_t ws_size = 0;
+  // device address of this GPU's copy of the static scratch array used by
+  // sps_apply_noalloc (set once at sap_create; never allocated or freed)
+  void *apply_scratch = nullptr;
+  size_t apply_scratch_bytes = 0;
   // kernel timing (sap_profile_enable): pending event pairs per kernel,
   // resolved into launch counts and milliseconds; free events are reused
   bool profiling = false;
@@ -210,6 +214,11 @@ size_t apply_workspace_bytes(sap_ctx *ctx, int64_t m, int zeta, int d, int ncols
 sap_status launch_apply(sap_ctx *ctx, const sps_sketch *S, const void *A, int64_t lda,
                         sap_dtype a_type, const double *b, int n, void *Y, int64_t ldy,
                         sap_dtype y_type, void *work, hipStream_t st);
+
+// Static scratch of the allocation-free apply (apply.hip): its size, and the
+// lookup of this device's copy (once per context, with the device current).
+constexpr size_t kNoAllocScratchBytes = size_t(128) << 20;
+sap_status apply_scratch_init(sap_ctx *ctx);
 
 // Householder QR (qr.hip).
 size_t qr_workspace_bytes(int rows, int cols);
