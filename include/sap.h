@@ -239,9 +239,16 @@ sap_status sap_lsqr(sap_ctx *ctx, const sap_problem *prob, const double *R, int6
  * problem has met its own stopping test or its maxiter.  probs, params, x and
  * info are host arrays of `count` entries; x[k] is a device pointer to n_k
  * doubles.  All problems share one A dtype (F32 or F64); each has its own m,
- * n, d, zeta, seed, tol and maxiter (mode is ignored).  The sketch of
- * problem k uses Philox stream word k.  The sketch apply and the passes over
- * A compute in FP64 whatever A's storage type.  Limits: n <= 1024,
+ * n, d, zeta, seed, tol, maxiter, mode and max_refine.  The sketch of
+ * problem k uses Philox stream word k.  The sketch apply accumulates in FP64.
+ * Modes: SAP_MODE_FP64 and SAP_MODE_MIXED_FP32 run every pass in FP64
+ * arithmetic over A in its storage type, to the stopping test of sap_solve;
+ * SAP_MODE_MIXED_FP32_REFINE (FP32 A) is the refinement form of sap_solve
+ * (FP32 inner passes and u, FP64 residual at each restart, tol = target
+ * relative correction, max_refine as there), with its outer loop kept on
+ * the device so that the problem advances with the batch; info[k].refinements
+ * counts its inner solves.  SAP_MODE_MIXED_BF16SA gives SAP_EINVAL.
+ * Limits: n <= 1024,
  * d <= 4096 (a strip of the sketch lives in LDS), m < 2^31.  Blocking.  Returns SAP_OK when every
  * problem converged, SAP_NOT_CONVERGED when some did not or were rank
  * deficient (per-problem status in info[k].status); SAP_EINVAL, SAP_ENOMEM,
@@ -260,8 +267,9 @@ sap_status sap_solve_batch(sap_ctx *ctx, int32_t count, const sap_problem *probs
  * stopping test (same test as sap_solve) or its maxiter, and its memory goes
  * back to the arena.  A problem's sketch is the one sap_solve draws for the
  * same seed, and its result does not depend on what else is in flight
- * beyond the rounding order of the sketch accumulation.  Limits as for
- * sap_solve_batch; all problems of one context share one A dtype.
+ * beyond the rounding order of the sketch accumulation.  Limits and modes
+ * as for sap_solve_batch (a request in the refinement form retires when its
+ * outer loop stops); all problems of one context share one A dtype.
  * ---------------------------------------------------------------------- */
 
 /* Start serving with an arena of arena_bytes of device memory (0: half the

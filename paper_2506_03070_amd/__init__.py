@@ -328,7 +328,8 @@ def sap_lsqr(A, b, Rt, x0, tol=1e-12, maxiter=200, ctx=None, x=None):
     return SolveResult(x, st, info.as_dict())
 
 
-def sap_solve_batch(As, bs, ds, zetas=8, seeds=1, tol=1e-12, maxiter=200, ctx=None, xs=None):
+def sap_solve_batch(As, bs, ds, zetas=8, seeds=1, tol=1e-12, maxiter=200, ctx=None, xs=None, mode=0,
+                    max_refine=0):
     """Solve many independent problems together (sap_solve_batch).  As, bs:
     lists of device tensors (A row-major, F32 or F64; b F64).  Returns
     (xs, statuses, infos)."""
@@ -339,8 +340,9 @@ def sap_solve_batch(As, bs, ds, zetas=8, seeds=1, tol=1e-12, maxiter=200, ctx=No
     seeds = seeds if isinstance(seeds, (list, tuple)) else [seeds] * count
     ds = ds if isinstance(ds, (list, tuple)) else [ds] * count
     probs = (SapProblem * count)(*[_problem(A, b) for A, b in zip(As, bs)])
-    pars = (SapParams * count)(*[SapParams(int(d), int(z), int(s), tol, maxiter, 0, 0)
-                                 for d, z, s in zip(ds, zetas, seeds)])
+    modes = mode if isinstance(mode, (list, tuple)) else [mode] * count
+    pars = (SapParams * count)(*[SapParams(int(d), int(z), int(s), tol, maxiter, int(md), int(max_refine))
+                                 for d, z, s, md in zip(ds, zetas, seeds, modes)])
     xs = xs or [torch.empty(A.shape[1], dtype=torch.float64, device=A.device) for A in As]
     xptrs = (_vp * count)(*[_vp(_dev(xx, torch.float64, "x")) for xx in xs])
     infos = (SapInfo * count)()
@@ -360,14 +362,14 @@ def sap_serve_start(arena_bytes=0, max_active=1024, ctx=None):
     ctx.check(lib().sap_serve_start(ctx.handle, int(arena_bytes), int(max_active)))
 
 
-def sap_submit(A, b, d, zeta=8, seed=1, tol=1e-12, maxiter=200, ctx=None, x=None):
+def sap_submit(A, b, d, zeta=8, seed=1, tol=1e-12, maxiter=200, ctx=None, x=None, mode=0, max_refine=0):
     """Queue one problem (sap_submit).  Returns the ticket; the tensors stay
     referenced here until sap_poll reports a terminal status."""
     torch = _torch()
     ctx = ctx or default_context()
     x = x if x is not None else torch.empty(A.shape[1], dtype=torch.float64, device=A.device)
     prob = _problem(A, b)
-    par = SapParams(int(d), int(zeta), int(seed), float(tol), int(maxiter), 0, 0)
+    par = SapParams(int(d), int(zeta), int(seed), float(tol), int(maxiter), int(mode), int(max_refine))
     ticket = _u64(0)
     st = lib().sap_submit(ctx.handle, ctypes.byref(prob), ctypes.byref(par), _vp(_dev(x, torch.float64, "x")),
                           ctypes.byref(ticket), _vp(_stream()))

@@ -14,8 +14,12 @@
 //              the iterations are replayed from a captured hipGraph until a
 //              device counter says every problem has stopped.
 // The pass reads A in its storage precision (FP32 or FP64) and accumulates
-// in FP64: on gfx950 the FP64 vector rate keeps this pass HBM-bound, so the
-// batched form needs no refinement loop.
+// in FP64 (on gfx950 the FP64 vector rate keeps this pass HBM-bound), except
+// for problems in the refinement form (SAP_MODE_MIXED_FP32_REFINE): their
+// inner LSQR solves run the pass in FP32 (products, accumulation and u), each
+// restart forms the residual r = b - A x with FP64 accumulation, and a
+// per-problem device kernel keeps the outer loop (x += delta until
+// ||delta|| <= tol ||x||), so one batch can mix both forms.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -64,11 +68,15 @@ struct BatchItem {
   int32_t G, nblk;
   int64_t rows_per_chunk;
   int32_t rank_deficient, pad;
+  int32_t refine, max_refine;  // refinement form (FP32 inner solves), its cap (0 = 10)
+  double *xprev;               // x before the current inner solve (refinement form)
 };
 
 namespace {
 
 using namespace qr_dev;
+
+constexpr double kInnerTolF32 = 0x1p-23;  // FP32 resolution of the inner solves' test
 
 constexpr int kBThreads = 1024;
 constexpr int kBWaves = kBThreads / kWave;
@@ -284,7 +292,14 @@ __global__ __launch_bounds__(1024) void batch_init_kernel(const BatchItem *__res
     st->proceed = 0;
     st->total_iters = 0;
     st->steps = 0;
-    st->rel = 0;
+    st->rel = it.refine ? 1 : 0;
+    if (it.refine) st->tol = kInnerTolF32;
+    st->refine = it.refine;
+    st->refinements = 0;
+    st->max_refine = it.max_refine > 0 ? it.max_refine : 10;
+    st->final_done = it.rank_deficient ? 1 : 0;
+    st->target = it.tol;
+    st->prev_delta = INFINITY;
   }
 }
 
@@ -357,25 +372,22 @@ __global__ __launch_bounds__(256) void batch_repack_kernel(const RepackJob *__re
 // threads and one group at a time.  The served form, whose rounds hold a few
 // large requests, uses PF; the batched form, many small problems, the other
 // (more waves to cover the per-row shuffles).
-template <typename TA, int VEC, int KJ, int U, bool PF>
-__global__ __launch_bounds__(PF ? 512 : kBThreads) void batch_pass_kernel(const BatchItem *__restrict__ items,
-                                                                          const int2 *__restrict__ work, int nwork,
-                                                                          int tune) {
+// The body of the pass for compute type TC (FP64, or FP32 in the inner
+// solves of the refinement form) and u storage type TU (FP32 in the
+// refinement form, whose residual pass computes in FP64 and rounds u).
+template <typename TA, typename TC, typename TU, int VEC, int KJ, int U, bool PF>
+__device__ __forceinline__ void batch_pass_body(const BatchItem &it, int chunk, int tune, TC *psh, TC *qacc,
+                                                double *nsh) {
   constexpr int TH = PF ? 512 : kBThreads;
   constexpr int NW = TH / kWave;
-  __shared__ double psh[64 * VEC * KJ];
-  __shared__ double qacc[64 * VEC * KJ];
-  __shared__ double nsh[NW];
-  const int2 wk = work[blockIdx.x];
-  const BatchItem &it = items[wk.x];
   const LsqrState *st = it.st;
-  if (st->done && !tune) return;
   const int n = it.n;
   const bool init = st->init != 0;
   const double *__restrict__ pv = init ? it.x : it.p;
-  const double *__restrict__ uin = init ? it.b : it.u;
-  double *uout = it.u;
-  const double c_ap = st->c_ap, c_u = st->c_u;
+  const TU *__restrict__ uin = init ? nullptr : reinterpret_cast<const TU *>(it.u);
+  const double *__restrict__ bin = it.b;
+  TU *uout = reinterpret_cast<TU *>(it.u);
+  const TC c_ap = static_cast<TC>(st->c_ap), c_u = static_cast<TC>(st->c_u);
   int L = 1;
   while (L * VEC * KJ < n && L < 64) L <<= 1;
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
@@ -386,20 +398,20 @@ __global__ __launch_bounds__(PF ? 512 : kBThreads) void batch_pass_kernel(const 
   const bool vec_ok = (VEC > 1);
 
   for (int c = threadIdx.x; c < 64 * VEC * KJ; c += TH) {
-    psh[c] = c < n ? pv[c] : 0.0;
-    qacc[c] = 0.0;
+    psh[c] = c < n ? static_cast<TC>(pv[c]) : TC(0);
+    qacc[c] = TC(0);
   }
   __syncthreads();
-  double q[KJ][VEC];
+  TC q[KJ][VEC];
 #pragma unroll
   for (int j = 0; j < KJ; ++j)
 #pragma unroll
-    for (int e = 0; e < VEC; ++e) q[j][e] = 0.0;
-  const int64_t r0 = static_cast<int64_t>(wk.y) * it.rows_per_chunk;
+    for (int e = 0; e < VEC; ++e) q[j][e] = TC(0);
+  const int64_t r0 = static_cast<int64_t>(chunk) * it.rows_per_chunk;
   const int64_t r1 = min(it.m, r0 + it.rows_per_chunk);
   double nrm = 0.0;
   const int64_t gstride = static_cast<int64_t>(NW) * RS * U;
-  auto load_group = [&](int64_t base, TA (&a)[U][KJ][VEC], double (&ui)[U]) {
+  auto load_group = [&](int64_t base, TA (&a)[U][KJ][VEC], TC (&ui)[U]) {
 #pragma unroll
     for (int uu = 0; uu < U; ++uu) {
       const int64_t row = base + uu * RS + slot;
@@ -415,28 +427,29 @@ __global__ __launch_bounds__(PF ? 512 : kBThreads) void batch_pass_kernel(const 
           for (int e = 0; e < VEC; ++e) a[uu][j][e] = (rv && c + e < n) ? __builtin_nontemporal_load(arow + c + e) : TA(0);
         }
       }
-      ui[uu] = rv ? uin[row] : 0.0;
+      ui[uu] = rv ? (init ? static_cast<TC>(bin[row]) : static_cast<TC>(uin[row])) : TC(0);
     }
   };
-  auto compute_group = [&](int64_t base, TA (&a)[U][KJ][VEC], double (&ui)[U]) {
+  auto compute_group = [&](int64_t base, TA (&a)[U][KJ][VEC], TC (&ui)[U]) {
 #pragma unroll
     for (int uu = 0; uu < U; ++uu) {
       const int64_t row = base + uu * RS + slot;
-      double s = 0.0;
+      TC s = TC(0);
 #pragma unroll
       for (int j = 0; j < KJ; ++j)
 #pragma unroll
-        for (int e = 0; e < VEC; ++e) s += static_cast<double>(a[uu][j][e]) * psh[(sub + L * j) * VEC + e];
+        for (int e = 0; e < VEC; ++e) s += static_cast<TC>(a[uu][j][e]) * psh[(sub + L * j) * VEC + e];
       for (int off = L >> 1; off >= 1; off >>= 1) s += __shfl_xor(s, off, kWave);
       if (row < r1) {
-        const double uh = c_ap * s + c_u * ui[uu];
+        const TC uh = c_ap * s + c_u * ui[uu];
+        const TU us = static_cast<TU>(uh);
 #pragma unroll
         for (int j = 0; j < KJ; ++j)
 #pragma unroll
-          for (int e = 0; e < VEC; ++e) q[j][e] += uh * static_cast<double>(a[uu][j][e]);
+          for (int e = 0; e < VEC; ++e) q[j][e] += static_cast<TC>(us) * static_cast<TC>(a[uu][j][e]);
         if (sub == 0) {
-          if (!tune) uout[row] = uh;
-          nrm += uh * uh;
+          if (!tune) uout[row] = us;
+          nrm += static_cast<double>(us) * static_cast<double>(us);
         }
       }
     }
@@ -444,7 +457,7 @@ __global__ __launch_bounds__(PF ? 512 : kBThreads) void batch_pass_kernel(const 
   int64_t base = r0 + static_cast<int64_t>(wave) * RS * U;
   if constexpr (PF) {
     TA a0[U][KJ][VEC], a1[U][KJ][VEC];
-    double u0[U], u1[U];
+    TC u0[U], u1[U];
     if (base < r1) load_group(base, a0, u0);
     for (; base < r1; base += 2 * gstride) {
       if (base + gstride < r1) load_group(base + gstride, a1, u1);
@@ -457,7 +470,7 @@ __global__ __launch_bounds__(PF ? 512 : kBThreads) void batch_pass_kernel(const 
   } else {
     for (; base < r1; base += gstride) {
       TA a[U][KJ][VEC];
-      double ui[U];
+      TC ui[U];
       load_group(base, a, ui);
       compute_group(base, a, ui);
     }
@@ -467,7 +480,7 @@ __global__ __launch_bounds__(PF ? 512 : kBThreads) void batch_pass_kernel(const 
   for (int j = 0; j < KJ; ++j)
 #pragma unroll
     for (int e = 0; e < VEC; ++e) {
-      double v = q[j][e];
+      TC v = q[j][e];
       for (int off = L; off < kWave; off <<= 1) v += __shfl_xor(v, off, kWave);
       q[j][e] = v;
     }
@@ -482,13 +495,47 @@ __global__ __launch_bounds__(PF ? 512 : kBThreads) void batch_pass_kernel(const 
     }
     __syncthreads();
   }
-  double *qdst = it.qpart + static_cast<int64_t>(wk.y) * n;
-  for (int c = threadIdx.x; c < n; c += TH) qdst[c] = qacc[c];
+  double *qdst = it.qpart + static_cast<int64_t>(chunk) * n;
+  for (int c = threadIdx.x; c < n; c += TH) qdst[c] = static_cast<double>(qacc[c]);
   if (threadIdx.x == 0) {
-    double s = 0.0;
-    for (int w = 0; w < NW; ++w) s += nsh[w];
-    it.nrmpart[wk.y] = s;
+    double sum = 0.0;
+    for (int w = 0; w < NW; ++w) sum += nsh[w];
+    it.nrmpart[chunk] = sum;
   }
+}
+
+// Packed pass: L lanes serve one row (L = the power of two covering n/VEC,
+// at most 64, chosen per problem), so a wavefront handles 64/L rows at once.
+// u <- c_ap (A p) + c_u u_in; q += u_i A[i, :].  At the initialisation step
+// (st->init) the pass reads u_in = b and p = x.  p sits in LDS (read per
+// element), q in registers; the waves' q partials are combined through one
+// LDS vector in wave order.  FP64 arithmetic, except the inner solves of the
+// refinement form (FP32 arithmetic and u; their residual pass is FP64 with u
+// rounded to FP32).
+// PF: 512-thread workgroups with two row groups in flight per wave (the next
+// group's loads issued before the current one is reduced); otherwise 1024
+// threads and one group at a time.  The served form, whose rounds hold a few
+// large requests, uses PF; the batched form, many small problems, the other
+// (more waves to cover the per-row shuffles).
+template <typename TA, int VEC, int KJ, int U, bool PF>
+__global__ __launch_bounds__(PF ? 512 : kBThreads) void batch_pass_kernel(const BatchItem *__restrict__ items,
+                                                                          const int2 *__restrict__ work, int nwork,
+                                                                          int tune) {
+  constexpr int NW = (PF ? 512 : kBThreads) / kWave;
+  __shared__ double psh[64 * VEC * KJ];
+  __shared__ double qacc[64 * VEC * KJ];
+  __shared__ double nsh[NW];
+  const int2 wk = work[blockIdx.x];
+  const BatchItem &it = items[wk.x];
+  const LsqrState *st = it.st;
+  if (st->done && !tune) return;
+  if (!it.refine)
+    batch_pass_body<TA, double, double, VEC, KJ, U, PF>(it, wk.y, tune, psh, qacc, nsh);
+  else if (st->init)
+    batch_pass_body<TA, double, float, VEC, KJ, U, PF>(it, wk.y, tune, psh, qacc, nsh);
+  else
+    batch_pass_body<TA, float, float, VEC, KJ, U, PF>(it, wk.y, tune, reinterpret_cast<float *>(psh),
+                                                      reinterpret_cast<float *>(qacc), nsh);
 }
 
 __global__ __launch_bounds__(kTrsvThreads) void batch_lower_kernel(const BatchItem *__restrict__ items, int *err) {
@@ -522,7 +569,70 @@ __global__ __launch_bounds__(kTrsvThreads) void batch_upper_kernel(const BatchIt
   __syncthreads();
   chain_block<true>(it.Y, it.d, n, it.Dup, it.p, it.flags + it.nblk, epoch, b, sh.rb, sh.red, err);
   if (b != 0) return;
-  upper_epilogue(n, it.p, it.w, it.x, st, done_count);
+  upper_epilogue(n, it.p, it.w, it.x, st, it.refine ? nullptr : done_count);
+}
+
+// The outer loop of the refinement form, after each iteration: for every
+// problem whose inner solve has just stopped, compare the correction it made
+// with x.  Converged (||x - x_prev|| <= tol ||x||, which includes a restart
+// that found r or (A M)^T r exactly zero), stagnated (a correction no smaller
+// than the previous one: the FP32 inner solves cannot resolve the remaining
+// error), out of iterations or out of refinements: the problem is finished
+// and counted in *done_count.  Otherwise x_prev = x and the LSQR state
+// restarts with an initialisation step, whose pass forms the FP64 residual
+// of the current x.  The flag epochs (steps) keep counting.
+__global__ __launch_bounds__(1024) void batch_refine_kernel(const BatchItem *__restrict__ items, int *done_count) {
+  __shared__ double scr[16];
+  __shared__ int restart;
+  const BatchItem &it = items[blockIdx.x];
+  if (!it.refine) return;
+  LsqrState *st = it.st;
+  if (!st->done || st->final_done) return;
+  const int n = it.n;
+  double a = 0.0, bb = 0.0;
+  for (int c = threadIdx.x; c < n; c += 1024) {
+    const double xc = it.x[c];
+    const double dx = xc - it.xprev[c];
+    a += dx * dx;
+    bb += xc * xc;
+  }
+  a = sqrt(wg_sum(a, scr));
+  bb = sqrt(wg_sum(bb, scr));
+  if (threadIdx.x == 0) {
+    const int nref = st->refinements + 1;
+    st->refinements = nref;
+    const bool conv = a <= st->target * bb;
+    const bool give_up = a >= st->prev_delta || st->total_iters >= st->maxiter || nref >= st->max_refine;
+    if (conv || give_up) {
+      st->converged = conv ? 1 : 0;
+      st->final_done = 1;
+      atomicAdd(done_count, 1);
+      restart = 0;
+    } else {
+      st->prev_delta = a;
+      st->alpha = st->beta = st->rhobar = st->phibar = 0.0;
+      st->alpha_new = st->beta_new = 0.0;
+      st->c_ap = -1.0;
+      st->c_u = 1.0;
+      st->resid_est = st->normar_est = 0.0;
+      st->iter = 0;
+      st->converged = 0;
+      st->proceed = 0;
+      st->init = 1;
+      st->done = 0;
+      restart = 1;
+    }
+  }
+  __syncthreads();
+  if (restart)
+    for (int c = threadIdx.x; c < n; c += 1024) it.xprev[c] = it.x[c];
+}
+
+// x_prev = x0 for the problems in the refinement form (after the x0 solve).
+__global__ __launch_bounds__(256) void batch_save_x_kernel(const BatchItem *__restrict__ items) {
+  const BatchItem &it = items[blockIdx.x];
+  if (!it.refine || it.rank_deficient) return;
+  for (int c = threadIdx.x; c < it.n; c += 256) it.xprev[c] = it.x[c];
 }
 
 __global__ void batch_count_rank_kernel(const BatchItem *__restrict__ items, int count, int *done_count) {
@@ -535,7 +645,7 @@ __global__ void batch_count_rank_kernel(const BatchItem *__restrict__ items, int
 // done[k] = problem k has stopped (served form).
 __global__ void serve_done_kernel(const BatchItem *__restrict__ items, int count, int *__restrict__ done) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k < count) done[k] = items[k].st->done;
+  if (k < count) done[k] = items[k].refine ? items[k].st->final_done : items[k].st->done;
 }
 
 template <int S, int NB>
@@ -621,7 +731,7 @@ size_t item_bytes(int64_t m, int n, int d, int zeta, sap_dtype at) {
   b += 256 + sizeof(int) * 3 * nblk;
   b += 256 + sizeof(LsqrState);
   b += 256 + sizeof(double) * m;
-  b += 4 * (256 + sizeof(double) * n);
+  b += 5 * (256 + sizeof(double) * n);
   b += 256 + sizeof(double) * gmax * n;
   b += 256 + sizeof(double) * gmax;
   return (b + 256 + 255) / 256 * 256;  // a multiple of 256: consecutive items stay aligned
@@ -650,6 +760,7 @@ void carve_item(BatchItem &it, void *base, sap_dtype at, int64_t rows_per_chunk)
   it.v = cv.take<double>(n);
   it.w = cv.take<double>(n);
   it.p = cv.take<double>(n);
+  it.xprev = cv.take<double>(n);
   const int64_t gmax = (m + kMinRowsPerChunk - 1) / kMinRowsPerChunk;
   it.qpart = cv.take<double>(static_cast<size_t>(gmax) * n);
   it.nrmpart = cv.take<double>(gmax);
@@ -711,6 +822,7 @@ sap_status setup_items(sap_ctx *ctx, BatchItem *ditems, const std::vector<BatchI
   batch_transpose_kernel<<<dim3(nt_max, nt_max, count), 256, 0, st>>>(ditems);
   batch_init_kernel<<<count, 1024, 0, st>>>(ditems);
   batch_x0_kernel<<<dim3(nblk_max, count), kTrsvThreads, 0, st>>>(ditems, dflags);
+  batch_save_x_kernel<<<count, 256, 0, st>>>(ditems);
   SAP_HIP_TRY(hipGetLastError());
   return SAP_OK;
 }
@@ -738,8 +850,13 @@ sap_status run_batch(sap_ctx *ctx, int count, const sap_problem *probs, const sa
     if (!p.A || !p.b || !x[k]) return fail(ctx, SAP_EINVAL, "sap_solve_batch: NULL pointer");
     if (p.n < 1 || p.m < static_cast<int64_t>(p.n) + 1 || p.lda < p.n || p.m > (int64_t(1) << 31))
       return fail(ctx, SAP_EINVAL, "sap_solve_batch: bad problem shape");
-    if (q.d < p.n + 1 || q.zeta < 1 || q.zeta > 64 || q.zeta > q.d || q.maxiter < 0 || !(q.tol >= 0.0))
+    if (q.d < p.n + 1 || q.zeta < 1 || q.zeta > 64 || q.zeta > q.d || q.maxiter < 0 || !(q.tol >= 0.0) ||
+        q.max_refine < 0)
       return fail(ctx, SAP_EINVAL, "sap_solve_batch: bad parameters");
+    if (q.mode != SAP_MODE_FP64 && q.mode != SAP_MODE_MIXED_FP32 && q.mode != SAP_MODE_MIXED_FP32_REFINE)
+      return fail(ctx, SAP_EINVAL, "sap_solve_batch: mode must be FP64, MIXED_FP32 or MIXED_FP32_REFINE");
+    if (q.mode == SAP_MODE_MIXED_FP32_REFINE && at != SAP_F32)
+      return fail(ctx, SAP_EINVAL, "sap_solve_batch: the refinement form needs FP32 A");
     const size_t es = (at == SAP_F32) ? 4 : 8;
     if (q.d > 4096) return fail(ctx, SAP_EINVAL, "sap_solve_batch: d > 4096 is not supported by the batched form");
     n_max = std::max(n_max, p.n);
@@ -798,6 +915,7 @@ sap_status run_batch(sap_ctx *ctx, int count, const sap_problem *probs, const sa
   BatchItem *ditems = cv.take<BatchItem>(count);
   std::vector<BatchItem> items(count);
   int64_t col_base = 0;
+  bool any_refine = false;
   for (int k = 0; k < count; ++k) {
     BatchItem &it = items[k];
     const sap_problem &p = probs[k];
@@ -816,6 +934,9 @@ sap_status run_batch(sap_ctx *ctx, int count, const sap_problem *probs, const sa
     it.h = 1.0 / std::sqrt(static_cast<double>(q.zeta));
     it.seed = q.seed;
     it.stream = static_cast<uint64_t>(k);
+    it.refine = q.mode == SAP_MODE_MIXED_FP32_REFINE ? 1 : 0;
+    it.max_refine = q.max_refine;
+    any_refine = any_refine || it.refine;
     it.col_base = col_base;
     col_base += p.m;
     carve_item(it, cv.take<char>(need[k]), at, rows_per_chunk);
@@ -955,6 +1076,7 @@ sap_status run_batch(sap_ctx *ctx, int count, const sap_problem *probs, const sa
     launch_pass_fn(pc, ditems, dpass, npass, 0, st);
     batch_lower_kernel<<<dim3(nblk_max, count), kTrsvThreads, 0, st>>>(ditems, dflags);
     batch_upper_kernel<<<dim3(nblk_max, count), kTrsvThreads, 0, st>>>(ditems, dflags, dflags + 1);
+    if (any_refine) batch_refine_kernel<<<count, 1024, 0, st>>>(ditems, dflags + 1);
   }
   hipError_t ce = hipStreamEndCapture(st, &graph);
   if (ce != hipSuccess) return hip_fail(ctx, ce, "hipStreamEndCapture");
@@ -972,7 +1094,12 @@ sap_status run_batch(sap_ctx *ctx, int count, const sap_problem *probs, const sa
     }
   } gguard{graph, gexec};
   int hflags[3] = {0, 0, 0};
-  const int max_launches = (maxiter_max + 1) / kIterPerGraph + 2;
+  // every restart of the refinement form takes one step that is not an
+  // iteration (the residual pass), at most max_refine of them per problem
+  int refine_steps = 0;
+  for (int k = 0; k < count; ++k)
+    if (items[k].refine) refine_steps = std::max(refine_steps, items[k].max_refine > 0 ? items[k].max_refine : 10);
+  const int max_launches = (maxiter_max + refine_steps + 1) / kIterPerGraph + 2;
   bool finished = false;
   for (int l = 0; l < max_launches; ++l) {
     SAP_HIP_TRY(hipGraphLaunch(gexec, st));
@@ -1009,6 +1136,7 @@ sap_status run_batch(sap_ctx *ctx, int count, const sap_problem *probs, const sa
       std::memset(&infos[k], 0, sizeof(sap_info));
       infos[k].status = sk;
       infos[k].iters = states[k].total_iters;
+      infos[k].refinements = states[k].refinements;
       infos[k].resid_est = states[k].resid_est;
       infos[k].normar_est = states[k].normar_est;
     }
@@ -1200,10 +1328,12 @@ hipError_t serve_round(Server *S, std::vector<ServeRequest *> &fresh) {
     std::vector<int2> pass_work;
     int n_max = 0;
     bool aligned = true;
+    bool any_refine = false;
     const int vm = (at == SAP_F32) ? 4 : 2;
     for (int k = 0; k < count; ++k) {
       items[k] = act[k]->item;
       n_max = std::max(n_max, items[k].n);
+      any_refine = any_refine || items[k].refine;
       if (reinterpret_cast<uintptr_t>(items[k].A) % 16 != 0 || items[k].lda % vm != 0) aligned = false;
       for (int g = 0; g < items[k].G; ++g) pass_work.push_back(make_int2(k, g));
     }
@@ -1217,6 +1347,7 @@ hipError_t serve_round(Server *S, std::vector<ServeRequest *> &fresh) {
       launch_pass_fn(pc, S->d_active, S->d_pass, static_cast<int>(pass_work.size()), 0, st);
       batch_lower_kernel<<<dim3(nblk_max, count), kTrsvThreads, 0, st>>>(S->d_active, S->d_flags);
       batch_upper_kernel<<<dim3(nblk_max, count), kTrsvThreads, 0, st>>>(S->d_active, S->d_flags, S->d_flags + 1);
+      if (any_refine) batch_refine_kernel<<<count, 1024, 0, st>>>(S->d_active, S->d_flags + 1);
     }
     serve_done_kernel<<<(count + 255) / 256, 256, 0, st>>>(S->d_active, count, S->d_done);
     if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -1255,6 +1386,7 @@ hipError_t serve_round(Server *S, std::vector<ServeRequest *> &fresh) {
       std::memset(&r->info, 0, sizeof(r->info));
       r->info.status = stt;
       r->info.iters = states[k].total_iters;
+      r->info.refinements = states[k].refinements;
       r->info.resid_est = states[k].resid_est;
       r->info.normar_est = states[k].normar_est;
       r->info.t_queue_ms = std::chrono::duration<double, std::milli>(r->t_admit - r->t_submit).count();
@@ -1405,8 +1537,12 @@ sap_status serve_submit(sap_ctx *ctx, const sap_problem *p, const sap_params *q,
   if (p->n < 1 || p->n > 1024 || p->m < static_cast<int64_t>(p->n) + 1 || p->lda < p->n || p->m > (int64_t(1) << 31))
     return fail(ctx, SAP_EINVAL, "sap_submit: bad problem shape (n <= 1024, m >= n + 1)");
   if (q->d < p->n + 1 || q->d > 4096 || q->zeta < 1 || q->zeta > 64 ||
-      q->zeta > q->d || q->maxiter < 0 || !(q->tol >= 0.0))
+      q->zeta > q->d || q->maxiter < 0 || !(q->tol >= 0.0) || q->max_refine < 0)
     return fail(ctx, SAP_EINVAL, "sap_submit: bad parameters");
+  if (q->mode != SAP_MODE_FP64 && q->mode != SAP_MODE_MIXED_FP32 && q->mode != SAP_MODE_MIXED_FP32_REFINE)
+    return fail(ctx, SAP_EINVAL, "sap_submit: mode must be FP64, MIXED_FP32 or MIXED_FP32_REFINE");
+  if (q->mode == SAP_MODE_MIXED_FP32_REFINE && p->a_type != SAP_F32)
+    return fail(ctx, SAP_EINVAL, "sap_submit: the refinement form needs FP32 A");
   const size_t bytes = item_bytes(p->m, p->n, q->d, q->zeta, p->a_type);
   hipEvent_t ready = nullptr;
   SAP_HIP_TRY(hipSetDevice(ctx->device));
@@ -1453,6 +1589,8 @@ sap_status serve_submit(sap_ctx *ctx, const sap_problem *p, const sap_params *q,
   it.h = 1.0 / std::sqrt(static_cast<double>(q->zeta));
   it.seed = q->seed;
   it.stream = 0;  // the sketch sap_solve draws for the same seed
+  it.refine = q->mode == SAP_MODE_MIXED_FP32_REFINE ? 1 : 0;
+  it.max_refine = q->max_refine;
   *ticket = r->ticket;
   S->queued.push_back(r.get());
   S->reqs[r->ticket] = std::move(r);

@@ -146,6 +146,14 @@ struct LsqrState {
   int32_t pad;
   double normref;        // scale of the phibar test: ||b||, or beta_1 when rel
   double normar0;        // ||(A M)^T r|| at the initialisation step (rel runs)
+  // Residual refinement kept on the device (batched and served forms): the
+  // outer loop around the FP32 inner solves.
+  int32_t refine;        // 1: FP32 inner solves, FP64 residual refinement
+  int32_t refinements;   // inner solves finished so far
+  int32_t max_refine;    // cap on the inner solves
+  int32_t final_done;    // the outer loop has stopped (converged or gave up)
+  double target;         // stop when ||x - x_prev|| <= target ||x||
+  double prev_delta;     // the previous correction ||x - x_prev||
 };
 
 }  // namespace sap

@@ -128,3 +128,59 @@ def test_batch_wide_problems_iterations(sap, orc):
         assert io["status"] == "ok"
         assert abs(infos[k]["iters"] - io["iters"]) <= 1, (k, infos[k]["iters"], io["iters"])
         assert np.linalg.norm(p.A @ (x - x_or)) <= 1e-11 * np.linalg.norm(p.b), k
+
+
+def test_batch_refine_form_parity(sap, orc):
+    """The refinement form in the batched form (SAP_MODE_MIXED_FP32_REFINE,
+    tol = 1e-8 target relative correction): FP32 inner passes and u, the FP64
+    residual at each restart, the outer loop on the device, mixed in one
+    batch with problems in FP64 arithmetic (modes alternate).  Against the
+    FP64 oracle on the FP32-rounded A: forward error <= 1e-8 and the paper's
+    metric <= 1e-10 for the refined problems (the mixed-form bars), the FP64
+    bars for the others.  Every refined problem needs at least one restart
+    beyond its first inner solve (its inner solves stop at a 1e-6 reduction)."""
+    import torch
+    print("batch refine form", flush=True)
+    probs = _batch(10, 61, np.float32, m_range=(5000, 60000), n_range=(32, 257), cond_exp=(2, 6))
+    As = [torch.from_numpy(np.ascontiguousarray(p.A)).cuda() for p in probs]
+    bs = [torch.from_numpy(p.b).cuda() for p in probs]
+    ds = [4 * p.A.shape[1] for p in probs]
+    modes = [sap.SAP_MODE_MIXED_FP32_REFINE if k % 2 == 0 else sap.SAP_MODE_MIXED_FP32 for k in range(len(probs))]
+    # tol: target relative correction for the refined problems, LSQR tol for the others
+    xs, st, infos = sap.sap_solve_batch(As, bs, ds, 8, 21, tol=1e-8, maxiter=1000, mode=modes, max_refine=12)
+    torch.cuda.synchronize()
+    xs12, st12, infos12 = sap.sap_solve_batch(As[1::2], bs[1::2], ds[1::2], 8, 21, tol=1e-12, maxiter=300)
+    torch.cuda.synchronize()
+    for k, p in enumerate(probs):
+        A64 = p.A.astype(np.float64)
+        x_or, io = orc.solve(A64, p.b, ds[k], 8, 21, tol=1e-12, maxiter=400, stream=k)
+        assert io["status"] == "ok"
+        nb, nx = np.linalg.norm(p.b), np.linalg.norm(x_or)
+        if modes[k] == sap.SAP_MODE_MIXED_FP32_REFINE:
+            x = xs[k].cpu().numpy()
+            fwd = np.linalg.norm(x - x_or) / nx
+            print(f"  refined k={k} n={p.A.shape[1]} iters={infos[k]['iters']} "
+                  f"refinements={infos[k]['refinements']} forward={fwd:.2e}", flush=True)
+            assert infos[k]["status"] == sap.SAP_OK, infos[k]
+            assert infos[k]["refinements"] >= 2
+            assert fwd <= 1e-8, k
+            assert np.linalg.norm(A64 @ (x - x_or)) <= 1e-10 * nb, k
+        else:
+            # the FP64-arithmetic problems of the mixed batch stop at tol 1e-8
+            # here; their own batch at tol 1e-12 meets the FP64 bars
+            x = xs12[k // 2].cpu().numpy()
+            assert infos12[k // 2]["status"] == sap.SAP_OK
+            assert np.linalg.norm(A64 @ (x - x_or)) <= 1e-11 * nb, k
+            assert np.linalg.norm(x - x_or) <= 1e-8 * nx, k
+
+
+def test_batch_refine_mode_checks(sap):
+    import torch
+    p = inputs.make_problem(4000, 10, kind="colscale", cond=10.0, seed=1)
+    A, b = torch.from_numpy(p.A).cuda(), torch.from_numpy(p.b).cuda()
+    with pytest.raises(sap.SapError) as e:  # the refinement form needs FP32 A
+        sap.sap_solve_batch([A], [b], [40], 8, 1, mode=sap.SAP_MODE_MIXED_FP32_REFINE)
+    assert e.value.status == sap.SAP_EINVAL
+    with pytest.raises(sap.SapError) as e:
+        sap.sap_solve_batch([A.float()], [b], [40], 8, 1, mode=sap.SAP_MODE_MIXED_BF16SA)
+    assert e.value.status == sap.SAP_EINVAL

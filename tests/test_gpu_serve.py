@@ -164,3 +164,46 @@ def test_serve_rank_deficient(sap, ctx):
     assert st == sap.SAP_RANK_DEFICIENT
     st, info, _ = sap.sap_poll(t_ok, wait=True, ctx=ctx)
     assert st == sap.SAP_OK
+
+
+def test_serve_refine_form(sap, orc, ctx):
+    """Served requests in the refinement form (FP32 A, FP32 inner solves,
+    FP64 residual refinement to a 1e-8 relative correction, the outer loop on
+    the device) beside requests in FP64 arithmetic: each refined request
+    meets the mixed-form bars against the FP64 oracle on its FP32-rounded A
+    (forward <= 1e-8, ||A(x - x_or)|| <= 1e-10 ||b||), alone and in the mix
+    alike (alone vs mix within 1e-9)."""
+    print("serve refine form", flush=True)
+    probs = [_problem(80 + k, int(8000 + 9000 * k), int(40 + 37 * k), 10.0 ** (3 + k % 3), np.float32)
+             for k in range(6)]
+    tensors = [(_dev(p.A), _dev(p.b)) for p in probs]
+    ds = [4 * p.A.shape[1] for p in probs]
+    R = sap.SAP_MODE_MIXED_FP32_REFINE
+    t = sap.sap_submit(*tensors[0], ds[0], 8, 200, tol=1e-8, maxiter=1000, mode=R, max_refine=12, ctx=ctx)
+    st, info, x_alone = sap.sap_poll(t, wait=True, ctx=ctx)
+    assert st == sap.SAP_OK, info
+    assert info["refinements"] >= 2
+    x_alone = x_alone.cpu().numpy()
+    tickets = []
+    for k, (A, b) in enumerate(tensors):
+        mode = R if k % 2 == 0 else sap.SAP_MODE_MIXED_FP32
+        tol = 1e-8 if mode == R else 1e-12
+        tickets.append(sap.sap_submit(A, b, ds[k], 8, 200 + k, tol=tol, maxiter=1000, mode=mode, max_refine=12,
+                                      ctx=ctx))
+    for k, tk in enumerate(tickets):
+        st, info, x = sap.sap_poll(tk, wait=True, ctx=ctx)
+        assert st == sap.SAP_OK, (k, info)
+        x = x.cpu().numpy()
+        p = probs[k]
+        if k % 2:
+            _check(orc, p, x, ds[k], 200 + k, f"fp64-arith {k}")
+            continue
+        A64 = p.A.astype(np.float64)
+        x_or, io = orc.solve(A64, p.b, ds[k], 8, 200 + k, tol=1e-12, maxiter=400, stream=0)
+        fwd = np.linalg.norm(x - x_or) / np.linalg.norm(x_or)
+        print(f"  refined k={k} iters={info['iters']} refinements={info['refinements']} forward={fwd:.2e}",
+              flush=True)
+        assert fwd <= 1e-8, k
+        assert np.linalg.norm(A64 @ (x - x_or)) <= 1e-10 * np.linalg.norm(p.b), k
+        if k == 0:
+            assert np.linalg.norm(x - x_alone) <= 1e-9 * np.linalg.norm(x_alone)
