@@ -8,12 +8,16 @@ Prints ONE JSON line.  `value` is solves per second of that workload;
 HIP-event timings taken on its own stream inside the timed region;
 `cpu_baseline` times the CPU oracle on a bounded row sample of the same
 workload and projects it to the full size.  `forms` adds the other three
-forms, each against the plain FP64 form on the same problems:
+forms, each against the plain FP64 form on the same problems at the same
+accuracy (the FP64 form's loosest LSQR tolerance whose results are as close
+to the FP64 reference as the mixed form's):
   * mixed   - one large solve, m = 2^22, n = 4096, d = 2n, A stored in FP32 (FP64
               arithmetic; FP32 refinement; BF16-input sketch with refinement);
-  * batched - 512 uneven FP32 problems in one sap_solve_batch call;
-  * served  - a Poisson request stream (200 req/s) through sap_submit/poll,
-              with p50/p99 latency.
+  * batched - 512 uneven FP32 problems in one sap_solve_batch call, refinement
+              form against the FP64 batched form and FP64 single solves;
+  * served  - a Poisson request stream (200 req/s for 10 s) through
+              sap_submit/poll, refinement form against the FP64 form served
+              the same way, with p50/p99 latency.
 """
 import argparse
 import json
@@ -47,7 +51,9 @@ def parse():
     ap.add_argument("--mixed-n", type=int, default=4096)
     ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--serve-rate", type=float, default=200.0)
-    ap.add_argument("--serve-duration", type=float, default=1.5)
+    ap.add_argument("--serve-duration", type=float, default=10.0)
+    ap.add_argument("--serve-pool", type=int, default=256,
+                    help="distinct problems in the served stream's device-resident pool")
     ap.add_argument("--no-adaptive-d", action="store_true",
                     help="skip the solve at the embedding dimension of eq. (4.2)")
     ap.add_argument("--gaussian-input", action="store_true",
@@ -175,22 +181,40 @@ def apply_bytes(m, n, d, zeta, esize, ysize):
     return m * n * esize + m * 8 + m * (zeta * 4 + 8) + d * (n + 1) * ysize
 
 
+# Target relative error of the mixed-precision forms, and the LSQR tolerances
+# tried for the FP64 form when matching that accuracy (the loosest one whose
+# results are as accurate is the comparison point).
+TARGET_REL_ERR = 1e-8
+FP64_MATCH_TOLS = (1e-8, 1e-10)
+
+
+def pick_matching(runs, bound):
+    """The first run (loosest tolerance first) whose max relative error is
+    within `bound`, else the last (tightest) one."""
+    for r in runs:
+        if r["rel_err_max"] <= bound:
+            return r
+    return runs[-1]
+
+
 def form_mixed(args, sap, torch, inputs):
-    """Mixed form (A stored FP32, FP64 arithmetic in the passes) against the
-    FP64 form on the same matrix (its exact FP64 copy)."""
+    """Mixed forms on one large matrix (A stored FP32) against the FP64 form
+    on its exact FP64 copy.  Accuracy of every result is measured against the
+    FP64 form at tol 1e-12; the FP64 form is also run at looser tolerances and
+    the loosest one that is as accurate as the refinement form is the
+    same-accuracy comparison."""
     m, n = args.mixed_m, args.mixed_n
     log(f"bench[mixed]: generating m={m} n={n} FP32 A")
     A32, b, _, meta = inputs.config2_torch("cuda", m=m, n=n)
     d, zeta, seed, tol, maxiter = meta["d"], meta["zeta"], meta["sketch_seed"], meta["tol"], meta["maxiter"]
     ctx = sap.default_context(0)
-    x32 = torch.empty(n, dtype=torch.float64, device="cuda")
-    x64 = torch.empty(n, dtype=torch.float64, device="cuda")
 
-    def timed(A, x, mode, tol_=None):
-        tol_ = tol if tol_ is None else tol_
+    def timed(A, mode, tol_, warm=True):
+        x = torch.empty(n, dtype=torch.float64, device="cuda")
         mx = maxiter if mode not in (sap.SAP_MODE_MIXED_FP32_REFINE, sap.SAP_MODE_MIXED_BF16SA) else 4 * maxiter
-        sap.sap_solve(A, b, d, zeta, seed, tol=tol_, maxiter=mx, x=x, mode=mode)  # warm-up
-        torch.cuda.synchronize()
+        if warm:
+            sap.sap_solve(A, b, d, zeta, seed, tol=tol_, maxiter=mx, x=x, mode=mode)
+            torch.cuda.synchronize()
         ctx.profile(True)
         ctx.profile_read(sap.PROF_PASS, reset=True)
         ctx.profile_read(sap.PROF_APPLY, reset=True)
@@ -204,44 +228,61 @@ def form_mixed(args, sap, torch, inputs):
         es = A.element_size()
         pb = pass_bytes(m, n, es)
         ab = apply_bytes(m, n, d, zeta, 2 if mode == sap.SAP_MODE_MIXED_BF16SA else es, 8)
-        return dict(solve_ms=dt * 1e3, status=r.info["status_name"], iters=r.info["iters"],
-                    refinements=r.info["refinements"], tol=tol_,
-                    phases_ms={"generate": r.info["t_generate_ms"], "apply": r.info["t_apply_ms"],
-                               "qr": r.info["t_qr_ms"], "iterate": r.info["t_iterate_ms"]},
-                    pass_gbs=pb / (mspass / max(1, min(npass, r.info["iters"] + max(1, r.info["refinements"])))
-                                   * 1e-3) / 1e9,
-                    sa_gbs=ab / (msap / max(1, nap) * 1e-3) / 1e9)
+        return x, dict(solve_ms=dt * 1e3, status=r.info["status_name"], iters=r.info["iters"],
+                       refinements=r.info["refinements"], tol=tol_,
+                       phases_ms={"generate": r.info["t_generate_ms"], "apply": r.info["t_apply_ms"],
+                                  "qr": r.info["t_qr_ms"], "iterate": r.info["t_iterate_ms"]},
+                       pass_gbs=pb / (mspass / max(1, min(npass, r.info["iters"] + max(1, r.info["refinements"])))
+                                      * 1e-3) / 1e9,
+                       sa_gbs=ab / (msap / max(1, nap) * 1e-3) / 1e9)
 
-    log("bench[mixed]: FP32-storage solve")
-    rm = timed(A32, x32, sap.SAP_MODE_MIXED_FP32)
+    log("bench[mixed]: FP32-storage solve (FP64 arithmetic)")
+    xm, rm = timed(A32, sap.SAP_MODE_MIXED_FP32, tol)
     log(f"bench[mixed]: {rm}")
     log("bench[mixed]: FP32 refinement form to a 1e-8 relative correction")
-    xr = torch.empty(n, dtype=torch.float64, device="cuda")
-    rr = timed(A32, xr, sap.SAP_MODE_MIXED_FP32_REFINE, tol_=1e-8)
+    xr, rr = timed(A32, sap.SAP_MODE_MIXED_FP32_REFINE, TARGET_REL_ERR)
     log(f"bench[mixed]: refine {rr}")
-    log("bench[mixed]: BF16-input sketch with the refinement form, to a 1e-8 relative correction")
-    xb = torch.empty(n, dtype=torch.float64, device="cuda")
-    rb = timed(A32, xb, sap.SAP_MODE_MIXED_BF16SA, tol_=1e-8)
+    log("bench[mixed]: BF16-input sketch with the refinement form")
+    xb, rb = timed(A32, sap.SAP_MODE_MIXED_BF16SA, TARGET_REL_ERR)
     log(f"bench[mixed]: bf16sa {rb}")
     log("bench[mixed]: widening A to FP64 for the FP64 form")
     A64 = widen(A32)
     del A32
     torch.cuda.empty_cache()
-    r64 = timed(A64, x64, sap.SAP_MODE_FP64)
-    log(f"bench[mixed]: fp64 {r64}")
+    x64, r64 = timed(A64, sap.SAP_MODE_FP64, tol)
+    log(f"bench[mixed]: fp64 tol {tol:g} {r64}")
+    fp64_runs = []
+    for t in FP64_MATCH_TOLS:
+        xt, rt = timed(A64, sap.SAP_MODE_FP64, t, warm=False)
+        rt["rel_err_max"] = rel(xt, x64)
+        fp64_runs.append(rt)
+        log(f"bench[mixed]: fp64 tol {t:g} {rt}")
     del A64
     torch.cuda.empty_cache()
+    for r_, x_ in ((rm, xm), (rr, xr), (rb, xb)):
+        r_["rel_err_vs_fp64"] = rel(x_, x64)
+    match = pick_matching(fp64_runs, max(TARGET_REL_ERR, rr["rel_err_vs_fp64"]))
     return {"workload": f"m={m} n={n} d={d} zeta={zeta}, A_ij = g_ij 10^(-6 j/(n-1)) stored FP32, "
-                        f"b = A x + 1e-8 noise, tol {tol}",
-            "mixed": rm, "fp64": r64, "speedup": r64["solve_ms"] / rm["solve_ms"],
-            "rel_diff_x": rel(x32, x64),
-            "refine": rr, "refine_speedup": r64["solve_ms"] / rr["solve_ms"], "refine_rel_diff_x": rel(xr, x64),
-            "bf16sa": rb, "bf16sa_speedup": r64["solve_ms"] / rb["solve_ms"], "bf16sa_rel_diff_x": rel(xb, x64)}
+                        f"b = A x + 1e-8 noise; errors relative to the FP64 form at tol {tol:g}",
+            "mixed": rm, "refine": rr, "bf16sa": rb, "fp64": r64, "fp64_looser": fp64_runs,
+            "fp64_same_accuracy": {"tol": match["tol"], "solve_ms": match["solve_ms"],
+                                   "rel_err": match["rel_err_max"]},
+            "speedup_mixed_vs_fp64_same_tol": r64["solve_ms"] / rm["solve_ms"],
+            "refine_speedup_same_accuracy": match["solve_ms"] / rr["solve_ms"],
+            "bf16sa_speedup_same_accuracy": match["solve_ms"] / rb["solve_ms"]}
+
+
+def _batch_errs(xs, xref):
+    e = sorted(rel(a, b) for a, b in zip(xs, xref))
+    return {"rel_err_median": e[len(e) // 2], "rel_err_max": e[-1]}
 
 
 def form_batched(args, sap, torch, inputs):
-    """Batched form over uneven FP32 problems against one-at-a-time FP64
-    solves of the same problems."""
+    """Batched form over uneven FP32 problems: the refinement form (FP32 inner
+    passes, FP64 residual, to a 1e-8 relative correction) against the FP64
+    form (FP64 copies of the matrices, FP64 arithmetic) in the same batched
+    machinery and as one-at-a-time single solves, at the same accuracy.
+    Errors are relative to the FP64 batched form at tol 1e-12."""
     shapes = inputs.batch_shapes(count=args.batch_count)
     log(f"bench[batched]: generating {len(shapes)} problems")
     As, bs = [], []
@@ -253,102 +294,161 @@ def form_batched(args, sap, torch, inputs):
     ds = [s["d"] for s in shapes]
     seeds = [s["seed"] + 1 for s in shapes]
     tot_bytes = sum(A.numel() * 4 for A in As)
-    sap.sap_solve_batch(As, bs, ds, 8, seeds, tol=1e-12, maxiter=300)  # warm-up and autotune
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    xs, st, infos = sap.sap_solve_batch(As, bs, ds, 8, seeds, tol=1e-12, maxiter=300)
-    torch.cuda.synchronize()
-    t_batch = time.perf_counter() - t0
-    n_ok = sum(1 for i in infos if i["status"] == sap.SAP_OK)
-    log(f"bench[batched]: {len(As)} problems in {t_batch * 1e3:.1f} ms ({n_ok} converged)")
-    # FP64 form, one solve after another on exact FP64 copies
     A64s = [A.to(torch.float64) for A in As]
+    torch.cuda.synchronize()
+
+    def run_batch(Alist, mode, tol, maxiter):
+        sap.sap_solve_batch(Alist, bs, ds, 8, seeds, tol=tol, maxiter=maxiter, mode=mode, max_refine=12)  # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        xs, st, infos = sap.sap_solve_batch(Alist, bs, ds, 8, seeds, tol=tol, maxiter=maxiter, mode=mode,
+                                            max_refine=12)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        ok = sum(1 for i in infos if i["status"] == sap.SAP_OK)
+        its = sorted(i["iters"] for i in infos)
+        return xs, {"ms": dt * 1e3, "solves_per_s": len(Alist) / dt, "converged": ok, "tol": tol,
+                    "iters_median": its[len(its) // 2]}
+
+    log("bench[batched]: FP64 reference (FP64 batched form, tol 1e-12)")
+    xref, rref = run_batch(A64s, sap.SAP_MODE_FP64, 1e-12, 300)
+    log("bench[batched]: refinement form")
+    xmix, rmix = run_batch(As, sap.SAP_MODE_MIXED_FP32_REFINE, TARGET_REL_ERR, 1000)
+    rmix.update(_batch_errs(xmix, xref))
+    log(f"bench[batched]: refine {rmix}")
+    fp64_runs = []
+    for t in FP64_MATCH_TOLS:
+        xt, rt = run_batch(A64s, sap.SAP_MODE_FP64, t, 300)
+        rt.update(_batch_errs(xt, xref))
+        fp64_runs.append(rt)
+        log(f"bench[batched]: fp64 tol {t:g} {rt}")
+    match = pick_matching(fp64_runs, max(TARGET_REL_ERR, rmix["rel_err_max"]))
+    # the FP64 form one solve after another, at the matching tolerance
     x64s = [torch.empty(A.shape[1], dtype=torch.float64, device="cuda") for A in As]
-    sap.sap_solve(A64s[0], bs[0], ds[0], 8, seeds[0], tol=1e-12, maxiter=300, x=x64s[0])
+    sap.sap_solve(A64s[0], bs[0], ds[0], 8, seeds[0], tol=match["tol"], maxiter=300, x=x64s[0])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(len(As)):
-        sap.sap_solve(A64s[k], bs[k], ds[k], 8, seeds[k], tol=1e-12, maxiter=300, x=x64s[k])
+        sap.sap_solve(A64s[k], bs[k], ds[k], 8, seeds[k], tol=match["tol"], maxiter=300, x=x64s[k])
     torch.cuda.synchronize()
     t_seq = time.perf_counter() - t0
-    diffs = sorted(rel(xs[k], x64s[k]) for k in range(len(As)))
+    seq = {"ms": t_seq * 1e3, "solves_per_s": len(As) / t_seq, "tol": match["tol"]}
+    seq.update(_batch_errs(x64s, xref))
     del A64s, As
     torch.cuda.empty_cache()
     return {"workload": f"{len(shapes)} problems, m ~ U[5000, 200000], n ~ U{{32..256}}, d = 4n, zeta = 8, "
-                        "FP32 A (column scales, cond log-uniform in [1e2, 1e8]), tol 1e-12",
-            "a_bytes": tot_bytes, "batch_ms": t_batch * 1e3, "solves_per_s": len(shapes) / t_batch,
-            "converged": n_ok, "fp64_sequential_ms": t_seq * 1e3, "fp64_solves_per_s": len(shapes) / t_seq,
-            "speedup": t_seq / t_batch, "rel_diff_x_median": diffs[len(diffs) // 2], "rel_diff_x_max": diffs[-1]}
+                        "FP32 A (column scales, cond log-uniform in [1e2, 1e8]), b = A x + 1e-8 noise; "
+                        "errors relative to the FP64 batched form at tol 1e-12",
+            "a_bytes": tot_bytes, "refine": rmix, "fp64_reference": rref, "fp64_batched": fp64_runs,
+            "fp64_sequential_same_accuracy": seq,
+            "speedup_vs_fp64_batched_same_accuracy": match["ms"] / rmix["ms"],
+            "speedup_vs_fp64_sequential_same_accuracy": seq["ms"] / rmix["ms"]}
 
 
-def form_served(args, sap, torch, inputs):
-    """Served form: requests arrive as a Poisson stream and are submitted at
-    their arrival times; latency = submit to finished.  The FP64 form serves
-    the same stream one solve at a time, first come first served."""
+def served_run(sap, torch, reqs, probs, bs_req, mode, tol, maxiter, tag):
+    """Submit the stream at its arrival times through sap_submit on a fresh
+    context; latency = submit to finished (the library's own clock)."""
     import numpy as np
-    reqs = inputs.served_stream(rate=args.serve_rate, duration=args.serve_duration)
-    log(f"bench[served]: generating {len(reqs)} requests")
-    probs = []
-    for k, r in enumerate(reqs):
-        A, b, _ = inputs.make_problem_torch(r["m"], r["n"], kind="colscale", cond=1e6, noise=1e-8,
-                                            seed=inputs.config_seed(4) + 13 * k, device="cuda",
-                                            dtype=torch.float32)
-        probs.append((A, b))
-    torch.cuda.synchronize()
     ctx = sap.Context(0)
-    # warm-up request (not counted)
-    t = sap.sap_submit(probs[0][0], probs[0][1], reqs[0]["d"], 8, 1, tol=1e-12, maxiter=300, ctx=ctx)
-    sap.sap_poll(t, wait=True, ctx=ctx)
+    A0, _ = probs[reqs[0]["pool"]]
+    t = sap.sap_submit(A0, bs_req[0], reqs[0]["d"], 8, 1, tol=tol, maxiter=maxiter, mode=mode, max_refine=12,
+                       ctx=ctx)
+    sap.sap_poll(t, wait=True, ctx=ctx)  # warm-up request (not counted)
     tickets = []
     t_start = time.perf_counter()
     for k, r in enumerate(reqs):
         delay = t_start + r["t"] - time.perf_counter()
         if delay > 0:
             time.sleep(delay)
-        A, b = probs[k]
-        tickets.append(sap.sap_submit(A, b, r["d"], 8, 101 + k, tol=1e-12, maxiter=300, ctx=ctx))
-    lat, xs, statuses = [], [], []
+        A, _ = probs[r["pool"]]
+        tickets.append(sap.sap_submit(A, bs_req[k], r["d"], 8, 101 + k, tol=tol, maxiter=maxiter, mode=mode,
+                                      max_refine=12, ctx=ctx))
+    lat, xs, ok = [], [], 0
     for t in tickets:
         st, info, x = sap.sap_poll(t, wait=True, ctx=ctx)
         lat.append(info["t_total_ms"])
         xs.append(x)
-        statuses.append(st)
+        ok += st == sap.SAP_OK
     t_end = time.perf_counter()
     stats = sap.sap_serve_stats(ctx)
     ctx.close()
-    log(f"bench[served]: {len(reqs)} requests served in {t_end - t_start:.2f} s")
-    # FP64 form, first come first served: solve durations measured back to
-    # back, queueing replayed against the same arrival times
-    A64s = [A.to(torch.float64) for A, _ in probs]
-    x64s = []
-    finish = 0.0
-    lat64 = []
-    for k, r in enumerate(reqs):
-        x64 = torch.empty(r["n"], dtype=torch.float64, device="cuda")
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        sap.sap_solve(A64s[k], probs[k][1], r["d"], 8, 101 + k, tol=1e-12, maxiter=300, x=x64)
-        torch.cuda.synchronize()
-        dur = time.perf_counter() - t0
-        start = max(r["t"], finish)
-        finish = start + dur
-        lat64.append((finish - r["t"]) * 1e3)
-        x64s.append(x64)
-    diffs = sorted(rel(xs[k], x64s[k]) for k in range(len(reqs)))
-    del A64s, probs
+    lat = np.asarray(lat)
+    log(f"bench[served]: {tag}: {len(reqs)} requests in {t_end - t_start:.2f} s")
+    return xs, {"tol": tol, "ok": int(ok), "p50_ms": float(np.percentile(lat, 50)),
+                "p99_ms": float(np.percentile(lat, 99)), "mean_ms": float(lat.mean()),
+                "solves_per_s": len(reqs) / (t_end - t_start), "wall_s": t_end - t_start, "serve_stats": stats}
+
+
+def form_served(args, sap, torch, inputs):
+    """Served form: a Poisson request stream over a device-resident pool of
+    problems (each request one pool matrix with its own right-hand side),
+    submitted at the arrival times.  The refinement form (FP32 A) and the FP64
+    form (FP64 copies of the pool, FP64 arithmetic, served the same way at
+    the tolerance that matches the refinement form's accuracy on a sample)
+    serve the same stream; accuracy is measured on a sample of requests
+    against single FP64 solves at tol 1e-12."""
+    import numpy as np
+    reqs = inputs.served_stream(rate=args.serve_rate, duration=args.serve_duration)
+    pool_shapes = inputs.served_stream(rate=1.0, duration=float(args.serve_pool) * 1.5,
+                                       seed=inputs.config_seed(4) + 1)[:args.serve_pool]
+    log(f"bench[served]: {len(reqs)} requests over a pool of {len(pool_shapes)} problems")
+    probs = []
+    for k, r in enumerate(pool_shapes):
+        A, _, _ = inputs.make_problem_torch(r["m"], r["n"], kind="colscale", cond=1e6, noise=1e-8,
+                                            seed=inputs.config_seed(4) + 13 * k, device="cuda", dtype=torch.float32)
+        probs.append((A, r["n"]))
+    probs64 = [(A.to(torch.float64), n) for A, n in probs]
+    rng = np.random.default_rng(inputs.config_seed(4) + 2)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(inputs.config_seed(4) + 3)
+    bs_req = []
+    for r in reqs:  # b = A x_true + 1e-8 noise, one x_true per request
+        r["pool"] = int(rng.integers(len(probs)))
+        A64, n = probs64[r["pool"]]
+        r["d"] = 4 * n
+        xt = torch.randn(n, generator=g, device="cuda", dtype=torch.float64)
+        bb = A64 @ xt
+        bb += 1e-8 * (bb.norm() / np.sqrt(A64.shape[0])) * torch.randn(A64.shape[0], generator=g, device="cuda",
+                                                                        dtype=torch.float64)
+        bs_req.append(bb)
+    torch.cuda.synchronize()
+    # accuracy sample: single FP64 solves at tol 1e-12 of the first requests
+    ns = min(48, len(reqs))
+    xref = []
+    for k in range(ns):
+        r = reqs[k]
+        xref.append(sap.sap_solve(probs64[r["pool"]][0], bs_req[k], r["d"], 8, 101 + k, tol=1e-12,
+                                  maxiter=300).x.clone())
+    # the FP64 tolerance matching the refinement form on the sample (batched solves of the sample)
+    sA = [probs[reqs[k]["pool"]][0] for k in range(ns)]
+    sA64 = [probs64[reqs[k]["pool"]][0] for k in range(ns)]
+    sds = [reqs[k]["d"] for k in range(ns)]
+    sseeds = [101 + k for k in range(ns)]
+    xs_r, _, _ = sap.sap_solve_batch(sA, bs_req[:ns], sds, 8, sseeds, tol=TARGET_REL_ERR, maxiter=1000,
+                                     mode=sap.SAP_MODE_MIXED_FP32_REFINE, max_refine=12)
+    err_r = max(rel(a, b) for a, b in zip(xs_r, xref))
+    tol64 = FP64_MATCH_TOLS[-1]
+    for t in FP64_MATCH_TOLS:
+        xs_t, _, _ = sap.sap_solve_batch(sA64, bs_req[:ns], sds, 8, sseeds, tol=t, maxiter=300)
+        if max(rel(a, b) for a, b in zip(xs_t, xref)) <= max(TARGET_REL_ERR, err_r):
+            tol64 = t
+            break
+    torch.cuda.synchronize()
+    log(f"bench[served]: FP64 tolerance matching the refinement form's accuracy: {tol64:g}")
+    xm, rm = served_run(sap, torch, reqs, probs, bs_req, sap.SAP_MODE_MIXED_FP32_REFINE, TARGET_REL_ERR, 1000,
+                        "refine")
+    rm.update(_batch_errs(xm[:ns], xref))
+    x64, r64 = served_run(sap, torch, reqs, probs64, bs_req, sap.SAP_MODE_FP64, tol64, 300, "fp64")
+    r64.update(_batch_errs(x64[:ns], xref))
+    del probs64, probs, bs_req
     torch.cuda.empty_cache()
-
-    def pct(v, q):
-        return float(np.percentile(np.asarray(v), q))
-
-    return {"workload": f"{len(reqs)} requests, Poisson {args.serve_rate:g} req/s, m ~ lognormal(median 1e5, "
-                        "sigma 1) clamped to [8n, 2^21], n in {64,128,256,512}, d = 4n, zeta = 8, FP32 A "
-                        "(column scales, cond 1e6), tol 1e-12",
-            "requests": len(reqs), "ok": sum(1 for s in statuses if s == sap.SAP_OK),
-            "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99), "solves_per_s": len(reqs) / (t_end - t_start),
-            "fp64_fcfs_p50_ms": pct(lat64, 50), "fp64_fcfs_p99_ms": pct(lat64, 99),
-            "fp64_fcfs_solves_per_s": len(reqs) / finish if finish > 0 else None,
-            "rel_diff_x_max": diffs[-1], "serve_stats": stats}
+    return {"workload": f"{len(reqs)} requests, Poisson {args.serve_rate:g} req/s for {args.serve_duration:g} s, "
+                        f"each one of a pool of {len(pool_shapes)} problems with its own b: m ~ lognormal(median "
+                        "1e5, sigma 1) clamped to [8n, 2^21], n in {64,128,256,512}, d = 4n, zeta = 8, FP32 A "
+                        f"(column scales, cond 1e6); accuracy on the first {ns} requests against FP64 solves at "
+                        "tol 1e-12",
+            "requests": len(reqs), "refine": rm, "fp64": r64,
+            "p99_speedup": r64["p99_ms"] / rm["p99_ms"], "p50_speedup": r64["p50_ms"] / rm["p50_ms"]}
 
 
 def adaptive_d(sap, torch, A, b, x, m, n, d, zeta, seed, tol, maxiter, pass_ms, qr_ms, fixed_ms, fixed_iters):
