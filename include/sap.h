@@ -192,13 +192,21 @@ typedef struct sap_problem {
 } sap_problem;
 
 typedef struct sap_params {
-    int32_t d;          /* embedding dimension, n + 1 <= d (paper: d = O(n)) */
+    int32_t d;          /* embedding dimension, n + 1 <= d (paper: d = O(n));
+                           0 = choose (Sec. 4.3): sap_solve takes sap_choose_d's
+                           pick, the batched and served forms eq. (4.2)'s d
+                           (cost ratio 1) capped at their d limit */
     int32_t zeta;       /* sketch nonzeros per column, 1..min(d, 64) */
     uint64_t seed;      /* sketch seed (stream word is 0 for sap_solve) */
     double tol;         /* LSQR stopping tolerance (see below), e.g. 1e-12 */
     int32_t maxiter;    /* LSQR iteration cap (summed over refinements) */
     int32_t mode;       /* sap_mode */
     int32_t max_refine; /* MIXED_FP32_REFINE: outer steps cap (0 = 10) */
+    int32_t fixed_iters; /* 0: stop on the test below.  > 0: run exactly this
+                           many iterations (fewer only on breakdown) and report
+                           SAP_OK; < 0: run the eq. (4.1) count for tol,
+                           ceil(2 log(tol) / log(n/d)) (the fixed-count mode of
+                           Sec. 4.2).  FP64 and MIXED_FP32 modes only. */
 } sap_params;
 
 typedef struct sap_info {
@@ -210,6 +218,8 @@ typedef struct sap_info {
     double t_generate_ms, t_apply_ms, t_qr_ms, t_iterate_ms; /* phase times */
     double t_queue_ms;   /* served form: submit -> admission */
     double t_total_ms;   /* served form: submit -> finished */
+    int32_t d_used;      /* the embedding dimension the solve used */
+    int32_t pad_;
 } sap_info;
 
 /* Solve min ||b - A x|| by Alg. 1 with a sparse sign sketch and LSQR (Alg. 2)
@@ -328,6 +338,25 @@ sap_status sap_embedding_dim(int64_t m, int32_t n, double eps, double cost_ratio
  * eq. (4.1), (n/d)^(t/2), reaches eps: t = ceil(2 log eps / log(n/d)).
  * Errors: SAP_EINVAL (iters null, n < 1, d <= n, eps outside (0, 1)). */
 sap_status sap_iteration_estimate(int32_t n, int32_t d, double eps, int32_t *iters);
+
+/* Machine-aware embedding dimension for one problem (device work and a
+ * context, unlike the two calls above; Sec. 4.3 weighs the QR
+ * against the iterations; here every phase is timed on this GPU).  Among the
+ * candidates d = k n (k = 1.25, 1.5, 2, 2.5, 3, 4, 5, 6, 8, 10, 12) and
+ * eq. (4.2)'s d, clipped to [n + 1, min(m, 16384)], it returns the one that
+ * minimises apply(d) + qr(d) + (t(d) + 1) (a m + f): t(d) the eq. (4.1)
+ * iteration estimate for eps, apply(d) the sketch apply timed on the first
+ * min(m, 65536) rows of the caller's A and scaled to m, qr(d) the QR of that
+ * d x (n + 1) sketch, and a m + f the cost of one LSQR iteration fitted from
+ * iterations timed on that slab and on half of it.  The timings are taken
+ * once per context for each (n, dtype, zeta, candidate d) and cached; the
+ * first call for a width costs roughly a few QRs.  Problems with m < 4096
+ * get eq. (4.2)'s d.  Blocking on `stream`; uses the context workspace.
+ * Errors: SAP_EINVAL (problem, zeta, eps outside (0, 1)), SAP_ENOMEM,
+ * SAP_EDEVICE. */
+sap_status sap_choose_d(sap_ctx *ctx, const sap_problem *prob, int32_t zeta, double eps, int32_t *d,
+                        void *stream);
+
 
 /* ------------------------------------------------------------------------
  * Kernel timing (measurement support).  When enabled, the library brackets

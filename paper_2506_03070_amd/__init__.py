@@ -23,7 +23,7 @@ SAP_MODE_FP64, SAP_MODE_MIXED_FP32, SAP_MODE_MIXED_FP32_REFINE, SAP_MODE_MIXED_B
 EXPORTS = ["sap_create", "sap_destroy", "sap_last_error", "sap_status_string", "sps_generate",
            "sps_apply", "sps_apply_noalloc", "sap_qr", "sap_trsv", "sap_solve", "sap_lsqr", "sap_profile_enable",
            "sap_profile_read", "sap_solve_batch", "sap_serve_start", "sap_submit", "sap_poll",
-           "sap_cancel", "sap_serve_stats", "sap_embedding_dim", "sap_iteration_estimate"]
+           "sap_cancel", "sap_serve_stats", "sap_embedding_dim", "sap_iteration_estimate", "sap_choose_d"]
 PROF_PASS, PROF_APPLY = 0, 1
 
 _vp = ctypes.c_void_p
@@ -44,13 +44,13 @@ class SapProblem(ctypes.Structure):
 
 class SapParams(ctypes.Structure):
     _fields_ = [("d", _i32), ("zeta", _i32), ("seed", _u64), ("tol", _f64), ("maxiter", _i32),
-                ("mode", _i32), ("max_refine", _i32)]
+                ("mode", _i32), ("max_refine", _i32), ("fixed_iters", _i32)]
 
 
 class SapInfo(ctypes.Structure):
     _fields_ = [("status", _i32), ("iters", _i32), ("refinements", _i32), ("resid_est", _f64), ("normar_est", _f64), ("t_generate_ms", _f64),
                 ("t_apply_ms", _f64), ("t_qr_ms", _f64), ("t_iterate_ms", _f64),
-                ("t_queue_ms", _f64), ("t_total_ms", _f64)]
+                ("t_queue_ms", _f64), ("t_total_ms", _f64), ("d_used", _i32), ("pad_", _i32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_} | {
@@ -121,6 +121,8 @@ def lib():
         L.sap_embedding_dim.restype = ctypes.c_int
         L.sap_iteration_estimate.argtypes = [_i32, _i32, _f64, ctypes.POINTER(_i32)]
         L.sap_iteration_estimate.restype = ctypes.c_int
+        L.sap_choose_d.argtypes = [_vp, ctypes.POINTER(SapProblem), _i32, _f64, ctypes.POINTER(_i32), _vp]
+        L.sap_choose_d.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -297,14 +299,15 @@ class SolveResult:
 
 
 def sap_solve(A, b, d, zeta=8, seed=1, tol=1e-12, maxiter=200, mode=None, ctx=None, x=None,
-              allow_not_converged=True, max_refine=0):
-    """min ||b - A x|| by sketch-and-precondition (Alg. 1) with LSQR (Alg. 2)."""
+              allow_not_converged=True, max_refine=0, fixed_iters=0):
+    """min ||b - A x|| by sketch-and-precondition (Alg. 1) with LSQR (Alg. 2).
+    d = 0 chooses d (sap_choose_d); fixed_iters as in sap_params."""
     torch = _torch()
     ctx = ctx or default_context()
     if mode is None:
         mode = SAP_MODE_FP64 if A.dtype == torch.float64 else SAP_MODE_MIXED_FP32
     prob = _problem(A, b)
-    par = SapParams(d, zeta, seed, tol, maxiter, mode, max_refine)
+    par = SapParams(d, zeta, seed, tol, maxiter, mode, max_refine, fixed_iters)
     x = x if x is not None else torch.empty(A.shape[1], dtype=torch.float64, device=A.device)
     info = SapInfo()
     st = lib().sap_solve(ctx.handle, ctypes.byref(prob), ctypes.byref(par), _dev(x, torch.float64, "x"),
@@ -329,7 +332,7 @@ def sap_lsqr(A, b, Rt, x0, tol=1e-12, maxiter=200, ctx=None, x=None):
 
 
 def sap_solve_batch(As, bs, ds, zetas=8, seeds=1, tol=1e-12, maxiter=200, ctx=None, xs=None, mode=0,
-                    max_refine=0):
+                    max_refine=0, fixed_iters=0):
     """Solve many independent problems together (sap_solve_batch).  As, bs:
     lists of device tensors (A row-major, F32 or F64; b F64).  Returns
     (xs, statuses, infos)."""
@@ -341,7 +344,8 @@ def sap_solve_batch(As, bs, ds, zetas=8, seeds=1, tol=1e-12, maxiter=200, ctx=No
     ds = ds if isinstance(ds, (list, tuple)) else [ds] * count
     probs = (SapProblem * count)(*[_problem(A, b) for A, b in zip(As, bs)])
     modes = mode if isinstance(mode, (list, tuple)) else [mode] * count
-    pars = (SapParams * count)(*[SapParams(int(d), int(z), int(s), tol, maxiter, int(md), int(max_refine))
+    pars = (SapParams * count)(*[SapParams(int(d), int(z), int(s), tol, maxiter, int(md), int(max_refine),
+                                           int(fixed_iters))
                                  for d, z, s, md in zip(ds, zetas, seeds, modes)])
     xs = xs or [torch.empty(A.shape[1], dtype=torch.float64, device=A.device) for A in As]
     xptrs = (_vp * count)(*[_vp(_dev(xx, torch.float64, "x")) for xx in xs])
@@ -362,14 +366,16 @@ def sap_serve_start(arena_bytes=0, max_active=1024, ctx=None):
     ctx.check(lib().sap_serve_start(ctx.handle, int(arena_bytes), int(max_active)))
 
 
-def sap_submit(A, b, d, zeta=8, seed=1, tol=1e-12, maxiter=200, ctx=None, x=None, mode=0, max_refine=0):
+def sap_submit(A, b, d, zeta=8, seed=1, tol=1e-12, maxiter=200, ctx=None, x=None, mode=0, max_refine=0,
+               fixed_iters=0):
     """Queue one problem (sap_submit).  Returns the ticket; the tensors stay
     referenced here until sap_poll reports a terminal status."""
     torch = _torch()
     ctx = ctx or default_context()
     x = x if x is not None else torch.empty(A.shape[1], dtype=torch.float64, device=A.device)
     prob = _problem(A, b)
-    par = SapParams(int(d), int(zeta), int(seed), float(tol), int(maxiter), int(mode), int(max_refine))
+    par = SapParams(int(d), int(zeta), int(seed), float(tol), int(maxiter), int(mode), int(max_refine),
+                    int(fixed_iters))
     ticket = _u64(0)
     st = lib().sap_submit(ctx.handle, ctypes.byref(prob), ctypes.byref(par), _vp(_dev(x, torch.float64, "x")),
                           ctypes.byref(ticket), _vp(_stream()))
@@ -411,6 +417,16 @@ def sap_embedding_dim(m, n, eps, cost_ratio=1.0):
     st = lib().sap_embedding_dim(int(m), int(n), float(eps), float(cost_ratio), ctypes.byref(d))
     if st != SAP_OK:
         raise SapError(st, "sap_embedding_dim: invalid arguments")
+    return d.value
+
+
+def sap_choose_d(A, b, zeta=8, eps=1e-12, ctx=None):
+    """Machine-aware embedding dimension for the problem (A, b) (sap_choose_d)."""
+    ctx = ctx or default_context()
+    d = _i32(0)
+    prob = _problem(A, b)
+    ctx.check(lib().sap_choose_d(ctx.handle, ctypes.byref(prob), int(zeta), float(eps), ctypes.byref(d),
+                                 _vp(_stream())))
     return d.value
 
 

@@ -196,6 +196,7 @@ sap_status sap_create(sap_ctx **out, int device, size_t hbm_budget) {
 void sap_destroy(sap_ctx *ctx) {
   if (!ctx) return;
   serve_destroy(ctx);
+  select_cache_free(ctx);
   (void)hipSetDevice(ctx->device);
   (void)hipDeviceSynchronize();
   prof_resolve(ctx);
@@ -365,14 +366,25 @@ sap_status sap_solve_batch(sap_ctx *ctx, int32_t count, const sap_problem *probs
   return run_batch(ctx, count, probs, params, x, info, static_cast<hipStream_t>(stream));
 }
 
-sap_status sap_solve(sap_ctx *ctx, const sap_problem *prob, const sap_params *par, double *x, sap_info *info,
+sap_status sap_solve(sap_ctx *ctx, const sap_problem *prob, const sap_params *par_in, double *x, sap_info *info,
                      void *stream) {
   if (!ctx) return SAP_EINVAL;
   sap_status s = check_problem(ctx, prob);
   if (s != SAP_OK) return s;
-  if (!par || !x) return fail(ctx, SAP_EINVAL, "sap_solve: NULL params or x");
+  if (!par_in || !x) return fail(ctx, SAP_EINVAL, "sap_solve: NULL params or x");
+  sap_params pv = *par_in;
+  const sap_params *par = &pv;
   const int64_t m = prob->m;
-  const int n = prob->n, d = par->d, nc = n + 1;
+  const int n = prob->n, nc = n + 1;
+  if (pv.d == 0) {  // choose d for this problem (Sec. 4.3)
+    if (!(pv.tol > 0.0 && pv.tol < 1.0)) return fail(ctx, SAP_EINVAL, "sap_solve: d = 0 needs tol in (0, 1)");
+    if (pv.zeta < 1 || pv.zeta > 64) return fail(ctx, SAP_EINVAL, "sap_solve: zeta must be in [1, 64]");
+    if (prob->a_type != SAP_F64 && prob->a_type != SAP_F32) return fail(ctx, SAP_EINVAL, "sap_solve: bad A dtype");
+    SAP_HIP_TRY(hipSetDevice(ctx->device));
+    s = choose_d(ctx, prob, pv.zeta, pv.tol, &pv.d, static_cast<hipStream_t>(stream));
+    if (s != SAP_OK) return s;
+  }
+  const int d = pv.d;
   if (d < nc) return fail(ctx, SAP_EINVAL, "sap_solve: need d >= n + 1");
   if (d > 16384) return fail(ctx, SAP_EINVAL, "sap_solve: d > 16384 is not supported");
   if (par->zeta < 1 || par->zeta > 64 || par->zeta > d) return fail(ctx, SAP_EINVAL, "sap_solve: zeta must be in [1, min(d, 64)]");
@@ -385,6 +397,20 @@ sap_status sap_solve(sap_ctx *ctx, const sap_problem *prob, const sap_params *pa
     if (par->max_refine < 0) return fail(ctx, SAP_EINVAL, "sap_solve: max_refine must be >= 0");
   } else {
     return fail(ctx, SAP_EINVAL, "sap_solve: unsupported mode");
+  }
+  // fixed-count mode (Sec. 4.2): a set number of iterations, no stopping test
+  int fixed = 0;
+  if (par->fixed_iters != 0) {
+    if (mode != SAP_MODE_FP64 && mode != SAP_MODE_MIXED_FP32)
+      return fail(ctx, SAP_EINVAL, "sap_solve: fixed_iters needs the FP64 or MIXED_FP32 mode");
+    if (par->fixed_iters > 0) {
+      fixed = par->fixed_iters;
+    } else {
+      int32_t t = 0;
+      if (sap_iteration_estimate(n, d, par->tol, &t) != SAP_OK)
+        return fail(ctx, SAP_EINVAL, "sap_solve: fixed_iters < 0 needs tol in (0, 1)");
+      fixed = t;
+    }
   }
   hipStream_t st = static_cast<hipStream_t>(stream);
   SAP_HIP_TRY(hipSetDevice(ctx->device));
@@ -466,9 +492,10 @@ sap_status sap_solve(sap_ctx *ctx, const sap_problem *prob, const sap_params *pa
   // MIXED_BF16SA iterates as MIXED_FP32_REFINE (FP32 passes, FP64 refinement)
   const int lsqr_mode = (mode == SAP_MODE_FP64) ? 0 : (mode == SAP_MODE_MIXED_FP32 ? 1 : 2);
   sap_info li{};
-  s = run_lsqr(ctx, prob, Y, d, nullptr, Y + static_cast<int64_t>(n) * d, par->tol, par->maxiter, lsqr_mode,
-               par->max_refine, x, &li, work, st);
+  s = run_lsqr(ctx, prob, Y, d, nullptr, Y + static_cast<int64_t>(n) * d, fixed ? 0.0 : par->tol,
+               fixed ? fixed : par->maxiter, lsqr_mode, par->max_refine, x, &li, work, st);
   if (s != SAP_OK && s != SAP_NOT_CONVERGED) return s;
+  if (fixed && s == SAP_NOT_CONVERGED) s = SAP_OK;  // the set count was run
   SAP_HIP_TRY(hipEventRecord(ev[4], st));
   SAP_HIP_TRY(hipEventSynchronize(ev[4]));
   prof_resolve(ctx);
@@ -484,6 +511,7 @@ sap_status sap_solve(sap_ctx *ctx, const sap_problem *prob, const sap_params *pa
     info->t_qr_ms = ms;
     (void)hipEventElapsedTime(&ms, ev[3], ev[4]);
     info->t_iterate_ms = ms;
+    info->d_used = d;
   }
   if (s == SAP_NOT_CONVERGED) (void)fail(ctx, s, "sap_solve: maxiter reached before the stopping test");
   return s;

@@ -836,9 +836,37 @@ struct BatchTuneKey {
 };
 static std::map<BatchTuneKey, int64_t> g_tune_rows;
 
-sap_status run_batch(sap_ctx *ctx, int count, const sap_problem *probs, const sap_params *par, double *const *x,
+// d = 0 (choose: eq. (4.2)'s d with cost ratio 1, within the batched form's
+// limit) and the fixed-count mode (maxiter = the set count, tol = 0).
+// Returns false when they cannot be resolved.
+constexpr int kBatchMaxD = 4096;
+bool resolve_params(const sap_problem &p, sap_params &q, int *fixed) {
+  *fixed = 0;
+  if (q.d == 0) {
+    int32_t d42 = 0;
+    if (!(q.tol > 0.0 && q.tol < 1.0) || sap_embedding_dim(p.m, p.n, q.tol, 1.0, &d42) != SAP_OK) return false;
+    q.d = static_cast<int32_t>(std::min<int64_t>(std::min<int64_t>(d42, kBatchMaxD), p.m));
+  }
+  if (q.fixed_iters != 0) {
+    if (q.mode != SAP_MODE_FP64 && q.mode != SAP_MODE_MIXED_FP32) return false;
+    int32_t t = q.fixed_iters;
+    if (t < 0 && (q.d <= p.n || sap_iteration_estimate(p.n, q.d, q.tol, &t) != SAP_OK)) return false;
+    *fixed = t;
+    q.maxiter = t;
+    q.tol = 0.0;
+  }
+  return true;
+}
+
+sap_status run_batch(sap_ctx *ctx, int count, const sap_problem *probs, const sap_params *par_in, double *const *x,
                      sap_info *infos, hipStream_t user_stream) {
   if (count < 1) return fail(ctx, SAP_EINVAL, "sap_solve_batch: count must be >= 1");
+  std::vector<sap_params> par_v(par_in, par_in + count);
+  std::vector<int> fixed_v(count, 0);
+  for (int k = 0; k < count; ++k)
+    if (!resolve_params(probs[k], par_v[k], &fixed_v[k]))
+      return fail(ctx, SAP_EINVAL, "sap_solve_batch: bad d = 0 or fixed_iters request");
+  const sap_params *par = par_v.data();
   const sap_dtype at = probs[0].a_type;
   int n_max = 0, maxiter_max = 0;
   bool aligned = true;
@@ -858,7 +886,7 @@ sap_status run_batch(sap_ctx *ctx, int count, const sap_problem *probs, const sa
     if (q.mode == SAP_MODE_MIXED_FP32_REFINE && at != SAP_F32)
       return fail(ctx, SAP_EINVAL, "sap_solve_batch: the refinement form needs FP32 A");
     const size_t es = (at == SAP_F32) ? 4 : 8;
-    if (q.d > 4096) return fail(ctx, SAP_EINVAL, "sap_solve_batch: d > 4096 is not supported by the batched form");
+    if (q.d > kBatchMaxD) return fail(ctx, SAP_EINVAL, "sap_solve_batch: d > 4096 is not supported by the batched form");
     n_max = std::max(n_max, p.n);
     maxiter_max = std::max(maxiter_max, q.maxiter);
     const int vm = 16 / static_cast<int>(es);
@@ -1130,13 +1158,16 @@ sap_status run_batch(sap_ctx *ctx, int count, const sap_problem *probs, const sa
   (void)hipEventDestroy(ev_out);
   bool all_ok = true;
   for (int k = 0; k < count; ++k) {
-    sap_status sk = back[k].rank_deficient ? SAP_RANK_DEFICIENT : (states[k].converged ? SAP_OK : SAP_NOT_CONVERGED);
+    const bool ran_fixed = fixed_v[k] > 0 && states[k].total_iters >= fixed_v[k];
+    sap_status sk = back[k].rank_deficient ? SAP_RANK_DEFICIENT
+                                           : ((states[k].converged || ran_fixed) ? SAP_OK : SAP_NOT_CONVERGED);
     if (sk != SAP_OK) all_ok = false;
     if (infos) {
       std::memset(&infos[k], 0, sizeof(sap_info));
       infos[k].status = sk;
       infos[k].iters = states[k].total_iters;
       infos[k].refinements = states[k].refinements;
+      infos[k].d_used = par[k].d;
       infos[k].resid_est = states[k].resid_est;
       infos[k].normar_est = states[k].normar_est;
     }
@@ -1160,6 +1191,7 @@ struct ServeRequest {
   sap_problem prob{};
   sap_params par{};
   double *x = nullptr;
+  int fixed = 0;  // fixed-count mode: the set number of iterations
   size_t bytes = 0, offset = 0;
   BatchItem item{};
   hipEvent_t ready = nullptr;  // inputs written: recorded on the submitter's stream
@@ -1380,13 +1412,15 @@ hipError_t serve_round(Server *S, std::vector<ServeRequest *> &fresh) {
       sap_status stt;
       if (r->cancel) stt = SAP_ECANCELED;
       else if (r->item.rank_deficient) stt = SAP_RANK_DEFICIENT;
-      else stt = states[k].converged ? SAP_OK : SAP_NOT_CONVERGED;
+      else stt = (states[k].converged || (r->fixed > 0 && states[k].total_iters >= r->fixed)) ? SAP_OK
+                                                                                               : SAP_NOT_CONVERGED;
       r->status = stt;
       r->t_done = now;
       std::memset(&r->info, 0, sizeof(r->info));
       r->info.status = stt;
       r->info.iters = states[k].total_iters;
       r->info.refinements = states[k].refinements;
+      r->info.d_used = r->par.d;
       r->info.resid_est = states[k].resid_est;
       r->info.normar_est = states[k].normar_est;
       r->info.t_queue_ms = std::chrono::duration<double, std::milli>(r->t_admit - r->t_submit).count();
@@ -1520,9 +1554,13 @@ sap_status serve_start(sap_ctx *ctx, size_t arena_bytes, int max_slots) {
   return SAP_OK;
 }
 
-sap_status serve_submit(sap_ctx *ctx, const sap_problem *p, const sap_params *q, double *x, uint64_t *ticket,
+sap_status serve_submit(sap_ctx *ctx, const sap_problem *p, const sap_params *q_in, double *x, uint64_t *ticket,
                         hipStream_t stream) {
-  if (!p || !q || !x || !ticket) return fail(ctx, SAP_EINVAL, "sap_submit: NULL argument");
+  if (!p || !q_in || !x || !ticket) return fail(ctx, SAP_EINVAL, "sap_submit: NULL argument");
+  sap_params qv = *q_in;
+  int fixed = 0;
+  if (!resolve_params(*p, qv, &fixed)) return fail(ctx, SAP_EINVAL, "sap_submit: bad d = 0 or fixed_iters request");
+  const sap_params *q = &qv;
   {
     static std::mutex start_mu;
     std::lock_guard<std::mutex> lk(start_mu);
@@ -1570,6 +1608,7 @@ sap_status serve_submit(sap_ctx *ctx, const sap_problem *p, const sap_params *q,
   r->ticket = S->next_ticket++;
   r->prob = *p;
   r->par = *q;
+  r->fixed = fixed;
   r->x = x;
   r->bytes = bytes;
   r->ready = ready;

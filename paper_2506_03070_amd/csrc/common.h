@@ -174,6 +174,8 @@ struct sap_ctx {
   // sps_apply_noalloc (set once at sap_create; never allocated or freed)
   void *apply_scratch = nullptr;
   size_t apply_scratch_bytes = 0;
+  // per-context timings of sap_choose_d (select.hip)
+  void *select_cache = nullptr;
   // kernel timing (sap_profile_enable): pending event pairs per kernel,
   // resolved into launch counts and milliseconds; free events are reused
   bool profiling = false;
@@ -227,6 +229,11 @@ sap_status launch_apply(sap_ctx *ctx, const sps_sketch *S, const void *A, int64_
 // lookup of this device's copy (once per context, with the device current).
 constexpr size_t kNoAllocScratchBytes = size_t(128) << 20;
 sap_status apply_scratch_init(sap_ctx *ctx);
+
+// Embedding-dimension choice (select.hip): d for a problem, timings cached
+// per context; the cache is freed by sap_destroy.
+sap_status choose_d(sap_ctx *ctx, const sap_problem *prob, int zeta, double eps, int32_t *d, hipStream_t st);
+void select_cache_free(sap_ctx *ctx);
 
 // Householder QR (qr.hip).
 size_t qr_workspace_bytes(int rows, int cols);

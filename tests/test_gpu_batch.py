@@ -184,3 +184,26 @@ def test_batch_refine_mode_checks(sap):
     with pytest.raises(sap.SapError) as e:
         sap.sap_solve_batch([A.float()], [b], [40], 8, 1, mode=sap.SAP_MODE_MIXED_BF16SA)
     assert e.value.status == sap.SAP_EINVAL
+
+
+def test_batch_auto_d_and_fixed_count(sap, orc):
+    """d = 0 in the batched form takes eq. (4.2)'s d (cost ratio 1) within the
+    form's d <= 4096; fixed_iters < 0 runs the eq. (4.1) count.  Each problem
+    against the oracle at the same d and count."""
+    import torch
+    probs = _batch(4, 77, np.float64, m_range=(20000, 40000), n_range=(30, 90))
+    As = [torch.from_numpy(np.ascontiguousarray(p.A)).cuda() for p in probs]
+    bs = [torch.from_numpy(p.b).cuda() for p in probs]
+    tol = 1e-10
+    xs, st, infos = sap.sap_solve_batch(As, bs, 0, 8, 13, tol=tol, maxiter=300, fixed_iters=-1)
+    torch.cuda.synchronize()
+    assert st == sap.SAP_OK, infos
+    for k, p in enumerate(probs):
+        m, n = p.A.shape
+        d = min(sap.sap_embedding_dim(m, n, tol), 4096, m)
+        T = sap.sap_iteration_estimate(n, d, tol)
+        print(f"  auto-d batch k={k} n={n}: d={infos[k]['d_used']} (eq. 4.2 {d}), iters={infos[k]['iters']} (T={T})",
+              flush=True)
+        assert infos[k]["d_used"] == d and infos[k]["iters"] == T
+        x_or, io = orc.solve(p.A, p.b, d, 8, 13, tol=0.0, maxiter=T, stream=k)
+        assert np.linalg.norm(p.A @ (xs[k].cpu().numpy() - x_or)) <= 1e-11 * np.linalg.norm(p.b), k

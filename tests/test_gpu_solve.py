@@ -307,3 +307,48 @@ def test_adaptive_embedding_dim_solve(sap, orc):
     torch.cuda.synchronize()
     assert fixed.status == sap.SAP_OK
     assert res.info["iters"] < fixed.info["iters"], (res.info["iters"], fixed.info["iters"])
+
+
+def test_choose_d_and_auto_d_solve(sap, orc):
+    """sap_choose_d (Sec. 4.3 with every phase timed on this GPU) returns one
+    of its candidates, k n for k in {1.25 .. 12} or eq. (4.2)'s d, clipped to
+    [n + 1, min(m, 16384)]; a solve with d = 0 uses that pick (info d_used)
+    and matches the oracle at the same d."""
+    import torch
+    m, n, eps = 60000, 80, 1e-12
+    p = inputs.make_problem(m, n, kind="svd", cond=1e6, noise=1e-6, seed=8080)
+    A, b = _dev(p.A), _dev(p.b)
+    d = sap.sap_choose_d(A, b, 8, eps)
+    cands = {max(n + 1, min(int(np.ceil(k * n)), m, 16384)) for k in (1.25, 1.5, 2, 2.5, 3, 4, 5, 6, 8, 10, 12)}
+    cands.add(max(n + 1, min(sap.sap_embedding_dim(m, n, eps), m, 16384)))
+    _note(f"choose_d m={m} n={n}: d={d} (candidates {sorted(cands)})")
+    assert d in cands
+    assert sap.sap_choose_d(A, b, 8, eps) == d  # cached timings: the same pick
+    res = sap.sap_solve(A, b, 0, 8, 5, tol=eps, maxiter=300)
+    torch.cuda.synchronize()
+    assert res.status == sap.SAP_OK and res.info["d_used"] == d
+    x_or, info_or = orc.solve(p.A, p.b, d, 8, 5, tol=eps, maxiter=300)
+    assert info_or["status"] == "ok"
+    assert np.linalg.norm(p.A @ (res.x.cpu().numpy() - x_or)) <= 1e-12 * np.linalg.norm(p.b)
+
+
+def test_fixed_count_mode(sap, orc):
+    """fixed_iters < 0 runs the eq. (4.1) count for tol (the fixed-count mode
+    of Sec. 4.2), > 0 a given count; both report SAP_OK after exactly that many
+    iterations and match the oracle run for the same count (tol 0)."""
+    import torch
+    m, n, d = 30000, 60, 240
+    p = inputs.make_problem(m, n, kind="svd", cond=1e6, noise=1e-4, seed=4141)
+    A, b = _dev(p.A), _dev(p.b)
+    for fixed, tol in ((-1, 1e-6), (7, 1e-12)):
+        T = sap.sap_iteration_estimate(n, d, tol) if fixed < 0 else fixed
+        _note(f"fixed count m={m} n={n} d={d} fixed_iters={fixed} -> {T}")
+        res = sap.sap_solve(A, b, d, 8, 6, tol=tol, maxiter=1000, fixed_iters=fixed)
+        torch.cuda.synchronize()
+        assert res.status == sap.SAP_OK and res.info["iters"] == T, res.info
+        x_or, io = orc.solve(p.A, p.b, d, 8, 6, tol=0.0, maxiter=T)
+        assert io["iters"] == T
+        assert np.linalg.norm(p.A @ (res.x.cpu().numpy() - x_or)) <= 1e-12 * np.linalg.norm(p.b)
+    with pytest.raises(sap.SapError) as e:  # not with the refinement form
+        sap.sap_solve(A.float(), b, d, 8, 6, tol=1e-8, mode=sap.SAP_MODE_MIXED_FP32_REFINE, fixed_iters=-1)
+    assert e.value.status == sap.SAP_EINVAL
