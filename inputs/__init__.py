@@ -82,6 +82,28 @@ def make_problem(m, n, kind="svd", cond=1e6, noise=1e-8, seed=BASE_SEED, row_sca
                              row_scale=row_scale))
 
 
+def make_sparse_problem(m, n, density=0.01, values="sign", noise=1e-8, seed=BASE_SEED):
+    """Sparse A in CSR form (scipy.sparse.csr_matrix, columns sorted within
+    rows, float64): each entry nonzero with probability `density`, value +-1
+    (Sec. 4.1's sparse recipe) or N(0,1) (values="gauss").  b = A x_true +
+    noise * N(0,1).  Returns (A, b, x_true)."""
+    import scipy.sparse as sp
+    rng = np.random.default_rng(seed)
+    nnz = rng.binomial(m * n, density)
+    flat = rng.choice(m * n, size=nnz, replace=False) if m * n <= (1 << 26) else np.unique(
+        rng.integers(0, m * n, size=nnz))
+    rows, cols = np.divmod(flat, n)
+    if values == "sign":
+        vals = np.where(rng.random(len(flat)) < 0.5, -1.0, 1.0)
+    else:
+        vals = rng.standard_normal(len(flat))
+    A = sp.csr_matrix((vals, (rows, cols)), shape=(m, n))
+    A.sort_indices()
+    x_true = rng.standard_normal(n)
+    b = A @ x_true + noise * rng.standard_normal(m)
+    return A, np.ascontiguousarray(b), x_true
+
+
 def config0() -> Problem:
     """Plain FP64 workload: m=20000, n=100, sigma 1..1e-6, noise 1e-8."""
     p = make_problem(20000, 100, kind="svd", cond=1e6, noise=1e-8, seed=config_seed(0))

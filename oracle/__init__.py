@@ -76,6 +76,13 @@ def lib():
         L.orc_solve.argtypes = [_i64, _i32, _vp, _i64, _vp, _i32, _i32, _u64, _u64, _f64, _i32, _vp, _vp,
                                 _vp, ctypes.POINTER(SolveInfo)]
         L.orc_direct_solve.argtypes = [_i64, _i32, _vp, _i64, _vp, _vp]
+        L.orc_matvec_csr.argtypes = [_i64, _vp, _vp, _vp, _vp, _vp]
+        L.orc_matvec_t_csr.argtypes = [_i64, _i32, _vp, _vp, _vp, _vp, _vp]
+        L.orc_apply_csr.argtypes = [_i64, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _i32, _f64, _vp, _i64]
+        L.orc_lsqr_csr.argtypes = [_i64, _i32, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _f64, _i32, _vp, _vp,
+                                   ctypes.POINTER(LsqrInfo)]
+        L.orc_solve_csr.argtypes = [_i64, _i32, _vp, _vp, _vp, _vp, _i32, _i32, _u64, _u64, _f64, _i32, _vp, _vp,
+                                    _vp, ctypes.POINTER(SolveInfo)]
         L.orc_lambert_w0.argtypes = [_f64]
         L.orc_lambert_w0.restype = _f64
         L.orc_embedding_dim.argtypes = [_i64, _i32, _f64, _f64]
@@ -307,6 +314,76 @@ def direct_solve(A, b):
     x = np.zeros(n)
     lib().orc_direct_solve(m, n, _p(A), n, _p(_f64c(b)), _p(x))
     return x
+
+
+# ---------------------------------------------------------- sparse (CSR) ----
+def _csr(A):
+    """(m, n, indptr int64, indices int32, values float64) of a scipy CSR matrix
+    (columns sorted within each row), or of a (indptr, indices, values, shape)
+    tuple."""
+    if isinstance(A, tuple):
+        indptr, indices, values, shape = A
+    else:
+        A = A.tocsr()
+        A.sort_indices()
+        indptr, indices, values, shape = A.indptr, A.indices, A.data, A.shape
+    return (int(shape[0]), int(shape[1]), np.ascontiguousarray(indptr, dtype=np.int64),
+            np.ascontiguousarray(indices, dtype=np.int32), np.ascontiguousarray(values, dtype=np.float64))
+
+
+def matvec_csr(A, x):
+    m, n, ip, ix, v = _csr(A)
+    y = np.zeros(m)
+    lib().orc_matvec_csr(m, _p(ip), _p(ix), _p(v), _p(_f64c(x)), _p(y))
+    return y
+
+
+def matvec_t_csr(A, u):
+    m, n, ip, ix, v = _csr(A)
+    y = np.zeros(n)
+    lib().orc_matvec_t_csr(m, n, _p(ip), _p(ix), _p(v), _p(_f64c(u)), _p(y))
+    return y
+
+
+def apply_csr(idx, sign, A, b, d, zeta):
+    """Y = S [A b] for A in CSR form, as a (d, ncols) array."""
+    m, n, ip, ix, v = _csr(A)
+    b = None if b is None else _f64c(b)
+    ncols = n + 1 if b is not None else n
+    Y = np.zeros((ncols, d))
+    lib().orc_apply_csr(m, d, zeta, _p(np.ascontiguousarray(idx, dtype=np.int32)),
+                        _p(np.ascontiguousarray(sign, dtype=np.uint64)), _p(ip), _p(ix), _p(v), _p(b), n,
+                        sketch_scale(zeta), _p(Y), d)
+    return Y.T
+
+
+def lsqr_csr(A, b, R, x0, tol=1e-12, maxiter=200, history=False):
+    """Alg. 2 on A R^-1 with A in CSR form."""
+    m, n, ip, ix, v = _csr(A)
+    R = np.asfortranarray(R, dtype=np.float64)
+    x = np.zeros(n)
+    hist = np.zeros((maxiter + 1, n)) if history else None
+    info = LsqrInfo()
+    lib().orc_lsqr_csr(m, n, _p(ip), _p(ix), _p(v), _p(_f64c(b)), R.ctypes.data_as(_vp), R.shape[0],
+                       _p(_f64c(x0)), tol, maxiter, _p(x), _p(hist), ctypes.byref(info))
+    d = dict(iters=info.iters, converged=bool(info.converged), resid_est=info.resid_est,
+             normar_est=info.normar_est)
+    if history:
+        return x, d, hist[:info.iters + 1]
+    return x, d
+
+
+def solve_csr(A, b, d, zeta, seed, tol=1e-12, maxiter=200, stream=0):
+    """Alg. 1 end to end with A in CSR form.  Returns (x, info dict)."""
+    m, n, ip, ix, v = _csr(A)
+    x = np.zeros(n)
+    x0 = np.zeros(n)
+    info = SolveInfo()
+    lib().orc_solve_csr(m, n, _p(ip), _p(ix), _p(v), _p(_f64c(b)), d, zeta, seed, stream, tol, maxiter, _p(x),
+                        _p(x0), None, ctypes.byref(info))
+    return x, dict(status=STATUS.get(info.status, str(info.status)), iters=info.iters,
+                   resid_est=info.resid_est, normar_est=info.normar_est, x0=x0, t_generate=info.t_generate,
+                   t_apply=info.t_apply, t_qr=info.t_qr, t_iterate=info.t_iterate)
 
 
 def lambert_w0(z):

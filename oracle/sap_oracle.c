@@ -27,6 +27,8 @@
  *   - Preconditioned LSQR exactly as Alg. 2 (Paige & Saunders 1982).
  *   - The whole of Alg. 1, and a direct Householder solve of [A b] for tiny
  *     problems.
+ *   - The same for a sparse A in CSR form: products, sketch apply, LSQR and
+ *     Alg. 1 on the stored entries, in the order of the dense routes.
  *
  * Parity pins for each function live in the CPU test suite.
  */
@@ -352,9 +354,17 @@ typedef struct orc_lsqr_info {
  *   phibar_{t+1} <= tol * ||b||       (compatible system), or
  *   beta_{t+1} == 0 or alpha_{t+1} == 0 (breakdown: x_t is exact).
  * maxiter <= 0 runs no iteration and returns x0. */
-void orc_lsqr(int64_t m, int32_t n, const double *A, int64_t lda, const double *b,
-              const double *R, int64_t ldr, const double *x0, double tol, int32_t maxiter,
-              double *x, double *history, orc_lsqr_info *info)
+/* The operator A of the least-squares problem: y = A x (m entries) and
+ * y = A^T u (n entries), for a dense or a CSR matrix. */
+typedef struct orc_op {
+    void (*av)(const void *ctx, const double *x, double *y);
+    void (*atv)(const void *ctx, const double *u, double *y);
+    const void *ctx;
+} orc_op;
+
+static void orc_lsqr_op(int64_t m, int32_t n, const orc_op *op, const double *b,
+                        const double *R, int64_t ldr, const double *x0, double tol, int32_t maxiter,
+                        double *x, double *history, orc_lsqr_info *info)
 {
     double *u = (double *)malloc(sizeof(double) * (size_t)m);
     double *v = (double *)malloc(sizeof(double) * (size_t)n);
@@ -371,7 +381,7 @@ void orc_lsqr(int64_t m, int32_t n, const double *A, int64_t lda, const double *
     double normb = orc_nrm2(m, b);
 
     /* beta_1 u_1 = b - A x_0 */
-    orc_matvec(m, n, A, lda, x0, u);
+    op->av(op->ctx, x0, u);
     for (int64_t i = 0; i < m; ++i)
         u[i] = b[i] - u[i];
     double beta = orc_nrm2(m, u);
@@ -384,7 +394,7 @@ void orc_lsqr(int64_t m, int32_t n, const double *A, int64_t lda, const double *
     for (int64_t i = 0; i < m; ++i)
         u[i] /= beta;
     /* alpha_1 v_1 = M^T A^T u_1 */
-    orc_matvec_t(m, n, A, lda, u, t1);
+    op->atv(op->ctx, u, t1);
     orc_forwardsub_t(R, ldr, n, t1, t2);
     double alpha = orc_nrm2(n, t2);
     info->normar_est = alpha * beta;
@@ -403,7 +413,7 @@ void orc_lsqr(int64_t m, int32_t n, const double *A, int64_t lda, const double *
         double *Ap = (double *)malloc(sizeof(double) * (size_t)m);
         for (int32_t t = 1; t <= maxiter; ++t) {
             /* u_hat = A M v_t - alpha_t u_t ; beta_{t+1} = ||u_hat|| */
-            orc_matvec(m, n, A, lda, p, Ap);
+            op->av(op->ctx, p, Ap);
             for (int64_t i = 0; i < m; ++i)
                 Ap[i] -= alpha * u[i];
             beta = orc_nrm2(m, Ap);
@@ -412,7 +422,7 @@ void orc_lsqr(int64_t m, int32_t n, const double *A, int64_t lda, const double *
                 for (int64_t i = 0; i < m; ++i)
                     u[i] = Ap[i] / beta;
                 /* v_hat = M^T A^T u_{t+1} - beta_{t+1} v_t ; alpha_{t+1} = ||v_hat|| */
-                orc_matvec_t(m, n, A, lda, u, t1);
+                op->atv(op->ctx, u, t1);
                 orc_forwardsub_t(R, ldr, n, t1, t2);
                 for (int32_t c = 0; c < n; ++c)
                     t2[c] -= beta * v[c];
@@ -455,6 +465,108 @@ done:
     free(u); free(v); free(w); free(p); free(t1); free(t2);
 }
 
+/* Dense row-major A (lda). */
+typedef struct orc_dense { int64_t m; int32_t n; const double *A; int64_t lda; } orc_dense;
+static void orc_dense_av(const void *ctx, const double *x, double *y)
+{
+    const orc_dense *D = (const orc_dense *)ctx;
+    orc_matvec(D->m, D->n, D->A, D->lda, x, y);
+}
+static void orc_dense_atv(const void *ctx, const double *u, double *y)
+{
+    const orc_dense *D = (const orc_dense *)ctx;
+    orc_matvec_t(D->m, D->n, D->A, D->lda, u, y);
+}
+
+void orc_lsqr(int64_t m, int32_t n, const double *A, int64_t lda, const double *b,
+              const double *R, int64_t ldr, const double *x0, double tol, int32_t maxiter,
+              double *x, double *history, orc_lsqr_info *info)
+{
+    orc_dense D = {m, n, A, lda};
+    orc_op op = {orc_dense_av, orc_dense_atv, &D};
+    orc_lsqr_op(m, n, &op, b, R, ldr, x0, tol, maxiter, x, history, info);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Sparse A in CSR form (Sec. 3 applies the sketch to sparse matrices; Table */
+/* 1 holds sparse problems): row i holds entries indptr[i] .. indptr[i+1]-1  */
+/* with columns indices[] ascending and values[].  Every sum below runs in   */
+/* the order of the dense routes (rows ascending, columns ascending), only   */
+/* skipping the zeros, so each CSR result equals the dense result on the     */
+/* densified matrix bit for bit.                                              */
+/* ------------------------------------------------------------------------ */
+void orc_matvec_csr(int64_t m, const int64_t *indptr, const int32_t *indices, const double *values,
+                    const double *x, double *y)
+{
+    for (int64_t i = 0; i < m; ++i) {
+        double acc = 0.0;
+        for (int64_t e = indptr[i]; e < indptr[i + 1]; ++e)
+            acc += values[e] * x[indices[e]];
+        y[i] = acc;
+    }
+}
+
+void orc_matvec_t_csr(int64_t m, int32_t n, const int64_t *indptr, const int32_t *indices,
+                      const double *values, const double *u, double *y)
+{
+    for (int32_t c = 0; c < n; ++c)
+        y[c] = 0.0;
+    for (int64_t i = 0; i < m; ++i)
+        for (int64_t e = indptr[i]; e < indptr[i + 1]; ++e)
+            y[indices[e]] += values[e] * u[i];
+}
+
+/* Sketch apply of [A b] with A in CSR: Y[r, c] gets s_ik a_ic for every
+ * stored entry (i, c) and every k with idx[i][k] = r, rows ascending; column
+ * n of Y is S b.  Scaled by h once at the end. */
+void orc_apply_csr(int64_t m, int32_t d, int32_t zeta, const int32_t *idx, const uint64_t *sign,
+                   const int64_t *indptr, const int32_t *indices, const double *values, const double *b,
+                   int32_t n, double h, double *Y, int64_t ldy)
+{
+    int32_t ncols = b ? n + 1 : n;
+    for (int32_t c = 0; c < ncols; ++c)
+        for (int32_t r = 0; r < d; ++r)
+            Y[r + (int64_t)c * ldy] = 0.0;
+    for (int64_t i = 0; i < m; ++i) {
+        for (int64_t e = indptr[i]; e < indptr[i + 1]; ++e) {
+            int32_t c = indices[e];
+            for (int k = 0; k < zeta; ++k) {
+                double s = ((sign[i] >> k) & 1) ? 1.0 : -1.0;
+                Y[idx[i * zeta + k] + (int64_t)c * ldy] += s * values[e];
+            }
+        }
+        if (b)
+            for (int k = 0; k < zeta; ++k) {
+                double s = ((sign[i] >> k) & 1) ? 1.0 : -1.0;
+                Y[idx[i * zeta + k] + (int64_t)n * ldy] += s * b[i];
+            }
+    }
+    for (int32_t c = 0; c < ncols; ++c)
+        for (int32_t r = 0; r < d; ++r)
+            Y[r + (int64_t)c * ldy] *= h;
+}
+
+typedef struct orc_csr { int64_t m; int32_t n; const int64_t *indptr; const int32_t *indices; const double *values; } orc_csr;
+static void orc_csr_av(const void *ctx, const double *x, double *y)
+{
+    const orc_csr *C = (const orc_csr *)ctx;
+    orc_matvec_csr(C->m, C->indptr, C->indices, C->values, x, y);
+}
+static void orc_csr_atv(const void *ctx, const double *u, double *y)
+{
+    const orc_csr *C = (const orc_csr *)ctx;
+    orc_matvec_t_csr(C->m, C->n, C->indptr, C->indices, C->values, u, y);
+}
+
+void orc_lsqr_csr(int64_t m, int32_t n, const int64_t *indptr, const int32_t *indices, const double *values,
+                  const double *b, const double *R, int64_t ldr, const double *x0, double tol, int32_t maxiter,
+                  double *x, double *history, orc_lsqr_info *info)
+{
+    orc_csr C = {m, n, indptr, indices, values};
+    orc_op op = {orc_csr_av, orc_csr_atv, &C};
+    orc_lsqr_op(m, n, &op, b, R, ldr, x0, tol, maxiter, x, history, info);
+}
+
 /* ------------------------------------------------------------------------ */
 /* Alg. 1 end to end.                                                         */
 /* ------------------------------------------------------------------------ */
@@ -490,6 +602,39 @@ int orc_rank_deficient(const double *R, int64_t ldr, int32_t n, int32_t d)
  * x0 = R^-1 (Q^T S b)[0:n], LSQR.
  * Y_out (nullable, d x (n+1) column-major, ld d) receives the factored Y
  * (R in the upper triangle).  x receives the solution. */
+/* The steps of Alg. 1 after the sketch: QR of Y, rank test, x0, LSQR.  Shared
+ * by the dense and the CSR solve. */
+static void orc_solve_finish(int64_t m, int32_t n, const orc_op *op, const double *b, int32_t d, double *Y,
+                             double *tau, double tol, int32_t maxiter, double *x, double *x0_out,
+                             orc_solve_info *info, double t2)
+{
+    int32_t nc = n + 1;
+    double *x0 = (double *)malloc(sizeof(double) * (size_t)n);
+    orc_householder_qr(Y, d, d, nc, tau);
+    double t3 = orc_now();
+    info->t_qr = t3 - t2;
+    if (orc_rank_deficient(Y, d, n, d)) {
+        info->status = 3;
+    } else {
+        /* x0 = R^-1 z with z = (Q^T S b)[0:n] = column n of the factored Y */
+        orc_backsub(Y, d, n, Y + (int64_t)n * d, x0);
+        if (x0_out)
+            memcpy(x0_out, x0, sizeof(double) * (size_t)n);
+        orc_lsqr_info li;
+        orc_lsqr_op(m, n, op, b, Y, d, x0, tol, maxiter, x, NULL, &li);
+        info->iters = li.iters;
+        info->resid_est = li.resid_est;
+        info->normar_est = li.normar_est;
+        info->status = li.converged ? 0 : 4;
+    }
+    info->t_iterate = orc_now() - t3;
+    free(x0);
+}
+
+/* Sample S (key (seed, stream)), form Y = S[A b], QR of Y,
+ * x0 = R^-1 (Q^T S b)[0:n], LSQR.
+ * Y_out (nullable, d x (n+1) column-major, ld d) receives the factored Y
+ * (R in the upper triangle).  x receives the solution. */
 void orc_solve(int64_t m, int32_t n, const double *A, int64_t lda, const double *b,
                int32_t d, int32_t zeta, uint64_t seed, uint64_t stream, double tol, int32_t maxiter,
                double *x, double *x0_out, double *Y_out, orc_solve_info *info)
@@ -504,36 +649,52 @@ void orc_solve(int64_t m, int32_t n, const double *A, int64_t lda, const double 
     uint64_t *sign = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)m);
     double *Y = (double *)malloc(sizeof(double) * (size_t)d * (size_t)nc);
     double *tau = (double *)malloc(sizeof(double) * (size_t)nc);
-    double *x0 = (double *)malloc(sizeof(double) * (size_t)n);
 
     double t0 = orc_now();
     orc_sketch(seed, stream, m, d, zeta, idx, sign, NULL);
     double t1 = orc_now();
     orc_apply_sparse(m, d, zeta, idx, sign, A, lda, b, n, 1.0 / sqrt((double)zeta), Y, d, NULL, 0);
     double t2 = orc_now();
-    orc_householder_qr(Y, d, d, nc, tau);
-    double t3 = orc_now();
     info->t_generate = t1 - t0;
     info->t_apply = t2 - t1;
-    info->t_qr = t3 - t2;
-    if (orc_rank_deficient(Y, d, n, d)) {
-        info->status = 3;
-    } else {
-        /* x0 = R^-1 z with z = (Q^T S b)[0:n] = column n of the factored Y */
-        orc_backsub(Y, d, n, Y + (int64_t)n * d, x0);
-        if (x0_out)
-            memcpy(x0_out, x0, sizeof(double) * (size_t)n);
-        orc_lsqr_info li;
-        orc_lsqr(m, n, A, lda, b, Y, d, x0, tol, maxiter, x, NULL, &li);
-        info->iters = li.iters;
-        info->resid_est = li.resid_est;
-        info->normar_est = li.normar_est;
-        info->status = li.converged ? 0 : 4;
-    }
-    info->t_iterate = orc_now() - t3;
+    orc_dense D = {m, n, A, lda};
+    orc_op op = {orc_dense_av, orc_dense_atv, &D};
+    orc_solve_finish(m, n, &op, b, d, Y, tau, tol, maxiter, x, x0_out, info, t2);
     if (Y_out)
         memcpy(Y_out, Y, sizeof(double) * (size_t)d * (size_t)nc);
-    free(idx); free(sign); free(Y); free(tau); free(x0);
+    free(idx); free(sign); free(Y); free(tau);
+}
+
+/* Alg. 1 with A in CSR form: the same steps, the sketch applied to the
+ * stored entries (orc_apply_csr) and the LSQR products on the CSR matrix. */
+void orc_solve_csr(int64_t m, int32_t n, const int64_t *indptr, const int32_t *indices, const double *values,
+                   const double *b, int32_t d, int32_t zeta, uint64_t seed, uint64_t stream, double tol,
+                   int32_t maxiter, double *x, double *x0_out, double *Y_out, orc_solve_info *info)
+{
+    memset(info, 0, sizeof(*info));
+    if (zeta < 1 || zeta > ORC_MAX_ZETA || d < zeta || d < n + 1 || m < 1 || n < 1) {
+        info->status = 1;
+        return;
+    }
+    int32_t nc = n + 1;
+    int32_t *idx = (int32_t *)malloc(sizeof(int32_t) * (size_t)m * (size_t)zeta);
+    uint64_t *sign = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)m);
+    double *Y = (double *)malloc(sizeof(double) * (size_t)d * (size_t)nc);
+    double *tau = (double *)malloc(sizeof(double) * (size_t)nc);
+
+    double t0 = orc_now();
+    orc_sketch(seed, stream, m, d, zeta, idx, sign, NULL);
+    double t1 = orc_now();
+    orc_apply_csr(m, d, zeta, idx, sign, indptr, indices, values, b, n, 1.0 / sqrt((double)zeta), Y, d);
+    double t2 = orc_now();
+    info->t_generate = t1 - t0;
+    info->t_apply = t2 - t1;
+    orc_csr C = {m, n, indptr, indices, values};
+    orc_op op = {orc_csr_av, orc_csr_atv, &C};
+    orc_solve_finish(m, n, &op, b, d, Y, tau, tol, maxiter, x, x0_out, info, t2);
+    if (Y_out)
+        memcpy(Y_out, Y, sizeof(double) * (size_t)d * (size_t)nc);
+    free(idx); free(sign); free(Y); free(tau);
 }
 
 /* Direct solve of min ||b - A x|| by Householder QR of [A b] (m x (n+1)),
