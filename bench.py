@@ -47,8 +47,11 @@ def parse():
     ap.add_argument("--zeta", type=int, default=8)
     ap.add_argument("--fig5-m", type=int, default=600000)
     ap.add_argument("--fig5-n", default="300,600,1000,1300")
-    ap.add_argument("--forms", default="mixed,batched,served,fig5",
-                    help="comma list of extra forms to run (mixed, batched, served, fig5; empty for none)")
+    ap.add_argument("--forms", default="mixed,batched,served,fig5,sparse",
+                    help="comma list of extra forms to run (mixed, batched, served, fig5, sparse; empty for none)")
+    ap.add_argument("--sparse-m", type=int, default=500000)
+    ap.add_argument("--sparse-n", type=int, default=500)
+    ap.add_argument("--sparse-reps", type=int, default=5)
     ap.add_argument("--mixed-m", type=int, default=1 << 22)
     ap.add_argument("--mixed-n", type=int, default=4096)
     ap.add_argument("--batch-count", type=int, default=512)
@@ -560,6 +563,102 @@ def form_fig5(args, sap, torch, inputs):
             "rows": rows}
 
 
+def _event_ms(torch, fn, reps):
+    """Median of reps event-timed calls of fn on the current stream."""
+    import numpy as np
+    fn()
+    ts = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fn()
+        e1.record()
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    return float(np.median(ts))
+
+
+def form_sparse(args, sap, torch, inputs):
+    """Sec. 4.1's sparse recipe at Table 1's size (m = 5e5, n = 500, +-1
+    entries at density 0.01): the sketch apply on the stored entries against
+    the dense apply of the same matrix held densely (Fig. 2's comparison,
+    over d and zeta), and Alg. 1 with the sparse LSQR pass against the dense
+    solve of the same matrix.  Rates on the stored-entry bytes: indptr
+    (8 (m + 1)), column indices (4 nnz) and values (8 nnz)."""
+    import numpy as np
+    m, n, dens = args.sparse_m, args.sparse_n, 0.01
+    A, b_np, _ = inputs.make_sparse_problem(m, n, dens, values="sign", noise=1e-6, seed=inputs.config_seed(6))
+    ip = torch.from_numpy(A.indptr.astype(np.int64)).cuda()
+    ix = torch.from_numpy(A.indices.astype(np.int32)).cuda()
+    v = torch.from_numpy(A.data.astype(np.float64)).cuda()
+    b = torch.from_numpy(b_np).cuda()
+    rows = torch.repeat_interleave(torch.arange(m, device="cuda"), ip[1:] - ip[:-1])
+    Ad = torch.zeros(m, n, dtype=torch.float64, device="cuda")
+    Ad[rows, ix.long()] = v
+    del rows
+    nnz = int(A.nnz)
+    nnz_bytes = 8 * (m + 1) + 12 * nnz
+    seed = inputs.config_seed(6) + 1
+    ctx = sap.default_context(0)
+    apply_rows = []
+    for zeta in (8, 12, 24):
+        for d in (2 * n, 4 * n, 8 * n):
+            idx, sign = sap.sps_generate(m, d, zeta, seed)
+            Ys = torch.empty(n + 1, d, dtype=torch.float64, device="cuda")
+            Yd = torch.empty(n + 1, d, dtype=torch.float64, device="cuda")
+            ms_s = _event_ms(torch, lambda: sap.sps_apply_csr(idx, sign, d, zeta, ip, ix, v, (m, n), b, Y=Ys), 5)
+            ms_d = _event_ms(torch, lambda: sap.sps_apply(idx, sign, d, zeta, Ad, b, Y=Yd), 5)
+            err = float((Ys - Yd).norm() / Yd.norm())
+            apply_rows.append({"zeta": zeta, "d": d, "sparse_ms": ms_s, "dense_ms": ms_d,
+                               "dense_over_sparse": ms_d / ms_s, "sparse_nnz_gbs": nnz_bytes / (ms_s * 1e-3) / 1e9,
+                               "rel_diff": err})
+            log(f"bench[sparse]: apply zeta={zeta} d={d}: sparse {ms_s:.3f} ms, dense {ms_d:.3f} ms, diff {err:.1e}")
+            del idx, sign, Ys, Yd
+    d, zeta, tol = 4 * n, 8, 1e-12
+    xs = torch.empty(n, dtype=torch.float64, device="cuda")
+    xd = torch.empty(n, dtype=torch.float64, device="cuda")
+    sap.sap_solve_csr(ip, ix, v, (m, n), b, d, zeta, seed, tol=tol, maxiter=300, x=xs)
+    ctx.profile(True)
+    ctx.profile_read(sap.PROF_PASS, reset=True)
+    ts, infos = [], []
+    for _ in range(args.sparse_reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = sap.sap_solve_csr(ip, ix, v, (m, n), b, d, zeta, seed, tol=tol, maxiter=300, x=xs)
+        ts.append((time.perf_counter() - t0) * 1e3)
+        infos.append(r.info)
+    ctx.profile(False)
+    n_pass, ms_pass = ctx.profile_read(sap.PROF_PASS)
+    n_full = sum(i["iters"] + 1 for i in infos)
+    pass_ms = ms_pass / max(1, min(n_pass, n_full))
+    pass_bytes_s = nnz_bytes + 16 * m  # + u read and written
+    sap.sap_solve(Ad, b, d, zeta, seed, tol=tol, maxiter=300, x=xd)
+    td = []
+    for _ in range(args.sparse_reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rd = sap.sap_solve(Ad, b, d, zeta, seed, tol=tol, maxiter=300, x=xd)
+        td.append((time.perf_counter() - t0) * 1e3)
+    res_s = float((b - Ad @ xs).norm())
+    res_d = float((b - Ad @ xd).norm())
+    i0 = infos[-1]
+    out = {"workload": f"Sec. 4.1 sparse recipe: m = {m}, n = {n}, +-1 at density {dens} (nnz {nnz}), "
+                       f"b = A x + 1e-6 noise; solve d = {d}, zeta = {zeta}, tol {tol:g}",
+           "apply": apply_rows,
+           "solve": {"sparse_ms": float(np.median(ts)), "dense_ms": float(np.median(td)),
+                     "dense_over_sparse": float(np.median(td) / np.median(ts)),
+                     "iters": i0["iters"], "dense_iters": rd.info["iters"],
+                     "phases_ms": {k: i0[k] for k in ("t_generate_ms", "t_apply_ms", "t_qr_ms", "t_iterate_ms")},
+                     "pass_avg_ms": pass_ms, "pass_bytes": pass_bytes_s,
+                     "pass_gbs": pass_bytes_s / (pass_ms * 1e-3) / 1e9,
+                     "residual_sparse": res_s, "residual_dense": res_d,
+                     "x_rel_diff": float((xs - xd).norm() / xd.norm())}}
+    log(f"bench[sparse]: solve {out['solve']}")
+    del Ad
+    torch.cuda.empty_cache()
+    return out
+
+
 def kernel_apply(args, sap, torch, inputs):
     """sps_apply alone: warm-up, then --steps applies timed with events on
     the current stream (the stream the library launches on).  One JSON line."""
@@ -726,7 +825,8 @@ def main():
     del A, r_vec
     torch.cuda.empty_cache()
     for f in [f for f in args.forms.split(",") if f]:
-        fn = {"mixed": form_mixed, "batched": form_batched, "served": form_served, "fig5": form_fig5}.get(f)
+        fn = {"mixed": form_mixed, "batched": form_batched, "served": form_served, "fig5": form_fig5,
+              "sparse": form_sparse}.get(f)
         if fn is None:
             log(f"bench: unknown form {f}")
             continue

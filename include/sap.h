@@ -133,7 +133,7 @@ typedef struct sps_sketch {
  * pointer is NULL. */
 sap_status sps_generate(sap_ctx *ctx, const sps_sketch *S, void *stream);
 
-/* Y = S [A b]  (Alg. 1, "form Y = SA"; b is sketched as column n of Y so that
+/* Y = S [A b]  (the sketching step of Alg. 1; b is sketched as column n of Y so that
  * Q^T S b comes out of the same factorisation).  A: device, row-major m x n,
  * lda >= n, dtype a_type in {F64, F32, BF16}.  b: device, m doubles, or NULL
  * (then Y has n columns).  Y: device, column-major d x (n + (b != NULL)),
@@ -242,6 +242,45 @@ sap_status sap_solve(sap_ctx *ctx, const sap_problem *prob, const sap_params *pa
 sap_status sap_lsqr(sap_ctx *ctx, const sap_problem *prob, const double *R, int64_t ldr,
                     const double *x0, double tol, int32_t maxiter, double *x, sap_info *info,
                     void *stream);
+
+/* ------------------------------------------------------------------------
+ * Sparse A (Sec. 3 applies the sketch to sparse matrices; Table 1 holds
+ * sparse problems).  CSR form, all arrays on the device, owned by the
+ * caller: row i holds the entries indptr[i] .. indptr[i+1]-1, with columns
+ * indices[e] in [0, n) and values values[e] (F64, or F32 for the MIXED_FP32
+ * mode); entries with a column outside [0, n) are ignored.  Limits: n <=
+ * 8192, m < 2^31.
+ * ---------------------------------------------------------------------- */
+typedef struct sap_csr {
+    int64_t m;               /* rows */
+    int32_t n;               /* columns */
+    int64_t nnz;             /* stored entries (= indptr[m]) */
+    const int64_t *indptr;   /* device, m + 1 */
+    const int32_t *indices;  /* device, nnz */
+    const void *values;      /* device, nnz of v_type */
+    sap_dtype v_type;        /* F64 or F32 */
+} sap_csr;
+
+/* Y = S [A b] for a CSR A (the sketching step of Alg. 1), Y column-major FP64
+ * d x (n + (b != NULL)), ldy >= d, d < 20000, in O(zeta (nnz + m)) work:
+ * the stored entries only.  The CSR arrays are checked on the device:
+ * indptr[0] = 0, indptr[m] = nnz, indptr non-decreasing, every column index
+ * in [0, n); column indices need not be sorted within a row.  The work is
+ * planned on the device; the call blocks only to read the check's result.
+ * Errors: SAP_EINVAL (shapes, the sketch's m differs from A's, a CSR array
+ * that fails the check: Y is then undefined), SAP_ENOMEM. */
+sap_status sps_apply_csr(sap_ctx *ctx, const sps_sketch *S, const sap_csr *A, const double *b, double *Y,
+                         int64_t ldy, void *stream);
+
+/* Alg. 1 and Alg. 2 for a CSR A: the sketch applied to the stored entries
+ * (sps_apply_csr), the QR and x0 as in sap_solve, and LSQR whose pass
+ * computes A p and A^T u from the stored entries in one sweep.  params as
+ * for sap_solve; modes FP64 (F64 values) and MIXED_FP32 (F32 values, FP64
+ * arithmetic); d = 0 takes eq. (4.2)'s d (cost ratio 1) within d <= 16384;
+ * fixed_iters as for sap_solve.  b: device, m doubles.  Blocking.  Errors as
+ * for sap_solve. */
+sap_status sap_solve_csr(sap_ctx *ctx, const sap_csr *A, const double *b, const sap_params *params, double *x,
+                         sap_info *info, void *stream);
 
 /* Many independent problems solved together (the batched form): each phase of
  * Alg. 1 is one launch over all problems, and the LSQR iterations of all

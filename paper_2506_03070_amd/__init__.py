@@ -23,7 +23,8 @@ SAP_MODE_FP64, SAP_MODE_MIXED_FP32, SAP_MODE_MIXED_FP32_REFINE, SAP_MODE_MIXED_B
 EXPORTS = ["sap_create", "sap_destroy", "sap_last_error", "sap_status_string", "sps_generate",
            "sps_apply", "sps_apply_noalloc", "sap_qr", "sap_trsv", "sap_solve", "sap_lsqr", "sap_profile_enable",
            "sap_profile_read", "sap_solve_batch", "sap_serve_start", "sap_submit", "sap_poll",
-           "sap_cancel", "sap_serve_stats", "sap_embedding_dim", "sap_iteration_estimate", "sap_choose_d"]
+           "sap_cancel", "sap_serve_stats", "sap_embedding_dim", "sap_iteration_estimate", "sap_choose_d",
+           "sps_apply_csr", "sap_solve_csr"]
 PROF_PASS, PROF_APPLY = 0, 1
 
 _vp = ctypes.c_void_p
@@ -40,6 +41,11 @@ class SpsSketch(ctypes.Structure):
 
 class SapProblem(ctypes.Structure):
     _fields_ = [("m", _i64), ("n", _i32), ("A", _vp), ("lda", _i64), ("a_type", _i32), ("b", _vp)]
+
+
+class SapCsr(ctypes.Structure):
+    _fields_ = [("m", _i64), ("n", _i32), ("nnz", _i64), ("indptr", _vp), ("indices", _vp), ("values", _vp),
+                ("v_type", _i32)]
 
 
 class SapParams(ctypes.Structure):
@@ -123,6 +129,11 @@ def lib():
         L.sap_iteration_estimate.restype = ctypes.c_int
         L.sap_choose_d.argtypes = [_vp, ctypes.POINTER(SapProblem), _i32, _f64, ctypes.POINTER(_i32), _vp]
         L.sap_choose_d.restype = ctypes.c_int
+        L.sps_apply_csr.argtypes = [_vp, ctypes.POINTER(SpsSketch), ctypes.POINTER(SapCsr), _vp, _vp, _i64, _vp]
+        L.sps_apply_csr.restype = ctypes.c_int
+        L.sap_solve_csr.argtypes = [_vp, ctypes.POINTER(SapCsr), _vp, ctypes.POINTER(SapParams), _vp,
+                                    ctypes.POINTER(SapInfo), _vp]
+        L.sap_solve_csr.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -259,6 +270,50 @@ def sps_apply_noalloc(idx, sign, d, zeta, A, b=None, y_dtype=None, ctx=None, see
     ctx.check(lib().sps_apply_noalloc(ctx.handle, ctypes.byref(S), _dev(A, name="A"), _ld(A), _dtype_code(A),
                                       bptr, n, _dev(Y, y_dtype, "Y"), _ld(Y), _dtype_code(Y), _vp(_stream())))
     return Y
+
+
+def _csr_struct(indptr, indices, values, shape):
+    torch = _torch()
+    m, n = shape
+    if indptr.dtype != torch.int64 or indices.dtype != torch.int32:
+        raise TypeError("CSR indptr must be int64 and indices int32")
+    return SapCsr(int(m), int(n), int(indices.numel()), _dev(indptr, name="indptr"),
+                  _dev(indices, name="indices") if indices.numel() else None,
+                  _dev(values, name="values") if values.numel() else None, _dtype_code(values))
+
+
+def sps_apply_csr(idx, sign, d, zeta, indptr, indices, values, shape, b=None, ctx=None, seed=0, stream_id=0, Y=None):
+    """Y = S [A b] for a CSR A given by device tensors (indptr int64 (m+1),
+    indices int32, values F64/F32) and shape (m, n).  Returns a (ncols, d)
+    float64 tensor whose rows are the columns of Y."""
+    torch = _torch()
+    ctx = ctx or default_context()
+    m, n = shape
+    ncols = n + (1 if b is not None else 0)
+    Y = Y if Y is not None else torch.empty((ncols, d), dtype=torch.float64, device=indptr.device)
+    S = _sketch_struct(m, d, zeta, seed, stream_id, idx, sign)
+    A = _csr_struct(indptr, indices, values, shape)
+    bptr = _dev(b, torch.float64, "b") if b is not None else None
+    ctx.check(lib().sps_apply_csr(ctx.handle, ctypes.byref(S), ctypes.byref(A), bptr, _dev(Y, torch.float64, "Y"),
+                                  _ld(Y), _vp(_stream())))
+    return Y
+
+
+def sap_solve_csr(indptr, indices, values, shape, b, d, zeta=8, seed=1, tol=1e-12, maxiter=200, mode=None,
+                  ctx=None, x=None, fixed_iters=0):
+    """min ||b - A x|| for a CSR A (sap_solve_csr)."""
+    torch = _torch()
+    ctx = ctx or default_context()
+    if mode is None:
+        mode = SAP_MODE_FP64 if values.dtype == torch.float64 else SAP_MODE_MIXED_FP32
+    A = _csr_struct(indptr, indices, values, shape)
+    par = SapParams(int(d), int(zeta), int(seed), float(tol), int(maxiter), int(mode), 0, int(fixed_iters))
+    x = x if x is not None else torch.empty(shape[1], dtype=torch.float64, device=indptr.device)
+    info = SapInfo()
+    st = lib().sap_solve_csr(ctx.handle, ctypes.byref(A), _vp(_dev(b, torch.float64, "b")), ctypes.byref(par),
+                             _vp(_dev(x, torch.float64, "x")), ctypes.byref(info), _vp(_stream()))
+    ctx.check(st, (SAP_OK, SAP_NOT_CONVERGED))
+    return SolveResult(x, st, info.as_dict())
 
 
 def sap_qr(Yt, ctx=None):

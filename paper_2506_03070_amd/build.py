@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(OUT_DIR, "libsap.so")
-SOURCES = ["api.hip", "sketch.hip", "apply.hip", "qr.hip", "lsqr.hip", "trsv.hip", "batch.hip", "embed.hip", "select.hip"]
+SOURCES = ["api.hip", "sketch.hip", "apply.hip", "qr.hip", "lsqr.hip", "trsv.hip", "batch.hip", "embed.hip", "select.hip", "sparse.hip"]
 ARCH = "gfx950"
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -100,7 +100,7 @@ struct SolveFlags {
   int gen_error;
   int rank_deficient;
   int nonfinite_b;
-  int pad;
+  int bad_csr;
 };
 
 __global__ void zero_flags_kernel(SolveFlags *f) {
@@ -108,6 +108,7 @@ __global__ void zero_flags_kernel(SolveFlags *f) {
     f->gen_error = 0;
     f->rank_deficient = 0;
     f->nonfinite_b = 0;
+    f->bad_csr = 0;
   }
 }
 
@@ -514,6 +515,174 @@ sap_status sap_solve(sap_ctx *ctx, const sap_problem *prob, const sap_params *pa
     info->d_used = d;
   }
   if (s == SAP_NOT_CONVERGED) (void)fail(ctx, s, "sap_solve: maxiter reached before the stopping test");
+  return s;
+}
+
+static sap_status check_csr(sap_ctx *ctx, const sap_csr *A) {
+  if (!A) return fail(ctx, SAP_EINVAL, "sparse A descriptor is NULL");
+  if (A->n < 1 || A->n > 8192) return fail(ctx, SAP_EINVAL, "sparse A: need 1 <= n <= 8192");
+  if (A->m < static_cast<int64_t>(A->n) + 1) return fail(ctx, SAP_EINVAL, "sparse A: need m >= n + 1");
+  if (A->m >= (int64_t(1) << 31)) return fail(ctx, SAP_EINVAL, "sparse A: need m < 2^31");
+  if (A->nnz < 0 || !A->indptr || (A->nnz > 0 && (!A->indices || !A->values)))
+    return fail(ctx, SAP_EINVAL, "sparse A: bad pointers or nnz");
+  if (A->v_type != SAP_F64 && A->v_type != SAP_F32) return fail(ctx, SAP_EINVAL, "sparse A: values must be F64 or F32");
+  return SAP_OK;
+}
+
+static SparseA to_sparse(const sap_csr *A) {
+  SparseA s;
+  s.m = A->m;
+  s.n = A->n;
+  s.nnz = A->nnz;
+  s.indptr = A->indptr;
+  s.indices = A->indices;
+  s.values = A->values;
+  s.v_type = A->v_type;
+  return s;
+}
+
+sap_status sps_apply_csr(sap_ctx *ctx, const sps_sketch *S, const sap_csr *A, const double *b, double *Y, int64_t ldy,
+                         void *stream) {
+  if (!ctx) return SAP_EINVAL;
+  sap_status s = check_sketch(ctx, S);
+  if (s != SAP_OK) return s;
+  s = check_csr(ctx, A);
+  if (s != SAP_OK) return s;
+  if (S->m != A->m) return fail(ctx, SAP_EINVAL, "sps_apply_csr: the sketch must have m columns");
+  if (!Y || ldy < S->d) return fail(ctx, SAP_EINVAL, "sps_apply_csr: need Y and ldy >= d");
+  if (S->d >= 20000) return fail(ctx, SAP_EINVAL, "sps_apply_csr: d >= 20000 is not supported");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  SAP_HIP_TRY(hipSetDevice(ctx->device));
+  const SparseA sa = to_sparse(A);
+  s = ensure_workspace(ctx, csr_apply_workspace_bytes(sa, S->d) + 512, st);
+  if (s != SAP_OK) return s;
+  Carve cv(ctx->ws);
+  int *bad = cv.take<int>(1);
+  void *work = cv.take<char>(csr_apply_workspace_bytes(sa, S->d));
+  hipEvent_t pb = prof_begin(ctx, st);
+  s = launch_csr_apply(ctx, S, sa, b, Y, ldy, bad, work, st);
+  prof_end(ctx, kProfApply, pb, st);
+  if (s != SAP_OK) return s;
+  int hbad = 0;
+  SAP_HIP_TRY(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, st));
+  SAP_HIP_TRY(hipStreamSynchronize(st));
+  if (hbad)
+    return fail(ctx, SAP_EINVAL,
+                "sps_apply_csr: indptr must start at 0, end at nnz and not decrease; column indices must lie in [0, n)");
+  return SAP_OK;
+}
+
+sap_status sap_solve_csr(sap_ctx *ctx, const sap_csr *A, const double *b, const sap_params *par_in, double *x,
+                         sap_info *info, void *stream) {
+  if (!ctx) return SAP_EINVAL;
+  sap_status s = check_csr(ctx, A);
+  if (s != SAP_OK) return s;
+  if (!par_in || !x || !b) return fail(ctx, SAP_EINVAL, "sap_solve_csr: NULL params, b or x");
+  sap_params pv = *par_in;
+  const int64_t m = A->m;
+  const int n = A->n, nc = n + 1;
+  if (pv.d == 0) {  // eq. (4.2) with cost ratio 1
+    int32_t d42 = 0;
+    if (!(pv.tol > 0.0 && pv.tol < 1.0) || sap_embedding_dim(m, n, pv.tol, 1.0, &d42) != SAP_OK)
+      return fail(ctx, SAP_EINVAL, "sap_solve_csr: d = 0 needs tol in (0, 1)");
+    pv.d = static_cast<int32_t>(std::min<int64_t>(std::min<int64_t>(d42, 16384), m));
+  }
+  const int d = pv.d;
+  if (d < nc || d > 16384) return fail(ctx, SAP_EINVAL, "sap_solve_csr: need n + 1 <= d <= 16384");
+  if (pv.zeta < 1 || pv.zeta > 64 || pv.zeta > d) return fail(ctx, SAP_EINVAL, "sap_solve_csr: bad zeta");
+  if (pv.maxiter < 0 || !(pv.tol >= 0.0)) return fail(ctx, SAP_EINVAL, "sap_solve_csr: need maxiter >= 0, tol >= 0");
+  if (pv.mode == SAP_MODE_FP64) {
+    if (A->v_type != SAP_F64) return fail(ctx, SAP_EINVAL, "sap_solve_csr: FP64 mode needs F64 values");
+  } else if (pv.mode == SAP_MODE_MIXED_FP32) {
+    if (A->v_type != SAP_F32) return fail(ctx, SAP_EINVAL, "sap_solve_csr: MIXED_FP32 needs F32 values");
+  } else {
+    return fail(ctx, SAP_EINVAL, "sap_solve_csr: mode must be FP64 or MIXED_FP32");
+  }
+  int fixed = 0;
+  if (pv.fixed_iters > 0) fixed = pv.fixed_iters;
+  else if (pv.fixed_iters < 0 && sap_iteration_estimate(n, d, pv.tol, &fixed) != SAP_OK)
+    return fail(ctx, SAP_EINVAL, "sap_solve_csr: fixed_iters < 0 needs tol in (0, 1)");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  SAP_HIP_TRY(hipSetDevice(ctx->device));
+  const SparseA sa = to_sparse(A);
+  size_t scratch = csr_apply_workspace_bytes(sa, d);
+  scratch = std::max(scratch, qr_workspace_bytes(d, nc));
+  scratch = std::max(scratch, lsqr_workspace_bytes(ctx, m, n));
+  const size_t total = 8 * 256 + 256 + static_cast<size_t>(m) * pv.zeta * sizeof(int32_t) +
+                       static_cast<size_t>(m) * sizeof(uint64_t) + static_cast<size_t>(d) * nc * sizeof(double) +
+                       static_cast<size_t>(nc) * sizeof(double) + scratch;
+  s = ensure_workspace(ctx, total, st);
+  if (s != SAP_OK) return s;
+  Carve cv(ctx->ws);
+  SolveFlags *flags = cv.take<SolveFlags>(1);
+  int32_t *idx = cv.take<int32_t>(static_cast<size_t>(m) * pv.zeta);
+  uint64_t *sign = cv.take<uint64_t>(static_cast<size_t>(m));
+  double *Y = cv.take<double>(static_cast<size_t>(d) * nc);
+  double *tau = cv.take<double>(nc);
+  void *work = cv.take<char>(scratch);
+  if (info) std::memset(info, 0, sizeof(*info));
+  hipEvent_t ev[5];
+  for (auto &e : ev) SAP_HIP_TRY(hipEventCreate(&e));
+  struct EvGuard {
+    hipEvent_t *e;
+    ~EvGuard() {
+      for (int k = 0; k < 5; ++k) (void)hipEventDestroy(e[k]);
+    }
+  } guard{ev};
+  zero_flags_kernel<<<1, 64, 0, st>>>(flags);
+  finite_check_kernel<<<256, 256, 0, st>>>(b, m, &flags->nonfinite_b);
+  SAP_HIP_TRY(hipGetLastError());
+  SAP_HIP_TRY(hipEventRecord(ev[0], st));
+  sps_sketch S{m, d, pv.zeta, pv.seed, 0, idx, sign};
+  s = launch_generate(ctx, &S, &flags->gen_error, st);
+  if (s != SAP_OK) return s;
+  SAP_HIP_TRY(hipEventRecord(ev[1], st));
+  hipEvent_t pb_apply = prof_begin(ctx, st);
+  s = launch_csr_apply(ctx, &S, sa, b, Y, d, &flags->bad_csr, work, st);
+  if (s != SAP_OK) return s;
+  prof_end(ctx, kProfApply, pb_apply, st);
+  SAP_HIP_TRY(hipEventRecord(ev[2], st));
+  s = launch_qr(ctx, Y, d, d, nc, tau, work, st);
+  if (s != SAP_OK) return s;
+  s = launch_rank_check(ctx, Y, d, n, d, &flags->rank_deficient, st);
+  if (s != SAP_OK) return s;
+  SAP_HIP_TRY(hipEventRecord(ev[3], st));
+  SolveFlags hf{};
+  SAP_HIP_TRY(hipMemcpyAsync(&hf, flags, sizeof(hf), hipMemcpyDeviceToHost, st));
+  SAP_HIP_TRY(hipStreamSynchronize(st));
+  if (hf.bad_csr)
+    return fail(ctx, SAP_EINVAL,
+                "sap_solve_csr: indptr must start at 0, end at nnz and not decrease; column indices must lie in [0, n)");
+  if (hf.nonfinite_b) return fail(ctx, SAP_EINVAL, "sap_solve_csr: b has non-finite entries");
+  if (hf.gen_error) return fail(ctx, SAP_EDEVICE, "sap_solve_csr: sketch generation hit its round cap");
+  if (hf.rank_deficient) {
+    if (info) info->status = SAP_RANK_DEFICIENT;
+    return fail(ctx, SAP_RANK_DEFICIENT, "sap_solve_csr: R is numerically singular (A rank deficient)");
+  }
+  sap_problem prob{m, n, nullptr, n, A->v_type, b};
+  sap_info li{};
+  s = run_lsqr(ctx, &prob, Y, d, nullptr, Y + static_cast<int64_t>(n) * d, fixed ? 0.0 : pv.tol,
+               fixed ? fixed : pv.maxiter, pv.mode == SAP_MODE_FP64 ? 0 : 1, 0, x, &li, work, st, &sa);
+  if (s != SAP_OK && s != SAP_NOT_CONVERGED) return s;
+  if (fixed && s == SAP_NOT_CONVERGED) s = SAP_OK;
+  SAP_HIP_TRY(hipEventRecord(ev[4], st));
+  SAP_HIP_TRY(hipEventSynchronize(ev[4]));
+  prof_resolve(ctx);
+  if (info) {
+    *info = li;
+    info->status = s;
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, ev[0], ev[1]);
+    info->t_generate_ms = ms;
+    (void)hipEventElapsedTime(&ms, ev[1], ev[2]);
+    info->t_apply_ms = ms;
+    (void)hipEventElapsedTime(&ms, ev[2], ev[3]);
+    info->t_qr_ms = ms;
+    (void)hipEventElapsedTime(&ms, ev[3], ev[4]);
+    info->t_iterate_ms = ms;
+    info->d_used = d;
+  }
+  if (s == SAP_NOT_CONVERGED) (void)fail(ctx, s, "sap_solve_csr: maxiter reached before the stopping test");
   return s;
 }
 

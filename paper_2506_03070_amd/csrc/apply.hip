@@ -1,4 +1,4 @@
-// Sketch apply Y = S [A b] on gfx950 (Alg. 1 "form Y = SA"; the paper calls a
+// Sketch apply Y = S [A b] on gfx950 (the sketching step of Alg. 1; the paper calls a
 // library sparse-times-dense product, Sec. 3).
 //
 // Design.  Column j of S has zeta nonzeros, so row i of [A b] is added, with

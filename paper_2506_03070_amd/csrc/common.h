@@ -248,14 +248,36 @@ size_t trsv_workspace_bytes(int n);
 sap_status launch_trsv(sap_ctx *ctx, const double *R, int64_t ldr, int n, int trans,
                        const double *rhs, double *x, void *work, hipStream_t st);
 
+// Sparse A in CSR form (sparse.hip): row i holds entries indptr[i] ..
+// indptr[i+1]-1 (columns `indices`, values of type v_type, F64 or F32).
+struct SparseA {
+  int64_t m = 0;
+  int n = 0;
+  int64_t nnz = 0;
+  const int64_t *indptr = nullptr;
+  const int32_t *indices = nullptr;
+  const void *values = nullptr;
+  sap_dtype v_type = SAP_F64;
+};
+size_t csr_apply_workspace_bytes(const SparseA &A, int d);
+// Y (F64, ldy) = S [A b], asynchronous.  *bad (device) is cleared, then set
+// when the CSR arrays fail the check (Y is then garbage); the caller reads it.
+sap_status launch_csr_apply(sap_ctx *ctx, const sps_sketch *S, const SparseA &A, const double *b, double *Y,
+                            int64_t ldy, int *bad, void *work, hipStream_t st);
+int csr_pass_grid(sap_ctx *ctx, const SparseA &A);
+void launch_csr_pass(sap_ctx *ctx, const SparseA &A, int grid, const double *p, const double *u_in, double *u_out,
+                     const LsqrState *st, double *qpart, double *nrmpart, hipStream_t s);
+
 // LSQR driver (lsqr.hip).  When z is non-null, x0 is ignored and the initial
 // guess is R^-1 z (the sketch-and-solve solution of Alg. 1).
 // mode 0: A in FP64; mode 1: A stored in FP32 (FP64 arithmetic); mode 2: A
 // stored in FP32, FP64 residual refinement around FP32 inner solves.
 size_t lsqr_workspace_bytes(sap_ctx *ctx, int64_t m, int n);
+// With sp non-null the passes run on that CSR matrix (modes 0 and 1; prob
+// then gives only m, n and b).
 sap_status run_lsqr(sap_ctx *ctx, const sap_problem *prob, const double *R, int64_t ldr,
                     const double *x0, const double *z, double tol, int maxiter, int mode, int max_refine,
-                    double *x, sap_info *info, void *work, hipStream_t st);
+                    double *x, sap_info *info, void *work, hipStream_t st, const SparseA *sp = nullptr);
 
 // Served form (batch.hip).
 sap_status serve_start(sap_ctx *ctx, size_t arena_bytes, int max_slots);

@@ -766,7 +766,7 @@ __global__ __launch_bounds__(1024) void delta_norm_kernel(const double *__restri
 // cannot resolve the remaining error) or after max_refine steps.
 sap_status run_lsqr(sap_ctx *ctx, const sap_problem *prob, const double *R, int64_t ldr, const double *x0,
                     const double *z, double tol, int maxiter, int mode, int max_refine, double *x, sap_info *info,
-                    void *work, hipStream_t s) {
+                    void *work, hipStream_t s, const SparseA *sp) {
   constexpr double kInnerTol = 0x1p-23;  // FP32 resolution of the inner test
   const int64_t m = prob->m;
   const int n = prob->n;
@@ -775,8 +775,15 @@ sap_status run_lsqr(sap_ctx *ctx, const sap_problem *prob, const double *R, int6
   const int nblk = (n + kTrsvB - 1) / kTrsvB;
   Carve cv(work);
   LsqrState *st = cv.take<LsqrState>(1);
-  const PassPlan plan = plan_pass(ctx, refine ? 2 : mode, m, n, prob->lda, prob->A);
-  const PassPlan plan_res = refine ? plan_pass(ctx, 3, m, n, prob->lda, prob->A) : plan;
+  if (sp && refine) return fail(ctx, SAP_EINVAL, "LSQR: the refinement form is not available for sparse A");
+  PassPlan plan{}, plan_res{};
+  if (sp) {
+    plan.grid = csr_pass_grid(ctx, *sp);
+    plan_res = plan;
+  } else {
+    plan = plan_pass(ctx, refine ? 2 : mode, m, n, prob->lda, prob->A);
+    plan_res = refine ? plan_pass(ctx, 3, m, n, prob->lda, prob->A) : plan;
+  }
   if (plan.grid > max_grid(ctx) || plan_res.grid > max_grid(ctx))
     return fail(ctx, SAP_EINVAL, "LSQR: internal grid larger than planned");
   double *qpart = cv.take<double>(static_cast<size_t>(max_grid(ctx)) * n);
@@ -849,7 +856,11 @@ sap_status run_lsqr(sap_ctx *ctx, const sap_problem *prob, const double *R, int6
   auto iteration = [&](const PassPlan &pl, const void *pv, const void *uin) {
     const int G = pl.grid;
     const int qsl = (G + kQSlice - 1) / kQSlice;
-    launch_pass(ctx, pl, prob->A, prob->lda, m, n, pv, uin, ubuf[ucur ^ 1], st, qpart, nrmpart, dyn, s);
+    if (sp)
+      launch_csr_pass(ctx, *sp, G, static_cast<const double *>(pv), static_cast<const double *>(uin), ubuf[ucur ^ 1],
+                      st, qpart, nrmpart, s);
+    else
+      launch_pass(ctx, pl, prob->A, prob->lda, m, n, pv, uin, ubuf[ucur ^ 1], st, qpart, nrmpart, dyn, s);
     ucur ^= 1;
     q_slices_kernel<<<dim3((n + 63) / 64, qsl), 256, 0, s>>>(qpart, G, n, qs);
     lsqr_mtq_kernel<<<ngemv, 1024, 0, s>>>(M, n, qs, qsl, nrmpart, G, v, vh, vpart, st);
