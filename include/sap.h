@@ -160,7 +160,7 @@ sap_status sps_apply(sap_ctx *ctx, const sps_sketch *S, const void *A, int64_t l
 sap_status sps_apply_noalloc(sap_ctx *ctx, const sps_sketch *S, const void *A, int64_t lda, sap_dtype a_type,
                              const double *b, int32_t n, void *Y, int64_t ldy, sap_dtype y_type, void *stream);
 
-/* Householder QR of Y (Alg. 1, "factor Q, R = QR(Y)"), in place, FP64.
+/* Householder QR of Y (the factorization step of Alg. 1), in place, FP64.
  * Y: device, column-major rows x cols (ldy >= rows), rows >= cols.  On return
  * the upper triangle holds R and the strict lower part the Householder
  * vectors v_k (unit leading entry implicit); tau (device, cols doubles)

@@ -83,6 +83,12 @@ def lib():
                                    ctypes.POINTER(LsqrInfo)]
         L.orc_solve_csr.argtypes = [_i64, _i32, _vp, _vp, _vp, _vp, _i32, _i32, _u64, _u64, _f64, _i32, _vp, _vp,
                                     _vp, ctypes.POINTER(SolveInfo)]
+        L.orc_hbm_params.argtypes = [_i32, _i32, _f64, _i32, ctypes.POINTER(_f64), ctypes.POINTER(_f64)]
+        L.orc_hbm_params.restype = ctypes.c_int
+        L.orc_hbm.argtypes = [_i64, _i32, _vp, _i64, _vp, _vp, _i64, _vp, _f64, _f64, _f64, _i32, _vp, _vp,
+                              ctypes.POINTER(LsqrInfo)]
+        L.orc_solve_hbm.argtypes = [_i64, _i32, _vp, _i64, _vp, _i32, _i32, _u64, _u64, _f64, _i32, _f64, _f64,
+                                    _vp, _vp, ctypes.POINTER(SolveInfo)]
         L.orc_lambert_w0.argtypes = [_f64]
         L.orc_lambert_w0.restype = _f64
         L.orc_embedding_dim.argtypes = [_i64, _i32, _f64, _f64]
@@ -384,6 +390,47 @@ def solve_csr(A, b, d, zeta, seed, tol=1e-12, maxiter=200, stream=0):
     return x, dict(status=STATUS.get(info.status, str(info.status)), iters=info.iters,
                    resid_est=info.resid_est, normar_est=info.normar_est, x0=x0, t_generate=info.t_generate,
                    t_apply=info.t_apply, t_qr=info.t_qr, t_iterate=info.t_iterate)
+
+
+# ------------------------------------------------- heavy-ball momentum ----
+def hbm_params(n, d, c=1.0, gd=False):
+    """(alpha, beta) of App. D.3 for eta = c sqrt(n/d): heavy ball, or gradient
+    descent when gd."""
+    a, b = _f64(0.0), _f64(0.0)
+    if lib().orc_hbm_params(int(n), int(d), float(c), 1 if gd else 0, ctypes.byref(a), ctypes.byref(b)) != 0:
+        raise ValueError("eta = c sqrt(n/d) must lie in [0, 1)")
+    return a.value, b.value
+
+
+def hbm(A, b, R, x0, alpha, beta, tol=1e-12, maxiter=200, history=False):
+    """Heavy-ball momentum (App. D.3) on A with M = R^-1.  Returns (x, info
+    dict[, iterates (t+1, n)])."""
+    A = _f64c(A)
+    m, n = A.shape
+    R = np.asfortranarray(R, dtype=np.float64)
+    x = np.zeros(n)
+    hist = np.zeros((maxiter + 1, n)) if history else None
+    info = LsqrInfo()
+    lib().orc_hbm(m, n, _p(A), n, _p(_f64c(b)), R.ctypes.data_as(_vp), R.shape[0], _p(_f64c(x0)), alpha, beta,
+                  tol, maxiter, _p(x), _p(hist), ctypes.byref(info))
+    d = dict(iters=info.iters, converged=bool(info.converged), resid_est=info.resid_est,
+             normar_est=info.normar_est)
+    if history:
+        return x, d, hist[:info.iters + 1]
+    return x, d
+
+
+def solve_hbm(A, b, d, zeta, seed, alpha, beta, tol=1e-12, maxiter=500, stream=0):
+    """Alg. 1 with heavy-ball momentum in place of LSQR.  Returns (x, info dict)."""
+    A = _f64c(A)
+    m, n = A.shape
+    x = np.zeros(n)
+    x0 = np.zeros(n)
+    info = SolveInfo()
+    lib().orc_solve_hbm(m, n, _p(A), n, _p(_f64c(b)), d, zeta, seed, stream, tol, maxiter, alpha, beta, _p(x),
+                        _p(x0), ctypes.byref(info))
+    return x, dict(status=STATUS.get(info.status, str(info.status)), iters=info.iters,
+                   resid_est=info.resid_est, normar_est=info.normar_est, x0=x0)
 
 
 def lambert_w0(z):

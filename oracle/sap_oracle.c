@@ -19,9 +19,10 @@
  *     rows with replacement, sort, redraw the first entry of every equal
  *     neighbour pair, repeat until distinct.  Signs +-1/sqrt(zeta) (Alg. 3),
  *     attached to the sorted positions.
- *   - Sketch apply Y = S [A b] (Alg. 1, "Form Y = SA"), dense and sparse route.
+ *   - Sketch apply Y = S [A b] (the sketching step of Alg. 1), dense and
+ *     sparse route.
  *   - Unblocked Householder QR with the LAPACK dlarfg sign convention
- *     (Alg. 1, "Factor Q, R = QR(Y)").
+ *     (the factorization step of Alg. 1).
  *   - Back / forward substitution with R and R^T (the preconditioner M = R^-1
  *     of Alg. 1 applied by triangular solves).
  *   - Preconditioned LSQR exactly as Alg. 2 (Paige & Saunders 1982).
@@ -29,6 +30,9 @@
  *     problems.
  *   - The same for a sparse A in CSR form: products, sketch apply, LSQR and
  *     Alg. 1 on the stored entries, in the order of the dense routes.
+ *   - Gradient descent with heavy-ball momentum (App. D.3) in place of LSQR,
+ *     with the step size and momentum the appendix derives from the
+ *     distortion estimate.
  *
  * Parity pins for each function live in the CPU test suite.
  */
@@ -568,6 +572,117 @@ void orc_lsqr_csr(int64_t m, int32_t n, const int64_t *indptr, const int32_t *in
 }
 
 /* ------------------------------------------------------------------------ */
+/* Gradient descent with heavy-ball momentum (App. D.3) in place of LSQR.    */
+/* ------------------------------------------------------------------------ */
+/* Step size and momentum of App. D.3 for a distortion estimate
+ * eta = c sqrt(n/d) (the paper's example takes c = 1 and mentions a larger c
+ * for robustness): heavy ball alpha = (1 - eta^2)^2, beta = eta^2; gradient
+ * descent (gd = 1) alpha = (1 - eta^2)^2 / (1 + eta^2), beta = 0.
+ * Returns 1 (and leaves the outputs alone) when eta is not in [0, 1). */
+int orc_hbm_params(int32_t n, int32_t d, double c, int32_t gd, double *alpha, double *beta)
+{
+    if (n < 1 || d < 1 || !(c > 0.0))
+        return 1;
+    double eta = c * sqrt((double)n / (double)d);
+    if (!(eta < 1.0))
+        return 1;
+    double e2 = eta * eta;
+    if (gd) {
+        *alpha = (1.0 - e2) * (1.0 - e2) / (1.0 + e2);
+        *beta = 0.0;
+    } else {
+        *alpha = (1.0 - e2) * (1.0 - e2);
+        *beta = e2;
+    }
+    return 0;
+}
+
+/* M M^T y = R^-1 R^-T y (two triangular solves), into out; tmp holds n. */
+static void orc_mmt(const double *R, int64_t ldr, int32_t n, const double *y, double *tmp, double *out)
+{
+    orc_forwardsub_t(R, ldr, n, y, tmp);
+    orc_backsub(R, ldr, n, tmp, out);
+}
+
+/* The paper's iteration, in its order:
+ *   x_{-1} = x_0,  v = M M^T A^T b,
+ *   for t = 1, 2, ...:  g_t = v - M M^T A^T A x_{t-1},
+ *                       x_t = x_{t-1} + alpha g_t + beta (x_{t-1} - x_{t-2}),
+ *                       stopping test.
+ * M = R^-1 by triangular solves.  The paper leaves the test open; reading (the
+ * counterpart of the LSQR test, with ||AM|| ~ 1): with r_t = b - A x_t and
+ * s_t = M^T A^T r_t, stop after update t when ||r_t|| = 0,
+ * ||s_t|| <= tol ||r_t|| or ||r_t|| <= tol ||b||.  At most maxiter updates;
+ * maxiter <= 0 returns x0.  info: iters = updates made, resid_est = ||r_t||,
+ * normar_est = ||s_t|| of the returned x.  history (nullable, maxiter + 1 rows
+ * of n) receives x_0, x_1, .... */
+static void orc_hbm_op(int64_t m, int32_t n, const orc_op *op, const double *b, const double *R, int64_t ldr,
+                       const double *x0, double alpha, double beta, double tol, int32_t maxiter, double *x,
+                       double *history, orc_lsqr_info *info)
+{
+    double *v = (double *)malloc(sizeof(double) * (size_t)n);
+    double *g = (double *)malloc(sizeof(double) * (size_t)n);
+    double *xprev = (double *)malloc(sizeof(double) * (size_t)n);
+    double *t1 = (double *)malloc(sizeof(double) * (size_t)n);
+    double *t2 = (double *)malloc(sizeof(double) * (size_t)n);
+    double *y = (double *)malloc(sizeof(double) * (size_t)m);
+
+    memcpy(x, x0, sizeof(double) * (size_t)n);
+    memcpy(xprev, x0, sizeof(double) * (size_t)n);
+    if (history)
+        memcpy(history, x0, sizeof(double) * (size_t)n);
+    info->iters = 0;
+    info->converged = 0;
+    info->resid_est = 0.0;
+    info->normar_est = 0.0;
+    double normb = orc_nrm2(m, b);
+    /* v = M M^T A^T b */
+    op->atv(op->ctx, b, t1);
+    orc_mmt(R, ldr, n, t1, t2, v);
+    for (int32_t t = 1; t <= maxiter; ++t) {
+        /* g_t = v - M M^T A^T A x_{t-1} */
+        op->av(op->ctx, x, y);
+        op->atv(op->ctx, y, t1);
+        orc_mmt(R, ldr, n, t1, t2, g);
+        for (int32_t c = 0; c < n; ++c)
+            g[c] = v[c] - g[c];
+        /* x_t = x_{t-1} + alpha g_t + beta (x_{t-1} - x_{t-2}) */
+        for (int32_t c = 0; c < n; ++c) {
+            double xn = x[c] + alpha * g[c] + beta * (x[c] - xprev[c]);
+            xprev[c] = x[c];
+            x[c] = xn;
+        }
+        info->iters = t;
+        if (history)
+            memcpy(history + (int64_t)t * n, x, sizeof(double) * (size_t)n);
+        /* stopping test on r_t and s_t = M^T A^T r_t */
+        op->av(op->ctx, x, y);
+        for (int64_t i = 0; i < m; ++i)
+            y[i] = b[i] - y[i];
+        double rn = orc_nrm2(m, y);
+        op->atv(op->ctx, y, t1);
+        orc_forwardsub_t(R, ldr, n, t1, t2);
+        double sn = orc_nrm2(n, t2);
+        info->resid_est = rn;
+        info->normar_est = sn;
+        if (rn == 0.0 || sn <= tol * rn || rn <= tol * normb) {
+            info->converged = 1;
+            break;
+        }
+    }
+    free(v); free(g); free(xprev); free(t1); free(t2); free(y);
+}
+
+void orc_hbm(int64_t m, int32_t n, const double *A, int64_t lda, const double *b, const double *R, int64_t ldr,
+             const double *x0, double alpha, double beta, double tol, int32_t maxiter, double *x, double *history,
+             orc_lsqr_info *info)
+{
+    orc_dense D = {m, n, A, lda};
+    orc_op op = {orc_dense_av, orc_dense_atv, &D};
+    orc_hbm_op(m, n, &op, b, R, ldr, x0, alpha, beta, tol, maxiter, x, history, info);
+}
+
+/* ------------------------------------------------------------------------ */
 /* Alg. 1 end to end.                                                         */
 /* ------------------------------------------------------------------------ */
 typedef struct orc_solve_info {
@@ -602,11 +717,12 @@ int orc_rank_deficient(const double *R, int64_t ldr, int32_t n, int32_t d)
  * x0 = R^-1 (Q^T S b)[0:n], LSQR.
  * Y_out (nullable, d x (n+1) column-major, ld d) receives the factored Y
  * (R in the upper triangle).  x receives the solution. */
-/* The steps of Alg. 1 after the sketch: QR of Y, rank test, x0, LSQR.  Shared
- * by the dense and the CSR solve. */
+/* The steps of Alg. 1 after the sketch: QR of Y, rank test, x0, LSQR (or,
+ * with hb non-null, heavy-ball momentum with step hb[0] and momentum hb[1]).
+ * Shared by the dense and the CSR solve. */
 static void orc_solve_finish(int64_t m, int32_t n, const orc_op *op, const double *b, int32_t d, double *Y,
-                             double *tau, double tol, int32_t maxiter, double *x, double *x0_out,
-                             orc_solve_info *info, double t2)
+                             double *tau, double tol, int32_t maxiter, const double *hb, double *x,
+                             double *x0_out, orc_solve_info *info, double t2)
 {
     int32_t nc = n + 1;
     double *x0 = (double *)malloc(sizeof(double) * (size_t)n);
@@ -621,7 +737,10 @@ static void orc_solve_finish(int64_t m, int32_t n, const orc_op *op, const doubl
         if (x0_out)
             memcpy(x0_out, x0, sizeof(double) * (size_t)n);
         orc_lsqr_info li;
-        orc_lsqr_op(m, n, op, b, Y, d, x0, tol, maxiter, x, NULL, &li);
+        if (hb) /* heavy-ball momentum (App. D.3): hb = {alpha, beta} */
+            orc_hbm_op(m, n, op, b, Y, d, x0, hb[0], hb[1], tol, maxiter, x, NULL, &li);
+        else
+            orc_lsqr_op(m, n, op, b, Y, d, x0, tol, maxiter, x, NULL, &li);
         info->iters = li.iters;
         info->resid_est = li.resid_est;
         info->normar_est = li.normar_est;
@@ -659,9 +778,40 @@ void orc_solve(int64_t m, int32_t n, const double *A, int64_t lda, const double 
     info->t_apply = t2 - t1;
     orc_dense D = {m, n, A, lda};
     orc_op op = {orc_dense_av, orc_dense_atv, &D};
-    orc_solve_finish(m, n, &op, b, d, Y, tau, tol, maxiter, x, x0_out, info, t2);
+    orc_solve_finish(m, n, &op, b, d, Y, tau, tol, maxiter, NULL, x, x0_out, info, t2);
     if (Y_out)
         memcpy(Y_out, Y, sizeof(double) * (size_t)d * (size_t)nc);
+    free(idx); free(sign); free(Y); free(tau);
+}
+
+/* Alg. 1 with heavy-ball momentum (App. D.3) in place of LSQR: the same
+ * sketch, QR and x0, then orc_hbm_op with step alpha and momentum beta. */
+void orc_solve_hbm(int64_t m, int32_t n, const double *A, int64_t lda, const double *b,
+                   int32_t d, int32_t zeta, uint64_t seed, uint64_t stream, double tol, int32_t maxiter,
+                   double alpha, double beta, double *x, double *x0_out, orc_solve_info *info)
+{
+    memset(info, 0, sizeof(*info));
+    if (zeta < 1 || zeta > ORC_MAX_ZETA || d < zeta || d < n + 1 || m < 1 || n < 1) {
+        info->status = 1;
+        return;
+    }
+    int32_t nc = n + 1;
+    int32_t *idx = (int32_t *)malloc(sizeof(int32_t) * (size_t)m * (size_t)zeta);
+    uint64_t *sign = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)m);
+    double *Y = (double *)malloc(sizeof(double) * (size_t)d * (size_t)nc);
+    double *tau = (double *)malloc(sizeof(double) * (size_t)nc);
+    double hb[2] = {alpha, beta};
+
+    double t0 = orc_now();
+    orc_sketch(seed, stream, m, d, zeta, idx, sign, NULL);
+    double t1 = orc_now();
+    orc_apply_sparse(m, d, zeta, idx, sign, A, lda, b, n, 1.0 / sqrt((double)zeta), Y, d, NULL, 0);
+    double t2 = orc_now();
+    info->t_generate = t1 - t0;
+    info->t_apply = t2 - t1;
+    orc_dense D = {m, n, A, lda};
+    orc_op op = {orc_dense_av, orc_dense_atv, &D};
+    orc_solve_finish(m, n, &op, b, d, Y, tau, tol, maxiter, hb, x, x0_out, info, t2);
     free(idx); free(sign); free(Y); free(tau);
 }
 
@@ -691,7 +841,7 @@ void orc_solve_csr(int64_t m, int32_t n, const int64_t *indptr, const int32_t *i
     info->t_apply = t2 - t1;
     orc_csr C = {m, n, indptr, indices, values};
     orc_op op = {orc_csr_av, orc_csr_atv, &C};
-    orc_solve_finish(m, n, &op, b, d, Y, tau, tol, maxiter, x, x0_out, info, t2);
+    orc_solve_finish(m, n, &op, b, d, Y, tau, tol, maxiter, NULL, x, x0_out, info, t2);
     if (Y_out)
         memcpy(Y_out, Y, sizeof(double) * (size_t)d * (size_t)nc);
     free(idx); free(sign); free(Y); free(tau);

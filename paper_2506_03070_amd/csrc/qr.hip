@@ -1,5 +1,5 @@
 // Blocked Householder QR of the sketch Y (d x ncols, column-major, FP64) on
-// gfx950 (Alg. 1 "factor Q, R = QR(Y)"; the paper calls a vendor QR).
+// gfx950 (the factorization step of Alg. 1; the paper calls a vendor QR).
 //
 // Right-looking blocked algorithm (Golub & Van Loan 5.2.2) with the compact
 // WY form Q = I - V T V^T of Schreiber & Van Loan (1989), one launch per
