@@ -234,6 +234,37 @@ typedef struct sap_info {
 sap_status sap_solve(sap_ctx *ctx, const sap_problem *prob, const sap_params *params, double *x,
                      sap_info *info, void *stream);
 
+/* Gradient descent with heavy-ball momentum (App. D.3) as the iterative
+ * method of Alg. 1, in place of LSQR: x_{t+1} = x_t + alpha g + beta (x_t -
+ * x_{t-1}) with g = M M^T A^T (b - A x_t), one fused pass over A a step.
+ * alpha > 0 takes (alpha, beta) as given (0 <= beta < 1); alpha <= 0 takes
+ * the appendix's pair for the distortion estimate eta = eta_scale sqrt(n/d)
+ * (eta_scale <= 0 means 1; the appendix mentions sqrt(1.1) for robustness):
+ * alpha = (1 - eta^2)^2 and beta = eta^2, or with gradient_descent = 1
+ * alpha = (1 - eta^2)^2 / (1 + eta^2) and beta = 0. */
+typedef struct sap_hbm_params {
+    double alpha;
+    double beta;
+    double eta_scale;
+    int32_t gradient_descent;
+    int32_t pad_;
+} sap_hbm_params;
+
+/* Alg. 1 with the momentum method of sap_hbm_params in place of LSQR: the
+ * sketch, QR and x0 of sap_solve, then steps from x0.  params as for
+ * sap_solve (d = 0 chooses d; fixed_iters runs a set number of steps); modes
+ * FP64 and MIXED_FP32.  Stopping (the appendix leaves the test open;
+ * reading, the counterpart of the LSQR test): stop at x_t, t >= 1, when
+ * ||r_t|| = 0, ||M^T A^T r_t|| <= tol ||r_t|| or ||r_t|| <= tol ||b||, with
+ * r_t = b - A x_t; at most maxiter steps.  info: iters = steps taken,
+ * resid_est = ||r_t||, normar_est = ||M^T A^T r_t|| of the returned x.
+ * The step direction is formed from r_t (the appendix writes it as
+ * v - M M^T A^T A x_t with v = M M^T A^T b, the same vector in exact
+ * arithmetic).  Blocking.  Errors as for sap_solve, and SAP_EINVAL for a
+ * derived eta >= 1 or beta outside [0, 1). */
+sap_status sap_solve_hbm(sap_ctx *ctx, const sap_problem *prob, const sap_params *params,
+                         const sap_hbm_params *hbm, double *x, sap_info *info, void *stream);
+
 /* Preconditioned LSQR alone (Alg. 2) on A M with M = R^-1 for a given R
  * (device, upper triangle of column-major n x n, leading dimension ldr) and
  * initial guess x0 (device, n doubles; may alias x).  A may be F64 or F32

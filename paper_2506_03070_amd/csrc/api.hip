@@ -367,8 +367,10 @@ sap_status sap_solve_batch(sap_ctx *ctx, int32_t count, const sap_problem *probs
   return run_batch(ctx, count, probs, params, x, info, static_cast<hipStream_t>(stream));
 }
 
-sap_status sap_solve(sap_ctx *ctx, const sap_problem *prob, const sap_params *par_in, double *x, sap_info *info,
-                     void *stream) {
+// Alg. 1 with LSQR (hb == nullptr) or heavy-ball momentum (App. D.3) as the
+// iterative method.
+static sap_status solve_dense(sap_ctx *ctx, const sap_problem *prob, const sap_params *par_in,
+                              const sap_hbm_params *hb, double *x, sap_info *info, void *stream) {
   if (!ctx) return SAP_EINVAL;
   sap_status s = check_problem(ctx, prob);
   if (s != SAP_OK) return s;
@@ -411,6 +413,24 @@ sap_status sap_solve(sap_ctx *ctx, const sap_problem *prob, const sap_params *pa
       if (sap_iteration_estimate(n, d, par->tol, &t) != SAP_OK)
         return fail(ctx, SAP_EINVAL, "sap_solve: fixed_iters < 0 needs tol in (0, 1)");
       fixed = t;
+    }
+  }
+  // step size and momentum of the momentum method
+  double hb_alpha = 0.0, hb_beta = 0.0;
+  if (hb) {
+    if (mode != SAP_MODE_FP64 && mode != SAP_MODE_MIXED_FP32)
+      return fail(ctx, SAP_EINVAL, "sap_solve_hbm: mode must be FP64 or MIXED_FP32");
+    if (hb->alpha > 0.0) {
+      if (!(hb->beta >= 0.0 && hb->beta < 1.0)) return fail(ctx, SAP_EINVAL, "sap_solve_hbm: need 0 <= beta < 1");
+      hb_alpha = hb->alpha;
+      hb_beta = hb->beta;
+    } else {
+      const double c = hb->eta_scale > 0.0 ? hb->eta_scale : 1.0;
+      const double eta = c * std::sqrt(static_cast<double>(n) / static_cast<double>(d));
+      if (!(eta < 1.0)) return fail(ctx, SAP_EINVAL, "sap_solve_hbm: eta_scale sqrt(n/d) must be below 1");
+      const double e2 = eta * eta;
+      hb_alpha = hb->gradient_descent ? (1.0 - e2) * (1.0 - e2) / (1.0 + e2) : (1.0 - e2) * (1.0 - e2);
+      hb_beta = hb->gradient_descent ? 0.0 : e2;
     }
   }
   hipStream_t st = static_cast<hipStream_t>(stream);
@@ -493,8 +513,12 @@ sap_status sap_solve(sap_ctx *ctx, const sap_problem *prob, const sap_params *pa
   // MIXED_BF16SA iterates as MIXED_FP32_REFINE (FP32 passes, FP64 refinement)
   const int lsqr_mode = (mode == SAP_MODE_FP64) ? 0 : (mode == SAP_MODE_MIXED_FP32 ? 1 : 2);
   sap_info li{};
-  s = run_lsqr(ctx, prob, Y, d, nullptr, Y + static_cast<int64_t>(n) * d, fixed ? 0.0 : par->tol,
-               fixed ? fixed : par->maxiter, lsqr_mode, par->max_refine, x, &li, work, st);
+  if (hb)
+    s = run_hbm(ctx, prob, Y, d, Y + static_cast<int64_t>(n) * d, fixed ? 0.0 : par->tol,
+                fixed ? fixed : par->maxiter, lsqr_mode, hb_alpha, hb_beta, x, &li, work, st);
+  else
+    s = run_lsqr(ctx, prob, Y, d, nullptr, Y + static_cast<int64_t>(n) * d, fixed ? 0.0 : par->tol,
+                 fixed ? fixed : par->maxiter, lsqr_mode, par->max_refine, x, &li, work, st);
   if (s != SAP_OK && s != SAP_NOT_CONVERGED) return s;
   if (fixed && s == SAP_NOT_CONVERGED) s = SAP_OK;  // the set count was run
   SAP_HIP_TRY(hipEventRecord(ev[4], st));
@@ -516,6 +540,18 @@ sap_status sap_solve(sap_ctx *ctx, const sap_problem *prob, const sap_params *pa
   }
   if (s == SAP_NOT_CONVERGED) (void)fail(ctx, s, "sap_solve: maxiter reached before the stopping test");
   return s;
+}
+
+sap_status sap_solve(sap_ctx *ctx, const sap_problem *prob, const sap_params *params, double *x, sap_info *info,
+                     void *stream) {
+  return solve_dense(ctx, prob, params, nullptr, x, info, stream);
+}
+
+sap_status sap_solve_hbm(sap_ctx *ctx, const sap_problem *prob, const sap_params *params,
+                         const sap_hbm_params *hbm, double *x, sap_info *info, void *stream) {
+  if (!ctx) return SAP_EINVAL;
+  if (!hbm) return fail(ctx, SAP_EINVAL, "sap_solve_hbm: NULL momentum parameters");
+  return solve_dense(ctx, prob, params, hbm, x, info, stream);
 }
 
 static sap_status check_csr(sap_ctx *ctx, const sap_csr *A) {

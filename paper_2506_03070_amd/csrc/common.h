@@ -278,6 +278,11 @@ size_t lsqr_workspace_bytes(sap_ctx *ctx, int64_t m, int n);
 sap_status run_lsqr(sap_ctx *ctx, const sap_problem *prob, const double *R, int64_t ldr,
                     const double *x0, const double *z, double tol, int maxiter, int mode, int max_refine,
                     double *x, sap_info *info, void *work, hipStream_t st, const SparseA *sp = nullptr);
+// Heavy-ball momentum (App. D.3) in place of LSQR (lsqr.hip): x0 = R^-1 z,
+// step alpha, momentum beta; the LSQR workspace; mode 0 (FP64) or 1 (FP32 A).
+sap_status run_hbm(sap_ctx *ctx, const sap_problem *prob, const double *R, int64_t ldr, const double *z,
+                   double tol, int maxiter, int mode, double alpha, double beta, double *x, sap_info *info,
+                   void *work, hipStream_t st);
 
 // Served form (batch.hip).
 sap_status serve_start(sap_ctx *ctx, size_t arena_bytes, int max_slots);

@@ -754,6 +754,183 @@ __global__ __launch_bounds__(1024) void delta_norm_kernel(const double *__restri
 
 }  // namespace
 
+namespace {
+
+// The LSQR (and momentum) buffers carved from the workspace, in the order
+// lsqr_workspace_bytes counts them.
+struct LsqrBufs {
+  LsqrState *st;
+  double *qpart, *nrmpart, *v, *w, *p, *xin;
+  // u alternates between two buffers: with several waves across a row
+  // (n > 1024), every wave of the row reads u_in[i] while one of them writes
+  // u_out[i], so a pass must not update u in place.  FP32 values in the
+  // refinement form.
+  double *ubuf[2];
+  int *flags, *flags_x0, *err;
+  unsigned int *ticket, *dyn;
+  double *normpart, *M, *Mt, *qs, *vh, *vpart;
+  float *p32;
+  double *xprev, *dnorm;
+  TrsvFactor f;
+  int nblk, nslices, ngemv;
+};
+
+LsqrBufs carve_lsqr(sap_ctx *ctx, void *work, int64_t m, int n) {
+  LsqrBufs B;
+  Carve cv(work);
+  B.nblk = (n + kTrsvB - 1) / kTrsvB;
+  B.st = cv.take<LsqrState>(1);
+  B.qpart = cv.take<double>(static_cast<size_t>(max_grid(ctx)) * n);
+  B.nrmpart = cv.take<double>(max_grid(ctx));
+  B.v = cv.take<double>(n);
+  B.w = cv.take<double>(n);
+  B.p = cv.take<double>(n);
+  B.xin = cv.take<double>(n);
+  B.ubuf[0] = cv.take<double>(m);
+  B.ubuf[1] = cv.take<double>(m);
+  B.flags = cv.take<int>(3 * B.nblk + 2);
+  B.flags_x0 = B.flags + 2 * B.nblk;
+  B.err = cv.take<int>(4);
+  B.ticket = reinterpret_cast<unsigned int *>(B.err + 1);
+  B.dyn = cv.take<unsigned int>(2);  // pass row-claim counters
+  B.normpart = cv.take<double>(4096);
+  B.nslices = (max_grid(ctx) + kQSlice - 1) / kQSlice;
+  B.M = cv.take<double>(static_cast<size_t>(n) * n);
+  B.Mt = cv.take<double>(static_cast<size_t>(n) * n);
+  B.qs = cv.take<double>(static_cast<size_t>(B.nslices) * n);
+  B.vh = cv.take<double>(n);
+  B.ngemv = (n + 15) / 16;
+  B.vpart = cv.take<double>(B.ngemv);
+  B.p32 = cv.take<float>(n);
+  B.xprev = cv.take<double>(n);
+  B.dnorm = cv.take<double>(2);
+  trsv_factor_carve(B.f, cv, n);
+  return B;
+}
+
+// x0 (R^-1 z when z is given, else a copy of x0), then M = R^-1 and M^T.
+sap_status setup_precond(sap_ctx *ctx, const double *R, int64_t ldr, const double *x0, const double *z, double *x,
+                         LsqrBufs &B, int n, hipStream_t s) {
+  sap_status sst = trsv_prepare(ctx, R, ldr, B.f, s);
+  if (sst != SAP_OK) return sst;
+  SAP_HIP_TRY(hipMemsetAsync(B.err, 0, 4 * sizeof(int), s));
+  if (z) {
+    // x0 = R^-1 z: the minimiser of ||S b - S A x|| (Alg. 1, initial guess)
+    sst = trsv_solve(ctx, B.f, true, z, x, B.flags_x0, B.err, s);
+    if (sst != SAP_OK) return sst;
+  } else {
+    // x0 may alias x: copy first.
+    copy_f64_kernel<<<(n + 255) / 256, 256, 0, s>>>(x0, B.xin, n);
+    copy_f64_kernel<<<(n + 255) / 256, 256, 0, s>>>(B.xin, x, n);
+  }
+  // M = R^-1 and its transpose (the columns a workgroup builds sit in LDS)
+  const unsigned nt = static_cast<unsigned>((n + 31) / 32);
+  const int ci = tri_inverse_cols(n);
+  const size_t lds = static_cast<size_t>(ci) * (static_cast<size_t>(n) + kInvWaves * kWave) * sizeof(double);
+  const unsigned gi = static_cast<unsigned>((n + ci - 1) / ci);
+  switch (ci) {
+    case 8: tri_inverse_kernel<8><<<gi, kInvThreads, lds, s>>>(R, ldr, n, B.f.Dup, B.M); break;
+    case 4: tri_inverse_kernel<4><<<gi, kInvThreads, lds, s>>>(R, ldr, n, B.f.Dup, B.M); break;
+    case 2: tri_inverse_kernel<2><<<gi, kInvThreads, lds, s>>>(R, ldr, n, B.f.Dup, B.M); break;
+    default: tri_inverse_kernel<1><<<gi, kInvThreads, lds, s>>>(R, ldr, n, B.f.Dup, B.M); break;
+  }
+  inverse_transpose_kernel<<<dim3(nt, nt), 256, 0, s>>>(B.M, n, B.Mt);
+  SAP_HIP_TRY(hipGetLastError());
+  return SAP_OK;
+}
+
+// ---- heavy-ball momentum (App. D.3) ----------------------------------------
+// s = M^T q (q summed from the pass slices: q = A^T r, r = b - A x); one wave
+// per entry j (column j of M, rows 0..j); per-workgroup partials of ||s||^2.
+__global__ __launch_bounds__(1024) void hbm_mtq_kernel(const double *__restrict__ M, int n,
+                                                       const double *__restrict__ qs, int nslices,
+                                                       double *__restrict__ sv, double *__restrict__ spart,
+                                                       const LsqrState *st) {
+  __shared__ double q[kMaxN];
+  __shared__ double wsum[16];
+  if (st->done) return;
+  const int t = threadIdx.x;
+  for (int c = t; c < n; c += 1024) {
+    double a = 0.0;
+    for (int k = 0; k < nslices; ++k) a += qs[static_cast<int64_t>(k) * n + c];
+    q[c] = a;
+  }
+  __syncthreads();
+  const int lane = t & (kWave - 1), wave = t / kWave;
+  const int j = blockIdx.x * 16 + wave;
+  double sq = 0.0;
+  if (j < n) {
+    const double *__restrict__ col = M + static_cast<int64_t>(j) * n;
+    double acc = 0.0;
+    for (int k = lane; k <= j; k += kWave) acc += col[k] * q[k];
+    acc = wave_sum_u(acc);
+    if (lane == 0) sv[j] = acc;
+    sq = acc * acc;
+  }
+  if (lane == 0) wsum[wave] = sq;
+  __syncthreads();
+  if (t == 0) {
+    double a = 0.0;
+    for (int w = 0; w < 16; ++w) a += wsum[w];
+    spart[blockIdx.x] = a;
+  }
+}
+
+// One step from x_t (t updates made): the stopping test on x_t when t >= 1
+// (||r_t|| = 0, ||s_t|| <= tol ||r_t|| or ||r_t|| <= tol ||b||), or the cap
+// t = maxiter; otherwise g = M s_t (the paper's g_{t+1}, formed from the
+// residual), delta <- alpha g + beta delta and x <- x + delta, so that
+// delta = x_{t+1} - x_t carries the momentum.  Every workgroup takes the same
+// decision from the same partials; only workgroup 0 writes the state.
+__global__ __launch_bounds__(1024) void hbm_step_kernel(const double *__restrict__ Mt, int n,
+                                                        const double *__restrict__ sv,
+                                                        const double *__restrict__ spart, int nspart,
+                                                        const double *__restrict__ nrmpart, int G, int t,
+                                                        double alpha, double beta, double *__restrict__ delta,
+                                                        double *__restrict__ x, LsqrState *st) {
+  __shared__ double scr[16];
+  __shared__ double ss[kMaxN];
+  if (st->done) return;
+  const double rn = beta_from_partials(nrmpart, G, scr);
+  double a = 0.0;
+  for (int k = threadIdx.x; k < nspart; k += 1024) a += spart[k];
+  const double sn = sqrt(wg_sum(a, scr));
+  const bool conv = t >= 1 && (rn == 0.0 || sn <= st->tol * rn || rn <= st->tol * st->normb);
+  if (conv || t >= st->maxiter) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      st->done = 1;
+      st->converged = conv ? 1 : 0;
+      st->total_iters = t;
+      st->resid_est = rn;
+      st->normar_est = sn;
+    }
+    return;
+  }
+  for (int c = threadIdx.x; c < n; c += 1024) ss[c] = sv[c];
+  __syncthreads();
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  const int rr = blockIdx.x * 16 + wave;
+  if (rr < n) {
+    const double *__restrict__ col = Mt + static_cast<int64_t>(rr) * n;
+    double acc = 0.0;
+    for (int k = rr + lane; k < n; k += kWave) acc += col[k] * ss[k];
+    acc = wave_sum_u(acc);
+    if (lane == 0) {
+      const double dl = alpha * acc + beta * delta[rr];
+      delta[rr] = dl;
+      x[rr] += dl;
+    }
+  }
+}
+
+__global__ void zero_f64_kernel(double *__restrict__ p, int n) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < n) p[i] = 0.0;
+}
+
+}  // namespace
+
+
 // Runs LSQR (Alg. 2) from x0 on A R^-1.  mode 0: A in FP64; mode 1: A
 // stored in FP32, FP64 arithmetic throughout; mode 2: A stored in FP32,
 // residual refinement: each outer step forms r = b - A x with FP64
@@ -772,9 +949,6 @@ sap_status run_lsqr(sap_ctx *ctx, const sap_problem *prob, const double *R, int6
   const int n = prob->n;
   if (n > kMaxN) return fail(ctx, SAP_EINVAL, "LSQR: n > 8192 is not supported");
   const bool refine = mode == 2;
-  const int nblk = (n + kTrsvB - 1) / kTrsvB;
-  Carve cv(work);
-  LsqrState *st = cv.take<LsqrState>(1);
   if (sp && refine) return fail(ctx, SAP_EINVAL, "LSQR: the refinement form is not available for sparse A");
   PassPlan plan{}, plan_res{};
   if (sp) {
@@ -786,64 +960,19 @@ sap_status run_lsqr(sap_ctx *ctx, const sap_problem *prob, const double *R, int6
   }
   if (plan.grid > max_grid(ctx) || plan_res.grid > max_grid(ctx))
     return fail(ctx, SAP_EINVAL, "LSQR: internal grid larger than planned");
-  double *qpart = cv.take<double>(static_cast<size_t>(max_grid(ctx)) * n);
-  double *nrmpart = cv.take<double>(max_grid(ctx));
-  double *v = cv.take<double>(n);
-  double *w = cv.take<double>(n);
-  double *p = cv.take<double>(n);
-  double *xin = cv.take<double>(n);
-  // u alternates between two buffers: with several waves across a row
-  // (n > 1024), every wave of the row reads u_in[i] while one of them writes
-  // u_out[i], so a pass must not update u in place.  FP32 values in the
-  // refinement form.
-  double *ubuf[2] = {cv.take<double>(m), cv.take<double>(m)};
+  LsqrBufs B = carve_lsqr(ctx, work, m, n);
+  LsqrState *st = B.st;
+  double *qpart = B.qpart, *nrmpart = B.nrmpart, *v = B.v, *w = B.w, *p = B.p;
+  double *ubuf[2] = {B.ubuf[0], B.ubuf[1]};
   int ucur = 0;  // ubuf[ucur] holds the current u
-  int *flags = cv.take<int>(3 * nblk + 2);
-  int *flags_x0 = flags + 2 * nblk;
-  int *err = cv.take<int>(4);
-  unsigned int *ticket = reinterpret_cast<unsigned int *>(err + 1);
-  unsigned int *dyn = cv.take<unsigned int>(2);  // pass row-claim counters
-  double *normpart = cv.take<double>(4096);
-  const int nslices = (max_grid(ctx) + kQSlice - 1) / kQSlice;
-  double *M = cv.take<double>(static_cast<size_t>(n) * n);
-  double *Mt = cv.take<double>(static_cast<size_t>(n) * n);
-  double *qs = cv.take<double>(static_cast<size_t>(nslices) * n);
-  double *vh = cv.take<double>(n);
-  const int ngemv = (n + 15) / 16;
-  double *vpart = cv.take<double>(ngemv);
-  float *p32 = cv.take<float>(n);
-  double *xprev = cv.take<double>(n);
-  double *dnorm = cv.take<double>(2);
-  TrsvFactor f;
-  trsv_factor_carve(f, cv, n);
-
-  sap_status sst = trsv_prepare(ctx, R, ldr, f, s);
+  int *flags = B.flags, *err = B.err;
+  unsigned int *ticket = B.ticket, *dyn = B.dyn;
+  double *normpart = B.normpart, *M = B.M, *Mt = B.Mt, *qs = B.qs, *vh = B.vh, *vpart = B.vpart;
+  float *p32 = B.p32;
+  double *xprev = B.xprev, *dnorm = B.dnorm;
+  const int nblk = B.nblk, ngemv = B.ngemv;
+  sap_status sst = setup_precond(ctx, R, ldr, x0, z, x, B, n, s);
   if (sst != SAP_OK) return sst;
-  SAP_HIP_TRY(hipMemsetAsync(err, 0, 4 * sizeof(int), s));
-  if (z) {
-    // x0 = R^-1 z: the minimiser of ||S b - S A x|| (Alg. 1, initial guess)
-    sst = trsv_solve(ctx, f, true, z, x, flags_x0, err, s);
-    if (sst != SAP_OK) return sst;
-  } else {
-    // x0 may alias x: copy first.
-    copy_f64_kernel<<<(n + 255) / 256, 256, 0, s>>>(x0, xin, n);
-    copy_f64_kernel<<<(n + 255) / 256, 256, 0, s>>>(xin, x, n);
-  }
-  // M = R^-1 and its transpose (the columns a workgroup builds sit in LDS)
-  {
-    const unsigned nt = static_cast<unsigned>((n + 31) / 32);
-    const int ci = tri_inverse_cols(n);
-    const size_t lds = static_cast<size_t>(ci) * (static_cast<size_t>(n) + kInvWaves * kWave) * sizeof(double);
-    const unsigned gi = static_cast<unsigned>((n + ci - 1) / ci);
-    switch (ci) {
-      case 8: tri_inverse_kernel<8><<<gi, kInvThreads, lds, s>>>(R, ldr, n, f.Dup, M); break;
-      case 4: tri_inverse_kernel<4><<<gi, kInvThreads, lds, s>>>(R, ldr, n, f.Dup, M); break;
-      case 2: tri_inverse_kernel<2><<<gi, kInvThreads, lds, s>>>(R, ldr, n, f.Dup, M); break;
-      default: tri_inverse_kernel<1><<<gi, kInvThreads, lds, s>>>(R, ldr, n, f.Dup, M); break;
-    }
-    inverse_transpose_kernel<<<dim3(nt, nt), 256, 0, s>>>(M, n, Mt);
-    SAP_HIP_TRY(hipGetLastError());
-  }
   lsqr_init_state_kernel<<<1, 256, 0, s>>>(st, refine ? kInnerTol : tol, maxiter, flags, 2 * nblk, 0,
                                            refine ? 1 : 0, dyn);
   const int ngrid = static_cast<int>(std::min<int64_t>(256, (m + 1023) / 1024));
@@ -929,6 +1058,59 @@ sap_status run_lsqr(sap_ctx *ctx, const sap_problem *prob, const double *R, int6
     info->normar_est = hs.normar_est;
   }
   return converged ? SAP_OK : SAP_NOT_CONVERGED;
+}
+
+// Heavy-ball momentum (App. D.3) in place of LSQR, on the dense pass: each
+// step is one fused pass (r = b - A x and q = A^T r), q from the slices,
+// s = M^T q, then the test and the update with g = M s.  The paper writes the
+// gradient as v - M M^T A^T A x with v = M M^T A^T b; forming r first gives
+// the same vector without the cancellation of those two terms near x*.
+sap_status run_hbm(sap_ctx *ctx, const sap_problem *prob, const double *R, int64_t ldr, const double *z,
+                   double tol, int maxiter, int mode, double alpha, double beta, double *x, sap_info *info,
+                   void *work, hipStream_t s) {
+  const int64_t m = prob->m;
+  const int n = prob->n;
+  if (n > kMaxN) return fail(ctx, SAP_EINVAL, "momentum: n > 8192 is not supported");
+  if (mode != 0 && mode != 1) return fail(ctx, SAP_EINVAL, "momentum: mode must be FP64 or MIXED_FP32");
+  const PassPlan plan = plan_pass(ctx, mode, m, n, prob->lda, prob->A);
+  if (plan.grid > max_grid(ctx)) return fail(ctx, SAP_EINVAL, "momentum: internal grid larger than planned");
+  LsqrBufs B = carve_lsqr(ctx, work, m, n);
+  sap_status sst = setup_precond(ctx, R, ldr, nullptr, z, x, B, n, s);
+  if (sst != SAP_OK) return sst;
+  LsqrState *st = B.st;
+  double *delta = B.w, *sv = B.vh;
+  // c_ap = -1, c_u = 1: every pass forms r = b - A x
+  lsqr_init_state_kernel<<<1, 256, 0, s>>>(st, tol, maxiter, B.flags, 2 * B.nblk, 0, 0, B.dyn);
+  zero_f64_kernel<<<(n + 255) / 256, 256, 0, s>>>(delta, n);
+  const int ngrid = static_cast<int>(std::min<int64_t>(256, (m + 1023) / 1024));
+  norm_kernel<<<ngrid, 1024, 0, s>>>(prob->b, m, B.normpart, B.ticket, st);
+  SAP_HIP_TRY(hipGetLastError());
+  const int G = plan.grid;
+  const int qsl = (G + kQSlice - 1) / kQSlice;
+  const int batch = 8;
+  const int max_batches = maxiter / batch + 2;
+  LsqrState hs{};
+  int t = 0;
+  for (int nbatch = 0;; ++nbatch) {
+    if (nbatch > max_batches) return fail(ctx, SAP_EDEVICE, "momentum: device never reported completion");
+    for (int k = 0; k < batch; ++k, ++t) {
+      launch_pass(ctx, plan, prob->A, prob->lda, m, n, x, prob->b, B.ubuf[0], st, B.qpart, B.nrmpart, B.dyn, s);
+      q_slices_kernel<<<dim3((n + 63) / 64, qsl), 256, 0, s>>>(B.qpart, G, n, B.qs);
+      hbm_mtq_kernel<<<B.ngemv, 1024, 0, s>>>(B.M, n, B.qs, qsl, sv, B.vpart, st);
+      hbm_step_kernel<<<B.ngemv, 1024, 0, s>>>(B.Mt, n, sv, B.vpart, B.ngemv, B.nrmpart, G, t, alpha, beta, delta,
+                                               x, st);
+    }
+    SAP_HIP_TRY(hipGetLastError());
+    SAP_HIP_TRY(hipMemcpyAsync(&hs, st, sizeof(LsqrState), hipMemcpyDeviceToHost, s));
+    SAP_HIP_TRY(hipStreamSynchronize(s));
+    if (hs.done) break;
+  }
+  if (info) {
+    info->iters = hs.total_iters;
+    info->resid_est = hs.resid_est;
+    info->normar_est = hs.normar_est;
+  }
+  return hs.converged ? SAP_OK : SAP_NOT_CONVERGED;
 }
 
 }  // namespace sap
