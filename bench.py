@@ -47,8 +47,10 @@ def parse():
     ap.add_argument("--zeta", type=int, default=8)
     ap.add_argument("--fig5-m", type=int, default=600000)
     ap.add_argument("--fig5-n", default="300,600,1000,1300")
-    ap.add_argument("--forms", default="mixed,batched,served,fig5,sparse",
-                    help="comma list of extra forms to run (mixed, batched, served, fig5, sparse; empty for none)")
+    ap.add_argument("--forms", default="mixed,batched,served,fig5,sparse,hbm",
+                    help="comma list of extra forms to run (mixed, batched, served, fig5, sparse, hbm; empty for none)")
+    ap.add_argument("--hbm-m", type=int, default=1 << 19)
+    ap.add_argument("--hbm-n", type=int, default=500)
     ap.add_argument("--sparse-m", type=int, default=500000)
     ap.add_argument("--sparse-n", type=int, default=500)
     ap.add_argument("--sparse-reps", type=int, default=5)
@@ -659,6 +661,52 @@ def form_sparse(args, sap, torch, inputs):
     return out
 
 
+def form_hbm(args, sap, torch, inputs):
+    """App. D.3's comparison (Fig. 6): LSQR, heavy-ball momentum with
+    eta = sqrt(n/d) and with the safer sqrt(1.1) sqrt(n/d), and gradient
+    descent, on a leverage-skewed dense problem and on the hard case of
+    Sec. 4.1 (the first n columns of the identity, where sqrt(n/d)
+    underestimates the distortion), to tol 1e-10 (maxiter 400).  Reports time,
+    steps and ||A(x - x_ref)|| / ||b|| with x_ref LSQR's solution."""
+    m, n, d, zeta, tol = args.hbm_m, args.hbm_n, 4 * args.hbm_n, 8, 1e-10
+    rows = []
+    for kind in ("svd", "identity"):
+        if kind == "svd":
+            A, b, _ = inputs.make_problem_torch(m, n, kind="svd", cond=1e8, noise=1e-6, seed=inputs.config_seed(7),
+                                                row_scale=True, device="cuda")
+        else:
+            A = torch.zeros(m, n, dtype=torch.float64, device="cuda")
+            A[torch.arange(n, device="cuda"), torch.arange(n, device="cuda")] = 1.0
+            g = torch.Generator(device="cuda")
+            g.manual_seed(inputs.config_seed(7) + 1)
+            b = torch.randn(m, generator=g, device="cuda", dtype=torch.float64)
+        x = torch.empty(n, dtype=torch.float64, device="cuda")
+        nb = float(b.norm())
+
+        def timed(fn):
+            fn()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = fn()
+            torch.cuda.synchronize()
+            return (time.perf_counter() - t0) * 1e3, r
+
+        ms, r = timed(lambda: sap.sap_solve(A, b, d, zeta, 13, tol=tol, maxiter=400, x=x))
+        xref = x.clone()
+        row = {"problem": kind, "lsqr": {"ms": ms, "iters": r.info["iters"], "status": r.info["status_name"]}}
+        for tag, kw in (("hbm", {}), ("hbm_safe", {"eta_scale": 1.1 ** 0.5}), ("gd", {"gradient_descent": True})):
+            ms, r = timed(lambda: sap.sap_solve_hbm(A, b, d, zeta, 13, tol=tol, maxiter=400, x=x, **kw))
+            err = float((A @ (x - xref)).norm()) / nb
+            row[tag] = {"ms": ms, "iters": r.info["iters"], "status": r.info["status_name"], "err_vs_lsqr": err}
+        log(f"bench[hbm]: {row}")
+        rows.append(row)
+        del A, b, x, xref
+        torch.cuda.empty_cache()
+    return {"workload": f"App. D.3 / Fig. 6: m = {m}, n = {n}, d = 4n, zeta = {zeta}, tol {tol:g}; "
+                        "leverage-skewed U diag(sigma) V^T (sigma 1..1e-8) and the first n columns of the identity",
+            "rows": rows}
+
+
 def kernel_apply(args, sap, torch, inputs):
     """sps_apply alone: warm-up, then --steps applies timed with events on
     the current stream (the stream the library launches on).  One JSON line."""
@@ -826,7 +874,7 @@ def main():
     torch.cuda.empty_cache()
     for f in [f for f in args.forms.split(",") if f]:
         fn = {"mixed": form_mixed, "batched": form_batched, "served": form_served, "fig5": form_fig5,
-              "sparse": form_sparse}.get(f)
+              "sparse": form_sparse, "hbm": form_hbm}.get(f)
         if fn is None:
             log(f"bench: unknown form {f}")
             continue
