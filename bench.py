@@ -66,9 +66,10 @@ def parse():
     ap.add_argument("--gaussian-input", action="store_true",
                     help="column-scaled Gaussian A of the same shape instead of the SVD-built one (cheap to "
                          "generate; for counter runs, where the kernels move the same bytes)")
-    ap.add_argument("--kernel", choices=["apply"], default=None,
+    ap.add_argument("--kernel", choices=["apply", "qr"], default=None,
                     help="time one kernel alone instead of the solve (for profiler runs): 'apply' times "
-                         "sps_apply (Y = S [A b]) on an --m x --n matrix of --a-dtype into a --y-dtype Y")
+                         "sps_apply (Y = S [A b]) on an --m x --n matrix of --a-dtype into a --y-dtype Y; "
+                         "'qr' times sap_qr on a --d x (--n + 1) FP64 matrix")
     ap.add_argument("--a-dtype", choices=["f64", "f32", "bf16"], default="f64")
     ap.add_argument("--y-dtype", choices=["f64", "f32"], default="f64")
     ap.add_argument("--copy-ref-mib", type=int, default=2048,
@@ -738,6 +739,36 @@ def kernel_apply(args, sap, torch, inputs):
           flush=True)
 
 
+def kernel_qr(args, sap, torch, inputs):
+    """sap_qr alone on a seeded Gaussian d x (n+1) FP64 matrix (the shape of
+    the sketch [SA Sb]): warm-up, then --steps factorisations of a fresh copy
+    timed with events.  One JSON line with the rate against the FP64 peak."""
+    d, nc = args.d, args.n + 1
+    g = torch.Generator(device="cuda")
+    g.manual_seed(inputs.config_seed(8))
+    Y0 = torch.randn(nc, d, generator=g, dtype=torch.float64, device="cuda")
+    Y = Y0.clone()
+    for _ in range(max(1, args.warmup)):
+        Y.copy_(Y0)
+        sap.sap_qr(Y)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(args.steps):
+        Y.copy_(Y0)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        sap.sap_qr(Y)
+        e1.record()
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    import numpy as np
+    ms = float(np.median(ts))
+    fl = qr_flops(d, nc)
+    print(json.dumps({"kernel": "qr", "d": d, "ncols": nc, "steps": args.steps, "median_ms": ms, "flops": fl,
+                      "tflops": fl / (ms * 1e-3) / 1e12, "frac_fp64": fl / (ms * 1e-3) / 1e9 / FP64_PEAK_GFLOPS}),
+          flush=True)
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -755,6 +786,9 @@ def main():
     torch.cuda.set_device(0)
     if args.kernel == "apply":
         kernel_apply(args, sap, torch, inputs)
+        return
+    if args.kernel == "qr":
+        kernel_qr(args, sap, torch, inputs)
         return
     copy_ref = copy_reference(torch, args.copy_ref_mib) if args.copy_ref_mib > 0 else None
     if copy_ref:

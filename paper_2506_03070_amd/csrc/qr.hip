@@ -88,176 +88,236 @@ __global__ __launch_bounds__(1024) void rank_check_kernel(const double *__restri
 // ---- two-level blocking for wide sketches -----------------------------------
 // Panels of kWy columns are factored by the kernels above (restricted to the
 // panel); the rest of the matrix is then updated once per panel with the
-// panel's compact WY form, Q_p^T C = C - V T^T (V^T C), as three tiled FP64
-// products (W = V^T C with the rows split over workgroups, W2 = T^T W, and
-// C -= V W2).  This reads and writes the trailing matrix once per kWy columns
-// instead of once per NB columns.
+// panel's compact WY form, Q_p^T C = C - V T^T (V^T C), on the FP64 matrix
+// cores (v_mfma_f64_16x16x4f64):
+//   W' = V^T [V C]   one pass over the panel's rows, split over workgroups;
+//                    its first kWy columns are the Gram matrix G = V^T V;
+//   W2 = T^T W       without forming T: T^-1 = diag(1 / tau) + the strict
+//                    upper triangle of G (Puglisi; Joffrain et al., "UT
+//                    transform"), so W2 solves (T^-1)^T W2 = W by forward
+//                    substitution, one thread per column, as
+//                    W2_i = tau_i (W_i - sum_{l<i} G_li W2_l) (tau_i = 0 drops
+//                    reflector i, as LAPACK's T does);
+//   C -= V W2        tiles of 64 x 64.
+// This reads and writes the trailing matrix once per kWy columns instead of
+// once per NB columns.
+//
+// Matrix-core lane layout (checked on the device): for D = A B + C with A
+// 16 x 4, B 4 x 16, lane l holds A[l % 16][l / 16] and B[l / 16][l % 16],
+// and register r of D holds D[l / 16 + 4 r][l % 16].
 constexpr int kWy = 64;        // panel width of the outer blocking
-constexpr int kWyRows = 64;    // rows per LDS sub-chunk
-constexpr int kWyTn = 32;      // trailing columns per workgroup
+constexpr int kWyRows = 64;    // rows per LDS sub-chunk / rows of an update tile
+constexpr int kWyTn = 64;      // columns of a tile
 constexpr int kWyThreads = 256;
+constexpr int kLdsPad = kWy + 1;
 
-// V entry of the panel at (panel-relative row r, column i), from the
-// factored panel stored in Y (unit diagonal implicit, zeros above).
-__device__ __forceinline__ double wy_v(const double *__restrict__ Yp, int64_t ldy, int rows, int pw, int r, int i) {
-  if (r >= rows || i >= pw || r < i) return 0.0;
-  if (r == i) return 1.0;
-  return Yp[r + static_cast<int64_t>(i) * ldy];
+typedef double mfma_d4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ mfma_d4 mfma_f64(double a, double b, mfma_d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-// Gp[s] = partial V^T V over row chunk s (kWy x kWy, column-major).
-__global__ __launch_bounds__(kWyThreads) void qr_gram_kernel(const double *__restrict__ Yp, int64_t ldy, int rows,
-                                                             int pw, int chunk, double *__restrict__ Gp) {
-  __shared__ double Vs[kWyRows][kWy + 1];
-  const int t = threadIdx.x;
-  const int i = t % kWy, jg = t / kWy;  // 4 groups of 16 columns
-  double acc[16];
+// Staging of a 64-row slice of the panel's V (rows r0 .. r0+63, all kWy
+// columns) and of 64 columns of B = [V C] into registers: thread t holds
+// elements e = t + 256 q (q < 16), row e % 64 and column e / 64, so that
+// the loads run down columns (contiguous) and are all issued before any is
+// used.
+constexpr int kStage = kWyRows * kWy / kWyThreads;  // 16
+
+__device__ __forceinline__ void stage_v(const double *__restrict__ Yp, int64_t ldy, int r_end, int pw, int r0,
+                                        double (&v)[kStage]) {
 #pragma unroll
-  for (int q = 0; q < 16; ++q) acc[q] = 0.0;
-  const int r_begin = blockIdx.x * chunk;
-  const int r_end = min(rows, r_begin + chunk);
-  for (int r0 = r_begin; r0 < r_end; r0 += kWyRows) {
-    __syncthreads();
-    for (int e = t; e < kWyRows * kWy; e += kWyThreads) {
-      const int rr = e % kWyRows, ii = e / kWyRows;
-      const int r = r0 + rr;
-      Vs[rr][ii] = r < r_end ? wy_v(Yp, ldy, rows, pw, r, ii) : 0.0;
-    }
-    __syncthreads();
-    for (int rr = 0; rr < kWyRows; ++rr) {
-      const double vi = Vs[rr][i];
-#pragma unroll
-      for (int q = 0; q < 16; ++q) acc[q] += vi * Vs[rr][jg * 16 + q];
-    }
+  for (int q = 0; q < kStage; ++q) {
+    const int e = static_cast<int>(threadIdx.x) + kWyThreads * q;
+    const int r = r0 + e % kWyRows, i = e / kWyRows;
+    const bool in = r < r_end && i < pw;
+    const double y = (in && r > i) ? Yp[r + static_cast<int64_t>(i) * ldy] : 0.0;
+    v[q] = (in && r == i) ? 1.0 : y;
   }
-  double *G = Gp + static_cast<int64_t>(blockIdx.x) * kWy * kWy;
-#pragma unroll
-  for (int q = 0; q < 16; ++q) G[i + (jg * 16 + q) * kWy] = acc[q];
 }
 
-// T of the panel (upper triangular, column-major kWy x kWy) from the Gram
-// partials and tau (LAPACK dlarft, forward columnwise):
-// T(i,i) = tau_i, T(0:i, i) = -tau_i T(0:i, 0:i) (V^T v_i)(0:i).
-__global__ __launch_bounds__(kWyThreads) void qr_build_t_kernel(const double *__restrict__ Gp, int nparts, int pw,
-                                                                const double *__restrict__ tau,
-                                                                double *__restrict__ T) {
-  __shared__ double G[kWy][kWy + 1];
-  __shared__ double Ts[kWy][kWy + 1];
-  const int t = threadIdx.x;
-  for (int e = t; e < kWy * kWy; e += kWyThreads) {
-    double s = 0.0;
-    for (int p = 0; p < nparts; ++p) s += Gp[static_cast<int64_t>(p) * kWy * kWy + e];
-    G[e % kWy][e / kWy] = s;
-    Ts[e % kWy][e / kWy] = 0.0;
+__device__ __forceinline__ void stage_b(const double *__restrict__ Yp, int64_t ldy, int r_end, int pw, int nball,
+                                        int r0, int j0, double (&v)[kStage]) {
+#pragma unroll
+  for (int q = 0; q < kStage; ++q) {
+    const int e = static_cast<int>(threadIdx.x) + kWyThreads * q;
+    const int r = r0 + e % kWyRows, j = j0 + e / kWyRows;
+    const bool in = r < r_end && j < nball;
+    // column j < pw of B is V's (unit diagonal, zeros above)
+    const bool ld = in && (j >= pw || r > j);
+    const double y = ld ? Yp[r + static_cast<int64_t>(j) * ldy] : 0.0;
+    v[q] = (in && j < pw && r == j) ? 1.0 : y;
   }
-  __syncthreads();
-  for (int i = 0; i < pw; ++i) {
-    const double ti = tau[i];
-    if (t < i) {
-      double s = 0.0;
-      for (int q = t; q < i; ++q) s += Ts[t][q] * G[q][i];
-      Ts[t][i] = -ti * s;
-    }
-    if (t == 0) Ts[i][i] = ti;
-    __syncthreads();
-  }
-  for (int e = t; e < kWy * kWy; e += kWyThreads) T[e] = Ts[e % kWy][e / kWy];
 }
 
-// Wp[s] = partial V^T C over row chunk s for trailing columns j0 .. j0+31
-// (Wp: kWy x ntr per chunk, column-major).
+__device__ __forceinline__ void unstage(double (*S)[kLdsPad], const double (&v)[kStage]) {
+#pragma unroll
+  for (int q = 0; q < kStage; ++q) {
+    const int e = static_cast<int>(threadIdx.x) + kWyThreads * q;
+    S[e % kWyRows][e / kWyRows] = v[q];
+  }
+}
+
+// Wp[s][i][j] = sum over the rows of chunk s of V(r, i) B(r, j), B = [V C],
+// for the 64 columns j0 .. j0+63 of B; row-major per chunk with leading
+// dimension ldw.  Wave w takes i in [16 w, 16 w + 16) and the tile's four
+// 16-column blocks.  The next 64-row slice is loaded into registers while
+// the matrix cores work on the current one.
 __global__ __launch_bounds__(kWyThreads) void qr_wy_w_kernel(const double *__restrict__ Yp, int64_t ldy, int rows,
-                                                             int pw, int ntr, int chunk, double *__restrict__ Wp) {
-  __shared__ double Vs[kWyRows][kWy + 1];
-  __shared__ double Cs[kWyRows][kWyTn + 1];
-  const int t = threadIdx.x;
-  const int i = t % kWy, jg = t / kWy;  // 4 groups of 8 columns
+                                                             int pw, int nball, int chunk, int64_t ldw,
+                                                             double *__restrict__ Wp) {
+  __shared__ double Vs[kWyRows][kLdsPad];
+  __shared__ double Bs[kWyRows][kLdsPad];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int j0 = blockIdx.x * kWyTn;
-  const double *__restrict__ C = Yp + static_cast<int64_t>(pw) * ldy;
-  double acc[8];
-#pragma unroll
-  for (int q = 0; q < 8; ++q) acc[q] = 0.0;
   const int r_begin = blockIdx.y * chunk;
   const int r_end = min(rows, r_begin + chunk);
+  mfma_d4 acc[4];
+#pragma unroll
+  for (int b = 0; b < 4; ++b) acc[b] = mfma_d4{0.0, 0.0, 0.0, 0.0};
+  double rv[kStage], rb[kStage];
+  stage_v(Yp, ldy, r_end, pw, r_begin, rv);
+  stage_b(Yp, ldy, r_end, pw, nball, r_begin, j0, rb);
   for (int r0 = r_begin; r0 < r_end; r0 += kWyRows) {
     __syncthreads();
-    for (int e = t; e < kWyRows * kWy; e += kWyThreads) {
-      const int rr = e % kWyRows, ii = e / kWyRows;
-      const int r = r0 + rr;
-      Vs[rr][ii] = r < r_end ? wy_v(Yp, ldy, rows, pw, r, ii) : 0.0;
-    }
-    for (int e = t; e < kWyRows * kWyTn; e += kWyThreads) {
-      const int rr = e % kWyRows, jj = e / kWyRows;
-      const int r = r0 + rr, j = j0 + jj;
-      Cs[rr][jj] = (r < r_end && j < ntr) ? C[r + static_cast<int64_t>(j) * ldy] : 0.0;
-    }
+    unstage(Vs, rv);
+    unstage(Bs, rb);
     __syncthreads();
-    for (int rr = 0; rr < kWyRows; ++rr) {
-      const double vi = Vs[rr][i];
+    if (r0 + kWyRows < r_end) {
+      stage_v(Yp, ldy, r_end, pw, r0 + kWyRows, rv);
+      stage_b(Yp, ldy, r_end, pw, nball, r0 + kWyRows, j0, rb);
+    }
+#pragma unroll 4
+    for (int kk = 0; kk < kWyRows; kk += 4) {
+      const double a = Vs[kk + (lane >> 4)][16 * w + (lane & 15)];
 #pragma unroll
-      for (int q = 0; q < 8; ++q) acc[q] += vi * Cs[rr][jg * 8 + q];
+      for (int b = 0; b < 4; ++b) acc[b] = mfma_f64(a, Bs[kk + (lane >> 4)][16 * b + (lane & 15)], acc[b]);
     }
   }
-  double *W = Wp + static_cast<int64_t>(blockIdx.y) * kWy * ntr;
+  double *W = Wp + static_cast<int64_t>(blockIdx.y) * kWy * ldw;
 #pragma unroll
-  for (int q = 0; q < 8; ++q) {
-    const int j = j0 + jg * 8 + q;
-    if (j < ntr) W[i + static_cast<int64_t>(j) * kWy] = acc[q];
+  for (int b = 0; b < 4; ++b) {
+    const int j = j0 + 16 * b + (lane & 15);
+    if (j >= nball) continue;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = 16 * w + (lane >> 4) + 4 * r;
+      W[static_cast<int64_t>(i) * ldw + j] = acc[b][r];
+    }
   }
 }
 
-// W2(:, j) = T^T sum_s Wp[s](:, j) for 4 columns per workgroup.
-__global__ __launch_bounds__(kWyThreads) void qr_wy_t2_kernel(const double *__restrict__ Wp, int nparts, int ntr,
-                                                              const double *__restrict__ T,
-                                                              double *__restrict__ W2) {
-  __shared__ double Ws[4][kWy];
-  const int t = threadIdx.x;
-  const int i = t % kWy, jj = t / kWy;
-  const int j = blockIdx.x * 4 + jj;
+// Ws = sum of the chunk partials Wp[s] (s ascending), kWy x nball row-major.
+__global__ __launch_bounds__(256) void qr_wy_sum_kernel(const double *__restrict__ Wp, int nparts, int64_t ldw,
+                                                        int nball, double *__restrict__ Ws) {
+  const int j = blockIdx.x * 256 + threadIdx.x, i = blockIdx.y;
+  if (j >= nball) return;
+  const double *src = Wp + static_cast<int64_t>(i) * ldw + j;
+  const int64_t stride = static_cast<int64_t>(kWy) * ldw;
   double s = 0.0;
-  if (j < ntr)
-    for (int p = 0; p < nparts; ++p) s += Wp[static_cast<int64_t>(p) * kWy * ntr + i + static_cast<int64_t>(j) * kWy];
-  Ws[jj][i] = s;
-  __syncthreads();
-  if (j >= ntr) return;
-  double a = 0.0;
-  for (int l = 0; l <= i; ++l) a += T[l + i * kWy] * Ws[jj][l];
-  W2[i + static_cast<int64_t>(j) * kWy] = a;
+  int p = 0;
+  for (; p + 4 <= nparts; p += 4) {
+    const double a0 = src[p * stride], a1 = src[(p + 1) * stride], a2 = src[(p + 2) * stride],
+                 a3 = src[(p + 3) * stride];
+    s += a0;
+    s += a1;
+    s += a2;
+    s += a3;
+  }
+  for (; p < nparts; ++p) s += src[p * stride];
+  Ws[static_cast<int64_t>(i) * ldw + j] = s;
 }
 
-// C(r0:r0+64, j0:j0+32) -= V(r0:r0+64, :) W2(:, j0:j0+32).
+// W2[:, j] for the trailing columns j (one thread each) from Ws = V^T [V C]:
+// G = V^T V is its first pw columns (every workgroup copies it to LDS), then
+// W2_i = tau_i (W_i - sum_{l<i} G_li W2_l).  Indices i >= pw carry tau_i = 0
+// (a narrower last panel).  W2 row-major kWy x ntr (leading dimension ntr).
+__global__ __launch_bounds__(kWyThreads) void qr_wy_t2_kernel(const double *__restrict__ Ws, int64_t ldw, int pw,
+                                                              int ntr, const double *__restrict__ tau,
+                                                              double *__restrict__ W2) {
+  __shared__ double G[kWy][kLdsPad];
+  __shared__ double ts[kWy];
+  const int t = threadIdx.x;
+  for (int e = t; e < kWy * kWy; e += kWyThreads) {
+    const int l = e / kWy, i = e % kWy;  // G[l][i]; l < i is used
+    G[l][i] = (l < pw && i < pw) ? Ws[static_cast<int64_t>(l) * ldw + i] : 0.0;
+  }
+  if (t < kWy) ts[t] = t < pw ? tau[t] : 0.0;
+  __syncthreads();
+  const int j = blockIdx.x * kWyThreads + t;
+  if (j >= ntr) return;
+  const int64_t col = pw + j;
+  double x[kWy];
+#pragma unroll
+  for (int i = 0; i < kWy; ++i) x[i] = Ws[static_cast<int64_t>(i) * ldw + col];
+#pragma unroll
+  for (int i = 0; i < kWy; ++i) {
+    double s = x[i];
+#pragma unroll
+    for (int l = 0; l < i; ++l) s -= G[l][i] * x[l];
+    x[i] = ts[i] * s;
+  }
+#pragma unroll
+  for (int i = 0; i < kWy; ++i) W2[static_cast<int64_t>(i) * ntr + j] = x[i];
+}
+
+// C(r0:r0+64, j0:j0+64) -= V(r0:r0+64, :) W2(:, j0:j0+64), C = Yp(:, pw:).
+// Computed as (W2^T V^T)^T so that the 16 lanes of a matrix-core output row
+// run down a column of C (contiguous).  Wave w takes columns j0 + 16 w ..
+// j0 + 16 w + 15 and the four 16-row blocks of the tile; its 16 values of C
+// are loaded before the matrix-core loop.
 __global__ __launch_bounds__(kWyThreads) void qr_wy_update_kernel(double *__restrict__ Yp, int64_t ldy, int rows,
                                                                   int pw, int ntr, const double *__restrict__ W2) {
-  __shared__ double Vs[kWyRows][kWy + 1];
-  __shared__ double Ws[kWy][kWyTn + 1];
-  const int t = threadIdx.x;
+  __shared__ double Vs[kWyRows][kLdsPad];
+  __shared__ double Ws[kWy][kLdsPad];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int r0 = blockIdx.x * kWyRows, j0 = blockIdx.y * kWyTn;
-  for (int e = t; e < kWyRows * kWy; e += kWyThreads) {
-    const int rr = e % kWyRows, ii = e / kWyRows;
-    Vs[rr][ii] = wy_v(Yp, ldy, rows, pw, r0 + rr, ii);
-  }
-  for (int e = t; e < kWy * kWyTn; e += kWyThreads) {
-    const int ii = e % kWy, jj = e / kWy;
-    const int j = j0 + jj;
-    Ws[ii][jj] = (j < ntr && ii < pw) ? W2[ii + static_cast<int64_t>(j) * kWy] : 0.0;
-  }
-  __syncthreads();
-  const int rr = t % kWyRows, jg = t / kWyRows;  // 4 groups of 8 columns
-  const int r = r0 + rr;
-  if (r >= rows) return;
-  double acc[8];
+  {
+    double rv[kStage], rw[kStage];
+    stage_v(Yp, ldy, rows, pw, r0, rv);
 #pragma unroll
-  for (int q = 0; q < 8; ++q) acc[q] = 0.0;
-  for (int ii = 0; ii < pw; ++ii) {
-    const double v = Vs[rr][ii];
+    for (int q = 0; q < kStage; ++q) {
+      const int e = t + kWyThreads * q;
+      const int jj = e % kWyTn, ii = e / kWyTn;
+      const int j = j0 + jj;
+      rw[q] = (j < ntr && ii < pw) ? W2[static_cast<int64_t>(ii) * ntr + j] : 0.0;
+    }
+    unstage(Vs, rv);
 #pragma unroll
-    for (int q = 0; q < 8; ++q) acc[q] += v * Ws[ii][jg * 8 + q];
+    for (int q = 0; q < kStage; ++q) {
+      const int e = t + kWyThreads * q;
+      Ws[e / kWyTn][e % kWyTn] = rw[q];
+    }
   }
   double *C = Yp + static_cast<int64_t>(pw) * ldy;
+  double cv[4][4];
 #pragma unroll
-  for (int q = 0; q < 8; ++q) {
-    const int j = j0 + jg * 8 + q;
-    if (j < ntr) C[r + static_cast<int64_t>(j) * ldy] -= acc[q];
+  for (int b = 0; b < 4; ++b) {
+    const int r = r0 + 16 * b + (lane & 15);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int j = j0 + 16 * w + (lane >> 4) + 4 * q;
+      cv[b][q] = (r < rows && j < ntr) ? C[r + static_cast<int64_t>(j) * ldy] : 0.0;
+    }
+  }
+  __syncthreads();
+  mfma_d4 acc[4];
+#pragma unroll
+  for (int b = 0; b < 4; ++b) acc[b] = mfma_d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+  for (int kk = 0; kk < kWy; kk += 4) {
+    const double a = Ws[kk + (lane >> 4)][16 * w + (lane & 15)];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[b] = mfma_f64(a, Vs[16 * b + (lane & 15)][kk + (lane >> 4)], acc[b]);
+  }
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    const int r = r0 + 16 * b + (lane & 15);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int j = j0 + 16 * w + (lane >> 4) + 4 * q;
+      if (r < rows && j < ntr) C[r + static_cast<int64_t>(j) * ldy] = cv[b][q] - acc[b][q];
+    }
   }
 }
 
@@ -306,18 +366,17 @@ sap_status qr_unblocked(sap_ctx *ctx, double *Y, int64_t ldy, int rows, int cols
 // two-level form does not shorten.
 bool use_blocked(int rows, int cols) { return cols > 3 * kWy && rows > 4096; }
 
-int gram_parts(int prow) { return std::max(1, std::min(8, (prow + 1023) / 1024)); }
 int round64(int x) { return (x + kWyRows - 1) / kWyRows * kWyRows; }
 constexpr int kMaxSplits = 16;
 
 sap_status qr_blocked(sap_ctx *ctx, double *Y, int64_t ldy, int rows, int cols, double *tau, void *work,
                       hipStream_t st) {
   const int kmax = std::min(rows, cols);
+  const int64_t ldw = cols;  // >= kWy + the widest trailing part
   Carve cv(work);
   void *pwork = cv.take<char>(kUnblockedBytes);
-  double *T = cv.take<double>(kWy * kWy);
-  double *Gp = cv.take<double>(static_cast<size_t>(8) * kWy * kWy);
-  double *Wp = cv.take<double>(static_cast<size_t>(kMaxSplits) * kWy * cols);
+  double *Wp = cv.take<double>(static_cast<size_t>(kMaxSplits) * kWy * ldw);
+  double *Wsum = cv.take<double>(static_cast<size_t>(kWy) * ldw);
   double *W2 = cv.take<double>(static_cast<size_t>(kWy) * cols);
   for (int k = 0; k < kmax; k += kWy) {
     const int pw = std::min(kWy, kmax - k);
@@ -327,19 +386,16 @@ sap_status qr_blocked(sap_ctx *ctx, double *Y, int64_t ldy, int rows, int cols, 
     if (s != SAP_OK) return s;
     const int ntr = cols - k - pw;
     if (ntr <= 0) continue;
-    int gparts = gram_parts(prow);
-    const int gchunk = round64((prow + gparts - 1) / gparts);
-    gparts = (prow + gchunk - 1) / gchunk;
-    qr_gram_kernel<<<gparts, kWyThreads, 0, st>>>(Yp, ldy, prow, pw, gchunk, Gp);
-    qr_build_t_kernel<<<1, kWyThreads, 0, st>>>(Gp, gparts, pw, tau + k, T);
-    const int ntiles = (ntr + kWyTn - 1) / kWyTn;
+    const int nball = pw + ntr;
+    const int ntiles = (nball + kWyTn - 1) / kWyTn;
     int splits = std::max(1, std::min({kMaxSplits, (2 * ctx->num_cus + ntiles - 1) / ntiles, (prow + 255) / 256}));
     const int chunk = round64((prow + splits - 1) / splits);
     splits = (prow + chunk - 1) / chunk;
-    qr_wy_w_kernel<<<dim3(ntiles, splits), kWyThreads, 0, st>>>(Yp, ldy, prow, pw, ntr, chunk, Wp);
-    qr_wy_t2_kernel<<<(ntr + 3) / 4, kWyThreads, 0, st>>>(Wp, splits, ntr, T, W2);
-    qr_wy_update_kernel<<<dim3((prow + kWyRows - 1) / kWyRows, ntiles), kWyThreads, 0, st>>>(Yp, ldy, prow, pw,
-                                                                                            ntr, W2);
+    qr_wy_w_kernel<<<dim3(ntiles, splits), kWyThreads, 0, st>>>(Yp, ldy, prow, pw, nball, chunk, ldw, Wp);
+    qr_wy_sum_kernel<<<dim3((nball + 255) / 256, kWy), 256, 0, st>>>(Wp, splits, ldw, nball, Wsum);
+    qr_wy_t2_kernel<<<(ntr + kWyThreads - 1) / kWyThreads, kWyThreads, 0, st>>>(Wsum, ldw, pw, ntr, tau + k, W2);
+    qr_wy_update_kernel<<<dim3((prow + kWyRows - 1) / kWyRows, (ntr + kWyTn - 1) / kWyTn), kWyThreads, 0, st>>>(
+        Yp, ldy, prow, pw, ntr, W2);
     SAP_HIP_TRY(hipGetLastError());
   }
   return SAP_OK;
@@ -350,8 +406,7 @@ sap_status qr_blocked(sap_ctx *ctx, double *Y, int64_t ldy, int rows, int cols, 
 size_t qr_workspace_bytes(int rows, int cols) {
   size_t b = kUnblockedBytes;
   if (use_blocked(rows, cols))
-    b += 8 * 256 + sizeof(double) * (static_cast<size_t>(kWy) * kWy * 9 +
-                                     static_cast<size_t>(kMaxSplits + 1) * kWy * cols);
+    b += 4 * 256 + sizeof(double) * static_cast<size_t>(kMaxSplits + 2) * kWy * cols;
   return b;
 }
 

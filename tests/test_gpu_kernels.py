@@ -212,7 +212,8 @@ def test_apply_ignores_out_of_range_rows(sap, orc):
 # ----------------------------------------------------------------- QR -----
 # rows > 4096 with cols > 192 takes the two-level (64-column panel, WY trailing update) path
 QR_CASES = [(400, 101), (4000, 1001), (1000, 1000), (5, 3), (700, 1), (2500, 64), (8192, 130), (16384, 40),
-            (513, 100), (1100, 17), (8192, 600), (5000, 257), (700, 259), (300, 300), (193, 193)]
+            (513, 100), (1100, 17), (8192, 600), (5000, 257), (700, 259), (300, 300), (193, 193),
+            (6000, 700), (4100, 193), (9000, 130)]
 
 
 @pytest.mark.parametrize("rows,cols", QR_CASES)
@@ -239,6 +240,25 @@ def test_qr_parity(sap, orc, rows, cols):
     if rows * cols <= 2_000_000:
         Q = orc.q_factor(F, tau.cpu().numpy())
         assert np.linalg.norm(Q @ R - Y) <= 1e-12 * np.linalg.norm(Y) * max(1, np.sqrt(rows) / 10)
+
+
+def test_qr_blocked_zero_reflector(sap, orc):
+    """A zero column in the two-level path gives tau = 0 inside a panel; the
+    compact-WY update must then drop that reflector (as LAPACK's T does)."""
+    import torch
+    rows, cols = 5000, 300
+    rng = np.random.default_rng(11)
+    Y = rng.standard_normal((rows, cols))
+    Y[:, 100] = 0.0
+    Yt = torch.from_numpy(np.ascontiguousarray(Y.T)).cuda()
+    tau = sap.sap_qr(Yt)
+    torch.cuda.synchronize()
+    F = Yt.cpu().numpy().T
+    Fo, tau_o = orc.householder_qr(Y)
+    assert tau_o[100] == 0.0 and tau.cpu().numpy()[100] == 0.0
+    R, Ro = np.triu(F[:cols]), np.triu(Fo[:cols])
+    assert np.linalg.norm(R.T @ R - Ro.T @ Ro) <= 1e-12 * np.linalg.norm(Ro) ** 2
+    assert np.allclose(R, Ro, rtol=0, atol=1e-10 * np.abs(Ro).max())
 
 
 def test_qr_invalid(sap):
