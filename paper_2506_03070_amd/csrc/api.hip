@@ -190,6 +190,15 @@ sap_status sap_create(sap_ctx **out, int device, size_t hbm_budget) {
     delete ctx;
     return SAP_EDEVICE;
   }
+  if (hipHostMalloc(&ctx->pinned, kPinnedBytes, hipHostMallocDefault) != hipSuccess ||
+      hipEventCreateWithFlags(&ctx->batch_ev[0], hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&ctx->batch_ev[1], hipEventDisableTiming) != hipSuccess) {
+    if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+    for (hipEvent_t e : ctx->batch_ev)
+      if (e) (void)hipEventDestroy(e);
+    delete ctx;
+    return SAP_EDEVICE;
+  }
   *out = ctx;
   return SAP_OK;
 }
@@ -202,6 +211,10 @@ void sap_destroy(sap_ctx *ctx) {
   (void)hipDeviceSynchronize();
   prof_resolve(ctx);
   for (hipEvent_t e : ctx->free_events) (void)hipEventDestroy(e);
+  batch_graphs_free(ctx);
+  for (hipEvent_t e : ctx->batch_ev)
+    if (e) (void)hipEventDestroy(e);
+  if (ctx->pinned) (void)hipHostFree(ctx->pinned);
   if (ctx->ws) (void)hipFree(ctx->ws);
   delete ctx;
 }

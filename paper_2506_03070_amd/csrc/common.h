@@ -176,6 +176,12 @@ struct sap_ctx {
   size_t apply_scratch_bytes = 0;
   // per-context timings of sap_choose_d (select.hip)
   void *select_cache = nullptr;
+  // captured LSQR / momentum iteration batches, replayed as hipGraphs
+  // (lsqr.hip), and the pinned host slots and events through which the
+  // state of one batch is read while the next one runs
+  void *batch_graphs = nullptr;
+  void *pinned = nullptr;
+  hipEvent_t batch_ev[2] = {nullptr, nullptr};
   // kernel timing (sap_profile_enable): pending event pairs per kernel,
   // resolved into launch counts and milliseconds; free events are reused
   bool profiling = false;
@@ -278,6 +284,10 @@ size_t lsqr_workspace_bytes(sap_ctx *ctx, int64_t m, int n);
 sap_status run_lsqr(sap_ctx *ctx, const sap_problem *prob, const double *R, int64_t ldr,
                     const double *x0, const double *z, double tol, int maxiter, int mode, int max_refine,
                     double *x, sap_info *info, void *work, hipStream_t st, const SparseA *sp = nullptr);
+// The iteration-batch graph cache (lsqr.hip), freed with the context.
+void batch_graphs_free(sap_ctx *ctx);
+constexpr size_t kPinnedBytes = 4096;
+
 // Heavy-ball momentum (App. D.3) in place of LSQR (lsqr.hip): x0 = R^-1 z,
 // step alpha, momentum beta; the LSQR workspace; mode 0 (FP64) or 1 (FP32 A).
 sap_status run_hbm(sap_ctx *ctx, const sap_problem *prob, const double *R, int64_t ldr, const double *z,

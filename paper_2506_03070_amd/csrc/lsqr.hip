@@ -21,7 +21,9 @@
 // the flag once per batch.
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 #include <mutex>
+#include <string>
 #include <unordered_map>
 
 #include "common.h"
@@ -839,13 +841,125 @@ sap_status setup_precond(sap_ctx *ctx, const double *R, int64_t ldr, const doubl
   return SAP_OK;
 }
 
+// ---- iteration batches -------------------------------------------------------
+// A batch of iterations is captured once into a hipGraph and replayed: the
+// launches of one batch are the same every time (the u buffers alternate an
+// even number of times), so the captured graph is valid for as long as every
+// value it bakes in is unchanged; the key lists them.  Capture runs on a
+// context-owned stream (the caller's may be the null stream); the graph is
+// launched on the caller's.  Timing mode (sap_profile_enable) records events
+// around each pass, so it launches directly.
+struct GraphKey {
+  uint64_t v[32];
+  int n = 0;
+  void add(uint64_t x) { v[n++] = x; }
+  void addp(const void *p) { add(static_cast<uint64_t>(reinterpret_cast<uintptr_t>(p))); }
+  void addd(double d) {
+    uint64_t u;
+    std::memcpy(&u, &d, sizeof u);
+    add(u);
+  }
+  bool operator==(const GraphKey &o) const { return n == o.n && std::memcmp(v, o.v, sizeof(uint64_t) * n) == 0; }
+};
+
+struct BatchGraphs {
+  struct Entry {
+    GraphKey key;
+    hipGraphExec_t exec = nullptr;
+  } e[4];
+  int next = 0;
+  hipStream_t cap = nullptr;
+};
+
+template <typename F>
+hipGraphExec_t batch_graph(sap_ctx *ctx, const GraphKey &key, F &&launch) {
+  if (ctx->profiling) return nullptr;
+  auto *G = static_cast<BatchGraphs *>(ctx->batch_graphs);
+  if (!G) {
+    G = new BatchGraphs();
+    ctx->batch_graphs = G;
+  }
+  for (auto &en : G->e)
+    if (en.exec && en.key == key) return en.exec;
+  if (!G->cap && hipStreamCreateWithFlags(&G->cap, hipStreamNonBlocking) != hipSuccess) {
+    G->cap = nullptr;
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  if (hipStreamBeginCapture(G->cap, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  launch(G->cap);
+  hipGraph_t g = nullptr;
+  if (hipStreamEndCapture(G->cap, &g) != hipSuccess || !g) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  hipGraphExec_t ex = nullptr;
+  const hipError_t ie = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (ie != hipSuccess || !ex) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  auto &slot = G->e[G->next];
+  G->next = (G->next + 1) % 4;
+  if (slot.exec) (void)hipGraphExecDestroy(slot.exec);
+  slot.exec = ex;
+  slot.key = key;
+  return ex;
+}
+
+// Host view of one batch's end state (pinned, two slots).
+struct BatchSlot {
+  LsqrState st;
+  int err;
+};
+
+// Run batches until the state reports done: batch k+1 is enqueued before the
+// state of batch k is waited for, so the device does not idle on the host's
+// read (a batch after `done` finds every kernel returning at once).  The
+// last state read lands in *hs, the error word in *herr.
+template <typename F>
+sap_status run_batches(sap_ctx *ctx, hipGraphExec_t exec, F &&launch_direct, const LsqrState *st, const int *err,
+                       int max_batches, LsqrState *hs, int *herr, hipStream_t s, const char *who) {
+  auto *slots = static_cast<BatchSlot *>(ctx->pinned);
+  auto enqueue = [&](int slot) -> hipError_t {
+    if (exec) {
+      const hipError_t e = hipGraphLaunch(exec, s);
+      if (e != hipSuccess) return e;
+    } else {
+      launch_direct(s);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    e = hipMemcpyAsync(&slots[slot].st, st, sizeof(LsqrState), hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) return e;
+    e = hipMemcpyAsync(&slots[slot].err, err, sizeof(int), hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) return e;
+    return hipEventRecord(ctx->batch_ev[slot], s);
+  };
+  SAP_HIP_TRY(enqueue(0));
+  for (int nbatch = 0;; ++nbatch) {
+    const int cur = nbatch & 1;
+    if (nbatch + 1 <= max_batches) SAP_HIP_TRY(enqueue(cur ^ 1));
+    SAP_HIP_TRY(hipEventSynchronize(ctx->batch_ev[cur]));
+    *hs = slots[cur].st;
+    *herr = slots[cur].err;
+    if (*herr) return fail(ctx, SAP_EDEVICE, std::string(who) + ": a triangular-solve wait expired");
+    if (hs->done) return SAP_OK;
+    if (nbatch + 1 > max_batches) return fail(ctx, SAP_EDEVICE, std::string(who) + ": device never reported completion");
+  }
+}
+
 // ---- heavy-ball momentum (App. D.3) ----------------------------------------
 // s = M^T q (q summed from the pass slices: q = A^T r, r = b - A x); one wave
 // per entry j (column j of M, rows 0..j); per-workgroup partials of ||s||^2.
 __global__ __launch_bounds__(1024) void hbm_mtq_kernel(const double *__restrict__ M, int n,
                                                        const double *__restrict__ qs, int nslices,
                                                        double *__restrict__ sv, double *__restrict__ spart,
-                                                       const LsqrState *st) {
+                                                       LsqrState *st) {
   __shared__ double q[kMaxN];
   __shared__ double wsum[16];
   if (st->done) return;
@@ -873,6 +987,9 @@ __global__ __launch_bounds__(1024) void hbm_mtq_kernel(const double *__restrict_
     double a = 0.0;
     for (int w = 0; w < 16; ++w) a += wsum[w];
     spart[blockIdx.x] = a;
+    // step counter of the momentum iteration (read by hbm_step_kernel only,
+    // which runs after this kernel; no workgroup here reads it)
+    if (blockIdx.x == 0) st->iter += 1;
   }
 }
 
@@ -885,12 +1002,13 @@ __global__ __launch_bounds__(1024) void hbm_mtq_kernel(const double *__restrict_
 __global__ __launch_bounds__(1024) void hbm_step_kernel(const double *__restrict__ Mt, int n,
                                                         const double *__restrict__ sv,
                                                         const double *__restrict__ spart, int nspart,
-                                                        const double *__restrict__ nrmpart, int G, int t,
+                                                        const double *__restrict__ nrmpart, int G,
                                                         double alpha, double beta, double *__restrict__ delta,
                                                         double *__restrict__ x, LsqrState *st) {
   __shared__ double scr[16];
   __shared__ double ss[kMaxN];
   if (st->done) return;
+  const int t = st->iter - 1;  // updates made: hbm_mtq_kernel advanced the counter for this step
   const double rn = beta_from_partials(nrmpart, G, scr);
   double a = 0.0;
   for (int k = threadIdx.x; k < nspart; k += 1024) a += spart[k];
@@ -982,19 +1100,19 @@ sap_status run_lsqr(sap_ctx *ctx, const sap_problem *prob, const double *R, int6
   // One iteration = pass over A; q from the pass partials; v_hat = M^T q /
   // beta - beta v; alpha, v, p = M v; rotation, x and w updates and the
   // stopping test.
-  auto iteration = [&](const PassPlan &pl, const void *pv, const void *uin) {
+  auto iteration = [&](const PassPlan &pl, const void *pv, const void *uin, hipStream_t ls) {
     const int G = pl.grid;
     const int qsl = (G + kQSlice - 1) / kQSlice;
     if (sp)
       launch_csr_pass(ctx, *sp, G, static_cast<const double *>(pv), static_cast<const double *>(uin), ubuf[ucur ^ 1],
-                      st, qpart, nrmpart, s);
+                      st, qpart, nrmpart, ls);
     else
-      launch_pass(ctx, pl, prob->A, prob->lda, m, n, pv, uin, ubuf[ucur ^ 1], st, qpart, nrmpart, dyn, s);
+      launch_pass(ctx, pl, prob->A, prob->lda, m, n, pv, uin, ubuf[ucur ^ 1], st, qpart, nrmpart, dyn, ls);
     ucur ^= 1;
-    q_slices_kernel<<<dim3((n + 63) / 64, qsl), 256, 0, s>>>(qpart, G, n, qs);
-    lsqr_mtq_kernel<<<ngemv, 1024, 0, s>>>(M, n, qs, qsl, nrmpart, G, v, vh, vpart, st);
-    lsqr_mv_kernel<<<ngemv, 1024, 0, s>>>(Mt, n, vh, vpart, ngemv, nrmpart, G, v, p, refine ? p32 : nullptr, st);
-    lsqr_update_kernel<<<1, kTrsvThreads, 0, s>>>(p, w, x, n, st);
+    q_slices_kernel<<<dim3((n + 63) / 64, qsl), 256, 0, ls>>>(qpart, G, n, qs);
+    lsqr_mtq_kernel<<<ngemv, 1024, 0, ls>>>(M, n, qs, qsl, nrmpart, G, v, vh, vpart, st);
+    lsqr_mv_kernel<<<ngemv, 1024, 0, ls>>>(Mt, n, vh, vpart, ngemv, nrmpart, G, v, p, refine ? p32 : nullptr, st);
+    lsqr_update_kernel<<<1, kTrsvThreads, 0, ls>>>(p, w, x, n, st);
   };
 
   const int batch = 8;
@@ -1010,7 +1128,7 @@ sap_status run_lsqr(sap_ctx *ctx, const sap_problem *prob, const double *R, int6
     if (refine) copy_f64_kernel<<<(n + 255) / 256, 256, 0, s>>>(x, xprev, n);
     // Initialisation: beta_1 u_1 = b - A x (the pass with p = x, u_in = b);
     // in the refinement form this is the FP64-accumulated residual pass.
-    iteration(plan_res, x, prob->b);
+    iteration(plan_res, x, prob->b, s);
     SAP_HIP_TRY(hipGetLastError());
     if (refine) {
       ++refinements;
@@ -1026,16 +1144,34 @@ sap_status run_lsqr(sap_ctx *ctx, const sap_problem *prob, const double *R, int6
     // sets `done` no later than iteration maxiter, so the batch count is
     // bounded.
     const int max_batches = maxiter / batch + 2;
-    for (int nbatch = 0;; ++nbatch) {
-      if (nbatch > max_batches) return fail(ctx, SAP_EDEVICE, "LSQR: device never reported completion");
-      for (int k = 0; k < batch; ++k) iteration(plan, refine ? static_cast<const void *>(p32) : p, ubuf[ucur]);
-      SAP_HIP_TRY(hipGetLastError());
-      SAP_HIP_TRY(hipMemcpyAsync(&hs, st, sizeof(LsqrState), hipMemcpyDeviceToHost, s));
-      SAP_HIP_TRY(hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, s));
-      SAP_HIP_TRY(hipStreamSynchronize(s));
-      if (herr) return fail(ctx, SAP_EDEVICE, "LSQR: a triangular-solve wait expired");
-      if (hs.done) break;
-    }
+    const void *pit = refine ? static_cast<const void *>(p32) : static_cast<const void *>(p);
+    auto launch_batch = [&](hipStream_t ls) {
+      for (int k = 0; k < batch; ++k) iteration(plan, pit, ubuf[ucur], ls);
+    };
+    GraphKey key;
+    key.add(1);  // LSQR
+    key.addp(work);
+    key.addp(prob->A);
+    key.add(static_cast<uint64_t>(prob->lda));
+    key.add(static_cast<uint64_t>(m));
+    key.add(static_cast<uint64_t>(n));
+    key.add(static_cast<uint64_t>(mode));
+    key.addp(x);
+    key.add(static_cast<uint64_t>(ucur));
+    key.addp(plan.fn);
+    key.add(static_cast<uint64_t>(plan.grid));
+    key.add(static_cast<uint64_t>(plan.rows_per_wg));
+    key.add(static_cast<uint64_t>(plan.dyn_begin));
+    key.add(static_cast<uint64_t>(plan.chunk));
+    key.addp(sp ? sp->indptr : nullptr);
+    key.addp(sp ? sp->indices : nullptr);
+    key.addp(sp ? sp->values : nullptr);
+    key.add(sp ? static_cast<uint64_t>(sp->nnz) : 0);
+    key.add(sp ? static_cast<uint64_t>(sp->v_type) : 0);
+    key.add(static_cast<uint64_t>(ctx->num_cus));
+    hipGraphExec_t exec = batch_graph(ctx, key, launch_batch);
+    sst = run_batches(ctx, exec, launch_batch, st, err, max_batches, &hs, &herr, s, "LSQR");
+    if (sst != SAP_OK) return sst;
     if (!refine) {
       converged = hs.converged != 0;
       break;
@@ -1090,27 +1226,53 @@ sap_status run_hbm(sap_ctx *ctx, const sap_problem *prob, const double *R, int64
   const int batch = 8;
   const int max_batches = maxiter / batch + 2;
   LsqrState hs{};
-  int t = 0;
-  for (int nbatch = 0;; ++nbatch) {
-    if (nbatch > max_batches) return fail(ctx, SAP_EDEVICE, "momentum: device never reported completion");
-    for (int k = 0; k < batch; ++k, ++t) {
-      launch_pass(ctx, plan, prob->A, prob->lda, m, n, x, prob->b, B.ubuf[0], st, B.qpart, B.nrmpart, B.dyn, s);
-      q_slices_kernel<<<dim3((n + 63) / 64, qsl), 256, 0, s>>>(B.qpart, G, n, B.qs);
-      hbm_mtq_kernel<<<B.ngemv, 1024, 0, s>>>(B.M, n, B.qs, qsl, sv, B.vpart, st);
-      hbm_step_kernel<<<B.ngemv, 1024, 0, s>>>(B.Mt, n, sv, B.vpart, B.ngemv, B.nrmpart, G, t, alpha, beta, delta,
-                                               x, st);
+  int herr = 0;
+  auto launch_batch = [&](hipStream_t ls) {
+    for (int k = 0; k < batch; ++k) {
+      launch_pass(ctx, plan, prob->A, prob->lda, m, n, x, prob->b, B.ubuf[0], st, B.qpart, B.nrmpart, B.dyn, ls);
+      q_slices_kernel<<<dim3((n + 63) / 64, qsl), 256, 0, ls>>>(B.qpart, G, n, B.qs);
+      hbm_mtq_kernel<<<B.ngemv, 1024, 0, ls>>>(B.M, n, B.qs, qsl, sv, B.vpart, st);
+      hbm_step_kernel<<<B.ngemv, 1024, 0, ls>>>(B.Mt, n, sv, B.vpart, B.ngemv, B.nrmpart, G, alpha, beta, delta, x,
+                                                st);
     }
-    SAP_HIP_TRY(hipGetLastError());
-    SAP_HIP_TRY(hipMemcpyAsync(&hs, st, sizeof(LsqrState), hipMemcpyDeviceToHost, s));
-    SAP_HIP_TRY(hipStreamSynchronize(s));
-    if (hs.done) break;
-  }
+  };
+  GraphKey key;
+  key.add(2);  // momentum
+  key.addp(work);
+  key.addp(prob->A);
+  key.addp(prob->b);
+  key.add(static_cast<uint64_t>(prob->lda));
+  key.add(static_cast<uint64_t>(m));
+  key.add(static_cast<uint64_t>(n));
+  key.add(static_cast<uint64_t>(mode));
+  key.addp(x);
+  key.addd(alpha);
+  key.addd(beta);
+  key.addp(plan.fn);
+  key.add(static_cast<uint64_t>(plan.grid));
+  key.add(static_cast<uint64_t>(plan.rows_per_wg));
+  key.add(static_cast<uint64_t>(plan.dyn_begin));
+  key.add(static_cast<uint64_t>(plan.chunk));
+  key.add(static_cast<uint64_t>(ctx->num_cus));
+  hipGraphExec_t exec = batch_graph(ctx, key, launch_batch);
+  sst = run_batches(ctx, exec, launch_batch, st, B.err, max_batches, &hs, &herr, s, "momentum");
+  if (sst != SAP_OK) return sst;
   if (info) {
     info->iters = hs.total_iters;
     info->resid_est = hs.resid_est;
     info->normar_est = hs.normar_est;
   }
   return hs.converged ? SAP_OK : SAP_NOT_CONVERGED;
+}
+
+void batch_graphs_free(sap_ctx *ctx) {
+  auto *G = static_cast<BatchGraphs *>(ctx->batch_graphs);
+  if (!G) return;
+  for (auto &en : G->e)
+    if (en.exec) (void)hipGraphExecDestroy(en.exec);
+  if (G->cap) (void)hipStreamDestroy(G->cap);
+  delete G;
+  ctx->batch_graphs = nullptr;
 }
 
 }  // namespace sap
