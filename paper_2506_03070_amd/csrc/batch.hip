@@ -1272,6 +1272,14 @@ struct Server {
   int *d_flags = nullptr, *d_flags_setup = nullptr, *d_done = nullptr;
   void *scratch = nullptr;
   int64_t n_submitted = 0, n_completed = 0, n_rejected = 0;
+  // a round's iteration launches, captured once per launch shape and
+  // replayed while the active set keeps that shape (the launches read the
+  // requests' parameters from d_active, so only the shape is baked in)
+  struct RoundGraph {
+    int64_t key[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    hipGraphExec_t exec = nullptr;
+  } round_graphs[4];
+  int rg_next = 0;
 };
 
 namespace {
@@ -1375,11 +1383,41 @@ hipError_t serve_round(Server *S, std::vector<ServeRequest *> &fresh) {
     const PassChoice pc = (at == SAP_F32) ? pick_batch_pass<float>(n_max, aligned, true)
                                            : pick_batch_pass<double>(n_max, aligned, true);
     const int nblk_max = (n_max + kTrsvB - 1) / kTrsvB;
-    for (int k = 0; k < S->iters_per_round; ++k) {
-      launch_pass_fn(pc, S->d_active, S->d_pass, static_cast<int>(pass_work.size()), 0, st);
-      batch_lower_kernel<<<dim3(nblk_max, count), kTrsvThreads, 0, st>>>(S->d_active, S->d_flags);
-      batch_upper_kernel<<<dim3(nblk_max, count), kTrsvThreads, 0, st>>>(S->d_active, S->d_flags, S->d_flags + 1);
-      if (any_refine) batch_refine_kernel<<<count, 1024, 0, st>>>(S->d_active, S->d_flags + 1);
+    const int nwork = static_cast<int>(pass_work.size());
+    auto launch_iters = [&](hipStream_t ls) {
+      for (int k = 0; k < S->iters_per_round; ++k) {
+        launch_pass_fn(pc, S->d_active, S->d_pass, nwork, 0, ls);
+        batch_lower_kernel<<<dim3(nblk_max, count), kTrsvThreads, 0, ls>>>(S->d_active, S->d_flags);
+        batch_upper_kernel<<<dim3(nblk_max, count), kTrsvThreads, 0, ls>>>(S->d_active, S->d_flags,
+                                                                          S->d_flags + 1);
+        if (any_refine) batch_refine_kernel<<<count, 1024, 0, ls>>>(S->d_active, S->d_flags + 1);
+      }
+    };
+    const int64_t key[8] = {static_cast<int64_t>(reinterpret_cast<uintptr_t>(pc.fn)), pc.threads, nwork, count,
+                            nblk_max, any_refine ? 1 : 0, S->iters_per_round, 1};
+    hipGraphExec_t ex = nullptr;
+    for (auto &g : S->round_graphs)
+      if (g.exec && std::equal(key, key + 8, g.key)) ex = g.exec;
+    if (!ex && !S->ctx->profiling && hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+      launch_iters(st);
+      hipGraph_t graph = nullptr;
+      if (hipStreamEndCapture(st, &graph) == hipSuccess && graph) {
+        if (hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0) != hipSuccess) ex = nullptr;
+        (void)hipGraphDestroy(graph);
+      }
+      (void)hipGetLastError();
+      if (ex) {
+        auto &slot = S->round_graphs[S->rg_next];
+        S->rg_next = (S->rg_next + 1) % 4;
+        if (slot.exec) (void)hipGraphExecDestroy(slot.exec);
+        slot.exec = ex;
+        std::copy(key, key + 8, slot.key);
+      }
+    }
+    if (ex) {
+      if ((e = hipGraphLaunch(ex, st)) != hipSuccess) return e;
+    } else {
+      launch_iters(st);
     }
     serve_done_kernel<<<(count + 255) / 256, 256, 0, st>>>(S->d_active, count, S->d_done);
     if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -1510,6 +1548,8 @@ void serve_destroy(sap_ctx *ctx) {
     if (kv.second->ready) (void)hipEventDestroy(kv.second->ready);
   if (S->st) (void)hipStreamSynchronize(S->st);
   if (S->st_setup) (void)hipStreamSynchronize(S->st_setup);
+  for (auto &g : S->round_graphs)
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
   if (S->st) (void)hipStreamDestroy(S->st);
   if (S->st_setup) (void)hipStreamDestroy(S->st_setup);
   if (S->arena_mem) (void)hipFree(S->arena_mem);
