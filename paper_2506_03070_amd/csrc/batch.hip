@@ -375,10 +375,9 @@ __global__ __launch_bounds__(256) void batch_repack_kernel(const RepackJob *__re
 // The body of the pass for compute type TC (FP64, or FP32 in the inner
 // solves of the refinement form) and u storage type TU (FP32 in the
 // refinement form, whose residual pass computes in FP64 and rounds u).
-template <typename TA, typename TC, typename TU, int VEC, int KJ, int U, bool PF>
+template <typename TA, typename TC, typename TU, int VEC, int KJ, int U, bool PF, int TH>
 __device__ __forceinline__ void batch_pass_body(const BatchItem &it, int chunk, int tune, TC *psh, TC *qacc,
                                                 double *nsh) {
-  constexpr int TH = PF ? 512 : kBThreads;
   constexpr int NW = TH / kWave;
   const LsqrState *st = it.st;
   const int n = it.n;
@@ -517,11 +516,15 @@ __device__ __forceinline__ void batch_pass_body(const BatchItem &it, int chunk, 
 // threads and one group at a time.  The served form, whose rounds hold a few
 // large requests, uses PF; the batched form, many small problems, the other
 // (more waves to cover the per-row shuffles).
+// skip_inner: the FP32 inner passes of the refinement form are left to
+// batch_pass_inner_kernel (launched after this one), whose single FP32 code
+// path needs far fewer registers than this kernel's FP64 ones.
 template <typename TA, int VEC, int KJ, int U, bool PF>
 __global__ __launch_bounds__(PF ? 512 : kBThreads) void batch_pass_kernel(const BatchItem *__restrict__ items,
                                                                           const int2 *__restrict__ work, int nwork,
-                                                                          int tune) {
-  constexpr int NW = (PF ? 512 : kBThreads) / kWave;
+                                                                          int tune, int skip_inner) {
+  constexpr int TH = PF ? 512 : kBThreads;
+  constexpr int NW = TH / kWave;
   __shared__ double psh[64 * VEC * KJ];
   __shared__ double qacc[64 * VEC * KJ];
   __shared__ double nsh[NW];
@@ -530,12 +533,30 @@ __global__ __launch_bounds__(PF ? 512 : kBThreads) void batch_pass_kernel(const 
   const LsqrState *st = it.st;
   if (st->done && !tune) return;
   if (!it.refine)
-    batch_pass_body<TA, double, double, VEC, KJ, U, PF>(it, wk.y, tune, psh, qacc, nsh);
+    batch_pass_body<TA, double, double, VEC, KJ, U, PF, TH>(it, wk.y, tune, psh, qacc, nsh);
   else if (st->init)
-    batch_pass_body<TA, double, float, VEC, KJ, U, PF>(it, wk.y, tune, psh, qacc, nsh);
-  else
-    batch_pass_body<TA, float, float, VEC, KJ, U, PF>(it, wk.y, tune, reinterpret_cast<float *>(psh),
-                                                      reinterpret_cast<float *>(qacc), nsh);
+    batch_pass_body<TA, double, float, VEC, KJ, U, PF, TH>(it, wk.y, tune, psh, qacc, nsh);
+  else if (!skip_inner)
+    batch_pass_body<TA, float, float, VEC, KJ, U, PF, TH>(it, wk.y, tune, reinterpret_cast<float *>(psh),
+                                                          reinterpret_cast<float *>(qacc), nsh);
+}
+
+// The FP32 inner passes of the refinement form alone (FP32 A, arithmetic and
+// u): 512-thread workgroups, two row groups in flight per wave.  Items of
+// other kinds return at once (batch_pass_kernel takes them).
+template <int VEC, int KJ, int U>
+__global__ __launch_bounds__(512) void batch_pass_inner_kernel(const BatchItem *__restrict__ items,
+                                                               const int2 *__restrict__ work, int nwork) {
+  constexpr int NW = 512 / kWave;
+  __shared__ double psh[64 * VEC * KJ];
+  __shared__ double qacc[64 * VEC * KJ];
+  __shared__ double nsh[NW];
+  const int2 wk = work[blockIdx.x];
+  const BatchItem &it = items[wk.x];
+  const LsqrState *st = it.st;
+  if (st->done || !it.refine || st->init) return;
+  batch_pass_body<float, float, float, VEC, KJ, U, true, 512>(it, wk.y, 0, reinterpret_cast<float *>(psh),
+                                                              reinterpret_cast<float *>(qacc), nsh);
 }
 
 __global__ __launch_bounds__(kTrsvThreads) void batch_lower_kernel(const BatchItem *__restrict__ items, int *err) {
@@ -664,6 +685,7 @@ struct PassChoice {
   const void *fn;
   int vec, kj;
   int threads;
+  const void *inner_fn = nullptr;  // FP32 inner passes of the refinement form (FP32 A only)
 };
 
 // E = KJ * VEC elements of a row per lane: 8 while the widest problem has
@@ -678,25 +700,43 @@ PassChoice pick_batch_pass(int n_max, bool aligned, bool pf) {
   constexpr bool f32 = sizeof(TA) == 4;
   auto fn = [](auto kernel) { return reinterpret_cast<const void *>(kernel); };
   const int th = pf ? 512 : kBThreads;
+  PassChoice c;
   if (n_max <= 512) {
-    if (aligned)
-      return {pf ? fn(&batch_pass_kernel<TA, vmax, 8 / vmax, f32 ? 4 : 2, true>)
-                 : fn(&batch_pass_kernel<TA, vmax, 8 / vmax, f32 ? 4 : 2, false>), vmax, 8 / vmax, th};
-    return {pf ? fn(&batch_pass_kernel<TA, 1, 8, 2, true>) : fn(&batch_pass_kernel<TA, 1, 8, 2, false>), 1, 8, th};
+    if (aligned) {
+      c = {pf ? fn(&batch_pass_kernel<TA, vmax, 8 / vmax, f32 ? 4 : 2, true>)
+              : fn(&batch_pass_kernel<TA, vmax, 8 / vmax, f32 ? 4 : 2, false>), vmax, 8 / vmax, th};
+      c.inner_fn = fn(&batch_pass_inner_kernel<vmax, 8 / vmax, f32 ? 4 : 2>);
+    } else {
+      c = {pf ? fn(&batch_pass_kernel<TA, 1, 8, 2, true>) : fn(&batch_pass_kernel<TA, 1, 8, 2, false>), 1, 8, th};
+      c.inner_fn = fn(&batch_pass_inner_kernel<1, 8, 2>);
+    }
+  } else if (aligned) {
+    c = {pf ? fn(&batch_pass_kernel<TA, vmax, 16 / vmax, f32 ? 2 : 1, true>)
+            : fn(&batch_pass_kernel<TA, vmax, 16 / vmax, f32 ? 2 : 1, false>), vmax, 16 / vmax, th};
+    c.inner_fn = fn(&batch_pass_inner_kernel<vmax, 16 / vmax, f32 ? 2 : 1>);
+  } else {
+    c = {pf ? fn(&batch_pass_kernel<TA, 1, 16, 1, true>) : fn(&batch_pass_kernel<TA, 1, 16, 1, false>), 1, 16, th};
+    c.inner_fn = fn(&batch_pass_inner_kernel<1, 16, 1>);
   }
-  if (aligned)
-    return {pf ? fn(&batch_pass_kernel<TA, vmax, 16 / vmax, f32 ? 2 : 1, true>)
-               : fn(&batch_pass_kernel<TA, vmax, 16 / vmax, f32 ? 2 : 1, false>), vmax, 16 / vmax, th};
-  return {pf ? fn(&batch_pass_kernel<TA, 1, 16, 1, true>) : fn(&batch_pass_kernel<TA, 1, 16, 1, false>), 1, 16, th};
+  if (!f32) c.inner_fn = nullptr;  // the refinement form needs FP32 A
+  return c;
 }
 
+// One pass over every work item.  split (when some problem is in the
+// refinement form): its FP32 inner passes run in batch_pass_inner_kernel.
 void launch_pass_fn(const PassChoice &pc, const BatchItem *items, const int2 *work, int nwork, int tune,
-                    hipStream_t st) {
+                    hipStream_t st, bool split = false) {
   const BatchItem *it_ = items;
   const int2 *w_ = work;
   int nw = nwork, tn = tune;
-  void *args[] = {&it_, &w_, &nw, &tn};
+  const bool sp = split && pc.inner_fn && !tune;
+  int skip = sp ? 1 : 0;
+  void *args[] = {&it_, &w_, &nw, &tn, &skip};
   (void)hipLaunchKernel(pc.fn, dim3(nwork), dim3(pc.threads), args, 0, st);
+  if (sp) {
+    void *iargs[] = {&it_, &w_, &nw};
+    (void)hipLaunchKernel(pc.inner_fn, dim3(nwork), dim3(512), iargs, 0, st);
+  }
 }
 
 }  // namespace
@@ -1101,7 +1141,7 @@ sap_status run_batch(sap_ctx *ctx, int count, const sap_problem *probs, const sa
   hipGraphExec_t gexec = nullptr;
   SAP_HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
   for (int k = 0; k < kIterPerGraph; ++k) {
-    launch_pass_fn(pc, ditems, dpass, npass, 0, st);
+    launch_pass_fn(pc, ditems, dpass, npass, 0, st, any_refine);
     batch_lower_kernel<<<dim3(nblk_max, count), kTrsvThreads, 0, st>>>(ditems, dflags);
     batch_upper_kernel<<<dim3(nblk_max, count), kTrsvThreads, 0, st>>>(ditems, dflags, dflags + 1);
     if (any_refine) batch_refine_kernel<<<count, 1024, 0, st>>>(ditems, dflags + 1);
@@ -1386,7 +1426,7 @@ hipError_t serve_round(Server *S, std::vector<ServeRequest *> &fresh) {
     const int nwork = static_cast<int>(pass_work.size());
     auto launch_iters = [&](hipStream_t ls) {
       for (int k = 0; k < S->iters_per_round; ++k) {
-        launch_pass_fn(pc, S->d_active, S->d_pass, nwork, 0, ls);
+        launch_pass_fn(pc, S->d_active, S->d_pass, nwork, 0, ls, any_refine);
         batch_lower_kernel<<<dim3(nblk_max, count), kTrsvThreads, 0, ls>>>(S->d_active, S->d_flags);
         batch_upper_kernel<<<dim3(nblk_max, count), kTrsvThreads, 0, ls>>>(S->d_active, S->d_flags,
                                                                           S->d_flags + 1);
