@@ -874,7 +874,11 @@ struct BatchTuneKey {
     return std::tie(a_type, n_bucket, count) < std::tie(o.a_type, o.n_bucket, o.count);
   }
 };
-static std::map<BatchTuneKey, int64_t> g_tune_rows;
+struct BatchTune {
+  int64_t rows_per_chunk;
+  bool pf;  // the pass variant: 512-thread workgroups with two row groups in flight
+};
+static std::map<BatchTuneKey, BatchTune> g_tune_rows;
 
 // d = 0 (choose: eq. (4.2)'s d with cost ratio 1, within the batched form's
 // limit) and the fixed-count mode (maxiter = the set count, tol = 0).
@@ -954,9 +958,13 @@ sap_status run_batch(sap_ctx *ctx, int count, const sap_problem *probs, const sa
   // ---- workspace layout ---------------------------------------------------------
   const BatchTuneKey key{static_cast<int>(at), (n_max + 63) / 64, count};
   int64_t rows_per_chunk = 4096;
+  bool pass_pf = false;
   auto tit = g_tune_rows.find(key);
   const bool have_tune = tit != g_tune_rows.end();
-  if (have_tune) rows_per_chunk = tit->second;
+  if (have_tune) {
+    rows_per_chunk = tit->second.rows_per_chunk;
+    pass_pf = tit->second.pf;
+  }
   std::vector<size_t> need(count);
   size_t total = 8 * 256 + sizeof(BatchItem) * count + static_cast<size_t>(count) * 256;
   int64_t total_chunks_max = 0;
@@ -1087,50 +1095,60 @@ sap_status run_batch(sap_ctx *ctx, int count, const sap_problem *probs, const sa
   SAP_HIP_TRY(hipMemcpyAsync(items.data(), ditems, sizeof(BatchItem) * count, hipMemcpyDeviceToHost, st));
   SAP_HIP_TRY(hipStreamSynchronize(st));
 
-  // ---- autotune the pass chunking once per batch shape ----
-  const PassChoice pc = (at == SAP_F32) ? pick_batch_pass<float>(n_max, aligned, false)
-                                         : pick_batch_pass<double>(n_max, aligned, false);
+  // ---- autotune the pass once per batch shape: rows per work item and the
+  // variant (1024-thread workgroups, one row group in flight per wave, or
+  // 512-thread workgroups with two), each timed on the device ----
+  auto pick = [&](bool pf) {
+    return (at == SAP_F32) ? pick_batch_pass<float>(n_max, aligned, pf) : pick_batch_pass<double>(n_max, aligned, pf);
+  };
   if (!have_tune) {
     const int64_t cands[] = {2048, 4096, 8192, 16384};
     float best_ms = 1e30f;
     int64_t best = rows_per_chunk;
+    bool best_pf = false;
     hipEvent_t e0, e1;
     SAP_HIP_TRY(hipEventCreate(&e0));
     SAP_HIP_TRY(hipEventCreate(&e1));
-    for (int64_t c : cands) {
-      std::vector<int2> wt = pass_table(c);
-      std::vector<BatchItem> tmp = items;
-      for (auto &it : tmp) {
-        it.rows_per_chunk = c;
-        it.G = static_cast<int>((it.m + c - 1) / c);
-      }
-      SAP_HIP_TRY(hipMemcpyAsync(ditems, tmp.data(), sizeof(BatchItem) * count, hipMemcpyHostToDevice, st));
-      SAP_HIP_TRY(hipMemcpyAsync(dpass, wt.data(), sizeof(int2) * wt.size(), hipMemcpyHostToDevice, st));
-      float ms_best = 1e30f;
-      for (int rep = 0; rep < 2; ++rep) {
-        SAP_HIP_TRY(hipEventRecord(e0, st));
-        launch_pass_fn(pc, ditems, dpass, static_cast<int>(wt.size()), 1, st);
-        SAP_HIP_TRY(hipEventRecord(e1, st));
-        SAP_HIP_TRY(hipEventSynchronize(e1));
-        float ms = 0.f;
-        SAP_HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-        ms_best = std::min(ms_best, ms);
-      }
-      if (ms_best < best_ms) {
-        best_ms = ms_best;
-        best = c;
+    for (const bool pf : {false, true}) {
+      const PassChoice pcv = pick(pf);
+      for (int64_t c : cands) {
+        std::vector<int2> wt = pass_table(c);
+        std::vector<BatchItem> tmp = items;
+        for (auto &it : tmp) {
+          it.rows_per_chunk = c;
+          it.G = static_cast<int>((it.m + c - 1) / c);
+        }
+        SAP_HIP_TRY(hipMemcpyAsync(ditems, tmp.data(), sizeof(BatchItem) * count, hipMemcpyHostToDevice, st));
+        SAP_HIP_TRY(hipMemcpyAsync(dpass, wt.data(), sizeof(int2) * wt.size(), hipMemcpyHostToDevice, st));
+        float ms_best = 1e30f;
+        for (int rep = 0; rep < 2; ++rep) {
+          SAP_HIP_TRY(hipEventRecord(e0, st));
+          launch_pass_fn(pcv, ditems, dpass, static_cast<int>(wt.size()), 1, st);
+          SAP_HIP_TRY(hipEventRecord(e1, st));
+          SAP_HIP_TRY(hipEventSynchronize(e1));
+          float ms = 0.f;
+          SAP_HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+          ms_best = std::min(ms_best, ms);
+        }
+        if (ms_best < best_ms) {
+          best_ms = ms_best;
+          best = c;
+          best_pf = pf;
+        }
       }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     rows_per_chunk = best;
-    g_tune_rows[key] = best;
+    pass_pf = best_pf;
+    g_tune_rows[key] = BatchTune{best, best_pf};
     for (auto &it : items) {
       it.rows_per_chunk = best;
       it.G = static_cast<int>((it.m + best - 1) / best);
     }
     SAP_HIP_TRY(hipMemcpyAsync(ditems, items.data(), sizeof(BatchItem) * count, hipMemcpyHostToDevice, st));
   }
+  const PassChoice pc = pick(pass_pf);
   std::vector<int2> pass_work = pass_table(rows_per_chunk);
   SAP_HIP_TRY(hipMemcpyAsync(dpass, pass_work.data(), sizeof(int2) * pass_work.size(), hipMemcpyHostToDevice, st));
   const int npass = static_cast<int>(pass_work.size());
