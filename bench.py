@@ -142,16 +142,22 @@ def copy_reference(torch, mib):
 
 TRAFFIC_PROFILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
                                "lsqr_pass_fp64_m1048576_n1000_counters.md")
-PASS_SOURCES = ("lsqr.hip", "lsqr_dev.h", "common.h")
+# the fused pass's own code: (file, first marker, last marker)
+PASS_SOURCES = (("lsqr.hip", "[fused-pass-begin]", "[fused-pass-end]"),
+                ("common.h", "[wave-helpers-begin]", "[wave-helpers-end]"))
 
 
 def pass_sources_sha256():
+    """Hash of the fused pass kernel's code (the marked regions), so that the
+    committed HBM counters are reported only while they describe it."""
     import hashlib
     h = hashlib.sha256()
-    for f in PASS_SOURCES:
+    for f, b, e in PASS_SOURCES:
         with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2506_03070_amd", "csrc", f),
-                  "rb") as fh:
-            h.update(fh.read())
+                  encoding="utf-8") as fh:
+            text = fh.read()
+        i, j = text.index(b), text.index(e)
+        h.update(text[i:j].encode("utf-8"))
     return h.hexdigest()
 
 

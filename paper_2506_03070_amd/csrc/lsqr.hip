@@ -1,24 +1,26 @@
 // Preconditioned LSQR (Alg. 2) on A M, M = R^-1, for gfx950.
 //
-// One iteration is three kernels on one stream, with no host round trip:
-//   1. pass  : one sweep over A computing, for every row i,
-//                u_i <- c_ap (A p)_i + c_u u_i        (p = M v_t)
-//              and accumulating q = A^T u and ||u||^2 from the same
-//              registers.  This is the one-synchronisation reorganisation of
-//              App. D.4.1: A^T is applied to the unnormalised u_hat and the
-//              scale 1/beta is folded into the next step, so A is read once
-//              per iteration instead of twice.  One 16-wave workgroup per CU
-//              writes one partial q.
-//   2. lower : the chain solve y = R^-T q (trsv.h), whose workgroups first
-//              reduce the partials of their block of q (fixed order); the
-//              last block's workgroup then forms v_hat = y/beta - beta v,
-//              alpha = ||v_hat||, v = v_hat/alpha.
-//   3. upper : the chain solve p = R^-1 v; the last block's workgroup does the
-//              plane rotation, x += (phi/rho) w, w = p - (theta/rho) w, the
-//              convergence test and the coefficients of the next pass.
+// One iteration is five kernels on one stream, with no host round trip:
+//   1. pass   : one sweep over A computing, for every row i,
+//                 u_i <- c_ap (A p)_i + c_u u_i        (p = M v_t)
+//               and accumulating q = A^T u and ||u||^2 from the same
+//               registers.  This is the one-synchronisation reorganisation
+//               of App. D.4.1: A^T is applied to the unnormalised u_hat and
+//               the scale 1/beta is folded into the next step, so A is read
+//               once per iteration instead of twice.  Each workgroup writes
+//               one partial q.
+//   2. q_slices: the partials summed in fixed-order slices;
+//   3. mtq    : v_hat = M^T q / beta - beta v and the partials of ||v_hat||^2
+//               (M = R^-1 formed once per solve, Sec. 3.2);
+//   4. mv     : alpha, v = v_hat / alpha, p = M v;
+//   5. update : plane rotation, x += (phi/rho) w, w = p - (theta/rho) w, the
+//               stopping test and the coefficients of the next pass.
 // All scalars stay in device memory.  Kernels early-exit once the device
-// `done` flag is set, so the host enqueues iterations in batches and reads
-// the flag once per batch.
+// `done` flag is set, so the host enqueues iterations in batches of eight
+// (captured once into a hipGraph and replayed) and reads the flag once per
+// batch, while the next batch runs.  The same file holds the refinement form
+// (FP32 inner passes, FP64 residual restarts) and heavy-ball momentum
+// (App. D.3), which reuses the pass with p = x and u_in = b.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -37,6 +39,8 @@ constexpr int kPassThreads = 512;
 constexpr int kPassWaves = kPassThreads / kWave;
 constexpr int kMaxN = 8192;
 
+// [fused-pass-begin] (the benchmark hashes this region, with the wavefront
+// helpers, to tell whether HBM counters taken on the pass still describe it)
 // --------------------------------------------------------------------------
 // Fused pass.  MODE 0: A in FP64.  MODE 1: A stored in FP32 (the mixed
 // form): p, the accumulation and u are FP64, an FP32 element is widened
@@ -263,6 +267,8 @@ __global__ __launch_bounds__(kPassThreads) void lsqr_pass_kernel(
     }
   }
 }
+
+// [fused-pass-end]
 
 // --------------------------------------------------------------------------
 // Explicit preconditioner M = R^-1 (the paper's choice, Sec. 3.2).  Formed
