@@ -70,7 +70,24 @@ struct BatchItem {
   int32_t rank_deficient, pad;
   int32_t refine, max_refine;  // refinement form (FP32 inner solves), its cap (0 = 10)
   double *xprev;               // x before the current inner solve (refinement form)
+  // sketch apply in row slices: aslices work items per strip, each over arows
+  // rows of [A b]; with more than one, unscaled partial sketches land in
+  // Ypart (slice-major, each d x (n+1) column-major) and are summed into Y
+  double *Ypart;
+  int64_t arows;
+  int32_t aslices, apad;
 };
+
+// Row slices of a problem's sketch apply: about kApplySliceRows rows each, at
+// most kMaxApplySlices, and their partial sketches no larger than half of
+// the problem's FP32 A.
+constexpr int64_t kApplySliceRows = 65536;
+constexpr int kMaxApplySlices = 16;
+inline int apply_slices(int64_t m, int n, int d) {
+  int sl = static_cast<int>(std::min<int64_t>(kMaxApplySlices, (m + kApplySliceRows - 1) / kApplySliceRows));
+  while (sl > 1 && static_cast<double>(sl) * (n + 1) * d * 8.0 > 2.0 * static_cast<double>(m) * n) --sl;
+  return std::max(1, sl);
+}
 
 namespace {
 
@@ -100,8 +117,11 @@ __global__ __launch_bounds__(256) void batch_generate_kernel(const BatchItem *__
 }
 
 // ---- apply -----------------------------------------------------------------
-// Work item = (problem, strip of W columns); the strip of Y (d + 1 spare
-// rows by W columns) is accumulated in FP64 in LDS.
+// Work item = (problem, strip of W columns, row slice): the strip of Y (d + 1
+// spare rows by W columns) is accumulated in FP64 in LDS over the slice's
+// rows; a problem of one slice writes h times it into Y, otherwise into its
+// slice of Ypart (summed by batch_apply_reduce_kernel).  work.y packs the
+// strip (low 20 bits) and the slice.
 template <typename TA, int W>
 __global__ __launch_bounds__(kBThreads) void batch_apply_kernel(const BatchItem *__restrict__ items,
                                                                 const int2 *__restrict__ work, int nwork) {
@@ -114,9 +134,13 @@ __global__ __launch_bounds__(kBThreads) void batch_apply_kernel(const BatchItem 
   if (wi >= nwork) return;
   const int2 wk = work[wi];
   const BatchItem &it = items[wk.x];
-  const int c0 = wk.y * kTileColsB;
+  const int strip = wk.y & 0xFFFFF, slice = wk.y >> 20;
+  const int c0 = strip * kTileColsB;
   const int d = it.d, n = it.n, ncols = it.n + 1, zeta = it.zeta;
-  const TA *__restrict__ A = static_cast<const TA *>(it.A);
+  const gmem<TA> *__restrict__ A = gview(static_cast<const TA *>(it.A));
+  const gmem<double> *__restrict__ bvec = gview(it.b);
+  const gmem<uint64_t> *__restrict__ sgn = gview(it.sign);
+  const gmem<int32_t> *__restrict__ idx = gview(it.idx);
   for (int e = threadIdx.x; e < (d + 1) * kTileColsB; e += kBThreads) acc[e] = TY(0);
   __syncthreads();
   // One row of [A b] per group of 16 lanes: its 16-column piece is loaded
@@ -127,15 +151,17 @@ __global__ __launch_bounds__(kBThreads) void batch_apply_kernel(const BatchItem 
   const int g = lane / kTileColsB, c = lane % kTileColsB;
   const int col = c0 + c;
   const bool col_a = col < n, col_b = col == n;
-  const int64_t m = it.m;
+  const int64_t r_lo = static_cast<int64_t>(slice) * it.arows;
+  const int64_t m = min(it.m, r_lo + it.arows);  // end of this slice's rows
   constexpr int U = 8;
   constexpr int64_t kStride = static_cast<int64_t>(kBWaves) * RPW * U;
   const bool fast = zeta == 8 && (reinterpret_cast<uintptr_t>(it.idx) % 16 == 0);
-  for (int64_t base = static_cast<int64_t>(wave) * RPW * U + g; base < m; base += kStride) {
+  for (int64_t base = r_lo + static_cast<int64_t>(wave) * RPW * U + g; base < m; base += kStride) {
     if (fast) {
       TY val[U];
       uint32_t sg[U];
-      int4 ix[U][2];
+      typedef int iv4 __attribute__((ext_vector_type(4)));
+      iv4 ix[U][2];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int64_t i0 = base + u * RPW;
@@ -143,10 +169,10 @@ __global__ __launch_bounds__(kBThreads) void batch_apply_kernel(const BatchItem 
         const int64_t i = ok ? i0 : m - 1;
         TY a = TY(0);
         if (col_a) a = static_cast<TY>(A[i * it.lda + col]);
-        else if (col_b) a = static_cast<TY>(it.b[i]);
+        else if (col_b) a = static_cast<TY>(bvec[i]);
         val[u] = ok ? a : TY(0);
-        sg[u] = static_cast<uint32_t>(it.sign[i]);
-        const int4 *ip = reinterpret_cast<const int4 *>(it.idx + i * 8);
+        sg[u] = static_cast<uint32_t>(sgn[i]);
+        const gmem<iv4> *ip = reinterpret_cast<const gmem<iv4> *>(idx + i * 8);
         ix[u][0] = ip[0];
         ix[u][1] = ip[1];
       }
@@ -166,9 +192,9 @@ __global__ __launch_bounds__(kBThreads) void batch_apply_kernel(const BatchItem 
         if (i >= m) break;
         TY a = TY(0);
         if (col_a) a = static_cast<TY>(A[i * it.lda + col]);
-        else if (col_b) a = static_cast<TY>(it.b[i]);
-        const uint64_t sg = it.sign[i];
-        const int32_t *ri = it.idx + i * zeta;
+        else if (col_b) a = static_cast<TY>(bvec[i]);
+        const uint64_t sg = sgn[i];
+        const gmem<int32_t> *ri = idx + i * zeta;
         for (int k0 = 0; k0 < zeta; k0 += 4) {
           int rr[4];
 #pragma unroll
@@ -182,13 +208,27 @@ __global__ __launch_bounds__(kBThreads) void batch_apply_kernel(const BatchItem 
     }
   }
   __syncthreads();
-  double *Y = it.Y;
-  const TY hs = static_cast<TY>(it.h);
+  const bool direct = it.aslices <= 1;
+  double *Y = direct ? it.Y : it.Ypart + static_cast<int64_t>(slice) * d * ncols;
+  const TY hs = direct ? static_cast<TY>(it.h) : TY(1);
   for (int e = threadIdx.x; e < d * kTileColsB; e += kBThreads) {
     const int q = e / d, r = e % d;
     const int cc = c0 + q;
     if (cc < ncols) Y[r + static_cast<int64_t>(cc) * d] = acc[r * kTileColsB + q] * hs;
   }
+}
+
+// Y = h * (sum of the slice partials, slice order) for the problems whose
+// apply ran in several row slices.  Grid: (element blocks of 256, problems).
+__global__ __launch_bounds__(256) void batch_apply_reduce_kernel(const BatchItem *__restrict__ items) {
+  const BatchItem &it = items[blockIdx.y];
+  if (it.aslices <= 1) return;
+  const int64_t tot = static_cast<int64_t>(it.d) * (it.n + 1);
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  if (e >= tot) return;
+  double s = 0.0;
+  for (int k = 0; k < it.aslices; ++k) s += it.Ypart[k * tot + e];
+  it.Y[e] = s * it.h;
 }
 
 // ---- QR ----------------------------------------------------------------------
@@ -383,18 +423,17 @@ __device__ __forceinline__ void batch_pass_body(const BatchItem &it, int chunk, 
   const int n = it.n;
   const bool init = st->init != 0;
   const double *__restrict__ pv = init ? it.x : it.p;
-  const TU *__restrict__ uin = init ? nullptr : reinterpret_cast<const TU *>(it.u);
-  const double *__restrict__ bin = it.b;
-  TU *uout = reinterpret_cast<TU *>(it.u);
+  const gmem<TU> *__restrict__ uin = init ? nullptr : gview(reinterpret_cast<const TU *>(it.u));
+  const gmem<double> *__restrict__ bin = gview(it.b);
+  gmem<TU> *uout = gview(reinterpret_cast<TU *>(it.u));
   const TC c_ap = static_cast<TC>(st->c_ap), c_u = static_cast<TC>(st->c_u);
   int L = 1;
   while (L * VEC * KJ < n && L < 64) L <<= 1;
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
   const int slot = lane / L, sub = lane % L;
   const int RS = kWave / L;  // rows per wavefront step
-  const TA *__restrict__ A = static_cast<const TA *>(it.A);
+  const gmem<TA> *__restrict__ A = gview(static_cast<const TA *>(it.A));
   const int64_t lda = it.lda;
-  const bool vec_ok = (VEC > 1);
 
   for (int c = threadIdx.x; c < 64 * VEC * KJ; c += TH) {
     psh[c] = c < n ? static_cast<TC>(pv[c]) : TC(0);
@@ -410,46 +449,82 @@ __device__ __forceinline__ void batch_pass_body(const BatchItem &it, int chunk, 
   const int64_t r1 = min(it.m, r0 + it.rows_per_chunk);
   double nrm = 0.0;
   const int64_t gstride = static_cast<int64_t>(NW) * RS * U;
+  // Loads without per-lane branches: a row past the chunk reads the chunk's
+  // last row (its results are dropped), a lane past the row's whole vectors
+  // reads the last whole vector (its p entries are zero and its q sums are
+  // never stored).  Only the vector that straddles n (n % VEC != 0) is read
+  // element by element.
+  const int cf = (n / VEC) * VEC;  // columns in whole vectors
+  const int clast = cf - VEC;      // start of the last whole vector (< 0: none)
   auto load_group = [&](int64_t base, TA (&a)[U][KJ][VEC], TC (&ui)[U]) {
 #pragma unroll
     for (int uu = 0; uu < U; ++uu) {
       const int64_t row = base + uu * RS + slot;
-      const bool rv = row < r1;
-      const TA *arow = A + row * lda;
+      const int64_t rowc = row < r1 ? row : r1 - 1;
+      const gmem<TA> *arow = A + rowc * lda;
 #pragma unroll
       for (int j = 0; j < KJ; ++j) {
         const int c = (sub + L * j) * VEC;
-        if (rv && vec_ok && c + VEC <= n) {
-          load_stream<TA, VEC>(arow + c, a[uu][j]);
+        if (clast >= 0) {
+          load_stream<TA, VEC>(arow + min(c, clast), a[uu][j]);
         } else {
 #pragma unroll
-          for (int e = 0; e < VEC; ++e) a[uu][j][e] = (rv && c + e < n) ? __builtin_nontemporal_load(arow + c + e) : TA(0);
+          for (int e = 0; e < VEC; ++e) a[uu][j][e] = TA(0);
+        }
+        if (cf != n && c == cf) {
+#pragma unroll
+          for (int e = 0; e < VEC; ++e) a[uu][j][e] = (c + e < n) ? __builtin_nontemporal_load(arow + c + e) : TA(0);
         }
       }
-      ui[uu] = rv ? (init ? static_cast<TC>(bin[row]) : static_cast<TC>(uin[row])) : TC(0);
+      ui[uu] = init ? static_cast<TC>(bin[rowc]) : static_cast<TC>(uin[rowc]);
     }
   };
+  // u_i <- c_ap (A_i p) + c_u u_i and q += u_i A_i for row i.
+  auto update_row = [&](int64_t row, TC s, TA (&ar)[KJ][VEC], TC ui) {
+    if (row >= r1) return;
+    const TC uh = c_ap * s + c_u * ui;
+    const TU us = static_cast<TU>(uh);
+#pragma unroll
+    for (int j = 0; j < KJ; ++j)
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) q[j][e] += static_cast<TC>(us) * static_cast<TC>(ar[j][e]);
+    if (sub == 0) {
+      if (!tune) uout[row] = us;
+      nrm += static_cast<double>(us) * static_cast<double>(us);
+    }
+  };
+  auto dot_row = [&](TA (&ar)[KJ][VEC]) {
+    TC s = TC(0);
+#pragma unroll
+    for (int j = 0; j < KJ; ++j)
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) s += static_cast<TC>(ar[j][e]) * psh[(sub + L * j) * VEC + e];
+    return s;
+  };
+  // Each row's dot product is reduced over its L lanes.  With 512 threads
+  // (registers to spare) the U rows of a group are reduced together, one
+  // cross-lane round trip per step for all of them; with 1024 threads (128
+  // registers) one row at a time, which keeps fewer values live.
   auto compute_group = [&](int64_t base, TA (&a)[U][KJ][VEC], TC (&ui)[U]) {
+    if constexpr (TH <= 512) {
+      TC s[U];
 #pragma unroll
-    for (int uu = 0; uu < U; ++uu) {
-      const int64_t row = base + uu * RS + slot;
-      TC s = TC(0);
+      for (int uu = 0; uu < U; ++uu) s[uu] = dot_row(a[uu]);
+      for (int off = L >> 1; off >= 1; off >>= 1) {
+        TC t[U];
 #pragma unroll
-      for (int j = 0; j < KJ; ++j)
+        for (int uu = 0; uu < U; ++uu) t[uu] = __shfl_xor(s[uu], off, kWave);
 #pragma unroll
-        for (int e = 0; e < VEC; ++e) s += static_cast<TC>(a[uu][j][e]) * psh[(sub + L * j) * VEC + e];
-      for (int off = L >> 1; off >= 1; off >>= 1) s += __shfl_xor(s, off, kWave);
-      if (row < r1) {
-        const TC uh = c_ap * s + c_u * ui[uu];
-        const TU us = static_cast<TU>(uh);
+        for (int uu = 0; uu < U; ++uu) s[uu] += t[uu];
+      }
 #pragma unroll
-        for (int j = 0; j < KJ; ++j)
+      for (int uu = 0; uu < U; ++uu) update_row(base + uu * RS + slot, s[uu], a[uu], ui[uu]);
+    } else {
 #pragma unroll
-          for (int e = 0; e < VEC; ++e) q[j][e] += static_cast<TC>(us) * static_cast<TC>(a[uu][j][e]);
-        if (sub == 0) {
-          if (!tune) uout[row] = us;
-          nrm += static_cast<double>(us) * static_cast<double>(us);
-        }
+      for (int uu = 0; uu < U; ++uu) {
+        TC s = dot_row(a[uu]);
+        for (int off = L >> 1; off >= 1; off >>= 1) s += __shfl_xor(s, off, kWave);
+        update_row(base + uu * RS + slot, s, a[uu], ui[uu]);
       }
     }
   };
@@ -474,15 +549,30 @@ __device__ __forceinline__ void batch_pass_body(const BatchItem &it, int chunk, 
       compute_group(base, a, ui);
     }
   }
-  // combine the row slots of the wavefront (lanes with equal `sub`), then waves
+  // combine the row slots of the wavefront (lanes with equal `sub`), then
+  // waves; as above, all values per step where registers allow
+  if constexpr (TH <= 512) {
+    for (int off = L; off < kWave; off <<= 1) {
+      TC t[KJ][VEC];
 #pragma unroll
-  for (int j = 0; j < KJ; ++j)
+      for (int j = 0; j < KJ; ++j)
 #pragma unroll
-    for (int e = 0; e < VEC; ++e) {
-      TC v = q[j][e];
-      for (int off = L; off < kWave; off <<= 1) v += __shfl_xor(v, off, kWave);
-      q[j][e] = v;
+        for (int e = 0; e < VEC; ++e) t[j][e] = __shfl_xor(q[j][e], off, kWave);
+#pragma unroll
+      for (int j = 0; j < KJ; ++j)
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) q[j][e] += t[j][e];
     }
+  } else {
+#pragma unroll
+    for (int j = 0; j < KJ; ++j)
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) {
+        TC v = q[j][e];
+        for (int off = L; off < kWave; off <<= 1) v += __shfl_xor(v, off, kWave);
+        q[j][e] = v;
+      }
+  }
   nrm = wave_sum(nrm);
   if (lane == 0) nsh[wave] = nrm;
   for (int w = 0; w < NW; ++w) {
@@ -494,12 +584,12 @@ __device__ __forceinline__ void batch_pass_body(const BatchItem &it, int chunk, 
     }
     __syncthreads();
   }
-  double *qdst = it.qpart + static_cast<int64_t>(chunk) * n;
+  gmem<double> *qdst = gview(it.qpart) + static_cast<int64_t>(chunk) * n;
   for (int c = threadIdx.x; c < n; c += TH) qdst[c] = static_cast<double>(qacc[c]);
   if (threadIdx.x == 0) {
     double sum = 0.0;
     for (int w = 0; w < NW; ++w) sum += nsh[w];
-    it.nrmpart[chunk] = sum;
+    gview(it.nrmpart)[chunk] = sum;
   }
 }
 
@@ -774,6 +864,8 @@ size_t item_bytes(int64_t m, int n, int d, int zeta, sap_dtype at) {
   b += 5 * (256 + sizeof(double) * n);
   b += 256 + sizeof(double) * gmax * n;
   b += 256 + sizeof(double) * gmax;
+  const int sl = apply_slices(m, n, d);
+  if (sl > 1) b += 256 + sizeof(double) * static_cast<size_t>(sl) * d * nc;
   return (b + 256 + 255) / 256 * 256;  // a multiple of 256: consecutive items stay aligned
 }
 
@@ -806,6 +898,9 @@ void carve_item(BatchItem &it, void *base, sap_dtype at, int64_t rows_per_chunk)
   it.nrmpart = cv.take<double>(gmax);
   it.rows_per_chunk = rows_per_chunk;
   it.G = static_cast<int>((m + rows_per_chunk - 1) / rows_per_chunk);
+  it.aslices = apply_slices(m, n, d);
+  it.arows = (m + it.aslices - 1) / it.aslices;
+  it.Ypart = it.aslices > 1 ? cv.take<double>(static_cast<size_t>(it.aslices) * d * nc) : nullptr;
 }
 
 // Phases S1-S7 setup for the `count` problems of a device items array:
@@ -846,6 +941,10 @@ sap_status setup_items(sap_ctx *ctx, BatchItem *ditems, const std::vector<BatchI
       case 8: batch_apply_kernel<double, 8><<<ag, kBThreads, lds, st>>>(ditems, dapply, napply); break;
       default: batch_apply_kernel<double, 4><<<ag, kBThreads, lds, st>>>(ditems, dapply, napply); break;
     }
+  }
+  {
+    const int64_t tot_max = static_cast<int64_t>(d_max) * (n_max + 1);
+    batch_apply_reduce_kernel<<<dim3(static_cast<unsigned>((tot_max + 255) / 256), count), 256, 0, st>>>(ditems);
   }
   SAP_HIP_TRY(hipGetLastError());
   const int sh = (d_max + kPanelThreads - 1) / kPanelThreads;
@@ -978,7 +1077,7 @@ sap_status run_batch(sap_ctx *ctx, int count, const sap_problem *probs, const sa
   const int aw = batch_apply_width(d_max);
   const int tiles_max = (n_max + 1 + aw - 1) / aw;
   total += 256 + sizeof(int2) * (total_chunks_max + 16);
-  total += 256 + sizeof(int2) * (static_cast<size_t>(count) * tiles_max + 16);
+  total += 256 + sizeof(int2) * (static_cast<size_t>(count) * tiles_max * kMaxApplySlices + 16);
   const size_t repack_total = repack_idx.empty() ? 0
                                                  : repack_bytes + 2 * 256 + sizeof(RepackJob) * repack_idx.size() +
                                                        sizeof(int2) * static_cast<size_t>(repack_chunks);
@@ -1018,7 +1117,7 @@ sap_status run_batch(sap_ctx *ctx, int count, const sap_problem *probs, const sa
     carve_item(it, cv.take<char>(need[k]), at, rows_per_chunk);
   }
   int2 *dpass = cv.take<int2>(total_chunks_max + 16);
-  int2 *dapply = cv.take<int2>(static_cast<size_t>(count) * tiles_max + 16);
+  int2 *dapply = cv.take<int2>(static_cast<size_t>(count) * tiles_max * kMaxApplySlices + 16);
   std::vector<RepackJob> jobs;
   std::vector<int2> repack_work;
   RepackJob *djobs = nullptr;
@@ -1050,7 +1149,8 @@ sap_status run_batch(sap_ctx *ctx, int count, const sap_problem *probs, const sa
   std::vector<int2> apply_work;
   for (int k = 0; k < count; ++k) {
     const int tiles = (items[k].n + 1 + aw - 1) / aw;
-    for (int t = 0; t < tiles; ++t) apply_work.push_back(make_int2(k, t));
+    for (int t = 0; t < tiles; ++t)
+      for (int sl = 0; sl < items[k].aslices; ++sl) apply_work.push_back(make_int2(k, t | (sl << 20)));
   }
   auto pass_table = [&](int64_t rpc_) {
     std::vector<int2> wt;
@@ -1352,7 +1452,7 @@ int64_t serve_rows_per_chunk(int n, sap_dtype at) {
   return r;
 }
 constexpr int kServeMaxChunks = 1 << 20;
-constexpr int kServeMaxApply = 1 << 18;
+constexpr int kServeMaxApply = 1 << 20;
 
 // A device error ends serving: every request not finished yet fails.
 void serve_fail_all(Server *S, const std::string &msg, std::vector<ServeRequest *> &fresh) {
@@ -1399,7 +1499,8 @@ hipError_t serve_round(Server *S, std::vector<ServeRequest *> &fresh) {
       col_base += it.m;
       new_items[k] = it;
       const int tiles = (it.n + 1 + aw - 1) / aw;
-      for (int t = 0; t < tiles; ++t) apply_work.push_back(make_int2(static_cast<int>(k), t));
+      for (int t = 0; t < tiles; ++t)
+        for (int sl = 0; sl < it.aslices; ++sl) apply_work.push_back(make_int2(static_cast<int>(k), t | (sl << 20)));
     }
     if (static_cast<int>(apply_work.size()) > kServeMaxApply) return hipErrorInvalidValue;
     for (ServeRequest *r : fresh)

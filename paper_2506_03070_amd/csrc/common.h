@@ -117,8 +117,6 @@ __device__ __forceinline__ double block_sum(double v, double *scratch, int nwave
     if (_e != hipSuccess) return ::sap::hip_fail(ctx, _e, #expr);  \
   } while (0)
 
-// Device-resident LSQR state.  All recurrence scalars stay on the device so
-// that an iteration needs no host round trip.
 // Streaming load of V consecutive elements (16 bytes or fewer) with the
 // nontemporal hint: data read once per pass should not displace what the
 // caches hold for reuse.  On gfx950 a read-only stream reaches ~90% of the
@@ -134,6 +132,36 @@ __device__ __forceinline__ void load_stream(const T *p, T (&out)[V]) {
     for (int e = 0; e < V; ++e) out[e] = v[e];
   }
 }
+
+// Global-memory views.  A pointer that a kernel reads from device memory (a
+// field of a work-item descriptor) is generic to the compiler, which then
+// emits flat loads and stores; a flat access also counts against the LDS
+// wait counter, so every LDS or cross-lane wait in a loop drains the loads
+// in flight.  Through these views the accesses are global ones.
+template <typename T>
+using gmem = __attribute__((address_space(1))) T;
+template <typename T>
+__device__ __forceinline__ const gmem<T> *gview(const T *p) {
+  return (const gmem<T> *)p;
+}
+template <typename T>
+__device__ __forceinline__ gmem<T> *gview(T *p) {
+  return (gmem<T> *)p;
+}
+template <typename T, int V>
+__device__ __forceinline__ void load_stream(const gmem<T> *p, T (&out)[V]) {
+  if constexpr (V == 1) {
+    out[0] = __builtin_nontemporal_load(p);
+  } else {
+    typedef T vec_t __attribute__((ext_vector_type(V)));
+    const vec_t v = __builtin_nontemporal_load(reinterpret_cast<const gmem<vec_t> *>(p));
+#pragma unroll
+    for (int e = 0; e < V; ++e) out[e] = v[e];
+  }
+}
+
+// Device-resident LSQR state.  All recurrence scalars stay on the device so
+// that an iteration needs no host round trip.
 
 struct LsqrState {
   double alpha, beta, rhobar, phibar;

@@ -207,3 +207,32 @@ def test_batch_auto_d_and_fixed_count(sap, orc):
         assert infos[k]["d_used"] == d and infos[k]["iters"] == T
         x_or, io = orc.solve(p.A, p.b, d, 8, 13, tol=0.0, maxiter=T, stream=k)
         assert np.linalg.norm(p.A @ (xs[k].cpu().numpy() - x_or)) <= 1e-11 * np.linalg.norm(p.b), k
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_batch_row_slices_fixed_count(sap, orc, dtype):
+    """Problems tall enough that the sketch apply splits their rows over
+    several work items (65536 rows a slice: 2, 3 and 4 slices here, the last
+    one ragged) beside one that does not.  A fixed count of 8 steps is run on
+    both sides: the iterate after 8 steps still depends on the preconditioner
+    (a sketch that lost or doubled rows moves it by ~1e-3 relative), so the
+    FP64 bars hold only if every slice's rows land in the sketch once."""
+    import torch
+    shapes = [(70001, 24), (140000, 100), (200003, 40), (5000, 30)]
+    print(f"batch row slices dtype={np.dtype(dtype).name} shapes={shapes}", flush=True)
+    probs = [inputs.make_problem(m, n, kind="colscale", cond=1e4, noise=1e-8, seed=5100 + k, dtype=dtype)
+             for k, (m, n) in enumerate(shapes)]
+    As = [torch.from_numpy(np.ascontiguousarray(p.A)).cuda() for p in probs]
+    bs = [torch.from_numpy(p.b).cuda() for p in probs]
+    ds = [4 * p.A.shape[1] for p in probs]
+    T = 8
+    xs, st, infos = sap.sap_solve_batch(As, bs, ds, 8, 31, tol=0.0, maxiter=T, fixed_iters=T)
+    torch.cuda.synchronize()
+    for k, p in enumerate(probs):
+        A64 = p.A.astype(np.float64)
+        x_or, io = orc.solve(A64, p.b, ds[k], 8, 31, tol=0.0, maxiter=T, stream=k)
+        x = xs[k].cpu().numpy()
+        assert infos[k]["iters"] == T, infos[k]
+        nb, nx = np.linalg.norm(p.b), np.linalg.norm(x_or)
+        assert np.linalg.norm(A64 @ (x - x_or)) <= 1e-11 * nb, k
+        assert np.linalg.norm(x - x_or) <= 1e-8 * nx, k

@@ -207,3 +207,29 @@ def test_serve_refine_form(sap, orc, ctx):
         assert np.linalg.norm(A64 @ (x - x_or)) <= 1e-10 * np.linalg.norm(p.b), k
         if k == 0:
             assert np.linalg.norm(x - x_alone) <= 1e-9 * np.linalg.norm(x_alone)
+
+
+def test_serve_row_slices_fixed_count(sap, orc, ctx):
+    """Tall requests whose sketch apply is split over row slices (2 and 4 of
+    65536 rows, the last ragged) served beside a short one, each run for a
+    fixed 8 steps: the iterate still depends on the preconditioner, so the
+    FP64 bars against the oracle at the same count hold only if every
+    slice's rows enter the sketch exactly once."""
+    print("serve row slices", flush=True)
+    shapes = [(131073, 32), (250000, 48), (6000, 20)]
+    probs = [_problem(50 + k, m, n, 1e4) for k, (m, n) in enumerate(shapes)]
+    T = 8
+    tickets, keep = [], []
+    for k, p in enumerate(probs):
+        A, b = _dev(p.A), _dev(p.b)
+        keep.append((A, b))
+        tickets.append(sap.sap_submit(A, b, 4 * p.A.shape[1], 8, 90 + k, tol=0.0, maxiter=T, ctx=ctx, fixed_iters=T))
+    for k, (p, t) in enumerate(zip(probs, tickets)):
+        st, info, x = sap.sap_poll(t, wait=True, ctx=ctx)
+        assert st == sap.SAP_OK, info
+        assert info["iters"] == T, info
+        A64 = p.A.astype(np.float64)
+        x_or, _ = orc.solve(A64, p.b, 4 * p.A.shape[1], 8, 90 + k, tol=0.0, maxiter=T, stream=0)
+        x = x.cpu().numpy()
+        assert np.linalg.norm(A64 @ (x - x_or)) <= 1e-11 * np.linalg.norm(p.b), k
+        assert np.linalg.norm(x - x_or) <= 1e-8 * np.linalg.norm(x_or), k
