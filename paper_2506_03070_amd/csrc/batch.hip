@@ -75,7 +75,10 @@ struct BatchItem {
   // Ypart (slice-major, each d x (n+1) column-major) and are summed into Y
   double *Ypart;
   int64_t arows;
-  int32_t aslices, apad;
+  int32_t aslices;
+  // A is this form's repacked copy: rows of whole 16-byte vectors whose
+  // entries past n are zero, m * lda elements in all
+  int32_t zero_pad;
 };
 
 // Row slices of a problem's sketch apply: about kApplySliceRows rows each, at
@@ -427,8 +430,16 @@ __device__ __forceinline__ void batch_pass_body(const BatchItem &it, int chunk, 
   const gmem<double> *__restrict__ bin = gview(it.b);
   gmem<TU> *uout = gview(reinterpret_cast<TU *>(it.u));
   const TC c_ap = static_cast<TC>(st->c_ap), c_u = static_cast<TC>(st->c_u);
-  int L = 1;
-  while (L * VEC * KJ < n && L < 64) L <<= 1;
+  // kje (<= KJ) vectors of a row per lane, on L lanes: fewer vectors per
+  // lane while a row would otherwise sit on fewer than 8 lanes, so that each
+  // load instruction reads whole 128-byte lines of a short row.
+  int kje = KJ, L = 1;
+  for (;;) {
+    L = 1;
+    while (L * VEC * kje < n && L < 64) L <<= 1;
+    if (L >= 8 || kje == 1) break;
+    kje >>= 1;
+  }
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
   const int slot = lane / L, sub = lane % L;
   const int RS = kWave / L;  // rows per wavefront step
@@ -453,9 +464,10 @@ __device__ __forceinline__ void batch_pass_body(const BatchItem &it, int chunk, 
   // last row (its results are dropped), a lane past the row's whole vectors
   // reads the last whole vector (its p entries are zero and its q sums are
   // never stored).  Only the vector that straddles n (n % VEC != 0) is read
-  // element by element.
-  const int cf = (n / VEC) * VEC;  // columns in whole vectors
-  const int clast = cf - VEC;      // start of the last whole vector (< 0: none)
+  // element by element, unless the rows are zero-padded to whole vectors.
+  const bool straddle = (n % VEC) != 0 && !it.zero_pad;
+  const int cf = (it.zero_pad ? n + VEC - 1 : n) / VEC * VEC;  // columns read as whole vectors
+  const int clast = cf - VEC;  // start of the last whole vector (< 0: none)
   auto load_group = [&](int64_t base, TA (&a)[U][KJ][VEC], TC (&ui)[U]) {
 #pragma unroll
     for (int uu = 0; uu < U; ++uu) {
@@ -464,6 +476,7 @@ __device__ __forceinline__ void batch_pass_body(const BatchItem &it, int chunk, 
       const gmem<TA> *arow = A + rowc * lda;
 #pragma unroll
       for (int j = 0; j < KJ; ++j) {
+        if (j > 0 && j >= kje) break;
         const int c = (sub + L * j) * VEC;
         if (clast >= 0) {
           load_stream<TA, VEC>(arow + min(c, clast), a[uu][j]);
@@ -471,7 +484,7 @@ __device__ __forceinline__ void batch_pass_body(const BatchItem &it, int chunk, 
 #pragma unroll
           for (int e = 0; e < VEC; ++e) a[uu][j][e] = TA(0);
         }
-        if (cf != n && c == cf) {
+        if (straddle && c == cf) {
 #pragma unroll
           for (int e = 0; e < VEC; ++e) a[uu][j][e] = (c + e < n) ? __builtin_nontemporal_load(arow + c + e) : TA(0);
         }
@@ -485,9 +498,11 @@ __device__ __forceinline__ void batch_pass_body(const BatchItem &it, int chunk, 
     const TC uh = c_ap * s + c_u * ui;
     const TU us = static_cast<TU>(uh);
 #pragma unroll
-    for (int j = 0; j < KJ; ++j)
+    for (int j = 0; j < KJ; ++j) {
+      if (j > 0 && j >= kje) break;
 #pragma unroll
       for (int e = 0; e < VEC; ++e) q[j][e] += static_cast<TC>(us) * static_cast<TC>(ar[j][e]);
+    }
     if (sub == 0) {
       if (!tune) uout[row] = us;
       nrm += static_cast<double>(us) * static_cast<double>(us);
@@ -496,9 +511,11 @@ __device__ __forceinline__ void batch_pass_body(const BatchItem &it, int chunk, 
   auto dot_row = [&](TA (&ar)[KJ][VEC]) {
     TC s = TC(0);
 #pragma unroll
-    for (int j = 0; j < KJ; ++j)
+    for (int j = 0; j < KJ; ++j) {
+      if (j > 0 && j >= kje) break;
 #pragma unroll
       for (int e = 0; e < VEC; ++e) s += static_cast<TC>(ar[j][e]) * psh[(sub + L * j) * VEC + e];
+    }
     return s;
   };
   // Each row's dot product is reduced over its L lanes.  With 512 threads
@@ -974,9 +991,15 @@ struct BatchTuneKey {
   }
 };
 struct BatchTune {
-  int64_t rows_per_chunk;
-  bool pf;  // the pass variant: 512-thread workgroups with two row groups in flight
+  int64_t chunk_elems;  // elements of A per pass work item
+  bool pf;              // the pass variant: 512-thread workgroups with two row groups in flight
 };
+
+// Rows of a pass work item for a problem of n columns: about `elems`
+// elements of A, at least kMinRowsPerChunk rows.
+int64_t batch_chunk_rows(int n, int64_t elems) {
+  return std::max<int64_t>(kMinRowsPerChunk, elems / std::max(1, n));
+}
 static std::map<BatchTuneKey, BatchTune> g_tune_rows;
 
 // d = 0 (choose: eq. (4.2)'s d with cost ratio 1, within the batched form's
@@ -1056,12 +1079,12 @@ sap_status run_batch(sap_ctx *ctx, int count, const sap_problem *probs, const sa
 
   // ---- workspace layout ---------------------------------------------------------
   const BatchTuneKey key{static_cast<int>(at), (n_max + 63) / 64, count};
-  int64_t rows_per_chunk = 4096;
+  int64_t chunk_elems = int64_t(1) << 19;
   bool pass_pf = false;
   auto tit = g_tune_rows.find(key);
   const bool have_tune = tit != g_tune_rows.end();
   if (have_tune) {
-    rows_per_chunk = tit->second.rows_per_chunk;
+    chunk_elems = tit->second.chunk_elems;
     pass_pf = tit->second.pf;
   }
   std::vector<size_t> need(count);
@@ -1114,7 +1137,7 @@ sap_status run_batch(sap_ctx *ctx, int count, const sap_problem *probs, const sa
     any_refine = any_refine || it.refine;
     it.col_base = col_base;
     col_base += p.m;
-    carve_item(it, cv.take<char>(need[k]), at, rows_per_chunk);
+    carve_item(it, cv.take<char>(need[k]), at, batch_chunk_rows(p.n, chunk_elems));
   }
   int2 *dpass = cv.take<int2>(total_chunks_max + 16);
   int2 *dapply = cv.take<int2>(static_cast<size_t>(count) * tiles_max * kMaxApplySlices + 16);
@@ -1140,6 +1163,7 @@ sap_status run_batch(sap_ctx *ctx, int count, const sap_problem *probs, const sa
         repack_work.push_back(make_int2(j, static_cast<int>(c)));
       jobs.push_back(jb);
       it.A = jb.dst;  // the solve reads the repacked rows
+      it.zero_pad = 1;
       it.lda = ldp;
     }
     aligned = true;
@@ -1152,12 +1176,21 @@ sap_status run_batch(sap_ctx *ctx, int count, const sap_problem *probs, const sa
     for (int t = 0; t < tiles; ++t)
       for (int sl = 0; sl < items[k].aslices; ++sl) apply_work.push_back(make_int2(k, t | (sl << 20)));
   }
-  auto pass_table = [&](int64_t rpc_) {
-    std::vector<int2> wt;
+  // Pass work items of about `elems` elements each, the largest first (each
+  // problem's last, shorter item goes to the end of the launch).
+  auto pass_table = [&](int64_t elems) {
+    std::vector<std::pair<int64_t, int2>> v;
     for (int k = 0; k < count; ++k) {
-      const int G = static_cast<int>((items[k].m + rpc_ - 1) / rpc_);
-      for (int g = 0; g < G; ++g) wt.push_back(make_int2(k, g));
+      const int64_t rows = batch_chunk_rows(items[k].n, elems);
+      const int G = static_cast<int>((items[k].m + rows - 1) / rows);
+      for (int g = 0; g < G; ++g) {
+        const int64_t r = std::min<int64_t>(items[k].m, (g + 1) * rows) - g * rows;
+        v.push_back({r * items[k].n, make_int2(k, g)});
+      }
     }
+    std::stable_sort(v.begin(), v.end(), [](const auto &a, const auto &b) { return a.first > b.first; });
+    std::vector<int2> wt(v.size());
+    for (size_t i = 0; i < v.size(); ++i) wt[i] = v[i].second;
     return wt;
   };
 
@@ -1195,16 +1228,16 @@ sap_status run_batch(sap_ctx *ctx, int count, const sap_problem *probs, const sa
   SAP_HIP_TRY(hipMemcpyAsync(items.data(), ditems, sizeof(BatchItem) * count, hipMemcpyDeviceToHost, st));
   SAP_HIP_TRY(hipStreamSynchronize(st));
 
-  // ---- autotune the pass once per batch shape: rows per work item and the
-  // variant (1024-thread workgroups, one row group in flight per wave, or
-  // 512-thread workgroups with two), each timed on the device ----
+  // ---- autotune the pass once per batch shape: elements per work item and
+  // the variant (1024-thread workgroups, one row group in flight per wave,
+  // or 512-thread workgroups with two), each timed on the device ----
   auto pick = [&](bool pf) {
     return (at == SAP_F32) ? pick_batch_pass<float>(n_max, aligned, pf) : pick_batch_pass<double>(n_max, aligned, pf);
   };
   if (!have_tune) {
-    const int64_t cands[] = {2048, 4096, 8192, 16384};
+    const int64_t cands[] = {int64_t(1) << 18, int64_t(1) << 19, int64_t(1) << 20, int64_t(1) << 21};
     float best_ms = 1e30f;
-    int64_t best = rows_per_chunk;
+    int64_t best = chunk_elems;
     bool best_pf = false;
     hipEvent_t e0, e1;
     SAP_HIP_TRY(hipEventCreate(&e0));
@@ -1215,8 +1248,8 @@ sap_status run_batch(sap_ctx *ctx, int count, const sap_problem *probs, const sa
         std::vector<int2> wt = pass_table(c);
         std::vector<BatchItem> tmp = items;
         for (auto &it : tmp) {
-          it.rows_per_chunk = c;
-          it.G = static_cast<int>((it.m + c - 1) / c);
+          it.rows_per_chunk = batch_chunk_rows(it.n, c);
+          it.G = static_cast<int>((it.m + it.rows_per_chunk - 1) / it.rows_per_chunk);
         }
         SAP_HIP_TRY(hipMemcpyAsync(ditems, tmp.data(), sizeof(BatchItem) * count, hipMemcpyHostToDevice, st));
         SAP_HIP_TRY(hipMemcpyAsync(dpass, wt.data(), sizeof(int2) * wt.size(), hipMemcpyHostToDevice, st));
@@ -1239,17 +1272,17 @@ sap_status run_batch(sap_ctx *ctx, int count, const sap_problem *probs, const sa
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    rows_per_chunk = best;
+    chunk_elems = best;
     pass_pf = best_pf;
     g_tune_rows[key] = BatchTune{best, best_pf};
     for (auto &it : items) {
-      it.rows_per_chunk = best;
-      it.G = static_cast<int>((it.m + best - 1) / best);
+      it.rows_per_chunk = batch_chunk_rows(it.n, best);
+      it.G = static_cast<int>((it.m + it.rows_per_chunk - 1) / it.rows_per_chunk);
     }
     SAP_HIP_TRY(hipMemcpyAsync(ditems, items.data(), sizeof(BatchItem) * count, hipMemcpyHostToDevice, st));
   }
   const PassChoice pc = pick(pass_pf);
-  std::vector<int2> pass_work = pass_table(rows_per_chunk);
+  std::vector<int2> pass_work = pass_table(chunk_elems);
   SAP_HIP_TRY(hipMemcpyAsync(dpass, pass_work.data(), sizeof(int2) * pass_work.size(), hipMemcpyHostToDevice, st));
   const int npass = static_cast<int>(pass_work.size());
 
@@ -1536,6 +1569,13 @@ hipError_t serve_round(Server *S, std::vector<ServeRequest *> &fresh) {
       if (reinterpret_cast<uintptr_t>(items[k].A) % 16 != 0 || items[k].lda % vm != 0) aligned = false;
       for (int g = 0; g < items[k].G; ++g) pass_work.push_back(make_int2(k, g));
     }
+    // the largest work items first: each request's shorter last item runs at the end
+    auto item_elems = [&](int2 w) {
+      const BatchItem &it = items[w.x];
+      return (std::min<int64_t>(it.m, (w.y + int64_t(1)) * it.rows_per_chunk) - w.y * it.rows_per_chunk) * it.n;
+    };
+    std::stable_sort(pass_work.begin(), pass_work.end(),
+                     [&](int2 a, int2 b) { return item_elems(a) > item_elems(b); });
     if (static_cast<int>(pass_work.size()) > kServeMaxChunks) return hipErrorInvalidValue;
     if ((e = hipMemcpyAsync(S->d_active, items.data(), sizeof(BatchItem) * count, hipMemcpyHostToDevice, st)) != hipSuccess) return e;
     if ((e = hipMemcpyAsync(S->d_pass, pass_work.data(), sizeof(int2) * pass_work.size(), hipMemcpyHostToDevice, st)) != hipSuccess) return e;
