@@ -328,7 +328,7 @@ sap_status sap_solve_csr(sap_ctx *ctx, const sap_csr *A, const double *b, const 
  * relative correction, max_refine as there), with its outer loop kept on
  * the device so that the problem advances with the batch; info[k].refinements
  * counts its inner solves.  SAP_MODE_MIXED_BF16SA gives SAP_EINVAL.
- * Limits: n <= 1024,
+ * Limits: 1 <= count <= 65535 (the problems index a grid dimension), n <= 1024,
  * d <= 4096 (a strip of the sketch lives in LDS), m < 2^31.  Blocking.  Returns SAP_OK when every
  * problem converged, SAP_NOT_CONVERGED when some did not or were rank
  * deficient (per-problem status in info[k].status); SAP_EINVAL, SAP_ENOMEM,

@@ -376,6 +376,7 @@ sap_status sap_solve_batch(sap_ctx *ctx, int32_t count, const sap_problem *probs
                            double *const *x, sap_info *info, void *stream) {
   if (!ctx) return SAP_EINVAL;
   if (count < 1 || !probs || !params || !x) return fail(ctx, SAP_EINVAL, "sap_solve_batch: bad arguments");
+  if (count > kMaxBatchCount) return fail(ctx, SAP_EINVAL, "sap_solve_batch: count must be at most 65535");
   SAP_HIP_TRY(hipSetDevice(ctx->device));
   return run_batch(ctx, count, probs, params, x, info, static_cast<hipStream_t>(stream));
 }

@@ -320,6 +320,9 @@ sap_status run_lsqr(sap_ctx *ctx, const sap_problem *prob, const double *R, int6
 // The iteration-batch graph cache (lsqr.hip), freed with the context.
 void batch_graphs_free(sap_ctx *ctx);
 constexpr size_t kPinnedBytes = 4096;
+// Problems of one sap_solve_batch call: the batched launches index them in a
+// grid dimension limited to 65535 blocks.
+constexpr int kMaxBatchCount = 65535;
 
 // Heavy-ball momentum (App. D.3) in place of LSQR (lsqr.hip): x0 = R^-1 z,
 // step alpha, momentum beta; the LSQR workspace; mode 0 (FP64) or 1 (FP32 A).

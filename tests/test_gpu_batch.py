@@ -186,6 +186,21 @@ def test_batch_refine_mode_checks(sap):
     assert e.value.status == sap.SAP_EINVAL
 
 
+def test_batch_count_limit(sap):
+    """More than 65535 problems in one call is refused before any device work
+    (the batched launches index the problems in a grid dimension)."""
+    import ctypes
+    count = 65536
+    probs = (sap.SapProblem * count)()
+    pars = (sap.SapParams * count)()
+    xs = (ctypes.c_void_p * count)()
+    infos = (sap.SapInfo * count)()
+    ctx = sap.default_context()
+    st = sap.lib().sap_solve_batch(ctx.handle, count, probs, pars, xs, infos, None)
+    assert st == sap.SAP_EINVAL
+    assert "65535" in ctx.last_error()
+
+
 def test_batch_auto_d_and_fixed_count(sap, orc):
     """d = 0 in the batched form takes eq. (4.2)'s d (cost ratio 1) within the
     form's d <= 4096; fixed_iters < 0 runs the eq. (4.1) count.  Each problem
