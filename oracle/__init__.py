@@ -89,6 +89,12 @@ def lib():
                               ctypes.POINTER(LsqrInfo)]
         L.orc_solve_hbm.argtypes = [_i64, _i32, _vp, _i64, _vp, _i32, _i32, _u64, _u64, _f64, _i32, _f64, _f64,
                                     _vp, _vp, ctypes.POINTER(SolveInfo)]
+        L.orc_cheb_basis.argtypes = [_i64, _i32, _vp, _i64, _vp, _i64, _vp, _i32, _f64, _f64, _vp, _vp]
+        L.orc_sstep.argtypes = [_i64, _i32, _vp, _i64, _vp, _vp, _i64, _vp, _i32, _f64, _f64, _f64, _i32, _vp,
+                                _vp, ctypes.POINTER(LsqrInfo)]
+        L.orc_sstep_interval.argtypes = [_f64, ctypes.POINTER(_f64), ctypes.POINTER(_f64)]
+        L.orc_solve_sstep.argtypes = [_i64, _i32, _vp, _i64, _vp, _i32, _i32, _u64, _u64, _f64, _i32, _i32, _f64,
+                                      _f64, _vp, _vp, ctypes.POINTER(SolveInfo)]
         L.orc_lambert_w0.argtypes = [_f64]
         L.orc_lambert_w0.restype = _f64
         L.orc_embedding_dim.argtypes = [_i64, _i32, _f64, _f64]
@@ -429,6 +435,60 @@ def solve_hbm(A, b, d, zeta, seed, alpha, beta, tol=1e-12, maxiter=500, stream=0
     info = SolveInfo()
     lib().orc_solve_hbm(m, n, _p(A), n, _p(_f64c(b)), d, zeta, seed, stream, tol, maxiter, alpha, beta, _p(x),
                         _p(x0), ctypes.byref(info))
+    return x, dict(status=STATUS.get(info.status, str(info.status)), iters=info.iters,
+                   resid_est=info.resid_est, normar_est=info.normar_est, x0=x0)
+
+
+def sstep_interval(eta):
+    """Chebyshev interval [(1 - eta)^2, (1 + eta)^2] of the s-step form for a
+    distortion estimate eta (App. D.4.2 with the embedding bound)."""
+    lo, hi = _f64(0.0), _f64(0.0)
+    lib().orc_sstep_interval(float(eta), ctypes.byref(lo), ctypes.byref(hi))
+    return lo.value, hi.value
+
+
+def cheb_basis(A, R, r0, s, lo, hi):
+    """Chebyshev basis u_0 .. u_{s-1} of K_s(Z, r0), Z = (A R^-1)^T (A R^-1),
+    on [lo, hi], and W = Z U.  Returns (U, W), each n x s."""
+    A = _f64c(A)
+    m, n = A.shape
+    R = np.asfortranarray(R, dtype=np.float64)
+    U = np.zeros((s, n))
+    W = np.zeros((s, n))
+    lib().orc_cheb_basis(m, n, _p(A), n, R.ctypes.data_as(_vp), R.shape[0], _p(_f64c(r0)), int(s), float(lo),
+                         float(hi), _p(U), _p(W))
+    return U.T.copy(), W.T.copy()
+
+
+def sstep(A, b, R, x0, s, lo, hi, tol=1e-12, maxiter=200, history=False):
+    """The s-step form (App. D.4.2) on A with M = R^-1 from x0: blocks of s
+    steps, each the CG iterate over its Krylov space in closed form.  Returns
+    (x, info dict[, x after each block (blocks, n)])."""
+    A = _f64c(A)
+    m, n = A.shape
+    R = np.asfortranarray(R, dtype=np.float64)
+    x = np.zeros(n)
+    nb = (max(maxiter, 0) + s - 1) // s
+    hist = np.zeros((max(nb, 1), n)) if history else None
+    info = LsqrInfo()
+    lib().orc_sstep(m, n, _p(A), n, _p(_f64c(b)), R.ctypes.data_as(_vp), R.shape[0], _p(_f64c(x0)), int(s),
+                    float(lo), float(hi), tol, int(maxiter), _p(x), _p(hist), ctypes.byref(info))
+    d = dict(iters=info.iters, converged=bool(info.converged), resid_est=info.resid_est,
+             normar_est=info.normar_est)
+    if history:
+        return x, d, hist[:info.iters // s]
+    return x, d
+
+
+def solve_sstep(A, b, d, zeta, seed, s, lo, hi, tol=1e-12, maxiter=500, stream=0):
+    """Alg. 1 with the s-step form in place of LSQR.  Returns (x, info dict)."""
+    A = _f64c(A)
+    m, n = A.shape
+    x = np.zeros(n)
+    x0 = np.zeros(n)
+    info = SolveInfo()
+    lib().orc_solve_sstep(m, n, _p(A), n, _p(_f64c(b)), d, zeta, seed, stream, tol, maxiter, int(s), float(lo),
+                          float(hi), _p(x), _p(x0), ctypes.byref(info))
     return x, dict(status=STATUS.get(info.status, str(info.status)), iters=info.iters,
                    resid_est=info.resid_est, normar_est=info.normar_est, x0=x0)
 

@@ -33,6 +33,9 @@
  *   - Gradient descent with heavy-ball momentum (App. D.3) in place of LSQR,
  *     with the step size and momentum the appendix derives from the
  *     distortion estimate.
+ *   - The s-step form of App. D.4.2: blocks of s Krylov steps, each the CG
+ *     iterate over the block's Krylov space in closed form, from a
+ *     Chebyshev basis (no inner products while it is built).
  *
  * Parity pins for each function live in the CPU test suite.
  */
@@ -683,6 +686,204 @@ void orc_hbm(int64_t m, int32_t n, const double *A, int64_t lda, const double *b
 }
 
 /* ------------------------------------------------------------------------ */
+/* s-step form (App. D.4.2).                                                  */
+/* ------------------------------------------------------------------------ */
+/* Z u = M^T A^T A M u with M = R^-1 (triangular solves); tn (n) and tm (m)
+ * are scratch. */
+static void orc_z_apply(int64_t m, int32_t n, const orc_op *op, const double *R, int64_t ldr, const double *u,
+                        double *tn, double *tm, double *out)
+{
+    orc_backsub(R, ldr, n, u, tn);      /* M u */
+    op->av(op->ctx, tn, tm);            /* A M u */
+    op->atv(op->ctx, tm, out);          /* A^T A M u */
+    orc_forwardsub_t(R, ldr, n, out, tn);
+    memcpy(out, tn, sizeof(double) * (size_t)n);  /* M^T A^T A M u */
+    (void)m;
+}
+
+/* Chebyshev basis of the Krylov space K_s(Z, r0), Z = (A M)^T (A M), on the
+ * interval [lo, hi] that the sketch's distortion puts around Z's spectrum
+ * (centre c = (hi + lo)/2, half-width h = (hi - lo)/2):
+ *   u_0 = r0,  u_1 = (Z u_0 - c u_0) / h,
+ *   u_{k+1} = 2 (Z u_k - c u_k) / h - u_{k-1},
+ * that is u_k = T_k((Z - c I)/h) r0; no inner products are taken.
+ * U (n x s, column-major, ld n) receives u_0 .. u_{s-1}; W (n x s) receives
+ * Z u_0 .. Z u_{s-1}.  Needs hi > lo. */
+static void orc_cheb_basis_op(int64_t m, int32_t n, const orc_op *op, const double *R, int64_t ldr,
+                              const double *r0, int32_t s, double lo, double hi, double *U, double *W)
+{
+    double *tn = (double *)malloc(sizeof(double) * (size_t)n);
+    double *tm = (double *)malloc(sizeof(double) * (size_t)m);
+    const double c = 0.5 * (hi + lo), h = 0.5 * (hi - lo);
+    memcpy(U, r0, sizeof(double) * (size_t)n);
+    for (int32_t k = 0; k < s; ++k) {
+        const double *uk = U + (int64_t)k * n;
+        double *wk = W + (int64_t)k * n;
+        orc_z_apply(m, n, op, R, ldr, uk, tn, tm, wk);
+        if (k + 1 < s) {
+            double *un = U + (int64_t)(k + 1) * n;
+            for (int32_t i = 0; i < n; ++i) {
+                const double y = (wk[i] - c * uk[i]) / h;
+                un[i] = (k == 0) ? y : 2.0 * y - U[(int64_t)(k - 1) * n + i];
+            }
+        }
+    }
+    free(tn); free(tm);
+}
+
+void orc_cheb_basis(int64_t m, int32_t n, const double *A, int64_t lda, const double *R, int64_t ldr,
+                    const double *r0, int32_t s, double lo, double hi, double *U, double *W)
+{
+    orc_dense D = {m, n, A, lda};
+    orc_op op = {orc_dense_av, orc_dense_atv, &D};
+    orc_cheb_basis_op(m, n, &op, R, ldr, r0, s, lo, hi, U, W);
+}
+
+/* Solve G c = g (s x s symmetric, column-major) by Cholesky.  A pivot at or
+ * below 1e-12 times its diagonal entry (the basis has become numerically
+ * dependent: the Krylov space is exhausted or the basis ill-conditioned)
+ * stops the factorisation; the system is then solved on the leading k steps
+ * and c_k .. c_{s-1} = 0.  Returns k. */
+static int32_t orc_gram_solve(int32_t s, const double *G, const double *g, double *c)
+{
+    double *L = (double *)calloc((size_t)s * (size_t)s, sizeof(double));
+    double *y = (double *)malloc(sizeof(double) * (size_t)s);
+    int32_t k = 0;
+    for (int32_t j = 0; j < s; ++j) {
+        double dj = G[j + (int64_t)j * s];
+        for (int32_t i = 0; i < j; ++i)
+            dj -= L[j + (int64_t)i * s] * L[j + (int64_t)i * s];
+        if (!(dj > 1e-12 * G[j + (int64_t)j * s]))
+            break;
+        const double ljj = sqrt(dj);
+        L[j + (int64_t)j * s] = ljj;
+        for (int32_t r = j + 1; r < s; ++r) {
+            double v = G[r + (int64_t)j * s];
+            for (int32_t i = 0; i < j; ++i)
+                v -= L[r + (int64_t)i * s] * L[j + (int64_t)i * s];
+            L[r + (int64_t)j * s] = v / ljj;
+        }
+        k = j + 1;
+    }
+    for (int32_t j = 0; j < s; ++j)
+        c[j] = 0.0;
+    for (int32_t j = 0; j < k; ++j) { /* L y = g */
+        double v = g[j];
+        for (int32_t i = 0; i < j; ++i)
+            v -= L[j + (int64_t)i * s] * y[i];
+        y[j] = v / L[j + (int64_t)j * s];
+    }
+    for (int32_t j = k - 1; j >= 0; --j) { /* L^T c = y */
+        double v = y[j];
+        for (int32_t i = j + 1; i < k; ++i)
+            v -= L[i + (int64_t)j * s] * c[i];
+        c[j] = v / L[j + (int64_t)j * s];
+    }
+    free(L); free(y);
+    return k;
+}
+
+/* The s-step method from x0.  Each block, from the current x:
+ *   r = b - A x (the data-space residual),  r0 = M^T A^T r,
+ *   stopping test (as the momentum method's, after at least one block):
+ *     ||r|| = 0, ||r0|| <= tol ||r|| or ||r|| <= tol ||b||;
+ *   the Chebyshev basis u_0 .. u_{s-1} of K_s(Z, r0) and W = Z U;
+ *   G = U^T Z U (from U^T W, symmetrised) and g = U^T r0;
+ *   G c = g;  x <- x + M U c.
+ * With Q = M U this is x + Q (Q^T A^T A Q)^-1 Q^T A^T r, the closed form of
+ * the CG iterate over x + M K_s(Z, r0): the minimiser of ||A (x_* - .)|| over
+ * that space, i.e. s CG (LSQR) steps from x in exact arithmetic.  Blocks run
+ * while fewer than maxiter steps have been made (s per block), so at most
+ * ceil(maxiter / s) blocks.  info: iters = steps made, resid_est = ||r||,
+ * normar_est = ||r0|| at the last test.  history (nullable, one row of n
+ * per block after the first x) receives x after each block. */
+static void orc_sstep_op(int64_t m, int32_t n, const orc_op *op, const double *b, const double *R, int64_t ldr,
+                         const double *x0, int32_t s, double lo, double hi, double tol, int32_t maxiter, double *x,
+                         double *history, orc_lsqr_info *info)
+{
+    double *r = (double *)malloc(sizeof(double) * (size_t)m);
+    double *t1 = (double *)malloc(sizeof(double) * (size_t)n);
+    double *r0 = (double *)malloc(sizeof(double) * (size_t)n);
+    double *U = (double *)malloc(sizeof(double) * (size_t)n * (size_t)s);
+    double *W = (double *)malloc(sizeof(double) * (size_t)n * (size_t)s);
+    double *G = (double *)malloc(sizeof(double) * (size_t)s * (size_t)s);
+    double *g = (double *)malloc(sizeof(double) * (size_t)s);
+    double *c = (double *)malloc(sizeof(double) * (size_t)s);
+    double *y = (double *)malloc(sizeof(double) * (size_t)n);
+
+    memcpy(x, x0, sizeof(double) * (size_t)n);
+    info->iters = 0;
+    info->converged = 0;
+    const double normb = orc_nrm2(m, b);
+    int32_t blocks = 0;
+    for (;;) {
+        op->av(op->ctx, x, r);
+        for (int64_t i = 0; i < m; ++i)
+            r[i] = b[i] - r[i];
+        const double rn = orc_nrm2(m, r);
+        op->atv(op->ctx, r, t1);
+        orc_forwardsub_t(R, ldr, n, t1, r0);
+        const double fn = orc_nrm2(n, r0);
+        info->resid_est = rn;
+        info->normar_est = fn;
+        if (info->iters >= 1 && (rn == 0.0 || fn <= tol * rn || rn <= tol * normb)) {
+            info->converged = 1;
+            break;
+        }
+        if (info->iters >= maxiter)
+            break;
+        orc_cheb_basis_op(m, n, op, R, ldr, r0, s, lo, hi, U, W);
+        for (int32_t j = 0; j < s; ++j) {
+            for (int32_t k = 0; k <= j; ++k) {
+                double a = 0.0, bb = 0.0;
+                for (int32_t i = 0; i < n; ++i) {
+                    a += U[i + (int64_t)j * n] * W[i + (int64_t)k * n];
+                    bb += U[i + (int64_t)k * n] * W[i + (int64_t)j * n];
+                }
+                G[j + (int64_t)k * s] = G[k + (int64_t)j * s] = 0.5 * (a + bb);
+            }
+            double a = 0.0;
+            for (int32_t i = 0; i < n; ++i)
+                a += U[i + (int64_t)j * n] * r0[i];
+            g[j] = a;
+        }
+        orc_gram_solve(s, G, g, c);
+        for (int32_t i = 0; i < n; ++i) {
+            double a = 0.0;
+            for (int32_t j = 0; j < s; ++j)
+                a += U[i + (int64_t)j * n] * c[j];
+            y[i] = a;
+        }
+        orc_backsub(R, ldr, n, y, t1); /* M U c */
+        for (int32_t i = 0; i < n; ++i)
+            x[i] += t1[i];
+        info->iters += s;
+        if (history)
+            memcpy(history + (int64_t)blocks * n, x, sizeof(double) * (size_t)n);
+        blocks += 1;
+    }
+    free(r); free(t1); free(r0); free(U); free(W); free(G); free(g); free(c); free(y);
+}
+
+void orc_sstep(int64_t m, int32_t n, const double *A, int64_t lda, const double *b, const double *R, int64_t ldr,
+               const double *x0, int32_t s, double lo, double hi, double tol, int32_t maxiter, double *x,
+               double *history, orc_lsqr_info *info)
+{
+    orc_dense D = {m, n, A, lda};
+    orc_op op = {orc_dense_av, orc_dense_atv, &D};
+    orc_sstep_op(m, n, &op, b, R, ldr, x0, s, lo, hi, tol, maxiter, x, history, info);
+}
+
+/* The Chebyshev interval for a distortion estimate eta in (0, 1): Z's
+ * eigenvalues are the squared singular values of A M, which a subspace
+ * embedding of distortion eta puts in [(1 - eta)^2, (1 + eta)^2]. */
+void orc_sstep_interval(double eta, double *lo, double *hi)
+{
+    *lo = (1.0 - eta) * (1.0 - eta);
+    *hi = (1.0 + eta) * (1.0 + eta);
+}
+
+/* ------------------------------------------------------------------------ */
 /* Alg. 1 end to end.                                                         */
 /* ------------------------------------------------------------------------ */
 typedef struct orc_solve_info {
@@ -717,11 +918,13 @@ int orc_rank_deficient(const double *R, int64_t ldr, int32_t n, int32_t d)
  * x0 = R^-1 (Q^T S b)[0:n], LSQR.
  * Y_out (nullable, d x (n+1) column-major, ld d) receives the factored Y
  * (R in the upper triangle).  x receives the solution. */
-/* The steps of Alg. 1 after the sketch: QR of Y, rank test, x0, LSQR (or,
- * with hb non-null, heavy-ball momentum with step hb[0] and momentum hb[1]).
- * Shared by the dense and the CSR solve. */
+/* The steps of Alg. 1 after the sketch: QR of Y, rank test, x0, then the
+ * iterative method: LSQR (method 0), heavy-ball momentum with step mp[0] and
+ * momentum mp[1] (method 1), or the s-step form with s = mp[0] and the
+ * Chebyshev interval [mp[1], mp[2]] (method 2).  Shared by the dense and the
+ * CSR solve. */
 static void orc_solve_finish(int64_t m, int32_t n, const orc_op *op, const double *b, int32_t d, double *Y,
-                             double *tau, double tol, int32_t maxiter, const double *hb, double *x,
+                             double *tau, double tol, int32_t maxiter, int32_t method, const double *mp, double *x,
                              double *x0_out, orc_solve_info *info, double t2)
 {
     int32_t nc = n + 1;
@@ -737,8 +940,10 @@ static void orc_solve_finish(int64_t m, int32_t n, const orc_op *op, const doubl
         if (x0_out)
             memcpy(x0_out, x0, sizeof(double) * (size_t)n);
         orc_lsqr_info li;
-        if (hb) /* heavy-ball momentum (App. D.3): hb = {alpha, beta} */
-            orc_hbm_op(m, n, op, b, Y, d, x0, hb[0], hb[1], tol, maxiter, x, NULL, &li);
+        if (method == 1) /* heavy-ball momentum (App. D.3) */
+            orc_hbm_op(m, n, op, b, Y, d, x0, mp[0], mp[1], tol, maxiter, x, NULL, &li);
+        else if (method == 2) /* s-step form (App. D.4.2) */
+            orc_sstep_op(m, n, op, b, Y, d, x0, (int32_t)mp[0], mp[1], mp[2], tol, maxiter, x, NULL, &li);
         else
             orc_lsqr_op(m, n, op, b, Y, d, x0, tol, maxiter, x, NULL, &li);
         info->iters = li.iters;
@@ -778,7 +983,7 @@ void orc_solve(int64_t m, int32_t n, const double *A, int64_t lda, const double 
     info->t_apply = t2 - t1;
     orc_dense D = {m, n, A, lda};
     orc_op op = {orc_dense_av, orc_dense_atv, &D};
-    orc_solve_finish(m, n, &op, b, d, Y, tau, tol, maxiter, NULL, x, x0_out, info, t2);
+    orc_solve_finish(m, n, &op, b, d, Y, tau, tol, maxiter, 0, NULL, x, x0_out, info, t2);
     if (Y_out)
         memcpy(Y_out, Y, sizeof(double) * (size_t)d * (size_t)nc);
     free(idx); free(sign); free(Y); free(tau);
@@ -811,7 +1016,39 @@ void orc_solve_hbm(int64_t m, int32_t n, const double *A, int64_t lda, const dou
     info->t_apply = t2 - t1;
     orc_dense D = {m, n, A, lda};
     orc_op op = {orc_dense_av, orc_dense_atv, &D};
-    orc_solve_finish(m, n, &op, b, d, Y, tau, tol, maxiter, hb, x, x0_out, info, t2);
+    orc_solve_finish(m, n, &op, b, d, Y, tau, tol, maxiter, 1, hb, x, x0_out, info, t2);
+    free(idx); free(sign); free(Y); free(tau);
+}
+
+/* Alg. 1 with the s-step form (App. D.4.2) in place of LSQR: the same
+ * sketch, QR and x0, then orc_sstep_op with s steps a block and the
+ * Chebyshev interval [lo, hi]. */
+void orc_solve_sstep(int64_t m, int32_t n, const double *A, int64_t lda, const double *b,
+                     int32_t d, int32_t zeta, uint64_t seed, uint64_t stream, double tol, int32_t maxiter,
+                     int32_t s, double lo, double hi, double *x, double *x0_out, orc_solve_info *info)
+{
+    memset(info, 0, sizeof(*info));
+    if (zeta < 1 || zeta > ORC_MAX_ZETA || d < zeta || d < n + 1 || m < 1 || n < 1 || s < 1 || !(hi > lo)) {
+        info->status = 1;
+        return;
+    }
+    int32_t nc = n + 1;
+    int32_t *idx = (int32_t *)malloc(sizeof(int32_t) * (size_t)m * (size_t)zeta);
+    uint64_t *sign = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)m);
+    double *Y = (double *)malloc(sizeof(double) * (size_t)d * (size_t)nc);
+    double *tau = (double *)malloc(sizeof(double) * (size_t)nc);
+    double mp[3] = {(double)s, lo, hi};
+
+    double t0 = orc_now();
+    orc_sketch(seed, stream, m, d, zeta, idx, sign, NULL);
+    double t1 = orc_now();
+    orc_apply_sparse(m, d, zeta, idx, sign, A, lda, b, n, 1.0 / sqrt((double)zeta), Y, d, NULL, 0);
+    double t2 = orc_now();
+    info->t_generate = t1 - t0;
+    info->t_apply = t2 - t1;
+    orc_dense D = {m, n, A, lda};
+    orc_op op = {orc_dense_av, orc_dense_atv, &D};
+    orc_solve_finish(m, n, &op, b, d, Y, tau, tol, maxiter, 2, mp, x, x0_out, info, t2);
     free(idx); free(sign); free(Y); free(tau);
 }
 
@@ -841,7 +1078,7 @@ void orc_solve_csr(int64_t m, int32_t n, const int64_t *indptr, const int32_t *i
     info->t_apply = t2 - t1;
     orc_csr C = {m, n, indptr, indices, values};
     orc_op op = {orc_csr_av, orc_csr_atv, &C};
-    orc_solve_finish(m, n, &op, b, d, Y, tau, tol, maxiter, NULL, x, x0_out, info, t2);
+    orc_solve_finish(m, n, &op, b, d, Y, tau, tol, maxiter, 0, NULL, x, x0_out, info, t2);
     if (Y_out)
         memcpy(Y_out, Y, sizeof(double) * (size_t)d * (size_t)nc);
     free(idx); free(sign); free(Y); free(tau);
