@@ -265,6 +265,36 @@ typedef struct sap_hbm_params {
 sap_status sap_solve_hbm(sap_ctx *ctx, const sap_problem *prob, const sap_params *params,
                          const sap_hbm_params *hbm, double *x, sap_info *info, void *stream);
 
+/* The s-step form of App. D.4.2 in place of LSQR: the sketch, QR and x0 of
+ * sap_solve, then blocks of s Krylov steps of the preconditioned normal
+ * equations Z y = f, Z = (A M)^T (A M), M = R^-1.  Each block, from the
+ * current x: r = b - A x and r0 = M^T A^T r (one pass over A); the stopping
+ * test of sap_solve_hbm on (||r||, ||r0||) after at least one block; the
+ * Chebyshev basis u_k = T_k((Z - c I)/h) r0, k < s, on the interval
+ * [(1 - eta)^2, (1 + eta)^2] the embedding bound gives for Z's spectrum
+ * (c, h its centre and half-width, eta = eta_scale sqrt(n/d), eta_scale 0
+ * meaning 1), built without inner products, one pass over A per step; then
+ * x += M U c with (U^T Z U) c = U^T r0, the CG iterate over x + M K_s(Z, r0)
+ * in closed form (the Gram system is solved by Cholesky and truncated where
+ * the basis turns numerically dependent).  s + 1 passes per block; blocks
+ * run while fewer than maxiter steps are made (maxiter rounds up to whole
+ * blocks).  params as for sap_solve (d = 0 chooses d; fixed_iters runs that
+ * many steps, rounded up to whole blocks); modes FP64 and MIXED_FP32.
+ * info: iters = steps made (s per block), resid_est = ||r||, normar_est =
+ * ||r0|| at the last test.  The test measures the true residual, whose
+ * normal-equation part has a rounding floor near u ||b||: tol far below
+ * that relative to ||r|| is not reached on inconsistent problems.
+ * Blocking.  Errors as for sap_solve, and SAP_EINVAL for s outside [1, 16]
+ * or a derived eta >= 1. */
+typedef struct sap_sstep_params {
+    int32_t s;          /* Krylov steps per block, 1..16 */
+    int32_t pad_;
+    double eta_scale;   /* eta = eta_scale sqrt(n/d); 0 means 1 */
+} sap_sstep_params;
+
+sap_status sap_solve_sstep(sap_ctx *ctx, const sap_problem *prob, const sap_params *params,
+                           const sap_sstep_params *ss, double *x, sap_info *info, void *stream);
+
 /* Preconditioned LSQR alone (Alg. 2) on A M with M = R^-1 for a given R
  * (device, upper triangle of column-major n x n, leading dimension ldr) and
  * initial guess x0 (device, n doubles; may alias x).  A may be F64 or F32

@@ -24,7 +24,7 @@ EXPORTS = ["sap_create", "sap_destroy", "sap_last_error", "sap_status_string", "
            "sps_apply", "sps_apply_noalloc", "sap_qr", "sap_trsv", "sap_solve", "sap_lsqr", "sap_profile_enable",
            "sap_profile_read", "sap_solve_batch", "sap_serve_start", "sap_submit", "sap_poll",
            "sap_cancel", "sap_serve_stats", "sap_embedding_dim", "sap_iteration_estimate", "sap_choose_d",
-           "sps_apply_csr", "sap_solve_csr", "sap_solve_hbm"]
+           "sps_apply_csr", "sap_solve_csr", "sap_solve_hbm", "sap_solve_sstep"]
 PROF_PASS, PROF_APPLY = 0, 1
 
 _vp = ctypes.c_void_p
@@ -50,6 +50,10 @@ class SapCsr(ctypes.Structure):
 
 class SapHbmParams(ctypes.Structure):
     _fields_ = [("alpha", _f64), ("beta", _f64), ("eta_scale", _f64), ("gradient_descent", _i32), ("pad_", _i32)]
+
+
+class SapSstepParams(ctypes.Structure):
+    _fields_ = [("s", _i32), ("pad_", _i32), ("eta_scale", _f64)]
 
 
 class SapParams(ctypes.Structure):
@@ -141,6 +145,9 @@ def lib():
         L.sap_solve_hbm.argtypes = [_vp, ctypes.POINTER(SapProblem), ctypes.POINTER(SapParams),
                                     ctypes.POINTER(SapHbmParams), _vp, ctypes.POINTER(SapInfo), _vp]
         L.sap_solve_hbm.restype = ctypes.c_int
+        L.sap_solve_sstep.argtypes = [_vp, ctypes.POINTER(SapProblem), ctypes.POINTER(SapParams),
+                                      ctypes.POINTER(SapSstepParams), _vp, ctypes.POINTER(SapInfo), _vp]
+        L.sap_solve_sstep.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -394,6 +401,25 @@ def sap_solve_hbm(A, b, d, zeta=8, seed=1, tol=1e-12, maxiter=500, mode=None, ct
     info = SapInfo()
     st = lib().sap_solve_hbm(ctx.handle, ctypes.byref(prob), ctypes.byref(par), ctypes.byref(hb),
                              _dev(x, torch.float64, "x"), ctypes.byref(info), _vp(_stream()))
+    ctx.check(st, (SAP_OK, SAP_NOT_CONVERGED))
+    return SolveResult(x, st, info.as_dict())
+
+
+def sap_solve_sstep(A, b, d, zeta=8, seed=1, tol=1e-12, maxiter=500, mode=None, ctx=None, x=None, s=8,
+                    eta_scale=1.0, fixed_iters=0):
+    """Alg. 1 with the s-step form (App. D.4.2) in place of LSQR: blocks of s
+    steps on the Chebyshev basis for eta = eta_scale sqrt(n/d)."""
+    torch = _torch()
+    ctx = ctx or default_context()
+    if mode is None:
+        mode = SAP_MODE_FP64 if A.dtype == torch.float64 else SAP_MODE_MIXED_FP32
+    prob = _problem(A, b)
+    par = SapParams(d, zeta, seed, tol, maxiter, mode, 0, fixed_iters)
+    ss = SapSstepParams(int(s), 0, float(eta_scale))
+    x = x if x is not None else torch.empty(A.shape[1], dtype=torch.float64, device=A.device)
+    info = SapInfo()
+    st = lib().sap_solve_sstep(ctx.handle, ctypes.byref(prob), ctypes.byref(par), ctypes.byref(ss),
+                               _dev(x, torch.float64, "x"), ctypes.byref(info), _vp(_stream()))
     ctx.check(st, (SAP_OK, SAP_NOT_CONVERGED))
     return SolveResult(x, st, info.as_dict())
 

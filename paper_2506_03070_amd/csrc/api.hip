@@ -381,10 +381,11 @@ sap_status sap_solve_batch(sap_ctx *ctx, int32_t count, const sap_problem *probs
   return run_batch(ctx, count, probs, params, x, info, static_cast<hipStream_t>(stream));
 }
 
-// Alg. 1 with LSQR (hb == nullptr) or heavy-ball momentum (App. D.3) as the
-// iterative method.
+// Alg. 1 with LSQR (hb and ss null), heavy-ball momentum (App. D.3, hb) or
+// the s-step form (App. D.4.2, ss) as the iterative method.
 static sap_status solve_dense(sap_ctx *ctx, const sap_problem *prob, const sap_params *par_in,
-                              const sap_hbm_params *hb, double *x, sap_info *info, void *stream) {
+                              const sap_hbm_params *hb, const sap_sstep_params *ss, double *x, sap_info *info,
+                              void *stream) {
   if (!ctx) return SAP_EINVAL;
   sap_status s = check_problem(ctx, prob);
   if (s != SAP_OK) return s;
@@ -447,6 +448,19 @@ static sap_status solve_dense(sap_ctx *ctx, const sap_problem *prob, const sap_p
       hb_beta = hb->gradient_descent ? 0.0 : e2;
     }
   }
+  // block size and Chebyshev interval of the s-step form: the embedding
+  // bound puts Z's spectrum in [(1 - eta)^2, (1 + eta)^2], eta = c sqrt(n/d)
+  double ss_lo = 0.0, ss_hi = 0.0;
+  if (ss) {
+    if (mode != SAP_MODE_FP64 && mode != SAP_MODE_MIXED_FP32)
+      return fail(ctx, SAP_EINVAL, "sap_solve_sstep: mode must be FP64 or MIXED_FP32");
+    if (ss->s < 1 || ss->s > 16) return fail(ctx, SAP_EINVAL, "sap_solve_sstep: need 1 <= s <= 16");
+    const double c = ss->eta_scale > 0.0 ? ss->eta_scale : 1.0;
+    const double eta = c * std::sqrt(static_cast<double>(n) / static_cast<double>(d));
+    if (!(eta < 1.0)) return fail(ctx, SAP_EINVAL, "sap_solve_sstep: eta_scale sqrt(n/d) must be below 1");
+    ss_lo = (1.0 - eta) * (1.0 - eta);
+    ss_hi = (1.0 + eta) * (1.0 + eta);
+  }
   hipStream_t st = static_cast<hipStream_t>(stream);
   SAP_HIP_TRY(hipSetDevice(ctx->device));
 
@@ -467,7 +481,9 @@ static sap_status solve_dense(sap_ctx *ctx, const sap_problem *prob, const sap_p
   const bool bf16sa = mode == SAP_MODE_MIXED_BF16SA;
   const int64_t ld_bf = (static_cast<int64_t>(n) + 7) / 8 * 8;
   const size_t bytes_bf = bf16sa ? static_cast<size_t>(m) * ld_bf * sizeof(__hip_bfloat16) : 0;
-  const size_t total = 9 * 256 + bytes_flags + bytes_idx + bytes_sign + bytes_Y + bytes_tau + bytes_bf + scratch;
+  const size_t bytes_ss = ss ? sstep_workspace_bytes(n, ss->s) : 0;
+  const size_t total =
+      10 * 256 + bytes_flags + bytes_idx + bytes_sign + bytes_Y + bytes_tau + bytes_bf + bytes_ss + scratch;
   s = ensure_workspace(ctx, total, st);
   if (s != SAP_OK) return s;
   Carve cv(ctx->ws);
@@ -478,6 +494,7 @@ static sap_status solve_dense(sap_ctx *ctx, const sap_problem *prob, const sap_p
   double *tau = cv.take<double>(nc);
   __hip_bfloat16 *Abf = bf16sa ? cv.take<__hip_bfloat16>(static_cast<size_t>(m) * ld_bf) : nullptr;
   void *work = cv.take<char>(scratch);
+  void *swork = ss ? cv.take<char>(bytes_ss) : nullptr;
 
   if (info) std::memset(info, 0, sizeof(*info));
   hipEvent_t ev[5];
@@ -527,7 +544,10 @@ static sap_status solve_dense(sap_ctx *ctx, const sap_problem *prob, const sap_p
   // MIXED_BF16SA iterates as MIXED_FP32_REFINE (FP32 passes, FP64 refinement)
   const int lsqr_mode = (mode == SAP_MODE_FP64) ? 0 : (mode == SAP_MODE_MIXED_FP32 ? 1 : 2);
   sap_info li{};
-  if (hb)
+  if (ss)
+    s = run_sstep(ctx, prob, Y, d, Y + static_cast<int64_t>(n) * d, fixed ? 0.0 : par->tol,
+                  fixed ? fixed : par->maxiter, lsqr_mode, ss->s, ss_lo, ss_hi, x, &li, work, swork, st);
+  else if (hb)
     s = run_hbm(ctx, prob, Y, d, Y + static_cast<int64_t>(n) * d, fixed ? 0.0 : par->tol,
                 fixed ? fixed : par->maxiter, lsqr_mode, hb_alpha, hb_beta, x, &li, work, st);
   else
@@ -558,14 +578,21 @@ static sap_status solve_dense(sap_ctx *ctx, const sap_problem *prob, const sap_p
 
 sap_status sap_solve(sap_ctx *ctx, const sap_problem *prob, const sap_params *params, double *x, sap_info *info,
                      void *stream) {
-  return solve_dense(ctx, prob, params, nullptr, x, info, stream);
+  return solve_dense(ctx, prob, params, nullptr, nullptr, x, info, stream);
 }
 
 sap_status sap_solve_hbm(sap_ctx *ctx, const sap_problem *prob, const sap_params *params,
                          const sap_hbm_params *hbm, double *x, sap_info *info, void *stream) {
   if (!ctx) return SAP_EINVAL;
   if (!hbm) return fail(ctx, SAP_EINVAL, "sap_solve_hbm: NULL momentum parameters");
-  return solve_dense(ctx, prob, params, hbm, x, info, stream);
+  return solve_dense(ctx, prob, params, hbm, nullptr, x, info, stream);
+}
+
+sap_status sap_solve_sstep(sap_ctx *ctx, const sap_problem *prob, const sap_params *params,
+                           const sap_sstep_params *ss, double *x, sap_info *info, void *stream) {
+  if (!ctx) return SAP_EINVAL;
+  if (!ss) return fail(ctx, SAP_EINVAL, "sap_solve_sstep: NULL s-step parameters");
+  return solve_dense(ctx, prob, params, nullptr, ss, x, info, stream);
 }
 
 static sap_status check_csr(sap_ctx *ctx, const sap_csr *A) {

@@ -326,6 +326,12 @@ constexpr int kMaxBatchCount = 65535;
 
 // Heavy-ball momentum (App. D.3) in place of LSQR (lsqr.hip): x0 = R^-1 z,
 // step alpha, momentum beta; the LSQR workspace; mode 0 (FP64) or 1 (FP32 A).
+// The s-step form of App. D.4.2 (s_steps Krylov steps per block, the
+// Chebyshev basis on [lo, hi]); swork: sstep_workspace_bytes(n, s_steps).
+size_t sstep_workspace_bytes(int n, int s);
+sap_status run_sstep(sap_ctx *ctx, const sap_problem *prob, const double *R, int64_t ldr, const double *z,
+                     double tol, int maxiter, int mode, int s_steps, double lo, double hi, double *x, sap_info *info,
+                     void *work, void *swork, hipStream_t s);
 sap_status run_hbm(sap_ctx *ctx, const sap_problem *prob, const double *R, int64_t ldr, const double *z,
                    double tol, int maxiter, int mode, double alpha, double beta, double *x, sap_info *info,
                    void *work, hipStream_t st);

@@ -38,6 +38,7 @@ namespace {
 constexpr int kPassThreads = 512;
 constexpr int kPassWaves = kPassThreads / kWave;
 constexpr int kMaxN = 8192;
+constexpr int kMaxSstep = 16;  // steps per block of the s-step form
 
 // [fused-pass-begin] (the benchmark hashes this region, with the wavefront
 // helpers, to tell whether HBM counters taken on the pass still describe it)
@@ -1052,6 +1053,138 @@ __global__ void zero_f64_kernel(double *__restrict__ p, int n) {
   if (i < n) p[i] = 0.0;
 }
 
+// ---- s-step form (App. D.4.2) --------------------------------------------
+// out = M in (or xacc += M in when xacc is non-null): one wave per row r,
+// row r of M read as column r of M^T (entries r .. n-1).
+__global__ __launch_bounds__(1024) void sstep_mv_kernel(const double *__restrict__ Mt, int n,
+                                                        const double *__restrict__ in, double *__restrict__ out,
+                                                        double *__restrict__ xacc) {
+  __shared__ double v[kMaxN];
+  for (int c = threadIdx.x; c < n; c += 1024) v[c] = in[c];
+  __syncthreads();
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  const int r = blockIdx.x * 16 + wave;
+  if (r >= n) return;
+  const double *__restrict__ col = Mt + static_cast<int64_t>(r) * n;
+  double acc = 0.0;
+  for (int k = r + lane; k < n; k += kWave) acc += col[k] * v[k];
+  acc = wave_sum_u(acc);
+  if (lane == 0) {
+    if (xacc) xacc[r] += acc;
+    else out[r] = acc;
+  }
+}
+
+// The next Chebyshev basis vector: u_{k+1} = (Z u_k - c u_k)/h for k = 0,
+// 2 (Z u_k - c u_k)/h - u_{k-1} after.
+__global__ void sstep_cheb_kernel(int n, int k, double c, double h, const double *__restrict__ wk,
+                                  const double *__restrict__ uk, const double *__restrict__ ukm1,
+                                  double *__restrict__ unext) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const double y = (wk[i] - c * uk[i]) / h;
+  unext[i] = k == 0 ? y : 2.0 * y - ukm1[i];
+}
+
+// Gram entries, one workgroup each (fixed summation order): block (j, k < s)
+// gives Graw[j + k s] = u_j . (Z u_k), block (j, s) gives g[j] = u_j . u_0.
+__global__ __launch_bounds__(256) void sstep_gram_kernel(const double *__restrict__ U,
+                                                         const double *__restrict__ W, int n, int s,
+                                                         double *__restrict__ Graw, double *__restrict__ g) {
+  __shared__ double scr[4];
+  const int j = blockIdx.x, k = blockIdx.y;
+  const double *__restrict__ a = U + static_cast<int64_t>(j) * n;
+  const double *__restrict__ b = (k < s) ? W + static_cast<int64_t>(k) * n : U;
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) acc += a[i] * b[i];
+  acc = wave_sum_u(acc);
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  if (lane == 0) scr[wave] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double t = scr[0] + scr[1] + scr[2] + scr[3];
+    if (k < s) Graw[j + static_cast<int64_t>(k) * s] = t;
+    else g[j] = t;
+  }
+}
+
+// (U^T Z U) c = U^T r0 by Cholesky of the symmetrised Gram matrix, one
+// thread (s <= kMaxSstep).  A pivot at or below 1e-12 of its diagonal entry
+// stops the factorisation: the basis has become numerically dependent, and
+// the system is solved on the steps before it (the rest of c is zero).
+__global__ void sstep_solve_kernel(int s, const double *__restrict__ Graw, const double *__restrict__ g,
+                                   double *__restrict__ c) {
+  if (threadIdx.x != 0) return;
+  double G[kMaxSstep * kMaxSstep], L[kMaxSstep * kMaxSstep], y[kMaxSstep];
+  for (int j = 0; j < s; ++j)
+    for (int k = 0; k < s; ++k) {
+      G[j + k * s] = 0.5 * (Graw[j + k * s] + Graw[k + j * s]);
+      L[j + k * s] = 0.0;
+    }
+  int kk = 0;
+  for (int j = 0; j < s; ++j) {
+    double dj = G[j + j * s];
+    for (int i = 0; i < j; ++i) dj -= L[j + i * s] * L[j + i * s];
+    if (!(dj > 1e-12 * G[j + j * s])) break;
+    const double ljj = sqrt(dj);
+    L[j + j * s] = ljj;
+    for (int r = j + 1; r < s; ++r) {
+      double v = G[r + j * s];
+      for (int i = 0; i < j; ++i) v -= L[r + i * s] * L[j + i * s];
+      L[r + j * s] = v / ljj;
+    }
+    kk = j + 1;
+  }
+  for (int j = 0; j < s; ++j) c[j] = 0.0;
+  for (int j = 0; j < kk; ++j) {
+    double v = g[j];
+    for (int i = 0; i < j; ++i) v -= L[j + i * s] * y[i];
+    y[j] = v / L[j + j * s];
+  }
+  for (int j = kk - 1; j >= 0; --j) {
+    double v = y[j];
+    for (int i = j + 1; i < kk; ++i) v -= L[i + j * s] * c[i];
+    c[j] = v / L[j + j * s];
+  }
+}
+
+// y = U c (n x s times s).
+__global__ void sstep_combine_kernel(const double *__restrict__ U, int n, int s, const double *__restrict__ c,
+                                     double *__restrict__ y) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  double a = 0.0;
+  for (int j = 0; j < s; ++j) a += U[i + static_cast<int64_t>(j) * n] * c[j];
+  y[i] = a;
+}
+
+// out[0] = ||r|| from the pass partials, out[1] = ||M^T A^T r|| from the
+// M^T q partials, out[2] = ||b|| (one workgroup, fixed order).
+__global__ __launch_bounds__(1024) void sstep_norms_kernel(const double *__restrict__ nrmpart, int G,
+                                                           const double *__restrict__ spart, int nsp,
+                                                           const LsqrState *__restrict__ st,
+                                                           double *__restrict__ out) {
+  __shared__ double scr[16];
+  const double rn = beta_from_partials(nrmpart, G, scr);
+  double a = 0.0;
+  for (int k = threadIdx.x; k < nsp; k += 1024) a += spart[k];
+  const double fn = sqrt(wg_sum(a, scr));
+  if (threadIdx.x == 0) {
+    out[0] = rn;
+    out[1] = fn;
+    out[2] = st->normb;
+  }
+}
+
+// The product state: every pass run with it forms u = A p (u_in unused).
+__global__ void sstep_zstate_kernel(const LsqrState *__restrict__ src, LsqrState *__restrict__ dst) {
+  if (threadIdx.x != 0) return;
+  *dst = *src;
+  dst->c_ap = 1.0;
+  dst->c_u = 0.0;
+  dst->done = 0;
+}
+
 }  // namespace
 
 
@@ -1269,6 +1402,98 @@ sap_status run_hbm(sap_ctx *ctx, const sap_problem *prob, const double *R, int64
     info->normar_est = hs.normar_est;
   }
   return hs.converged ? SAP_OK : SAP_NOT_CONVERGED;
+}
+
+size_t sstep_workspace_bytes(int n, int s) {
+  return 16 * 256 + sizeof(LsqrState) + sizeof(double) * (2 * static_cast<size_t>(n) * s + n + s * s + 2 * s + 4);
+}
+
+// The s-step form of App. D.4.2 from x0 = R^-1 z: blocks of s Krylov steps.
+// Per block, from the current x: the residual pass (u = b - A x, q = A^T u)
+// and r0 = M^T q with ||r||, ||r0|| read back for the stopping test (after
+// at least one block: ||r|| = 0, ||r0|| <= tol ||r|| or ||r|| <= tol ||b||);
+// then the Chebyshev basis u_0 = r0, u_{k+1} from Z u_k = M^T A^T A M u_k,
+// one fused pass each (p = M u_k, u = A p, q = A^T u), no inner products;
+// G = U^T Z U and g = U^T r0 (s^2 + s dots); (G c = g) by Cholesky; x += M U c.
+// s + 1 passes over A per block of s steps.  Blocks run while fewer than
+// maxiter steps have been made.
+sap_status run_sstep(sap_ctx *ctx, const sap_problem *prob, const double *R, int64_t ldr, const double *z,
+                     double tol, int maxiter, int mode, int s_steps, double lo, double hi, double *x, sap_info *info,
+                     void *work, void *swork, hipStream_t s) {
+  const int64_t m = prob->m;
+  const int n = prob->n;
+  const int S = s_steps;
+  if (n > kMaxN) return fail(ctx, SAP_EINVAL, "s-step: n > 8192 is not supported");
+  if (mode != 0 && mode != 1) return fail(ctx, SAP_EINVAL, "s-step: mode must be FP64 or MIXED_FP32");
+  if (S < 1 || S > kMaxSstep || !(hi > lo)) return fail(ctx, SAP_EINVAL, "s-step: bad block size or interval");
+  const PassPlan plan = plan_pass(ctx, mode, m, n, prob->lda, prob->A);
+  if (plan.grid > max_grid(ctx)) return fail(ctx, SAP_EINVAL, "s-step: internal grid larger than planned");
+  LsqrBufs B = carve_lsqr(ctx, work, m, n);
+  sap_status sst = setup_precond(ctx, R, ldr, nullptr, z, x, B, n, s);
+  if (sst != SAP_OK) return sst;
+  Carve cv(swork);
+  LsqrState *stz = cv.take<LsqrState>(1);
+  double *U = cv.take<double>(static_cast<size_t>(n) * S);
+  double *W = cv.take<double>(static_cast<size_t>(n) * S);
+  double *y = cv.take<double>(n);
+  double *Graw = cv.take<double>(static_cast<size_t>(S) * S);
+  double *g = cv.take<double>(S);
+  double *cc = cv.take<double>(S);
+  double *dn = cv.take<double>(4);
+  LsqrState *st = B.st;  // residual passes: c_ap = -1, c_u = 1
+  lsqr_init_state_kernel<<<1, 256, 0, s>>>(st, tol, maxiter, B.flags, 2 * B.nblk, 0, 0, B.dyn);
+  const int ngrid = static_cast<int>(std::min<int64_t>(256, (m + 1023) / 1024));
+  norm_kernel<<<ngrid, 1024, 0, s>>>(prob->b, m, B.normpart, B.ticket, st);
+  sstep_zstate_kernel<<<1, 64, 0, s>>>(st, stz);
+  SAP_HIP_TRY(hipGetLastError());
+  const int G = plan.grid;
+  const int qsl = (G + kQSlice - 1) / kQSlice;
+  const unsigned nv = static_cast<unsigned>((n + 255) / 256);
+  const double cen = 0.5 * (hi + lo), half = 0.5 * (hi - lo);
+  // r = b - A x, q = A^T r, out = M^T q (and its norm partials in B.vpart)
+  auto product = [&](const double *pv, LsqrState *pst, double *out) {
+    launch_pass(ctx, plan, prob->A, prob->lda, m, n, pv, prob->b, B.ubuf[0], pst, B.qpart, B.nrmpart, B.dyn, s);
+    q_slices_kernel<<<dim3((n + 63) / 64, qsl), 256, 0, s>>>(B.qpart, G, n, B.qs);
+    hbm_mtq_kernel<<<B.ngemv, 1024, 0, s>>>(B.M, n, B.qs, qsl, out, B.vpart, pst);
+  };
+  auto *hn = static_cast<double *>(ctx->pinned);  // rn, ||r0||, ||b||, error flag
+  int steps = 0;
+  bool conv = false;
+  for (;;) {
+    product(x, st, U);  // u_0 = r0 = M^T A^T (b - A x)
+    sstep_norms_kernel<<<1, 1024, 0, s>>>(B.nrmpart, G, B.vpart, B.ngemv, st, dn);
+    SAP_HIP_TRY(hipGetLastError());
+    SAP_HIP_TRY(hipMemcpyAsync(hn, dn, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
+    SAP_HIP_TRY(hipMemcpyAsync(hn + 3, B.err, sizeof(int), hipMemcpyDeviceToHost, s));
+    SAP_HIP_TRY(hipStreamSynchronize(s));
+    if (*reinterpret_cast<const int *>(hn + 3)) return fail(ctx, SAP_EDEVICE, "s-step: a block wait expired");
+    const double rn = hn[0], fn = hn[1], nb = hn[2];
+    if (info) {
+      info->resid_est = rn;
+      info->normar_est = fn;
+    }
+    if (steps >= 1 && (rn == 0.0 || fn <= tol * rn || rn <= tol * nb)) {
+      conv = true;
+      break;
+    }
+    if (steps >= maxiter) break;
+    for (int k = 0; k < S; ++k) {
+      double *uk = U + static_cast<int64_t>(k) * n;
+      sstep_mv_kernel<<<B.ngemv, 1024, 0, s>>>(B.Mt, n, uk, B.p, nullptr);  // p = M u_k
+      product(B.p, stz, W + static_cast<int64_t>(k) * n);                   // Z u_k
+      if (k + 1 < S)
+        sstep_cheb_kernel<<<nv, 256, 0, s>>>(n, k, cen, half, W + static_cast<int64_t>(k) * n, uk,
+                                             k > 0 ? uk - n : uk, uk + n);
+    }
+    sstep_gram_kernel<<<dim3(S, S + 1), 256, 0, s>>>(U, W, n, S, Graw, g);
+    sstep_solve_kernel<<<1, 64, 0, s>>>(S, Graw, g, cc);
+    sstep_combine_kernel<<<nv, 256, 0, s>>>(U, n, S, cc, y);
+    sstep_mv_kernel<<<B.ngemv, 1024, 0, s>>>(B.Mt, n, y, nullptr, x);  // x += M U c
+    SAP_HIP_TRY(hipGetLastError());
+    steps += S;
+  }
+  if (info) info->iters = steps;
+  return conv ? SAP_OK : SAP_NOT_CONVERGED;
 }
 
 void batch_graphs_free(sap_ctx *ctx) {

@@ -1,0 +1,114 @@
+"""GPU parity of the s-step form (sap_solve_sstep, App. D.4.2) against the
+oracle's orc_solve_sstep: the same sketch, QR and x0 as the LSQR solve, then
+blocks of s steps on the Chebyshev basis for eta = sqrt(n/d).  The GPU
+applies M = R^-1 explicitly where the oracle uses triangular solves, and
+sums in a different order, so the bars are the FP64 ones of the other
+solvers: ||A(x - x_or)|| <= 1e-11 ||b|| and, at cond <= 1e4,
+||x - x_or|| <= 1e-8 ||x_or||."""
+import numpy as np
+import pytest
+
+import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sap():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2506_03070_amd as sap
+    sap.lib()
+    return sap
+
+
+def _bars(A64, b, x, x_or, forward=True):
+    nb = np.linalg.norm(b)
+    assert np.linalg.norm(A64 @ (x - x_or)) <= 1e-11 * nb
+    if forward:
+        assert np.linalg.norm(x - x_or) <= 1e-8 * np.linalg.norm(x_or)
+
+
+@pytest.mark.parametrize("m,n,d,s,blocks", [(20000, 100, 400, 4, 3), (20000, 100, 400, 8, 2),
+                                            (65536, 300, 1200, 6, 2), (9000, 65, 260, 1, 5)])
+def test_sstep_fixed_count_parity(sap, orc, m, n, d, s, blocks):
+    """fixed_iters = blocks * s on both sides: every block's basis, Gram
+    system and update must agree for the iterates to."""
+    import torch
+    print(f"sstep fixed m={m} n={n} d={d} s={s} blocks={blocks}", flush=True)
+    p = inputs.make_problem(m, n, kind="colscale", cond=1e4, noise=1e-6, seed=900 + s)
+    A, b = torch.from_numpy(p.A).cuda(), torch.from_numpy(p.b).cuda()
+    T = blocks * s
+    r = sap.sap_solve_sstep(A, b, d, 8, 17, tol=0.0, maxiter=T, s=s, fixed_iters=T)
+    torch.cuda.synchronize()
+    assert r.status == sap.SAP_OK and r.info["iters"] == T, r.info
+    lo, hi = orc.sstep_interval(np.sqrt(n / d))
+    x_or, io = orc.solve_sstep(p.A, p.b, d, 8, 17, s, lo, hi, tol=0.0, maxiter=T)
+    assert io["iters"] == T
+    _bars(p.A, p.b, r.x.cpu().numpy(), x_or)
+
+
+@pytest.mark.parametrize("s", [4, 8])
+def test_sstep_tolerance_solve(sap, orc, s):
+    """tol 1e-10 (above the true residual's rounding floor on this
+    inconsistent problem): both sides stop after the same number of blocks
+    (one block either way at the boundary) and agree to the FP64 bars."""
+    import torch
+    m, n, d = 30000, 120, 480
+    print(f"sstep tol s={s}", flush=True)
+    p = inputs.make_problem(m, n, kind="colscale", cond=1e4, noise=1e-6, seed=950 + s)
+    A, b = torch.from_numpy(p.A).cuda(), torch.from_numpy(p.b).cuda()
+    r = sap.sap_solve_sstep(A, b, d, 8, 23, tol=1e-10, maxiter=400, s=s)
+    torch.cuda.synchronize()
+    lo, hi = orc.sstep_interval(np.sqrt(n / d))
+    x_or, io = orc.solve_sstep(p.A, p.b, d, 8, 23, s, lo, hi, tol=1e-10, maxiter=400)
+    assert r.status == sap.SAP_OK and io["status"] == "ok", (r.info, io)
+    assert r.info["iters"] % s == 0 and abs(r.info["iters"] - io["iters"]) <= s
+    _bars(p.A, p.b, r.x.cpu().numpy(), x_or)
+    x_ref = np.linalg.lstsq(p.A, p.b, rcond=None)[0]
+    assert np.linalg.norm(p.A @ (r.x.cpu().numpy() - x_ref)) <= 1e-10 * np.linalg.norm(p.b)
+
+
+def test_sstep_block_wider_than_n(sap, orc):
+    """n = 5 < s = 8: the Gram system is truncated where the basis exhausts
+    the space; one block then gives the least-squares solution."""
+    import torch
+    m, n, d, s = 6000, 5, 40, 8
+    p = inputs.make_problem(m, n, kind="colscale", cond=10.0, noise=1e-3, seed=977)
+    A, b = torch.from_numpy(p.A).cuda(), torch.from_numpy(p.b).cuda()
+    r = sap.sap_solve_sstep(A, b, d, 8, 5, tol=0.0, maxiter=s, s=s, fixed_iters=s)
+    torch.cuda.synchronize()
+    x = r.x.cpu().numpy()
+    assert np.all(np.isfinite(x))
+    x_ref = np.linalg.lstsq(p.A, p.b, rcond=None)[0]
+    assert np.linalg.norm(p.A @ (x - x_ref)) <= 1e-11 * np.linalg.norm(p.b)
+
+
+def test_sstep_fp32_storage(sap, orc):
+    """MIXED_FP32: A stored in FP32, FP64 arithmetic; the oracle runs on the
+    FP32-rounded A in FP64."""
+    import torch
+    m, n, d, s = 20000, 90, 360, 6
+    p = inputs.make_problem(m, n, kind="colscale", cond=1e3, noise=1e-6, seed=981, dtype=np.float32)
+    A, b = torch.from_numpy(np.ascontiguousarray(p.A)).cuda(), torch.from_numpy(p.b).cuda()
+    T = 2 * s
+    r = sap.sap_solve_sstep(A, b, d, 8, 9, tol=0.0, maxiter=T, s=s, fixed_iters=T)
+    torch.cuda.synchronize()
+    A64 = p.A.astype(np.float64)
+    lo, hi = orc.sstep_interval(np.sqrt(n / d))
+    x_or, _ = orc.solve_sstep(A64, p.b, d, 8, 9, s, lo, hi, tol=0.0, maxiter=T)
+    _bars(A64, p.b, r.x.cpu().numpy(), x_or)
+
+
+def test_sstep_argument_errors(sap):
+    import torch
+    p = inputs.make_problem(4000, 10, kind="colscale", cond=10.0, seed=3)
+    A, b = torch.from_numpy(p.A).cuda(), torch.from_numpy(p.b).cuda()
+    for kw in (dict(s=0), dict(s=17), dict(s=4, eta_scale=2.0)):
+        with pytest.raises(sap.SapError) as e:
+            sap.sap_solve_sstep(A, b, 40, 8, 1, **kw)   # eta = 2 sqrt(10/40) = 1
+        assert e.value.status == sap.SAP_EINVAL, kw
+    with pytest.raises(sap.SapError) as e:
+        sap.sap_solve_sstep(A, b, 40, 8, 1, s=4, mode=sap.SAP_MODE_MIXED_FP32_REFINE)
+    assert e.value.status == sap.SAP_EINVAL
