@@ -673,8 +673,10 @@ def form_hbm(args, sap, torch, inputs):
     eta = sqrt(n/d) and with the safer sqrt(1.1) sqrt(n/d), and gradient
     descent, on a leverage-skewed dense problem and on the hard case of
     Sec. 4.1 (the first n columns of the identity, where sqrt(n/d)
-    underestimates the distortion), to tol 1e-10 (maxiter 400).  Reports time,
-    steps and ||A(x - x_ref)|| / ||b|| with x_ref LSQR's solution."""
+    underestimates the distortion), to tol 1e-10 (maxiter 400); beside them
+    the s-step form of App. D.4.2 with blocks of 4 and 8 steps (s + 1 passes
+    over A per block).  Reports time, steps, passes over A and
+    ||A(x - x_ref)|| / ||b|| with x_ref LSQR's solution."""
     m, n, d, zeta, tol = args.hbm_m, args.hbm_n, 4 * args.hbm_n, 8, 1e-10
     rows = []
     for kind in ("svd", "identity"):
@@ -705,6 +707,12 @@ def form_hbm(args, sap, torch, inputs):
             ms, r = timed(lambda: sap.sap_solve_hbm(A, b, d, zeta, 13, tol=tol, maxiter=400, x=x, **kw))
             err = float((A @ (x - xref)).norm()) / nb
             row[tag] = {"ms": ms, "iters": r.info["iters"], "status": r.info["status_name"], "err_vs_lsqr": err}
+        for s in (4, 8):
+            ms, r = timed(lambda: sap.sap_solve_sstep(A, b, d, zeta, 13, tol=tol, maxiter=400, x=x, s=s))
+            err = float((A @ (x - xref)).norm()) / nb
+            steps = r.info["iters"]
+            row[f"sstep{s}"] = {"ms": ms, "iters": steps, "passes": steps + steps // s + 1,
+                                "status": r.info["status_name"], "err_vs_lsqr": err}
         log(f"bench[hbm]: {row}")
         rows.append(row)
         del A, b, x, xref
