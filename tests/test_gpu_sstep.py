@@ -31,7 +31,8 @@ def _bars(A64, b, x, x_or, forward=True):
 
 
 @pytest.mark.parametrize("m,n,d,s,blocks", [(20000, 100, 400, 4, 3), (20000, 100, 400, 8, 2),
-                                            (65536, 300, 1200, 6, 2), (9000, 65, 260, 1, 5)])
+                                            (65536, 300, 1200, 6, 2), (9000, 65, 260, 1, 5),
+                                            (12000, 1100, 2200, 4, 2)])
 def test_sstep_fixed_count_parity(sap, orc, m, n, d, s, blocks):
     """fixed_iters = blocks * s on both sides: every block's basis, Gram
     system and update must agree for the iterates to."""
