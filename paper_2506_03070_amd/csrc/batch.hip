@@ -83,9 +83,11 @@ struct BatchItem {
 
 // Row slices of a problem's sketch apply: about kApplySliceRows rows each, at
 // most kMaxApplySlices, and their partial sketches no larger than half of
-// the problem's FP32 A.
-constexpr int64_t kApplySliceRows = 65536;
-constexpr int kMaxApplySlices = 16;
+// the problem's FP32 A.  Short slices let the one or two requests a served
+// round admits spread over many CUs (a request of 1e5 rows and 129 columns
+// in strips of 32 makes 5 x 13 work items).
+constexpr int64_t kApplySliceRows = 8192;
+constexpr int kMaxApplySlices = 32;
 inline int apply_slices(int64_t m, int n, int d) {
   int sl = static_cast<int>(std::min<int64_t>(kMaxApplySlices, (m + kApplySliceRows - 1) / kApplySliceRows));
   while (sl > 1 && static_cast<double>(sl) * (n + 1) * d * 8.0 > 2.0 * static_cast<double>(m) * n) --sl;

@@ -210,8 +210,8 @@ def test_serve_refine_form(sap, orc, ctx):
 
 
 def test_serve_row_slices_fixed_count(sap, orc, ctx):
-    """Tall requests whose sketch apply is split over row slices (2 and 4 of
-    65536 rows, the last ragged) served beside a short one, each run for a
+    """Tall requests whose sketch apply is split over row slices (17 and 31
+    of 8192 rows or more, the last ragged) served beside a short one, each run for a
     fixed 8 steps: the iterate still depends on the preconditioner, so the
     FP64 bars against the oracle at the same count hold only if every
     slice's rows enter the sketch exactly once."""
