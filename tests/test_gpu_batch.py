@@ -229,9 +229,10 @@ def test_batch_row_slices_fixed_count(sap, orc, dtype):
     """Problems tall enough that the sketch apply splits their rows over
     several work items (8192 rows a slice, at most 32: 9, 18 and 25 slices
     here, the last one ragged) beside one that does not (5000 rows).  A
-    fixed count of 8 steps is run on both sides: the iterate after 8 steps still depends on the preconditioner
-    (a sketch that lost or doubled rows moves it by ~1e-3 relative), so the
-    FP64 bars hold only if every slice's rows land in the sketch once."""
+    fixed count of 8 steps is run on both sides: the iterate after 8 steps
+    still depends on the preconditioner (a sketch that lost or doubled rows
+    moves it by ~1e-3 relative), so the FP64 bars hold only if every slice's
+    rows land in the sketch once."""
     import torch
     shapes = [(70001, 24), (140000, 100), (200003, 40), (5000, 30)]
     print(f"batch row slices dtype={np.dtype(dtype).name} shapes={shapes}", flush=True)
