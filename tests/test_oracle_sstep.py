@@ -185,3 +185,21 @@ def test_consistent_problem_stops_after_one_block():
     x, info = orc.solve_sstep(A, b, d, 8, 3, s, lo, hi, tol=1e-12, maxiter=100)
     assert info["status"] == "ok" and info["iters"] == s
     assert np.all(np.isfinite(x))
+
+
+def test_one_long_block_stalls_restarted_blocks_do_not():
+    """One block over a long Krylov space (the closed form with t = 32) stops
+    near 1e-11 relative: the Chebyshev basis on the embedding interval turns
+    numerically dependent after ~16 steps and the Gram system is truncated.
+    Blocks of 8 restarted from each block's residual reach the LSQR accuracy."""
+    m, n, d = 3000, 40, 160
+    p = inputs.make_problem(m, n, kind="colscale", cond=1e6, noise=1e-6, seed=74)
+    xs = np.linalg.lstsq(p.A, p.b, rcond=None)[0]
+    nb = np.linalg.norm(p.b)
+    lo, hi = orc.sstep_interval(np.sqrt(n / d))
+    x1, _ = orc.solve_sstep(p.A, p.b, d, 8, 5, 32, lo, hi, tol=0.0, maxiter=32)
+    x8, _ = orc.solve_sstep(p.A, p.b, d, 8, 5, 8, lo, hi, tol=0.0, maxiter=48)
+    e1 = np.linalg.norm(p.A @ (x1 - xs)) / nb
+    e8 = np.linalg.norm(p.A @ (x8 - xs)) / nb
+    assert 1e-13 < e1 < 1e-9
+    assert e8 < 1e-13
