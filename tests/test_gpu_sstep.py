@@ -113,3 +113,27 @@ def test_sstep_argument_errors(sap):
     with pytest.raises(sap.SapError) as e:
         sap.sap_solve_sstep(A, b, 40, 8, 1, s=4, mode=sap.SAP_MODE_MIXED_FP32_REFINE)
     assert e.value.status == sap.SAP_EINVAL
+
+
+def test_sstep_rank_deficient_and_auto_d(sap, orc):
+    """A rank-deficient A is reported as sap_solve reports it; d = 0 takes the
+    timed selector's d (info d_used), and the blocks then match the oracle run
+    at that d with the interval its eta gives."""
+    import torch
+    p = inputs.make_problem(3000, 10, kind="svd", cond=1e2, seed=16)
+    A = p.A.copy()
+    A[:, 7] = A[:, 2]
+    with pytest.raises(sap.SapError) as e:
+        sap.sap_solve_sstep(torch.from_numpy(A).cuda(), torch.from_numpy(p.b).cuda(), 40, 8, 1, s=4)
+    assert e.value.status == sap.SAP_RANK_DEFICIENT
+    m, n, s, T = 30000, 60, 8, 16
+    print(f"sstep auto d m={m} n={n}", flush=True)
+    p = inputs.make_problem(m, n, kind="colscale", cond=1e4, noise=1e-6, seed=990)
+    A, b = torch.from_numpy(p.A).cuda(), torch.from_numpy(p.b).cuda()
+    r = sap.sap_solve_sstep(A, b, 0, 8, 3, tol=1e-10, maxiter=T, s=s, fixed_iters=T)  # tol prices d
+    torch.cuda.synchronize()
+    d = r.info["d_used"]
+    assert r.status == sap.SAP_OK and n + 1 < d <= 16384, r.info
+    lo, hi = orc.sstep_interval(np.sqrt(n / d))
+    x_or, _ = orc.solve_sstep(p.A, p.b, d, 8, 3, s, lo, hi, tol=0.0, maxiter=T)
+    _bars(p.A, p.b, r.x.cpu().numpy(), x_or)
