@@ -66,10 +66,11 @@ def parse():
     ap.add_argument("--gaussian-input", action="store_true",
                     help="column-scaled Gaussian A of the same shape instead of the SVD-built one (cheap to "
                          "generate; for counter runs, where the kernels move the same bytes)")
-    ap.add_argument("--kernel", choices=["apply", "qr"], default=None,
+    ap.add_argument("--kernel", choices=["apply", "qr", "batch"], default=None,
                     help="time one kernel alone instead of the solve (for profiler runs): 'apply' times "
                          "sps_apply (Y = S [A b]) on an --m x --n matrix of --a-dtype into a --y-dtype Y; "
-                         "'qr' times sap_qr on a --d x (--n + 1) FP64 matrix")
+                         "'qr' times sap_qr on a --d x (--n + 1) FP64 matrix; 'batch' times the batched "
+                         "refinement form on the --batch-count problems of the batched form")
     ap.add_argument("--a-dtype", choices=["f64", "f32", "bf16"], default="f64")
     ap.add_argument("--y-dtype", choices=["f64", "f32"], default="f64")
     ap.add_argument("--copy-ref-mib", type=int, default=2048,
@@ -783,6 +784,38 @@ def kernel_qr(args, sap, torch, inputs):
           flush=True)
 
 
+def kernel_batch(args, sap, torch, inputs):
+    """The batched form's refinement-form solve alone (the problems of
+    form_batched, FP32 A, target 1e-8): a warm-up, then --steps timed
+    batches.  One JSON line."""
+    shapes = inputs.batch_shapes(count=args.batch_count)
+    As, bs = [], []
+    for s in shapes:
+        A, b, _ = inputs.make_problem_torch(s["m"], s["n"], kind="colscale", cond=s["cond"], noise=1e-8,
+                                            seed=s["seed"], device="cuda", dtype=torch.float32)
+        As.append(A)
+        bs.append(b)
+    ds = [s["d"] for s in shapes]
+    seeds = [s["seed"] + 1 for s in shapes]
+    mode = sap.SAP_MODE_MIXED_FP32_REFINE
+
+    def run():
+        return sap.sap_solve_batch(As, bs, ds, 8, seeds, tol=1e-8, maxiter=1000, mode=mode, max_refine=12)
+    for _ in range(max(1, args.warmup)):
+        run()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(args.steps):
+        t0 = time.perf_counter()
+        _, _, infos = run()
+        torch.cuda.synchronize()
+        ts.append((time.perf_counter() - t0) * 1e3)
+    import numpy as np
+    print(json.dumps({"kernel": "batch", "problems": len(As), "a_bytes": sum(A.numel() * 4 for A in As),
+                      "steps": args.steps, "median_ms": float(np.median(ts)),
+                      "converged": sum(1 for i in infos if i["status"] == sap.SAP_OK)}), flush=True)
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -803,6 +836,9 @@ def main():
         return
     if args.kernel == "qr":
         kernel_qr(args, sap, torch, inputs)
+        return
+    if args.kernel == "batch":
+        kernel_batch(args, sap, torch, inputs)
         return
     copy_ref = copy_reference(torch, args.copy_ref_mib) if args.copy_ref_mib > 0 else None
     if copy_ref:
