@@ -420,6 +420,23 @@ __global__ __launch_bounds__(256) void batch_repack_kernel(const RepackJob *__re
 // The body of the pass for compute type TC (FP64, or FP32 in the inner
 // solves of the refinement form) and u storage type TU (FP32 in the
 // refinement form, whose residual pass computes in FP64 and rounds u).
+// v plus the value of another lane of its row of 16, chosen by a DPP
+// control: 0xB1 (quad_perm 1,0,3,2: lane ^ 1), 0x4E (quad_perm 2,3,0,1:
+// lane ^ 2), 0x141 (row_half_mirror: lane 7 - i within 8, the other quad),
+// 0x140 (row_mirror: lane 15 - i within 16, the other half).  A VALU move,
+// no LDS round trip.
+template <int CTRL>
+__device__ __forceinline__ float dpp_add(float v) {
+  return v + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_add(double v) {
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  const int mlo = __builtin_amdgcn_update_dpp(0, lo, CTRL, 0xF, 0xF, false);
+  const int mhi = __builtin_amdgcn_update_dpp(0, hi, CTRL, 0xF, 0xF, false);
+  return v + __hiloint2double(mhi, mlo);
+}
+
 template <typename TA, typename TC, typename TU, int VEC, int KJ, int U, bool PF, int TH>
 __device__ __forceinline__ void batch_pass_body(const BatchItem &it, int chunk, int tune, TC *psh, TC *qacc,
                                                 double *nsh) {
@@ -529,7 +546,25 @@ __device__ __forceinline__ void batch_pass_body(const BatchItem &it, int chunk, 
       TC s[U];
 #pragma unroll
       for (int uu = 0; uu < U; ++uu) s[uu] = dot_row(a[uu]);
-      for (int off = L >> 1; off >= 1; off >>= 1) {
+      // within a row of 16 lanes by DPP moves (the L lanes of a row are
+      // aligned), beyond it by cross-lane shuffles
+      if (L >= 2) {
+#pragma unroll
+        for (int uu = 0; uu < U; ++uu) s[uu] = dpp_add<0xB1>(s[uu]);
+      }
+      if (L >= 4) {
+#pragma unroll
+        for (int uu = 0; uu < U; ++uu) s[uu] = dpp_add<0x4E>(s[uu]);
+      }
+      if (L >= 8) {
+#pragma unroll
+        for (int uu = 0; uu < U; ++uu) s[uu] = dpp_add<0x141>(s[uu]);
+      }
+      if (L >= 16) {
+#pragma unroll
+        for (int uu = 0; uu < U; ++uu) s[uu] = dpp_add<0x140>(s[uu]);
+      }
+      for (int off = 16; off < L; off <<= 1) {
         TC t[U];
 #pragma unroll
         for (int uu = 0; uu < U; ++uu) t[uu] = __shfl_xor(s[uu], off, kWave);
