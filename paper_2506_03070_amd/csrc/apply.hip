@@ -55,9 +55,14 @@ __device__ __forceinline__ TY load_as(const TA *p) {
 // general path loads the indices four at a time and skips indices outside
 // the range.
 // C16 (with FAST): the row indices come from a 16-bit copy (idx16, 8 per row,
-// one 16-byte load), for sketches that many strips re-read.
-template <typename TA, typename TY, int W, bool FAST, bool C16>
-__global__ __launch_bounds__(kApplyThreads) void apply_strip_kernel(
+// one 16-byte load), for sketches that many strips re-read: C16 = 1 keeps the
+// sign word, C16 = 2 (d <= 32767) reads each sign from bit 15 of its index,
+// so a row costs the strips 16 bytes of sketch instead of 24.
+// The strip fills the LDS, so a CU holds one workgroup (4 waves a SIMD);
+// telling the compiler so lets it keep every load of a batch in flight
+// instead of trading registers for an occupancy it never gets.
+template <typename TA, typename TY, int W, bool FAST, int C16>
+__global__ __launch_bounds__(kApplyThreads) __attribute__((amdgpu_waves_per_eu(1, 4))) void apply_strip_kernel(
     const int32_t *__restrict__ idx, const uint16_t *__restrict__ idx16, const uint64_t *__restrict__ sign,
     int zeta, const TA *__restrict__ A,
     int64_t lda, const double *__restrict__ b, int64_t m, int n, int ncols, int d, int dr, int nstrips,
@@ -96,6 +101,7 @@ __global__ __launch_bounds__(kApplyThreads) void apply_strip_kernel(
       TY val[kUnroll];
       uint32_t sg[kUnroll];
       int4 ix[kUnroll][2];
+      uint4 raw[kUnroll];  // 16-bit copy: decoded after every load of the batch is issued
 #pragma unroll
       for (int u = 0; u < kUnroll; ++u) {
         const int64_t i0 = base + u * RPW;
@@ -105,14 +111,11 @@ __global__ __launch_bounds__(kApplyThreads) void apply_strip_kernel(
         if (col_a) a = load_as<TA, TY>(A + i * lda + col);
         else if (col_b) a = static_cast<TY>(b[i]);
         val[u] = ok ? a : TY(0);
-        sg[u] = static_cast<uint32_t>(sign[i]);
-        if constexpr (C16) {
-          const int4 v = *reinterpret_cast<const int4 *>(idx16 + i * 8);
-          ix[u][0] = make_int4(v.x & 0xFFFF, static_cast<unsigned>(v.x) >> 16, v.y & 0xFFFF,
-                               static_cast<unsigned>(v.y) >> 16);
-          ix[u][1] = make_int4(v.z & 0xFFFF, static_cast<unsigned>(v.z) >> 16, v.w & 0xFFFF,
-                               static_cast<unsigned>(v.w) >> 16);
+        if constexpr (C16 != 0) {
+          raw[u] = *reinterpret_cast<const uint4 *>(idx16 + i * 8);
+          if constexpr (C16 == 1) sg[u] = static_cast<uint32_t>(sign[i]);
         } else {
+          sg[u] = static_cast<uint32_t>(sign[i]);
           const int4 *ip = reinterpret_cast<const int4 *>(idx + i * 8);
           ix[u][0] = ip[0];
           ix[u][1] = ip[1];
@@ -120,12 +123,31 @@ __global__ __launch_bounds__(kApplyThreads) void apply_strip_kernel(
       }
 #pragma unroll
       for (int u = 0; u < kUnroll; ++u) {
-        const int rr[8] = {ix[u][0].x, ix[u][0].y, ix[u][0].z, ix[u][0].w,
-                           ix[u][1].x, ix[u][1].y, ix[u][1].z, ix[u][1].w};
+        int rr[8];
+        bool pos[8];
+        if constexpr (C16 != 0) {
+          const uint32_t wd[4] = {raw[u].x, raw[u].y, raw[u].z, raw[u].w};
+#pragma unroll
+          for (int k = 0; k < 8; ++k) {
+            const uint32_t half = (k & 1) ? (wd[k >> 1] >> 16) : (wd[k >> 1] & 0xFFFFu);
+            if constexpr (C16 == 2) {
+              rr[k] = static_cast<int>(half & 0x7FFFu);
+              pos[k] = (half & 0x8000u) != 0;
+            } else {
+              rr[k] = static_cast<int>(half);
+              pos[k] = ((sg[u] >> k) & 1u) != 0;
+            }
+          }
+        } else {
+          rr[0] = ix[u][0].x; rr[1] = ix[u][0].y; rr[2] = ix[u][0].z; rr[3] = ix[u][0].w;
+          rr[4] = ix[u][1].x; rr[5] = ix[u][1].y; rr[6] = ix[u][1].z; rr[7] = ix[u][1].w;
+#pragma unroll
+          for (int k = 0; k < 8; ++k) pos[k] = ((sg[u] >> k) & 1u) != 0;
+        }
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
           const int r = static_cast<unsigned>(rr[k]) < static_cast<unsigned>(d) ? rr[k] : d;
-          const TY v = ((sg[u] >> k) & 1u) ? val[u] : -val[u];
+          const TY v = pos[k] ? val[u] : -val[u];
           atomicAdd(acc + r * W + c, v);
         }
       }
@@ -181,13 +203,24 @@ __global__ __launch_bounds__(256) void apply_reduce_kernel(const TY *__restrict_
 }
 
 // 16-bit copy of the row indices (zeta = 8, d <= 65535); an index outside
-// [0, d) becomes 65535 (>= d), which the apply adds into its spare row.
-__global__ __launch_bounds__(256) void idx16_kernel(const int32_t *__restrict__ idx, int64_t count, int d,
+// [0, d) becomes the largest value of its field (>= d), which the apply adds
+// into its spare row.  With d <= kPackSignMaxD the index takes bits 0-14 and
+// the sign of the nonzero (bit k of the row's sign word) bit 15.
+constexpr int kPackSignMaxD = 32767;
+
+__global__ __launch_bounds__(256) void idx16_kernel(const int32_t *__restrict__ idx,
+                                                    const uint64_t *__restrict__ sign, int64_t count, int d,
                                                     uint16_t *__restrict__ out) {
   const int64_t stride = static_cast<int64_t>(gridDim.x) * 256;
+  const bool pack = d <= kPackSignMaxD;
   for (int64_t e = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; e < count; e += stride) {
     const int32_t v = idx[e];
-    out[e] = static_cast<uint16_t>(v >= 0 && v < d ? v : 65535);
+    if (pack) {
+      const uint32_t s = static_cast<uint32_t>(sign[e >> 3] >> (e & 7)) & 1u;
+      out[e] = static_cast<uint16_t>((v >= 0 && v < d ? v : 0x7FFF) | (s << 15));
+    } else {
+      out[e] = static_cast<uint16_t>(v >= 0 && v < d ? v : 65535);
+    }
   }
 }
 
@@ -243,16 +276,20 @@ void launch_strip(const ApplyPlan &p, dim3 grid, size_t lds, hipStream_t st, con
   // The 16-bit copy is read with 16-byte loads whatever S->idx's alignment
   // (the copy is 256-byte aligned); the 32-bit indices only when S->idx is.
   const bool fast = S->zeta == 8 && p.nranges == 1 && (reinterpret_cast<uintptr_t>(S->idx) % 16 == 0);
-  if (S->zeta == 8 && p.nranges == 1 && idx16 != nullptr)
-    apply_strip_kernel<TA, TY, W, true, true><<<grid, kApplyThreads, lds, st>>>(
+  if (S->zeta == 8 && p.nranges == 1 && idx16 != nullptr && S->d <= kPackSignMaxD)
+    apply_strip_kernel<TA, TY, W, true, 2><<<grid, kApplyThreads, lds, st>>>(
+        S->idx, idx16, S->sign, S->zeta, A, lda, b, S->m, n, ncols, S->d, p.dr, p.nstrips, p.nranges, p.nslices,
+        p.rows_per_slice, out, ldo, slice_stride, h, scale_now);
+  else if (S->zeta == 8 && p.nranges == 1 && idx16 != nullptr)
+    apply_strip_kernel<TA, TY, W, true, 1><<<grid, kApplyThreads, lds, st>>>(
         S->idx, idx16, S->sign, S->zeta, A, lda, b, S->m, n, ncols, S->d, p.dr, p.nstrips, p.nranges, p.nslices,
         p.rows_per_slice, out, ldo, slice_stride, h, scale_now);
   else if (fast)
-    apply_strip_kernel<TA, TY, W, true, false><<<grid, kApplyThreads, lds, st>>>(
+    apply_strip_kernel<TA, TY, W, true, 0><<<grid, kApplyThreads, lds, st>>>(
         S->idx, nullptr, S->sign, S->zeta, A, lda, b, S->m, n, ncols, S->d, p.dr, p.nstrips, p.nranges, p.nslices,
         p.rows_per_slice, out, ldo, slice_stride, h, scale_now);
   else
-    apply_strip_kernel<TA, TY, W, false, false><<<grid, kApplyThreads, lds, st>>>(
+    apply_strip_kernel<TA, TY, W, false, 0><<<grid, kApplyThreads, lds, st>>>(
         S->idx, nullptr, S->sign, S->zeta, A, lda, b, S->m, n, ncols, S->d, p.dr, p.nstrips, p.nranges, p.nslices,
         p.rows_per_slice, out, ldo, slice_stride, h, scale_now);
 }
@@ -278,7 +315,7 @@ sap_status apply_typed(sap_ctx *ctx, const sps_sketch *S, const TA *A, int64_t l
     uint16_t *c = cv.take<uint16_t>(static_cast<size_t>(S->m) * 8);
     const int64_t count = S->m * 8;
     const unsigned g = static_cast<unsigned>(std::min<int64_t>((count + 255) / 256, int64_t(ctx->num_cus) * 16));
-    idx16_kernel<<<g, 256, 0, st>>>(S->idx, count, S->d, c);
+    idx16_kernel<<<g, 256, 0, st>>>(S->idx, S->sign, count, S->d, c);
     SAP_HIP_TRY(hipGetLastError());
     idx16 = c;
   }

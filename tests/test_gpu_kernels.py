@@ -314,3 +314,41 @@ def test_apply_compact_index_path(sap, orc):
         np.add.at(exact, idx_ref[:, k], s[:, k:k + 1] * Ab)
     got = Y.cpu().numpy().T[:, cols + [n]]
     assert np.array_equal(got, exact.astype(np.float64) * orc.sketch_scale(zeta))
+
+
+@pytest.mark.parametrize("m,n,d,ydt", [(800000, 2047, 8192, "f64"), (200000, 2047, 35000, "f32")])
+def test_apply_compact_out_of_range(sap, orc, m, n, d, ydt):
+    """Both forms of the 16-bit index copy with planted indices outside [0, d):
+    d = 8192 packs each nonzero's sign into bit 15 of its index, d = 35000
+    (one FP32 column a strip) keeps the sign words.  The planted nonzeros must
+    be dropped and every other sum exact (integer A and b), so sampled columns
+    of Y equal the exact integer sums times 1/sqrt(zeta) bit for bit."""
+    import torch
+    zeta = 8
+    _note(f"apply-compact-oob m={m} n={n} d={d} Y={ydt}")
+    g = torch.Generator(device="cuda")
+    g.manual_seed(813)
+    A = torch.randint(-8, 9, (m, n), generator=g, device="cuda", dtype=torch.int32).to(torch.float32)
+    b = torch.randint(-8, 9, (m,), generator=g, device="cuda", dtype=torch.int32).to(torch.float64)
+    idx_ref, sign_ref = orc.sketch(2025, 0, m, d, zeta)
+    bad = idx_ref.copy()
+    bad[::7, 1] = d + 5
+    bad[::11, 6] = -3
+    bad[::13, 7] = 70000
+    Y = sap.sps_apply(torch.from_numpy(bad).cuda(), torch.from_numpy(sign_ref.view(np.int64)).cuda(), d, zeta, A,
+                      b, y_dtype=torch.float64 if ydt == "f64" else torch.float32)
+    torch.cuda.synchronize()
+    cols = [0, 1, 2, 1023, 1024, 2046]
+    Ab = np.column_stack([A[:, cols].cpu().numpy().astype(np.int64), b.cpu().numpy().astype(np.int64)])
+    keep = (bad >= 0) & (bad < d)
+    s = orc.sign_values(sign_ref, zeta).astype(np.int64) * keep
+    exact = np.zeros((d, len(cols) + 1), dtype=np.int64)
+    for k in range(zeta):
+        np.add.at(exact, np.where(keep[:, k], bad[:, k], 0), s[:, k:k + 1] * Ab)
+    got = Y.cpu().numpy().T[:, cols + [n]]
+    if ydt == "f64":
+        ref = exact.astype(np.float64) * orc.sketch_scale(zeta)
+    else:
+        assert np.abs(exact).max() < 2**24
+        ref = exact.astype(np.float32) * np.float32(orc.sketch_scale(zeta))
+    assert np.array_equal(got, ref)
