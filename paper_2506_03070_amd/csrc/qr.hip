@@ -13,11 +13,22 @@
 //     reduction for the norm below the diagonal and one batched reduction that
 //     gives both v_j^T C (the update of the panel columns to its right) and
 //     V_{<j}^T v_j (the next column of T).
+// Chained form (sketches up to 4096 rows): the same block reflectors in one
+// launch.  Workgroup j (numbered in the order the workgroups start, from an
+// atomic ticket) owns columns 4j .. 4j+3 in registers for the whole
+// factorisation; it applies panel k as soon as panel k's owner has published
+// it (its reflectors and T written through to the coherence point shared by
+// the XCDs, then a flag), then factors its own panel and publishes it.  The
+// trailing matrix never goes back to memory between panels, and no launch
+// boundary separates them: a panel's critical path is one block apply and one
+// panel factorisation.  A workgroup only waits for workgroups that started
+// before it, so the chain completes whatever number of them is resident.
 // Sign convention: LAPACK dlarfg, beta = -sign(alpha) ||(alpha, x)||.
 #include <algorithm>
 
 #include "common.h"
 #include "qr_dev.h"
+#include "trsv.h"
 
 namespace sap {
 namespace {
@@ -56,6 +67,132 @@ __global__ __launch_bounds__(TH) void qr_step_kernel(double *__restrict__ Y, int
     factor_panel<S, NB>(C, sh, ncb, d - k1, k1 - k0, k1, tau, Tnext);
   }
   store_block<S, NB, TH>(Y, ldy, k0, dr, c0, ncb, C);
+}
+
+// Chained QR: C <- (I - V T^T V^T) C for a block held at fixed rows (thread t
+// holds rows t + TH s of the whole column block), with panel k's reflectors
+// (columns k0 .. k0+nbp-1 of Y, rows from k0, unit diagonal implicit) and T
+// read through the coherence point, since another workgroup wrote them
+// during this launch.  Rows above the panel have V = 0 and are unchanged.
+template <int S, int NB, int TH>
+__device__ __forceinline__ void chain_apply_panel(const double *__restrict__ Y, int64_t ldy, int d, int k0, int nbp,
+                                                  const double *__restrict__ T, double (&C)[S][NB], int ncb,
+                                                  PanelShared<NB, TH> &sh) {
+  const int t = threadIdx.x;
+  const int lane = t & (kWave - 1), wave = t / kWave;
+  const double tload = t < NB * NB ? load_coherent(T + t) : 0.0;
+  double V[S][NB];
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    const int r = t + TH * s;
+    const int lr = r - k0;
+    const int rr = min(max(r, k0), d - 1);  // in-range address; masked below
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      const double y = load_coherent(Y + static_cast<int64_t>(k0 + min(i, nbp - 1)) * ldy + rr);
+      V[s][i] = (i < nbp && lr >= 0 && r < d) ? vval(lr, i, y) : 0.0;
+    }
+  }
+  if (t < NB * NB) sh.Tl[t] = tload;
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < NB; ++i)
+#pragma unroll
+    for (int c = 0; c < NB; ++c) {
+      double acc = 0.0;
+#pragma unroll
+      for (int s = 0; s < S; ++s) acc += V[s][i] * C[s][c];
+      acc = wave_sum_u(acc);
+      if (lane == 0) sh.red[wave][i * NB + c] = acc;
+    }
+  __syncthreads();
+  if (t < NB * NB) {
+    const int i = t / NB, c = t % NB;
+    double s_ = 0.0;
+    for (int l = 0; l <= i && l < nbp; ++l) {
+      double wlc = 0.0;
+      for (int w = 0; w < (TH / kWave); ++w) wlc += sh.red[w][l * NB + c];
+      s_ += sh.Tl[l + i * NB] * wlc;
+    }
+    sh.W2[i][c] = (i < nbp && c < ncb) ? s_ : 0.0;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int s = 0; s < S; ++s)
+#pragma unroll
+    for (int c = 0; c < NB; ++c) {
+      double acc = 0.0;
+#pragma unroll
+      for (int i = 0; i < NB; ++i) acc += V[s][i] * sh.W2[i][c];
+      C[s][c] -= acc;
+    }
+}
+
+// A wait of the chain gives up after this many polls (a producer that never
+// ran, which the start-ordered tickets rule out); the block is then NaN.
+constexpr int kQrSpinLimit = 1 << 20;
+
+// One launch of ceil(cols / NB) workgroups; w: the ticket word and one flag
+// per panel, zero on entry; Tall: NB x NB per panel.
+template <int S, int NB, int TH>
+__global__ __launch_bounds__(TH) void qr_chain_kernel(double *__restrict__ Y, int64_t ldy, int d, int cols,
+                                                      double *__restrict__ Tall, double *__restrict__ tau,
+                                                      int *__restrict__ w) {
+  __shared__ PanelShared<NB, TH> sh;
+  __shared__ double Tsh[NB * NB];
+  __shared__ int jsh, failed;
+  const int t = threadIdx.x;
+  if (t == 0) {
+    jsh = atomicAdd(w, 1);
+    failed = 0;
+  }
+  __syncthreads();
+  const int j = jsh;
+  int *flags = w + 1;
+  const int c0 = j * NB;
+  const int ncb = min(NB, cols - c0);
+  double C[S][NB];
+  load_block<S, NB, TH>(Y, ldy, 0, d, c0, ncb, C);
+  for (int k = 0; k < j; ++k) {
+    if (t == 0) {
+      int spins = 0;
+      while (__hip_atomic_load(flags + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < 1) {
+        __builtin_amdgcn_s_sleep(1);
+        if (++spins > kQrSpinLimit) {
+          failed = 1;
+          break;
+        }
+      }
+    }
+    __syncthreads();
+    if (failed) break;  // uniform
+    chain_apply_panel<S, NB, TH>(Y, ldy, d, k * NB, min(NB, cols - k * NB), Tall + k * NB * NB, C, ncb, sh);
+  }
+  if (failed) {
+#pragma unroll
+    for (int s = 0; s < S; ++s)
+#pragma unroll
+      for (int c = 0; c < NB; ++c) C[s][c] = __builtin_nan("");
+  } else {
+    factor_panel<S, NB>(C, sh, ncb, d - c0, c0, c0, tau, Tsh);
+    __syncthreads();
+    if (t < NB * NB) store_coherent(Tall + j * NB * NB + t, Tsh[t]);
+  }
+  double *__restrict__ base = Y + static_cast<int64_t>(c0) * ldy;
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    const int r = t + TH * s;
+    if (r < d) {
+#pragma unroll
+      for (int c = 0; c < NB; ++c)
+        if (c < ncb) store_coherent(base + static_cast<int64_t>(c) * ldy + r, C[s][c]);
+    }
+  }
+  publish_flag(flags + j, 1);
+}
+
+__global__ void qr_chain_zero_kernel(int *w, int count) {
+  for (int i = threadIdx.x; i < count; i += blockDim.x) w[i] = 0;
 }
 
 // Rank test on R's diagonal: deficient when min |R_kk| <= d * 2^-53 * max |R_kk|.
@@ -343,6 +480,29 @@ sap_status qr_run(sap_ctx *ctx, double *Y, int64_t ldy, int rows, int cols, doub
 }
 
 constexpr size_t kUnblockedBytes = 4 * 256 + 2 * sizeof(double) * 16 * 16;
+constexpr int kChainNB = 4;
+constexpr int kChainMaxRows = 4096;
+
+size_t chain_bytes(int cols) {
+  const size_t nblk = static_cast<size_t>((cols + kChainNB - 1) / kChainNB);
+  return 2 * 256 + sizeof(double) * kChainNB * kChainNB * nblk + sizeof(int) * (nblk + 1);
+}
+
+template <int S>
+sap_status qr_chain(sap_ctx *ctx, double *Y, int64_t ldy, int rows, int cols, double *tau, void *work,
+                    hipStream_t st) {
+  constexpr int TH = 512;
+  static_assert(S * TH >= kChainMaxRows || S < 8, "rows per thread");
+  const int nblk = (cols + kChainNB - 1) / kChainNB;
+  Carve cv(work);
+  double *Tall = cv.take<double>(static_cast<size_t>(kChainNB) * kChainNB * nblk);
+  int *w = cv.take<int>(static_cast<size_t>(nblk) + 1);
+  qr_chain_zero_kernel<<<1, 256, 0, st>>>(w, nblk + 1);
+  SAP_HIP_TRY(hipGetLastError());
+  qr_chain_kernel<S, kChainNB, TH><<<nblk, TH, 0, st>>>(Y, ldy, rows, cols, Tall, tau, w);
+  SAP_HIP_TRY(hipGetLastError());
+  return SAP_OK;
+}
 
 sap_status qr_unblocked(sap_ctx *ctx, double *Y, int64_t ldy, int rows, int cols, double *tau, void *work,
                         hipStream_t st) {
@@ -353,10 +513,10 @@ sap_status qr_unblocked(sap_ctx *ctx, double *Y, int64_t ldy, int rows, int cols
   // sums, which more waves lengthen.)  4-column steps up to 2048 rows as
   // well: twice the launches of 8-column steps, each with half the panel's
   // dependent column reductions (2000 x 501: 2.09 -> 1.67 ms).
-  if (rows <= 512) return qr_run<1, 4, 512>(ctx, Y, ldy, rows, cols, tau, work, st);
-  if (rows <= 1024) return qr_run<2, 4, 512>(ctx, Y, ldy, rows, cols, tau, work, st);
-  if (rows <= 2048) return qr_run<4, 4, 512>(ctx, Y, ldy, rows, cols, tau, work, st);
-  if (rows <= 4096) return qr_run<8, 4, 512>(ctx, Y, ldy, rows, cols, tau, work, st);
+  if (rows <= 512) return qr_chain<1>(ctx, Y, ldy, rows, cols, tau, work, st);
+  if (rows <= 1024) return qr_chain<2>(ctx, Y, ldy, rows, cols, tau, work, st);
+  if (rows <= 2048) return qr_chain<4>(ctx, Y, ldy, rows, cols, tau, work, st);
+  if (rows <= kChainMaxRows) return qr_chain<8>(ctx, Y, ldy, rows, cols, tau, work, st);
   if (rows <= 8192) return qr_run<16, 2, 512>(ctx, Y, ldy, rows, cols, tau, work, st);
   if (rows <= 16384) return qr_run<32, 1, 512>(ctx, Y, ldy, rows, cols, tau, work, st);
   return fail(ctx, SAP_EINVAL, "sap_qr: more than 16384 rows is not supported");
@@ -376,7 +536,7 @@ sap_status qr_blocked(sap_ctx *ctx, double *Y, int64_t ldy, int rows, int cols, 
   const int kmax = std::min(rows, cols);
   const int64_t ldw = cols;  // >= kWy + the widest trailing part
   Carve cv(work);
-  void *pwork = cv.take<char>(kUnblockedBytes);
+  void *pwork = cv.take<char>(kUnblockedBytes + chain_bytes(kWy));
   double *Wp = cv.take<double>(static_cast<size_t>(kMaxSplits) * kWy * ldw);
   double *Wsum = cv.take<double>(static_cast<size_t>(kWy) * ldw);
   double *W2 = cv.take<double>(static_cast<size_t>(kWy) * cols);
@@ -406,7 +566,7 @@ sap_status qr_blocked(sap_ctx *ctx, double *Y, int64_t ldy, int rows, int cols, 
 }  // namespace
 
 size_t qr_workspace_bytes(int rows, int cols) {
-  size_t b = kUnblockedBytes;
+  size_t b = kUnblockedBytes + chain_bytes(cols);
   if (use_blocked(rows, cols))
     b += 4 * 256 + sizeof(double) * static_cast<size_t>(kMaxSplits + 2) * kWy * cols;
   return b;

@@ -213,7 +213,9 @@ def test_apply_ignores_out_of_range_rows(sap, orc):
 # rows > 4096 with cols > 192 takes the two-level (64-column panel, WY trailing update) path
 QR_CASES = [(400, 101), (4000, 1001), (1000, 1000), (5, 3), (700, 1), (2500, 64), (8192, 130), (16384, 40),
             (513, 100), (1100, 17), (8192, 600), (5000, 257), (700, 259), (300, 300), (193, 193),
-            (6000, 700), (4100, 193), (9000, 130)]
+            (6000, 700), (4100, 193), (9000, 130),
+            # chained one-level path with more workgroups (one per 4 columns) than compute units
+            (1200, 1200)]
 
 
 @pytest.mark.parametrize("rows,cols", QR_CASES)
@@ -242,11 +244,13 @@ def test_qr_parity(sap, orc, rows, cols):
         assert np.linalg.norm(Q @ R - Y) <= 1e-12 * np.linalg.norm(Y) * max(1, np.sqrt(rows) / 10)
 
 
-def test_qr_blocked_zero_reflector(sap, orc):
-    """A zero column in the two-level path gives tau = 0 inside a panel; the
-    compact-WY update must then drop that reflector (as LAPACK's T does)."""
+@pytest.mark.parametrize("rows", [5000, 3000])
+def test_qr_blocked_zero_reflector(sap, orc, rows):
+    """A zero column gives tau = 0 inside a panel; the block reflector must then
+    drop that reflector (as LAPACK's T does): the two-level path's compact-WY
+    update at 5000 rows, the chained one-level path's T at 3000 rows."""
     import torch
-    rows, cols = 5000, 300
+    cols = 300
     rng = np.random.default_rng(11)
     Y = rng.standard_normal((rows, cols))
     Y[:, 100] = 0.0
