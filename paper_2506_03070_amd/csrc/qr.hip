@@ -1,28 +1,27 @@
 // Blocked Householder QR of the sketch Y (d x ncols, column-major, FP64) on
 // gfx950 (the factorization step of Alg. 1; the paper calls a vendor QR).
 //
-// Right-looking blocked algorithm (Golub & Van Loan 5.2.2) with the compact
-// WY form Q = I - V T V^T of Schreiber & Van Loan (1989), one launch per
-// panel of NB columns:
-//   * every 512-thread workgroup owns a block of NB trailing columns, holds
-//     its rows in registers (thread t owns rows t, t+512, ...), and applies
-//     Q_k^T = I - V T^T V^T to it: W = V^T C is NB*NB workgroup-wide sums,
-//     W2 = T^T W, C -= V W2; the block is read once and written once;
-//   * workgroup 0's block is the next panel, which it factors on the spot
-//     (look-ahead) into the other of two T buffers: per column one workgroup
-//     reduction for the norm below the diagonal and one batched reduction that
-//     gives both v_j^T C (the update of the panel columns to its right) and
-//     V_{<j}^T v_j (the next column of T).
-// Chained form (sketches up to 4096 rows): the same block reflectors in one
-// launch.  Workgroup j (numbered in the order the workgroups start, from an
-// atomic ticket) owns columns 4j .. 4j+3 in registers for the whole
-// factorisation; it applies panel k as soon as panel k's owner has published
-// it (its reflectors and T written through to the coherence point shared by
-// the XCDs, then a flag), then factors its own panel and publishes it.  The
-// trailing matrix never goes back to memory between panels, and no launch
+// Blocked Householder QR (Golub & Van Loan 5.2.2) with the compact WY form
+// Q = I - V T V^T of Schreiber & Van Loan (1989), in one launch (the chained
+// form): workgroup j, numbered in the order the workgroups start (an atomic
+// ticket), owns columns NB j .. NB j + NB-1 (NB = 4 up to 4096 rows, 2 up to
+// 8192, 1 up to 16384) and holds all their rows in registers for the whole
+// factorisation (thread t owns rows t, t+512, ...).
+//   * it applies panel k, Q_k^T = I - V T^T V^T (W = V^T C as NB*NB
+//     workgroup-wide sums, W2 = T^T W, C -= V W2), as soon as panel k's owner
+//     has published it: reflectors and T written through to the coherence
+//     point shared by the XCDs, then a flag;
+//   * it then factors its own panel, one workgroup reduction per column for
+//     the norm below the diagonal and one batched reduction that gives both
+//     v_j^T C (the update of the panel columns to its right) and V_{<j}^T v_j
+//     (the next column of T), and publishes it.
+// The trailing matrix never goes back to memory between panels and no launch
 // boundary separates them: a panel's critical path is one block apply and one
 // panel factorisation.  A workgroup only waits for workgroups that started
 // before it, so the chain completes whatever number of them is resident.
+// Sketches taller than 4096 rows and wider than 192 columns take the
+// two-level form below: 64-column panels factored by the chained form, the
+// trailing matrix updated on the FP64 matrix cores.
 // Sign convention: LAPACK dlarfg, beta = -sign(alpha) ||(alpha, x)||.
 #include <algorithm>
 
@@ -34,40 +33,6 @@ namespace sap {
 namespace {
 
 using namespace qr_dev;
-
-// The first panel (columns 0 .. nb-1).  TH threads, S rows each.
-template <int S, int NB, int TH>
-__global__ __launch_bounds__(TH) void qr_first_panel_kernel(double *__restrict__ Y, int64_t ldy, int d, int nb,
-                                                            double *__restrict__ tau, double *__restrict__ Tout) {
-  __shared__ PanelShared<NB, TH> sh;
-  double P[S][NB];
-  load_block<S, NB, TH>(Y, ldy, 0, d, 0, nb, P);
-  factor_panel<S, NB>(P, sh, nb, d, 0, 0, tau, Tout);
-  store_block<S, NB, TH>(Y, ldy, 0, d, 0, nb, P);
-}
-
-// One step of the right-looking factorisation: every workgroup applies
-// Q_k^T (panel k = columns k0 .. k0+nb-1) to its block of NB trailing
-// columns; workgroup 0's block is panel k+1, which it then factors at once
-// (look-ahead) into Tnext.
-template <int S, int NB, int TH>
-__global__ __launch_bounds__(TH) void qr_step_kernel(double *__restrict__ Y, int64_t ldy, int d, int ncols, int k0,
-                                                     int nb, const double *__restrict__ Tcur,
-                                                     double *__restrict__ Tnext, double *__restrict__ tau) {
-  __shared__ PanelShared<NB, TH> sh;
-  const int c0 = k0 + nb + static_cast<int>(blockIdx.x) * NB;
-  const int ncb = min(NB, ncols - c0);
-  const int dr = d - k0;
-  double C[S][NB];
-  load_block<S, NB, TH>(Y, ldy, k0, dr, c0, ncb, C);
-  apply_panel_qt<S, NB>(Y, ldy, dr, k0, nb, Tcur, C, ncb, sh);
-  if (blockIdx.x == 0) {
-    // panel k+1 starts at row and column k1 = c0; rows k0..k1-1 ride along
-    const int k1 = c0;
-    factor_panel<S, NB>(C, sh, ncb, d - k1, k1 - k0, k1, tau, Tnext);
-  }
-  store_block<S, NB, TH>(Y, ldy, k0, dr, c0, ncb, C);
-}
 
 // Chained QR: C <- (I - V T^T V^T) C for a block held at fixed rows (thread t
 // holds rows t + TH s of the whole column block), with panel k's reflectors
@@ -458,73 +423,51 @@ __global__ __launch_bounds__(kWyThreads) void qr_wy_update_kernel(double *__rest
   }
 }
 
-template <int S, int NB, int TH>
-sap_status qr_run(sap_ctx *ctx, double *Y, int64_t ldy, int rows, int cols, double *tau, void *work,
-                  hipStream_t st) {
-  Carve cv(work);
-  double *T[2] = {cv.take<double>(NB * NB), cv.take<double>(NB * NB)};
-  const int kmax = rows < cols ? rows : cols;
-  int nb = kmax < NB ? kmax : NB;
-  qr_first_panel_kernel<S, NB, TH><<<1, TH, 0, st>>>(Y, ldy, rows, nb, tau, T[0]);
-  SAP_HIP_TRY(hipGetLastError());
-  int cur = 0;
-  for (int k0 = 0; k0 + nb < cols; k0 += NB) {
-    const int trailing = cols - (k0 + nb);
-    const int nblocks = (trailing + NB - 1) / NB;
-    qr_step_kernel<S, NB, TH><<<nblocks, TH, 0, st>>>(Y, ldy, rows, cols, k0, nb, T[cur], T[1 - cur], tau);
-    SAP_HIP_TRY(hipGetLastError());
-    cur ^= 1;
-    nb = (cols - (k0 + NB)) < NB ? (cols - (k0 + NB)) : NB;
-  }
-  return SAP_OK;
-}
-
 constexpr size_t kUnblockedBytes = 4 * 256 + 2 * sizeof(double) * 16 * 16;
-constexpr int kChainNB = 4;
-constexpr int kChainMaxRows = 4096;
-
+// Workspace of the chained form for any NB <= 4: NB x NB of T per block and
+// one ticket word plus one flag per block.
 size_t chain_bytes(int cols) {
-  const size_t nblk = static_cast<size_t>((cols + kChainNB - 1) / kChainNB);
-  return 2 * 256 + sizeof(double) * kChainNB * kChainNB * nblk + sizeof(int) * (nblk + 1);
+  const size_t c = static_cast<size_t>(cols);
+  return 2 * 256 + sizeof(double) * 16 * ((c + 3) / 4) + sizeof(int) * (c + 1);
 }
 
-template <int S>
+template <int S, int NB>
 sap_status qr_chain(sap_ctx *ctx, double *Y, int64_t ldy, int rows, int cols, double *tau, void *work,
                     hipStream_t st) {
   constexpr int TH = 512;
-  static_assert(S * TH >= kChainMaxRows || S < 8, "rows per thread");
-  const int nblk = (cols + kChainNB - 1) / kChainNB;
+  if (rows > S * TH) return fail(ctx, SAP_EINVAL, "sap_qr: rows exceed the register block");
+  const int nblk = (cols + NB - 1) / NB;
   Carve cv(work);
-  double *Tall = cv.take<double>(static_cast<size_t>(kChainNB) * kChainNB * nblk);
+  double *Tall = cv.take<double>(static_cast<size_t>(NB) * NB * nblk);
   int *w = cv.take<int>(static_cast<size_t>(nblk) + 1);
   qr_chain_zero_kernel<<<1, 256, 0, st>>>(w, nblk + 1);
   SAP_HIP_TRY(hipGetLastError());
-  qr_chain_kernel<S, kChainNB, TH><<<nblk, TH, 0, st>>>(Y, ldy, rows, cols, Tall, tau, w);
+  qr_chain_kernel<S, NB, TH><<<nblk, TH, 0, st>>>(Y, ldy, rows, cols, Tall, tau, w);
   SAP_HIP_TRY(hipGetLastError());
   return SAP_OK;
 }
 
 sap_status qr_unblocked(sap_ctx *ctx, double *Y, int64_t ldy, int rows, int cols, double *tau, void *work,
                         hipStream_t st) {
-  // S rows per thread, NB columns per step, TH threads: the register blocks
-  // (S * NB doubles per thread, twice: V and C) must fit in the 256 VGPRs a
-  // lane keeps at 512 threads.  (1024-thread steps, S halved, measured ~20%
-  // slower at 4000 x 1001: the steps are bound by barriers and cross-wave
-  // sums, which more waves lengthen.)  4-column steps up to 2048 rows as
-  // well: twice the launches of 8-column steps, each with half the panel's
-  // dependent column reductions (2000 x 501: 2.09 -> 1.67 ms).
-  if (rows <= 512) return qr_chain<1>(ctx, Y, ldy, rows, cols, tau, work, st);
-  if (rows <= 1024) return qr_chain<2>(ctx, Y, ldy, rows, cols, tau, work, st);
-  if (rows <= 2048) return qr_chain<4>(ctx, Y, ldy, rows, cols, tau, work, st);
-  if (rows <= kChainMaxRows) return qr_chain<8>(ctx, Y, ldy, rows, cols, tau, work, st);
-  if (rows <= 8192) return qr_run<16, 2, 512>(ctx, Y, ldy, rows, cols, tau, work, st);
-  if (rows <= 16384) return qr_run<32, 1, 512>(ctx, Y, ldy, rows, cols, tau, work, st);
+  // S rows per thread, NB columns per block, 512 threads: the register
+  // blocks (S * NB doubles per thread, twice: V and C) must fit in the 256
+  // VGPRs a lane keeps at 512 threads.  (1024 threads with S halved measured
+  // ~20% slower at 4000 x 1001: the panels are bound by barriers and
+  // cross-wave sums, which more waves lengthen.)  4-column blocks up to 2048
+  // rows as well: 8-column panels measured 20-25% slower there, twice the
+  // dependent column reductions per panel.
+  if (rows <= 512) return qr_chain<1, 4>(ctx, Y, ldy, rows, cols, tau, work, st);
+  if (rows <= 1024) return qr_chain<2, 4>(ctx, Y, ldy, rows, cols, tau, work, st);
+  if (rows <= 2048) return qr_chain<4, 4>(ctx, Y, ldy, rows, cols, tau, work, st);
+  if (rows <= 4096) return qr_chain<8, 4>(ctx, Y, ldy, rows, cols, tau, work, st);
+  if (rows <= 8192) return qr_chain<16, 2>(ctx, Y, ldy, rows, cols, tau, work, st);
+  if (rows <= 16384) return qr_chain<32, 1>(ctx, Y, ldy, rows, cols, tau, work, st);
   return fail(ctx, SAP_EINVAL, "sap_qr: more than 16384 rows is not supported");
 }
 
-// The two-level form pays off where the one-level steps are bound by the
-// traffic of the trailing matrix (tall sketches, narrow NB); below that the
-// one-level steps are bound by the panel's reduction latency, which the
+// The two-level form pays off where the one-level panels are bound by the
+// trailing matrix (tall sketches, narrow NB); below that the one-level
+// panels are bound by the panel's reduction latency, which the
 // two-level form does not shorten.
 bool use_blocked(int rows, int cols) { return cols > 3 * kWy && rows > 4096; }
 
