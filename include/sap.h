@@ -42,7 +42,7 @@ extern "C" {
 
 typedef enum sap_status {
     SAP_OK = 0,
-    SAP_EINVAL = 1,          /* invalid argument (shape, pointer, dtype, non-finite b) */
+    SAP_EINVAL = 1,          /* invalid argument (shape, pointer, dtype, non-finite b or A) */
     SAP_ENOMEM = 2,          /* workspace would exceed the context's HBM budget */
     SAP_RANK_DEFICIENT = 3,  /* min |R_kk| <= d * 2^-53 * max |R_kk| */
     SAP_NOT_CONVERGED = 4,   /* maxiter reached; x holds the last iterate */
@@ -228,7 +228,8 @@ typedef struct sap_info {
  * with ||A M|| ~ 1 by Lemma 2.4): stop after iteration t when
  * alpha_{t+1} |c_t| <= tol, or phibar_{t+1} <= tol ||b||, or on breakdown
  * (beta or alpha exactly 0).  Blocking: returns when x is written.
- * Errors: SAP_EINVAL (shapes, dtype/mode mismatch, non-finite b),
+ * Errors: SAP_EINVAL (shapes, dtype/mode mismatch, non-finite b, non-finite A
+ * found through a non-finite diagonal of the sketch's R),
  * SAP_ENOMEM, SAP_RANK_DEFICIENT (x untouched), SAP_NOT_CONVERGED (x holds
  * the last iterate), SAP_EDEVICE. */
 sap_status sap_solve(sap_ctx *ctx, const sap_problem *prob, const sap_params *params, double *x,

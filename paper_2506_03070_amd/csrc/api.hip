@@ -536,6 +536,7 @@ static sap_status solve_dense(sap_ctx *ctx, const sap_problem *prob, const sap_p
   SAP_HIP_TRY(hipStreamSynchronize(st));
   if (hf.nonfinite_b) return fail(ctx, SAP_EINVAL, "sap_solve: b has non-finite entries");
   if (hf.gen_error) return fail(ctx, SAP_EDEVICE, "sap_solve: sketch generation hit its round cap");
+  if (hf.rank_deficient == 2) return fail(ctx, SAP_EINVAL, "sap_solve: the sketch's R is not finite (non-finite A)");
   if (hf.rank_deficient) {
     if (info) info->status = SAP_RANK_DEFICIENT;
     return fail(ctx, SAP_RANK_DEFICIENT, "sap_solve: R is numerically singular (A rank deficient)");
@@ -732,6 +733,8 @@ sap_status sap_solve_csr(sap_ctx *ctx, const sap_csr *A, const double *b, const 
                 "sap_solve_csr: indptr must start at 0, end at nnz and not decrease; column indices must lie in [0, n)");
   if (hf.nonfinite_b) return fail(ctx, SAP_EINVAL, "sap_solve_csr: b has non-finite entries");
   if (hf.gen_error) return fail(ctx, SAP_EDEVICE, "sap_solve_csr: sketch generation hit its round cap");
+  if (hf.rank_deficient == 2)
+    return fail(ctx, SAP_EINVAL, "sap_solve_csr: the sketch's R is not finite (non-finite A)");
   if (hf.rank_deficient) {
     if (info) info->status = SAP_RANK_DEFICIENT;
     return fail(ctx, SAP_RANK_DEFICIENT, "sap_solve_csr: R is numerically singular (A rank deficient)");

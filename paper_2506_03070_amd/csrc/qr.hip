@@ -94,7 +94,8 @@ __device__ __forceinline__ void chain_apply_panel(const double *__restrict__ Y, 
 }
 
 // A wait of the chain gives up after this many polls (a producer that never
-// ran, which the start-ordered tickets rule out); the block is then NaN.
+// ran, which the start-ordered tickets rule out); the block is then NaN, which
+// the rank test that follows every solve's QR reports as a non-finite R.
 constexpr int kQrSpinLimit = 1 << 20;
 
 // One launch of ceil(cols / NB) workgroups; w: the ticket word and one flag
@@ -160,16 +161,23 @@ __global__ void qr_chain_zero_kernel(int *w, int count) {
   for (int i = threadIdx.x; i < count; i += blockDim.x) w[i] = 0;
 }
 
-// Rank test on R's diagonal: deficient when min |R_kk| <= d * 2^-53 * max |R_kk|.
+// Rank test on R's diagonal: deficient (1) when min |R_kk| <= d * 2^-53 * max |R_kk|,
+// 2 when an R_kk is not finite.
 __global__ __launch_bounds__(1024) void rank_check_kernel(const double *__restrict__ R, int64_t ldr,
                                                           int n, int d, int *__restrict__ flag) {
   __shared__ double smax[16], smin[16];
+  __shared__ int sbad;
+  if (threadIdx.x == 0) sbad = 0;
+  __syncthreads();
   double mx = 0.0, mn = INFINITY;
+  bool bad = false;
   for (int k = threadIdx.x; k < n; k += 1024) {
     const double a = fabs(R[k + static_cast<int64_t>(k) * ldr]);
+    bad = bad || !isfinite(a);
     mx = fmax(mx, a);
     mn = fmin(mn, a);
   }
+  if (bad) atomicOr(&sbad, 1);
   mx = wave_max(mx);
   mn = -wave_max(-mn);
   const int lane = threadIdx.x & 63, wave = threadIdx.x / 64;
@@ -183,7 +191,8 @@ __global__ __launch_bounds__(1024) void rank_check_kernel(const double *__restri
       mx = fmax(mx, smax[w]);
       mn = fmin(mn, smin[w]);
     }
-    *flag = !(mn > static_cast<double>(d) * 0x1p-53 * mx);
+    // 2: a non-finite diagonal (non-finite A, or a chained-QR wait that expired)
+    *flag = sbad ? 2 : !(mn > static_cast<double>(d) * 0x1p-53 * mx);
   }
 }
 

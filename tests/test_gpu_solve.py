@@ -229,6 +229,12 @@ def test_solve_errors(sap):
     with pytest.raises(sap.SapError) as e:
         sap.sap_solve(_dev(p.A), _dev(bad), 40, 8, 1)
     assert e.value.status == sap.SAP_EINVAL
+    badA = p.A.copy()
+    badA[123, 4] = np.inf
+    _note("solve inf A")
+    with pytest.raises(sap.SapError) as e:
+        sap.sap_solve(_dev(badA), _dev(p.b), 40, 8, 1)
+    assert e.value.status == sap.SAP_EINVAL and "not finite" in str(e.value)
     _note("solve dtype mismatch")
     with pytest.raises(sap.SapError) as e:
         sap.sap_solve(_dev(p.A.astype(np.float32)), _dev(p.b), 40, 8, 1, mode=sap.SAP_MODE_FP64)
