@@ -244,6 +244,27 @@ def test_qr_parity(sap, orc, rows, cols):
         assert np.linalg.norm(Q @ R - Y) <= 1e-12 * np.linalg.norm(Y) * max(1, np.sqrt(rows) / 10)
 
 
+@pytest.mark.parametrize("rows,cols", [(4000, 1001), (2048, 1500), (8192, 700)])
+def test_qr_chain_reproducible(sap, rows, cols):
+    """The chained QR hands each block to whichever workgroup draws its ticket,
+    but no sum crosses workgroups, so repeated factorisations of the same
+    matrix must agree bit for bit (here with more blocks than compute units at
+    2048 x 1500, and through the two-level path's chained panels at 8192 rows)."""
+    import torch
+    _note(f"qr-repro rows={rows} cols={cols}")
+    g = torch.Generator(device="cuda")
+    g.manual_seed(rows + cols)
+    Y0 = torch.randn(cols, rows, generator=g, dtype=torch.float64, device="cuda")
+    outs = []
+    for _ in range(3):
+        Y = Y0.clone()
+        tau = sap.sap_qr(Y)
+        torch.cuda.synchronize()
+        outs.append((Y.cpu(), tau.cpu()))
+    for Y, tau in outs[1:]:
+        assert torch.equal(Y, outs[0][0]) and torch.equal(tau, outs[0][1])
+
+
 @pytest.mark.parametrize("rows", [5000, 3000])
 def test_qr_blocked_zero_reflector(sap, orc, rows):
     """A zero column gives tau = 0 inside a panel; the block reflector must then
