@@ -1,6 +1,7 @@
-// Device code of the blocked Householder QR (qr.hip), shared by the single
-// and batched launches: register-block panel factorisation with the LAPACK
-// dlarfg sign convention and the compact-WY block-reflector apply.
+// Device code of the blocked Householder QR, shared by the chained single QR
+// (qr.hip) and the batched step launches (batch.hip): register-block panel
+// factorisation with the LAPACK dlarfg sign convention, block loads and
+// stores, and the compact-WY block-reflector apply of the batched steps.
 #pragma once
 
 #include "common.h"
